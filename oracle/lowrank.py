@@ -1,0 +1,346 @@
+"""Low-rank SI-DSA of the oracle: Alg. 1 with the low-rank SI of Sec. 3.1-3.4 and Alg. 2.
+
+Steps of one low-rank SI (outer iteration n), in the paper's order (Sec. 3.1):
+  1. sweep the p sampled ordinates, eq. (sampled-sweep);
+  2. MGS2-A (Alg. 2): append the snapshots to the spatial basis X, R gets a column
+     (c, alpha) per snapshot; snapshots of one batch are processed one after the
+     other (Sec. 3.4);
+  3. incremental update of the projected operators X^T Sigma_t X, X^T D_x^{+-} X,
+     X^T D_y^{+-} X and the projected right-hand sides (Sec. 3.4, bordering);
+  4. q random previously unsampled candidates, Galerkin projection
+     eq. (galerkin-projection), residuals, greedy choice of the p largest (Sec. 3.2);
+  5. stopping test (Sec. 3.3): residual check eq. (residual-chk), then the full
+     projection phi^{n,k} = X (C w) and the test eq. (phi-diff);
+  6. after the inner loop, the truncated SVD C = U S V^T and X^{n} = X U (Sec. 3.3).
+
+Readings (also implemented by the GPU library; each is listed in the design doc):
+  * X is empty at the start of every outer iteration and p initial angles are
+    drawn at random (r_k = p k, Sec. 3.2 "Initial sampling");
+  * "angles" in the sampling are the distinct (Omega_x, Omega_y) of the ordinate set:
+    in 2D X-Y geometry D_j depends on Omega_j only through (Omega_x, Omega_y)
+    (eq. (upwind-operator)), so ordinates with equal (Omega_x, Omega_y) (the Omega_z
+    twins of the full-sphere CL rule) share eq. (SI), its sweep and its Galerkin
+    projection; one sweep samples the whole class and candidates are drawn among
+    unsampled classes.  (Sampling a twin separately adds nothing to X, and two
+    consecutive stop checks with an unchanged X pass the phi-difference test
+    spuriously);
+  * the residual source Sigma_s phi^{(k)} is read as Sigma_s phi^{n-1} (the source of
+    eq. (sampled-sweep)); eps_res and eps_diff are absolute thresholds on the
+    coefficient 2-norm;
+  * random draws: a caller-supplied stream of uint64 values u; a draw of k items from
+    the ascending list of n unsampled class indices is a partial Fisher-Yates shuffle with
+    swap index i + floor(u (n - i) / 2^64); candidates are all unsampled ordinates
+    when fewer than q remain;
+  * classes are numbered in the order of their smallest ordinate index; greedy order:
+    residual norm descending, class index ascending on ties;
+  * the next samples are the top p of the current candidates, also after a failed
+    phi-difference test; the inner loop also ends when every class is sampled;
+  * MGS2-A breakdown (not specified by the paper): if alpha <= tol_break * ||psi||,
+    the snapshot is not appended and the sampled class keeps the coefficient c;
+  * truncation rank r' = smallest l with sum_{i>l} s_i <= eps_svd sum_i s_i.
+"""
+import numpy as np
+import scipy.linalg as sla
+
+from . import dg, sweep
+
+MASK64 = (1 << 64) - 1
+
+
+class RandomStream:
+    """Consumes a caller-given array of uint64 values in order."""
+
+    def __init__(self, values):
+        self.v = np.asarray(values, dtype=np.uint64)
+        self.i = 0
+
+    def next(self):
+        if self.i >= self.v.size:
+            raise RuntimeError("random stream exhausted")
+        u = int(self.v[self.i])
+        self.i += 1
+        return u
+
+
+def draw(stream, pool, k):
+    """Draw k distinct items from the ascending list `pool` (partial Fisher-Yates)."""
+    arr = sorted(int(x) for x in pool)
+    n = len(arr)
+    k = min(k, n)
+    for i in range(k):
+        u = stream.next()
+        j = i + ((u * (n - i)) >> 64)
+        arr[i], arr[j] = arr[j], arr[i]
+    return arr[:k]
+
+
+def truncation_rank(s, eps_svd):
+    """Smallest l with sum_{i>l} s_i <= eps_svd * sum_i s_i (l1 tail, Sec. 4 setting)."""
+    s = np.asarray(s, dtype=np.float64)
+    if s.size == 0:
+        return 0
+    total = s.sum()
+    if total == 0.0:
+        return 0
+    for l in range(s.size + 1):
+        if s[l:].sum() <= eps_svd * total:
+            return l
+    return s.size
+
+
+def direction_classes(dirs, tol=1e-12):
+    """Group ordinates with equal (Omega_x, Omega_y); classes ordered by smallest member.
+
+    Returns (cls [N] class id of each ordinate, reps [K] smallest ordinate of each class).
+    """
+    n = len(dirs)
+    cls = -np.ones(n, dtype=np.int64)
+    reps = []
+    for j in range(n):
+        if cls[j] >= 0:
+            continue
+        cls[j] = len(reps)
+        for i in range(j + 1, n):
+            if cls[i] < 0 and abs(dirs[i, 0] - dirs[j, 0]) <= tol and abs(dirs[i, 1] - dirs[j, 1]) <= tol:
+                cls[i] = len(reps)
+        reps.append(j)
+    return cls, np.array(reps, dtype=np.int64)
+
+
+class LowRankSI:
+    """One low-rank SI solve (Sec. 3.1) for a fixed source Sigma_s phi^{n-1} + G."""
+
+    def __init__(self, prob, ops, p, q, eps_res, eps_diff, eps_mgs=1e-10, m_max=4,
+                 tol_break=1e-12, nthreads=0):
+        self.prob, self.ops = prob, ops
+        self.p, self.q = p, q
+        self.eps_res, self.eps_diff = eps_res, eps_diff
+        self.eps_mgs, self.m_max, self.tol_break = eps_mgs, m_max, tol_break
+        self.nthreads = nthreads
+
+    # ---------------- Alg. 2 (MGS2-A) ----------------
+    def mgs2a_append(self, psi):
+        """Orthogonalise one snapshot against X (Alg. 2, one pass of the l-loop).
+
+        Returns the R column for this snapshot (length r_new) and whether it was appended.
+        """
+        X = self.X
+        r = X.shape[1]
+        psi_hat = psi.copy()
+        c = np.zeros(r)
+        for _ in range(2):
+            dc = X.T @ psi_hat
+            psi_hat = psi_hat - X @ dc
+            c = c + dc
+        alpha = float(np.linalg.norm(psi_hat))
+        if alpha <= self.tol_break * float(np.linalg.norm(psi)):
+            self.breakdowns += 1
+            return c, False
+        psi_hat = psi_hat / alpha
+        for _ in range(self.m_max):
+            if r == 0 or abs(float(X[:, 0] @ psi_hat)) <= self.eps_mgs:
+                break
+            psi_hat = alpha * psi_hat
+            dc = X.T @ psi_hat
+            psi_hat = psi_hat - X @ dc
+            c = c + dc
+            alpha = float(np.linalg.norm(psi_hat))
+            psi_hat = psi_hat / alpha
+        if r > 0 and abs(float(X[:, 0] @ psi_hat)) > self.eps_mgs:
+            self.mgs_failures += 1
+        self.X = np.concatenate([X, psi_hat[:, None]], axis=1)
+        return np.concatenate([c, [alpha]]), True
+
+    # ---------------- incremental bordering (Sec. 3.4) ----------------
+    def border(self, P):
+        """Grow the projected operators and right-hand sides by the new columns P."""
+        if P.shape[1] == 0:
+            return
+        X = self.X                      # already contains P as its last columns
+        r_old = X.shape[1] - P.shape[1]
+        Xo = X[:, :r_old]
+        o = self.ops
+
+        def grow(M, Aop):
+            AP = Aop @ P                # new column block  X^T (A P)
+            ATP = Aop.T @ P             # new row block     P^T A X_old = (X_old^T A^T P)^T
+            col = X.T @ AP
+            row = (Xo.T @ ATP).T
+            out = np.zeros((X.shape[1], X.shape[1]))
+            out[:r_old, :r_old] = M
+            out[:, r_old:] = col
+            out[r_old:, :r_old] = row
+            return out
+
+        self.T = grow(self.T, o["Sig_t"])
+        self.Dxm = grow(self.Dxm, o["Dxm"]); self.Dxp = grow(self.Dxp, o["Dxp"])
+        self.Dym = grow(self.Dym, o["Dym"]); self.Dyp = grow(self.Dyp, o["Dyp"])
+        self.b_src = np.concatenate([self.b_src, P.T @ self.src])
+        self.b_side = np.concatenate([self.b_side, (P.T @ o["gside"].T).T], axis=1)
+
+    # ---------------- Galerkin projection, eq. (galerkin-projection) ----------------
+    def reduced_system(self, j):
+        """X^T (D_j + Sigma_t) X and X^T (Sigma_s phi^{n-1} + G~_j) for ordinate j."""
+        ox, oy = self.prob.dirs[j, 0], self.prob.dirs[j, 1]
+        A = self.T.copy()
+        A += ox * (self.Dxm if ox >= 0 else self.Dxp)
+        A += oy * (self.Dym if oy >= 0 else self.Dyp)
+        b = self.b_src.copy()
+        if ox > 0: b += ox * self.b_side[0]
+        elif ox < 0: b += -ox * self.b_side[1]
+        if oy > 0: b += oy * self.b_side[2]
+        elif oy < 0: b += -oy * self.b_side[3]
+        return A, b
+
+    def galerkin(self, j):
+        A, b = self.reduced_system(j)
+        return sla.solve(A, b)
+
+    def residual_norm(self, j, c):
+        """||Sigma_s phi^{n-1} + G~_j - (D_j + Sigma_t) X c||_2 (Sec. 3.2)."""
+        o = self.ops
+        ox, oy = self.prob.dirs[j, 0], self.prob.dirs[j, 1]
+        v = self.X @ c
+        Dv = ox * ((o["Dxm"] if ox >= 0 else o["Dxp"]) @ v) + oy * ((o["Dym"] if oy >= 0 else o["Dyp"]) @ v)
+        res = self.src + self.prob.g_bc(j) - Dv - o["Sig_t"] @ v
+        return float(np.linalg.norm(res))
+
+    def class_coefficients(self):
+        """Coefficients of every class: R columns if sampled, Galerkin otherwise."""
+        r = self.X.shape[1]
+        K = len(self.reps)
+        Cc = np.zeros((r, K))
+        for c in range(K):
+            if c in self.coef:
+                cc = self.coef[c]
+                Cc[:cc.size, c] = cc
+            else:
+                Cc[:, c] = self.galerkin(self.reps[c])
+        return Cc
+
+    # ---------------- the inner loop (Sec. 3.1-3.3) ----------------
+    def run(self, src, phi_prev, stream, replay=None):
+        """Low-rank SI for the source `src`.  `replay` forces the sampled classes per
+        inner iteration (a list of lists of class ids)."""
+        prob = self.prob
+        n = prob.mesh.ndof
+        self.cls, self.reps = direction_classes(prob.dirs)
+        K = len(self.reps)
+        wc = np.zeros(K)
+        np.add.at(wc, self.cls, prob.w)
+        self.src = src
+        self.X = np.zeros((n, 0))
+        self.T = np.zeros((0, 0)); self.Dxm = self.T.copy(); self.Dxp = self.T.copy()
+        self.Dym = self.T.copy(); self.Dyp = self.T.copy()
+        self.b_src = np.zeros(0); self.b_side = np.zeros((4, 0))
+        self.coef = {}
+        self.mgs_failures = 0
+        self.breakdowns = 0
+        self.n_swept = 0
+        log = []
+        phi_old = phi_prev.copy()
+        k = 0
+        samples = list(replay[0]) if replay is not None else draw(stream, range(K), self.p)
+        while True:
+            k += 1
+            # 1. sweeps of the sampled angles, eq. (sampled-sweep)
+            psi, _ = sweep.sweep(prob.mesh, prob.dirs, self.reps[samples], prob.sigma_t, src,
+                                 prob.bnd, want_psi=True, nthreads=self.nthreads)
+            self.n_swept += len(samples)
+            # 2. MGS2-A, one snapshot after the other
+            r_before = self.X.shape[1]
+            for i, c in enumerate(samples):
+                col, _ = self.mgs2a_append(psi[i])
+                self.coef[c] = col
+            # 3. bordering with the appended columns
+            self.border(self.X[:, r_before:])
+            entry = dict(k=k, samples=list(samples), rank=self.X.shape[1])
+            unsampled = [c for c in range(K) if c not in self.coef]
+            if not unsampled:
+                Cc = self.class_coefficients()
+                phi = self.X @ (Cc @ wc)
+                entry.update(stop="all_sampled")
+                log.append(entry)
+                break
+            # 4. candidates, Galerkin, residuals
+            cand = draw(stream, unsampled, self.q)
+            res = {c: self.residual_norm(self.reps[c], self.galerkin(self.reps[c])) for c in cand}
+            entry.update(candidates=list(cand), residuals=[res[c] for c in cand])
+            order = sorted(cand, key=lambda c: (-res[c], c))
+            # 5. stopping test, Sec. 3.3
+            stop = False
+            if max(res.values()) < self.eps_res:
+                Cc = self.class_coefficients()
+                phi = self.X @ (Cc @ wc)
+                dphi = float(np.linalg.norm(phi - phi_old))
+                entry.update(phi_diff=dphi)
+                if dphi <= self.eps_diff:
+                    stop = True
+                else:
+                    phi_old = phi
+            log.append(entry)
+            if stop:
+                break
+            if replay is not None:
+                if k >= len(replay):
+                    raise RuntimeError("replay sequence exhausted")
+                samples = list(replay[k])
+            else:
+                samples = order[:self.p]
+        self.C = Cc[:, self.cls]            # r x N_Omega, every ordinate takes its class column
+        self.phi = phi
+        self.log = log
+        return phi
+
+    def truncate(self, eps_svd):
+        """Truncated SVD of C and X^{n} = X U (Sec. 3.3, construction after convergence)."""
+        U, s, Vt = np.linalg.svd(self.C, full_matrices=False)
+        rp = truncation_rank(s, eps_svd)
+        return self.X @ U[:, :rp], s[:rp], Vt[:rp].T, s
+
+
+def operators(prob):
+    """The sparse operators the low-rank SI needs (Appendix B)."""
+    Dxm, Dxp, Dym, Dyp = dg.directional_operators(prob.mesh)
+    mesh = prob.mesh
+    gside = np.zeros((4, mesh.ndof))
+    # unit boundary vectors of the four sides (per unit |Omega . n|)
+    for s, (ox, oy) in enumerate(((1.0, 0.0), (-1.0, 0.0), (0.0, 1.0), (0.0, -1.0))):
+        gside[s] = dg.boundary_vector(mesh, prob.bnd, ox, oy)
+    return dict(Dxm=Dxm.tocsr(), Dxp=Dxp.tocsr(), Dym=Dym.tocsr(), Dyp=Dyp.tocsr(),
+                Sig_t=dg.cell_sigma_diag(mesh, prob.sigma_t).tocsr(), gside=gside)
+
+
+def lr_si_dsa(prob, eps_si, p, q, eps_res, eps_diff, eps_svd, rand, eps_mgs=1e-10, m_max=4,
+              max_outer=100, phi0=None, use_dsa=True, replay=None, tol_break=1e-12,
+              nthreads=0, keep_factors=True):
+    """Alg. 1.  `rand` is the uint64 stream; `replay` optionally forces samples per outer."""
+    ops = operators(prob)
+    stream = RandomStream(rand)
+    phi_prev = np.zeros(prob.mesh.ndof) if phi0 is None else np.asarray(phi0, dtype=np.float64).copy()
+    hist, logs, ranks, sampled = [], [], [], []
+    lr = LowRankSI(prob, ops, p, q, eps_res, eps_diff, eps_mgs, m_max, tol_break, nthreads)
+    mgs_fail = 0
+    out = None
+    phi_star = phi_prev
+    for n in range(1, max_outer + 1):
+        src = prob.sig_s4 * phi_prev + prob.G
+        phi_star = lr.run(src, phi_prev, stream, None if replay is None else replay[n - 1])
+        mgs_fail += lr.mgs_failures
+        Xn, S, V, s_all = lr.truncate(eps_svd)
+        ranks.append(S.size)
+        sampled.append(lr.n_swept)
+        logs.append(lr.log)
+        d = float(np.max(np.abs(phi_star - phi_prev)))
+        hist.append(d)
+        if d <= eps_si:
+            out = dict(phi=phi_star, iters=n, converged=True)
+            break
+        phi_prev = phi_star + prob.dsa().correction(phi_star, phi_prev) if use_dsa else phi_star
+    if out is None:
+        out = dict(phi=phi_star, iters=max_outer, converged=False)
+    out.update(history=hist, logs=logs, ranks=ranks, n_sampled=sampled, mgs_failures=mgs_fail,
+               rand_used=stream.i)
+    if keep_factors:
+        out.update(X=Xn, S=S, V=V, singular_values=s_all, C=lr.C, Xfull=lr.X)
+    return out
