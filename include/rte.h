@@ -1,0 +1,200 @@
+/*
+ * rte.h -- C ABI of the MI355X (gfx950) library for the rank-adaptive,
+ * sweep-based SI-DSA of the steady first-order radiative transfer equation
+ * (W. Guo, Z. Peng, arXiv 2603.25233).
+ *
+ * Problem (paper Sec. 2, eq. (rte)): mono-energetic, isotropic scattering,
+ *     Omega . grad psi + sigma_t psi = sigma_s phi + G,  phi = (1/4pi) int psi,
+ * on a rectangle [x0,x1] x [y0,y1] with isotropic inflow data g (vacuum: g = 0).
+ * Discretisation (Sec. 2.1, Appendix A/B): discrete ordinates with normalised
+ * weights (sum w_j = 1) and upwind DG-Q1 on a uniform nx x ny Cartesian mesh, giving
+ * eq. (mat-vec-a):  (D_j + Sigma_t) psi_j = Sigma_s phi + G + g_j^bc.
+ *
+ * Conventions shared by every entry point
+ *   - Cell (a, b) (a along x, b along y) has index c = b*nx + a; a scalar field is
+ *     [ny][nx]; a DG field is [ny][nx][4] (ndof = 4*nx*ny).  The cell basis is
+ *     orthonormal: eta_{pq} = l_p(x) l_q(y), l_0 = 1/sqrt(h), l_1 = sqrt(3) xi/sqrt(h)
+ *     with xi in [-1,1] the cell-local coordinate, local index k = 2q + p.
+ *   - Inflow data g: [4][max(nx,ny)][2] face moments g_m = int_face g l_m(s) ds on
+ *     the sides L (x = x0), R (x = x1), B (y = y0), T (y = y1); s = y on L/R and
+ *     s = x on B/T, l_1 increasing with s.  NULL means vacuum.
+ *   - "HOST" pointers are read on the host during the call.  "DEV" pointers are
+ *     device (HBM) pointers owned by the caller; the library never frees them.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Sweeps are asynchronous
+ *     on it; the solver returns after its work on `stream` has finished (its
+ *     sampling and stopping decisions are taken on the host).
+ *   - Every call returns an rte_status; on error nothing is thrown or aborted and
+ *     rte_last_error() gives a message (thread-local, valid until the next call
+ *     from the same thread).  Workspace is allocated with hipMalloc inside the call
+ *     and freed before it returns.
+ *   - The library runs on the current HIP device.
+ */
+#ifndef RTE_H
+#define RTE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RTE_OK = 0,
+  RTE_ENOCONV = 1,       /* iteration cap reached: outputs hold the last iterate      */
+  RTE_EINVAL = -1,       /* invalid argument (message says which)                     */
+  RTE_ENOMEM = -2,       /* device or host allocation failed                          */
+  RTE_EHIP = -3,         /* a HIP runtime call failed                                 */
+  RTE_ERAND = -4         /* the caller's random stream ran out                        */
+} rte_status;
+
+typedef enum {
+  RTE_FP64 = 0,          /* every step in float64                                     */
+  RTE_MIXED = 1          /* float32 sweeps, basis and projections; float64 reduced
+                            solves, residual norms, SVD, convergence tests and DSA    */
+} rte_precision;
+
+/* The discrete problem, eq. (mat-vec-a).                                           */
+typedef struct {
+  int32_t nx, ny;              /* cells along x, y (1 <= ny <= 1024 for the sweep)   */
+  double x0, x1, y0, y1;       /* domain, x0 < x1, y0 < y1                            */
+  int32_t n_dirs;              /* number of ordinates N_Omega                         */
+  const double* dirs;          /* HOST [n_dirs][3] unit vectors Omega_j               */
+  const double* wts;           /* HOST [n_dirs] weights, sum within 1e-12 of 1        */
+  const double* sigma_t;       /* DEV [ny][nx] total cross section, > 0               */
+  const double* sigma_s;       /* DEV [ny][nx] scattering, 0 <= sigma_s <= sigma_t    */
+  const double* G;             /* DEV [ny][nx][4] moments int_cell G eta_k, or NULL   */
+  const double* bc;            /* DEV [4][max(nx,ny)][2] inflow face moments, or NULL */
+} rte_problem;
+
+/*
+ * Transport sweep (paper Sec. 2.2, "Transport sweeps"; eqs. (SI), (sampled-sweep)).
+ * For each selected ordinate j = dir_idx[i] solves
+ *     (D_j + Sigma_t) psi_i = src + g_j^bc
+ * exactly, by one pass over the cells in upwind order.
+ *   dir_idx  HOST [n_sel] ordinate indices in [0, n_dirs)  (repeats allowed).
+ *   src      DEV  [ny][nx][4] isotropic right-hand side (e.g. Sigma_s phi + G);
+ *            float64, or float32 when prec == RTE_MIXED.
+ *   psi      DEV  [n_sel][ny][nx][4] output (same type as src), or NULL.
+ *   phi      DEV  [ny][nx][4] output (same type): overwritten with
+ *            sum_i wts[dir_idx[i]] psi_i, or NULL.  At least one of psi, phi.
+ * prob->G is not used (src is the whole isotropic right-hand side); prob->bc is.
+ */
+rte_status rte_sweep(const rte_problem* prob, const int32_t* dir_idx, int32_t n_sel,
+                     const void* src, void* psi, void* phi, rte_precision prec,
+                     void* stream);
+
+/*
+ * Adjoint sweep: solves (D_j + Sigma_t)^T mu_i = src + b_j for each j = dir_idx[i],
+ * where b_j holds |Omega_j . n| int_face g eta_k on the OUTFLOW sides of Omega_j
+ * (g = prob->bc): the right-hand side of the adjoint of an exit-current functional.
+ * The transposed operator is taken in downwind order with transposed cell blocks
+ * and couplings (D(Omega)^T = D(-Omega) for upwind DG).  Arguments as rte_sweep.
+ */
+rte_status rte_adjoint_sweep(const rte_problem* prob, const int32_t* dir_idx,
+                             int32_t n_sel, const void* src, void* psi, void* phi,
+                             rte_precision prec, void* stream);
+
+/* Solver settings (paper Sec. 2.2, Alg. 1, Sec. 3.2-3.4 and the settings of Sec. 4). */
+typedef struct {
+  int32_t full_rank;     /* 1: full-rank SI-DSA (every ordinate swept per outer step) */
+  int32_t adjoint;       /* 1: solve the adjoint system with adjoint sweeps
+                            (full_rank only); G must be NULL                          */
+  int32_t use_dsa;       /* 1: apply the diffusion correction (default 1)            */
+  int32_t p;             /* angles added per inner iteration (>= 1)                   */
+  int32_t q;             /* random candidates per inner iteration (>= p)              */
+  int32_t m_max;         /* MGS2-A cleanup passes (Alg. 2), 4 in the paper            */
+  int32_t max_outer;     /* cap on outer iterations                                   */
+  int32_t max_rank;      /* cap on the basis size (0: number of distinct angles)      */
+  double eps_si;         /* outer test ||phi^{n,*} - phi^{n-1}||_inf <= eps_si        */
+  double eps_res;        /* inner residual threshold, eq. (residual-chk)              */
+  double eps_diff;       /* inner phi-difference threshold, eq. (phi-diff)            */
+  double eps_svd;        /* truncation tolerance (l1 tail of singular values)         */
+  double eps_mgs;        /* MGS2-A orthogonality threshold                            */
+  double eps_dsa;        /* relative residual of the DSA conjugate gradient           */
+  rte_precision prec;
+  const uint64_t* rand;  /* HOST random stream consumed by the sampling (low rank)     */
+  int64_t n_rand;
+  const int32_t* replay; /* HOST optional forced samples: groups "count, id, id, ..."
+                            consumed one group per inner iteration; NULL = greedy      */
+  int64_t n_replay;
+  double* phi_checkpoints;  /* DEV [max_outer][ny][nx][4]: phi^{n,*} of every outer
+                               iteration, or NULL                                     */
+} rte_solve_params;
+
+/* What the solver reports (all HOST; optional arrays may be NULL).                    */
+typedef struct {
+  int32_t outer_iters;   /* SI steps taken, counting the last one                     */
+  int32_t converged;
+  int32_t rank;          /* r' after the final truncation (low rank)                  */
+  int32_t n_swept;       /* angles swept over all outer iterations (low rank)         */
+  int32_t mgs_failures;  /* Alg. 2 orthogonality failures                             */
+  int32_t breakdowns;    /* snapshots already in span(X) (not appended)               */
+  int32_t dsa_iters;     /* conjugate-gradient iterations over all DSA solves          */
+  double* history;       /* [max_outer] ||phi^{n,*} - phi^{n-1}||_inf per outer step   */
+  int32_t* ranks;        /* [max_outer] r' per outer step (low rank)                   */
+  int32_t* swept;        /* [max_outer] angles swept per outer step (low rank)         */
+  int32_t* sample_log;   /* [sample_log_cap] angle classes in the order swept          */
+  int32_t sample_log_cap, sample_log_len;
+  double* resid_log;     /* [resid_log_cap] candidate residual norms in draw order     */
+  int32_t resid_log_cap, resid_log_len;
+  double ms_sweep, ms_lowrank, ms_dsa, ms_total;   /* phase wall times               */
+} rte_solve_result;
+
+/*
+ * SI-DSA (paper Alg. 1).  full_rank = 1: the SI step sweeps all ordinates and
+ * phi^{n,*} = sum_j w_j psi_j (Sec. 2.2).  full_rank = 0: the low-rank SI of
+ * Sec. 3 (greedy random angle sampling, MGS2-A, incremental projected operators,
+ * inner stopping test, one truncated SVD after the inner loop).  The outer test
+ * is taken before the DSA step; the returned phi is phi^{n,*} of the last step.
+ *   phi0     DEV [ny][nx][4] initial scalar flux, or NULL (zero).
+ *   phi_out  DEV [ny][nx][4] result.
+ *   X, S, V  DEV optional low-rank factors of the last outer step (Sec. 3.3):
+ *            X [max_rank][ny*nx*4] (column i contiguous), S [max_rank],
+ *            V [max_rank][n_dirs] (column i contiguous); res->rank columns are set.
+ * Returns RTE_OK, RTE_ENOCONV (outputs hold the last iterate), or an error.
+ */
+rte_status rte_lowrank_si_dsa_solve(const rte_problem* prob, const rte_solve_params* params,
+                                    const double* phi0, double* phi_out, double* X,
+                                    double* S, double* V, rte_solve_result* res,
+                                    void* stream);
+
+/*
+ * Exit partial currents of a converged scalar flux: regenerates psi_j by one sweep
+ * of Sigma_s phi + G (+ inflow) and returns, for every boundary face e,
+ *     J_e = sum_j w_j (Omega_j . n_e)^+ |e|^{-1} int_e psi_j ds.
+ *   phi  DEV [ny][nx][4];  J  DEV [4][max(nx,ny)] (unused tail entries set to 0).
+ */
+rte_status rte_exit_currents(const rte_problem* prob, const double* phi, double* J,
+                             void* stream);
+
+/*
+ * Cross-section gradients by the discrete adjoint.  With psi_j regenerated from
+ * the forward flux phi and mu_j from the adjoint flux phi_adj (adjoint sweeps with
+ * boundary data bc_adj), per cell c:
+ *     grad_sigma_a[c] = - sum_j w_j <mu_j, psi_j>_c
+ *     grad_sigma_s[c] = grad_sigma_a[c] + <phi_adj, phi>_c.
+ *   phi, phi_adj DEV [ny][nx][4]; bc_adj DEV [4][max(nx,ny)][2];
+ *   grad_sigma_a, grad_sigma_s DEV [ny][nx].
+ */
+rte_status rte_cross_section_gradient(const rte_problem* prob, const double* phi,
+                                      const double* phi_adj, const double* bc_adj,
+                                      double* grad_sigma_a, double* grad_sigma_s,
+                                      void* stream);
+
+/* Chebyshev-Legendre rule CL(n_theta, n_z) (Appendix A): dirs HOST [n][3], wts HOST [n],
+ * n = n_theta * n_z, index j = j2 * n_theta + j1 (j2 over ascending Omega_z).       */
+rte_status rte_cl_quadrature(int32_t n_theta, int32_t n_z, double* dirs, double* wts);
+
+/* Adds the moments of G = value on the box [bx0,bx1] x [by0,by1] to G_host
+ * [ny][nx][4] (Appendix B, G(k) = int_cell G eta_k), integrated exactly.            */
+rte_status rte_box_source_moments(int32_t nx, int32_t ny, double x0, double x1, double y0,
+                                  double y1, double value, double bx0, double bx1,
+                                  double by0, double by1, double* G_host);
+
+const char* rte_last_error(void);
+int32_t rte_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTE_H */

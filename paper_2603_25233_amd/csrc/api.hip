@@ -1,0 +1,311 @@
+// C ABI entry points of the rte library: validation, set-up helpers (Appendix A/B)
+// and the sweep entry points.  The SI-DSA solver lives in solver.hip.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+namespace rte {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+const char* last_error() { return g_err; }
+
+Geom make_geom(const rte_problem* p) {
+  Geom g;
+  g.nx = p->nx;
+  g.ny = p->ny;
+  g.mb = p->nx > p->ny ? p->nx : p->ny;
+  g.x0 = p->x0; g.x1 = p->x1; g.y0 = p->y0; g.y1 = p->y1;
+  g.hx = (p->x1 - p->x0) / p->nx;
+  g.hy = (p->y1 - p->y0) / p->ny;
+  g.ncell = (long)p->nx * p->ny;
+  g.ndof = 4 * g.ncell;
+  return g;
+}
+
+namespace {
+__global__ void check_sigma_kernel(const double* st, const double* ss, long n, int* bad) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double t = st[i];
+  int b = 0;
+  if (!(t > 0.0) || !std::isfinite(t)) b |= 1;
+  if (ss) {
+    const double s = ss[i];
+    if (!(s >= 0.0) || !(s <= t)) b |= 2;
+  }
+  if (b) atomicOr(bad, b);
+}
+
+__global__ void fill_kernel(double* p, double v, long n) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <typename T>
+__global__ void source_kernel(const double* __restrict__ sigma_s, const double* __restrict__ phi,
+                              const double* __restrict__ G, T* __restrict__ out, long ndof) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ndof) return;
+  double v = sigma_s[i >> 2] * phi[i];
+  if (G) v += G[i];
+  out[i] = T(v);
+}
+
+// per-block max |a-b| -> out[block]
+__global__ void maxdiff_kernel(const double* __restrict__ a, const double* __restrict__ b, long n,
+                               double* __restrict__ out) {
+  __shared__ double red[256];
+  double m = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x)
+    m = fmax(m, fabs(a[i] - b[i]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+}  // namespace
+
+void validate_problem(const rte_problem* p, bool need_materials) {
+  RTE_REQUIRE(p != nullptr, "problem is NULL");
+  RTE_REQUIRE(p->nx >= 1 && p->ny >= 1, "nx, ny must be >= 1 (got %d, %d)", p->nx, p->ny);
+  RTE_REQUIRE(p->x1 > p->x0 && p->y1 > p->y0, "empty domain");
+  RTE_REQUIRE(p->n_dirs >= 1, "n_dirs must be >= 1");
+  RTE_REQUIRE(p->dirs && p->wts, "dirs and wts are required");
+  RTE_REQUIRE(p->sigma_t, "sigma_t is required");
+  double sw = 0.0;
+  for (int j = 0; j < p->n_dirs; ++j) {
+    const double* o = p->dirs + 3 * j;
+    const double nrm = o[0] * o[0] + o[1] * o[1] + o[2] * o[2];
+    RTE_REQUIRE(std::fabs(nrm - 1.0) < 1e-10, "direction %d is not a unit vector", j);
+    RTE_REQUIRE(p->wts[j] >= 0.0, "weight %d is negative", j);
+    sw += p->wts[j];
+  }
+  RTE_REQUIRE(std::fabs(sw - 1.0) <= 1e-12, "weights sum to %.17g, not 1", sw);
+  if (need_materials) {
+    RTE_REQUIRE(p->sigma_s, "sigma_s is required");
+    const long n = (long)p->nx * p->ny;
+    DevBuf<int> bad(1);
+    RTE_CHECK_HIP(hipMemset(bad.get(), 0, sizeof(int)));
+    hipLaunchKernelGGL(check_sigma_kernel, dim3((n + 255) / 256), dim3(256), 0, 0, p->sigma_t,
+                       p->sigma_s, n, bad.get());
+    RTE_CHECK_HIP(hipGetLastError());
+    int hb = 0;
+    RTE_CHECK_HIP(hipMemcpy(&hb, bad.get(), sizeof(int), hipMemcpyDeviceToHost));
+    RTE_REQUIRE(!(hb & 1), "sigma_t must be finite and > 0 in every cell");
+    RTE_REQUIRE(!(hb & 2), "sigma_s must satisfy 0 <= sigma_s <= sigma_t in every cell");
+  }
+}
+
+void device_fill(double* p, double v, long n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, v, n);
+  RTE_CHECK_HIP(hipGetLastError());
+}
+
+template <typename T>
+void make_source(const Geom& g, const double* sigma_s, const double* phi, const double* G,
+                 T* out, hipStream_t st) {
+  hipLaunchKernelGGL((source_kernel<T>), dim3((g.ndof + 255) / 256), dim3(256), 0, st, sigma_s,
+                     phi, G, out, g.ndof);
+  RTE_CHECK_HIP(hipGetLastError());
+}
+template void make_source<double>(const Geom&, const double*, const double*, const double*,
+                                  double*, hipStream_t);
+template void make_source<float>(const Geom&, const double*, const double*, const double*,
+                                 float*, hipStream_t);
+
+double max_abs_diff(const double* a, const double* b, long n, hipStream_t st) {
+  const int nb = 512;
+  DevBuf<double> part(nb);
+  hipLaunchKernelGGL(maxdiff_kernel, dim3(nb), dim3(256), 0, st, a, b, n, part.get());
+  RTE_CHECK_HIP(hipGetLastError());
+  std::vector<double> h(nb);
+  RTE_CHECK_HIP(hipMemcpyAsync(h.data(), part.get(), nb * sizeof(double), hipMemcpyDeviceToHost, st));
+  RTE_CHECK_HIP(hipStreamSynchronize(st));
+  double m = 0.0;
+  for (double x : h) m = x > m ? x : m;
+  return m;
+}
+
+static std::vector<SweepDir> sweep_dirs(const rte_problem* p, const Geom& g, const int32_t* idx,
+                                        int n, bool adjoint) {
+  std::vector<SweepDir> v(n);
+  for (int i = 0; i < n; ++i) {
+    const int j = idx[i];
+    RTE_REQUIRE(j >= 0 && j < p->n_dirs, "dir_idx[%d] = %d out of range", i, j);
+    const double ox = p->dirs[3 * j], oy = p->dirs[3 * j + 1];
+    SweepDir d;
+    d.a = std::fabs(ox) / g.hx;
+    d.b = std::fabs(oy) / g.hy;
+    d.w = p->wts[j];
+    // (D_j + Sigma_t)^T = D_{-Omega_j} + Sigma_t: the adjoint sweeps the reversed ordinate
+    d.sx = ((ox >= 0.0) != adjoint) ? 1 : -1;
+    d.sy = ((oy >= 0.0) != adjoint) ? 1 : -1;
+    d.slot = i;
+    d.pad = 0;
+    v[i] = d;
+  }
+  return v;
+}
+
+static rte_status sweep_common(const rte_problem* prob, const int32_t* dir_idx, int32_t n_sel,
+                               const void* src, void* psi, void* phi, rte_precision prec,
+                               void* stream, bool adjoint) {
+  try {
+    validate_problem(prob, false);
+    RTE_REQUIRE(dir_idx && n_sel >= 1, "dir_idx / n_sel");
+    RTE_REQUIRE(src, "src is NULL");
+    RTE_REQUIRE(psi || phi, "one of psi, phi is required");
+    RTE_REQUIRE(prec == RTE_FP64 || prec == RTE_MIXED, "unknown precision %d", (int)prec);
+    Geom g = make_geom(prob);
+    std::vector<SweepDir> dirs = sweep_dirs(prob, g, dir_idx, n_sel, adjoint);
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == RTE_FP64)
+      launch_sweep<double>(g, dirs, prob->sigma_t, (const double*)src, prob->bc, (double*)psi,
+                           (double*)phi, st);
+    else
+      launch_sweep<float>(g, dirs, prob->sigma_t, (const float*)src, prob->bc, (float*)psi,
+                          (float*)phi, st);
+    return RTE_OK;
+  } catch (const Error& e) {
+    return e.code;
+  }
+}
+
+// Gauss-Legendre nodes/weights on [-1,1] by Newton's method on P_n; nodes mirrored so
+// that x_{n-1-i} = -x_i exactly.
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = pk;
+      }
+      if (n == 1) { p1 = z; p0 = 1.0; }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    // recompute the derivative at the converged node
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = pk;
+    }
+    if (n == 1) { p1 = z; p0 = 1.0; }
+    dp = n * (z * p1 - p0) / (z * z - 1.0);
+    const double wi = 2.0 / ((1.0 - z * z) * dp * dp);
+    // z is the i-th largest node
+    x[n - 1 - i] = z;
+    x[i] = -z;
+    w[n - 1 - i] = wi;
+    w[i] = wi;
+  }
+  if (n % 2 == 1) x[n / 2] = 0.0;
+}
+
+}  // namespace rte
+
+using namespace rte;
+
+extern "C" {
+
+const char* rte_last_error(void) { return rte::last_error(); }
+
+int32_t rte_abi_version(void) { return 1; }
+
+rte_status rte_sweep(const rte_problem* prob, const int32_t* dir_idx, int32_t n_sel,
+                     const void* src, void* psi, void* phi, rte_precision prec, void* stream) {
+  return sweep_common(prob, dir_idx, n_sel, src, psi, phi, prec, stream, false);
+}
+
+rte_status rte_adjoint_sweep(const rte_problem* prob, const int32_t* dir_idx, int32_t n_sel,
+                             const void* src, void* psi, void* phi, rte_precision prec,
+                             void* stream) {
+  return sweep_common(prob, dir_idx, n_sel, src, psi, phi, prec, stream, true);
+}
+
+rte_status rte_cl_quadrature(int32_t n_theta, int32_t n_z, double* dirs, double* wts) {
+  try {
+    RTE_REQUIRE(n_theta >= 1 && n_z >= 1, "CL rule needs n_theta, n_z >= 1");
+    RTE_REQUIRE(dirs && wts, "output arrays are NULL");
+    std::vector<double> mu, wz;
+    gauss_legendre(n_z, mu, wz);
+    for (int a = 0; a < n_z; ++a) {
+      const double s = std::sqrt(1.0 - mu[a] * mu[a]);
+      for (int b = 0; b < n_theta; ++b) {
+        const double th = (2.0 * b + 1.0) * M_PI / n_theta;
+        const int j = a * n_theta + b;
+        dirs[3 * j] = std::cos(th) * s;
+        dirs[3 * j + 1] = std::sin(th) * s;
+        dirs[3 * j + 2] = mu[a];
+        wts[j] = 0.5 * wz[a] / n_theta;
+      }
+    }
+    return RTE_OK;
+  } catch (const Error& e) {
+    return e.code;
+  }
+}
+
+rte_status rte_box_source_moments(int32_t nx, int32_t ny, double x0, double x1, double y0,
+                                  double y1, double value, double bx0, double bx1, double by0,
+                                  double by1, double* G) {
+  try {
+    RTE_REQUIRE(nx >= 1 && ny >= 1 && x1 > x0 && y1 > y0, "bad mesh");
+    RTE_REQUIRE(G, "G is NULL");
+    const double hx = (x1 - x0) / nx, hy = (y1 - y0) / ny;
+    const double r3 = std::sqrt(3.0);
+    // int over [lo,hi] of l_0, l_1 on a cell of centre c and width h
+    auto moments = [&](double lo, double hi, double c, double h, double m[2]) {
+      const double xl = 2.0 * (lo - c) / h, xh = 2.0 * (hi - c) / h;
+      m[0] = (hi - lo) / std::sqrt(h);
+      m[1] = r3 * std::sqrt(h) * 0.25 * (xh * xh - xl * xl);
+    };
+    for (int b = 0; b < ny; ++b) {
+      const double ya = y0 + b * hy, yb = ya + hy;
+      const double lo_y = std::max(ya, by0), hi_y = std::min(yb, by1);
+      if (hi_y <= lo_y) continue;
+      double my[2];
+      moments(lo_y, hi_y, ya + 0.5 * hy, hy, my);
+      for (int a = 0; a < nx; ++a) {
+        const double xa = x0 + a * hx, xb = xa + hx;
+        const double lo_x = std::max(xa, bx0), hi_x = std::min(xb, bx1);
+        if (hi_x <= lo_x) continue;
+        double mx[2];
+        moments(lo_x, hi_x, xa + 0.5 * hx, hx, mx);
+        double* c = G + 4 * ((long)b * nx + a);
+        for (int q = 0; q < 2; ++q)
+          for (int p = 0; p < 2; ++p) c[2 * q + p] += value * mx[p] * my[q];
+      }
+    }
+    return RTE_OK;
+  } catch (const Error& e) {
+    return e.code;
+  }
+}
+
+}  // extern "C"

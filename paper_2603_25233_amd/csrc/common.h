@@ -1,0 +1,122 @@
+// Internal declarations of the rte library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/rte.h"
+
+namespace rte {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+const char* last_error();
+
+struct Error {
+  rte_status code;
+};
+
+#define RTE_CHECK_HIP(expr)                                                            \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      ::rte::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                       __LINE__);                                                      \
+      throw ::rte::Error{e_ == hipErrorOutOfMemory ? RTE_ENOMEM : RTE_EHIP};           \
+    }                                                                                  \
+  } while (0)
+
+#define RTE_REQUIRE(cond, ...)             \
+  do {                                     \
+    if (!(cond)) {                         \
+      ::rte::set_error(__VA_ARGS__);       \
+      throw ::rte::Error{RTE_EINVAL};      \
+    }                                      \
+  } while (0)
+
+// Device buffer owned by one library call (freed on scope exit, also on error).
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t count) { alloc(count); }
+  void alloc(size_t count) {
+    release();
+    n = count;
+    if (count) RTE_CHECK_HIP(hipMalloc(&p, count * sizeof(T)));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  ~DevBuf() { release(); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  T* get() const { return p; }
+};
+
+// ---------------------------------------------------------------- problem on the host
+struct Geom {
+  int nx, ny, mb;          // cells; mb = max(nx, ny) (length of a boundary-data side)
+  double x0, x1, y0, y1, hx, hy;
+  long ncell, ndof;
+};
+
+Geom make_geom(const rte_problem* p);
+void validate_problem(const rte_problem* p, bool need_materials);
+
+// Per-direction sweep parameters (canonical frame: the sweep always runs towards
+// +x and +y after a reflection of the cell coordinates by the direction signs).
+struct SweepDir {
+  double a;      // |Omega_x| / hx
+  double b;      // |Omega_y| / hy
+  double w;      // weight used when accumulating phi
+  int sx, sy;    // signs of the direction actually swept (+1 / -1)
+  int slot;      // output slot in psi
+  int pad;
+};
+
+// A sweep plan groups directions of one quadrant into workgroups of D directions
+// (padding entries have slot = -1).  `groups` is uploaded to the device by the caller.
+struct SweepPlan {
+  std::vector<SweepDir> groups;
+  int D = 1, ngroups = 0, nt = 64;
+};
+SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool want_phi,
+                          size_t elem_bytes);
+// Enqueues the sweep (no synchronisation).  part: [ngroups][ndof] scratch when phi != null.
+template <typename T>
+void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
+                   const double* sigma_t, const T* src, const double* bc, T* psi, T* phi,
+                   T* part, hipStream_t st);
+// One-shot sweep with its own temporaries; returns after completion on `st`.
+template <typename T>
+void launch_sweep(const Geom& g, const std::vector<SweepDir>& dirs, const double* sigma_t,
+                  const T* src, const double* bc, T* psi, T* phi, hipStream_t st);
+
+// ---------------------------------------------------------------- DSA (diffusion correction)
+struct DSA;
+DSA* dsa_create(const Geom& g, const double* sigma_t_dev, const double* sigma_s_dev,
+                hipStream_t st);
+void dsa_destroy(DSA* d);
+// delta = A^{-1} Sigma_s (phi_star - phi_prev);  phi_next = phi_star + delta.
+// Returns the number of CG iterations.
+int dsa_apply(DSA* d, const double* phi_star, const double* phi_prev, double* phi_next,
+              double rel_tol, hipStream_t st);
+
+// ---------------------------------------------------------------- small device helpers
+void device_fill(double* p, double v, long n, hipStream_t st);
+// out = sigma_s * phi + G (per cell), G may be null
+template <typename T>
+void make_source(const Geom& g, const double* sigma_s, const double* phi, const double* G,
+                 T* out, hipStream_t st);
+// host value of max |a - b| (synchronises)
+double max_abs_diff(const double* a, const double* b, long n, hipStream_t st);
+
+}  // namespace rte

@@ -1,0 +1,289 @@
+"""ctypes binding of librte.so (include/rte.h).  Argument marshalling only.
+
+Device arrays are torch tensors on the current HIP device; their data pointers
+and the current torch stream are handed to the C ABI.  Every computation of the
+method runs in the HIP library: if librte.so is not built this module raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librte.so")
+
+RTE_OK, RTE_ENOCONV = 0, 1
+RTE_FP64, RTE_MIXED = 0, 1
+SIDE_L, SIDE_R, SIDE_B, SIDE_T = 0, 1, 2, 3
+
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int32)
+
+
+class Problem_(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("x0", ctypes.c_double), ("x1", ctypes.c_double),
+                ("y0", ctypes.c_double), ("y1", ctypes.c_double),
+                ("n_dirs", ctypes.c_int32), ("dirs", _D), ("wts", _D),
+                ("sigma_t", _P), ("sigma_s", _P), ("G", _P), ("bc", _P)]
+
+
+class Params_(ctypes.Structure):
+    _fields_ = [("full_rank", ctypes.c_int32), ("adjoint", ctypes.c_int32),
+                ("use_dsa", ctypes.c_int32), ("p", ctypes.c_int32), ("q", ctypes.c_int32),
+                ("m_max", ctypes.c_int32), ("max_outer", ctypes.c_int32),
+                ("max_rank", ctypes.c_int32),
+                ("eps_si", ctypes.c_double), ("eps_res", ctypes.c_double),
+                ("eps_diff", ctypes.c_double), ("eps_svd", ctypes.c_double),
+                ("eps_mgs", ctypes.c_double), ("eps_dsa", ctypes.c_double),
+                ("prec", ctypes.c_int), ("rand", ctypes.POINTER(ctypes.c_uint64)),
+                ("n_rand", ctypes.c_int64), ("replay", _I), ("n_replay", ctypes.c_int64),
+                ("phi_checkpoints", _P)]
+
+
+class Result_(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("rank", ctypes.c_int32), ("n_swept", ctypes.c_int32),
+                ("mgs_failures", ctypes.c_int32), ("breakdowns", ctypes.c_int32),
+                ("dsa_iters", ctypes.c_int32),
+                ("history", _D), ("ranks", _I), ("swept", _I),
+                ("sample_log", _I), ("sample_log_cap", ctypes.c_int32),
+                ("sample_log_len", ctypes.c_int32),
+                ("resid_log", _D), ("resid_log_cap", ctypes.c_int32),
+                ("resid_log_len", ctypes.c_int32),
+                ("ms_sweep", ctypes.c_double), ("ms_lowrank", ctypes.c_double),
+                ("ms_dsa", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+
+# every entry point of include/rte.h with its argument types
+SIGNATURES = {
+    "rte_sweep": ([ctypes.POINTER(Problem_), _I, ctypes.c_int32, _P, _P, _P, ctypes.c_int, _P],
+                  ctypes.c_int),
+    "rte_adjoint_sweep": ([ctypes.POINTER(Problem_), _I, ctypes.c_int32, _P, _P, _P,
+                           ctypes.c_int, _P], ctypes.c_int),
+    "rte_lowrank_si_dsa_solve": ([ctypes.POINTER(Problem_), ctypes.POINTER(Params_), _P, _P, _P,
+                                  _P, _P, ctypes.POINTER(Result_), _P], ctypes.c_int),
+    "rte_exit_currents": ([ctypes.POINTER(Problem_), _P, _P, _P], ctypes.c_int),
+    "rte_cross_section_gradient": ([ctypes.POINTER(Problem_), _P, _P, _P, _P, _P, _P],
+                                   ctypes.c_int),
+    "rte_cl_quadrature": ([ctypes.c_int32, ctypes.c_int32, _D, _D], ctypes.c_int),
+    "rte_box_source_moments": ([ctypes.c_int32, ctypes.c_int32] + [ctypes.c_double] * 9 + [_D],
+                               ctypes.c_int),
+    "rte_last_error": ([], ctypes.c_char_p),
+    "rte_abi_version": ([], ctypes.c_int32),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded librte.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("librte.so is not built: run `python -m paper_2603_25233_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+class RTEError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("rte status %d: %s" % (code, msg))
+        self.code = code
+
+
+def _check(code, allow_noconv=False):
+    if code == RTE_OK or (allow_noconv and code == RTE_ENOCONV):
+        return code
+    raise RTEError(code, lib().rte_last_error().decode())
+
+
+def _dptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ------------------------------------------------------------------ set-up helpers
+
+def cl_quadrature(n_theta, n_z):
+    """CL(n_theta, n_z) rule from the library (Appendix A): (dirs [N,3], wts [N])."""
+    n = n_theta * n_z
+    d = np.zeros((n, 3)); w = np.zeros(n)
+    _check(lib().rte_cl_quadrature(n_theta, n_z, d.ctypes.data_as(_D), w.ctypes.data_as(_D)))
+    return d, w
+
+
+def box_source_moments(nx, ny, domain, boxes):
+    """Moments of a sum of constant-on-a-box sources, [ny, nx, 4] float64 (host)."""
+    G = np.zeros((ny, nx, 4))
+    x0, x1, y0, y1 = domain
+    for value, (bx0, bx1, by0, by1) in boxes:
+        _check(lib().rte_box_source_moments(nx, ny, x0, x1, y0, y1, value, bx0, bx1, by0, by1,
+                                            G.ctypes.data_as(_D)))
+    return G
+
+
+def inflow_moments(nx, ny, domain, faces):
+    """Face moments [4, max(nx,ny), 2] of piecewise-constant isotropic inflow.
+
+    faces: iterable of (side, face index, value); the first face moment of a
+    constant g on a face of length h is g * sqrt(h).
+    """
+    x0, x1, y0, y1 = domain
+    hx, hy = (x1 - x0) / nx, (y1 - y0) / ny
+    bc = np.zeros((4, max(nx, ny), 2))
+    for side, i, val in faces:
+        h = hy if side in (SIDE_L, SIDE_R) else hx
+        bc[side, i, 0] += val * np.sqrt(h)
+    return bc
+
+
+class Problem:
+    """Device-resident problem (eq. (mat-vec-a)).  Keeps the tensors alive."""
+
+    def __init__(self, nx, ny, domain, dirs, wts, sigma_t, sigma_s, G=None, bc=None,
+                 device="cuda"):
+        self.nx, self.ny = int(nx), int(ny)
+        self.domain = tuple(float(v) for v in domain)
+        self.dirs = np.ascontiguousarray(dirs, dtype=np.float64)
+        self.wts = np.ascontiguousarray(wts, dtype=np.float64)
+        dev = torch.device(device)
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.sigma_t = torch.as_tensor(np.asarray(sigma_t, dtype=np.float64).reshape(ny, nx), **f64).contiguous()
+        self.sigma_s = torch.as_tensor(np.asarray(sigma_s, dtype=np.float64).reshape(ny, nx), **f64).contiguous()
+        self.G = None if G is None else torch.as_tensor(np.asarray(G, dtype=np.float64).reshape(ny, nx, 4), **f64).contiguous()
+        self.bc = None if bc is None else torch.as_tensor(np.asarray(bc, dtype=np.float64).reshape(4, max(nx, ny), 2), **f64).contiguous()
+        self.device = dev
+
+    @property
+    def n_dirs(self):
+        return len(self.wts)
+
+    @property
+    def ndof(self):
+        return 4 * self.nx * self.ny
+
+    def c(self, G="self", bc="self", sigma_t=None, sigma_s=None):
+        x0, x1, y0, y1 = self.domain
+        G = self.G if isinstance(G, str) else G
+        bc = self.bc if isinstance(bc, str) else bc
+        st = self.sigma_t if sigma_t is None else sigma_t
+        ss = self.sigma_s if sigma_s is None else sigma_s
+        s = Problem_(self.nx, self.ny, x0, x1, y0, y1, self.n_dirs,
+                     self.dirs.ctypes.data_as(_D), self.wts.ctypes.data_as(_D),
+                     _dptr(st), _dptr(ss), _dptr(G), _dptr(bc))
+        s._keep = (self.dirs, self.wts, G, bc, st, ss)
+        return s
+
+
+def _sweep(entry, prob, dir_idx, src, want_psi=True, want_phi=False, mixed=False):
+    dt = torch.float32 if mixed else torch.float64
+    idx = np.ascontiguousarray(dir_idx, dtype=np.int32).reshape(-1)
+    src = src.to(dt).contiguous()
+    psi = torch.empty((idx.size, prob.ny, prob.nx, 4), dtype=dt, device=prob.device) if want_psi else None
+    phi = torch.empty((prob.ny, prob.nx, 4), dtype=dt, device=prob.device) if want_phi else None
+    cp = prob.c()
+    _check(entry(ctypes.byref(cp), idx.ctypes.data_as(_I), idx.size, _dptr(src), _dptr(psi),
+                 _dptr(phi), RTE_MIXED if mixed else RTE_FP64, _stream()))
+    return psi, phi
+
+
+def sweep(prob, dir_idx, src, want_psi=True, want_phi=False, mixed=False):
+    """(D_j + Sigma_t) psi_i = src + g_j^bc for j = dir_idx[i] (rte_sweep)."""
+    return _sweep(lib().rte_sweep, prob, dir_idx, src, want_psi, want_phi, mixed)
+
+
+def adjoint_sweep(prob, dir_idx, src, want_psi=True, want_phi=False, mixed=False):
+    """(D_j + Sigma_t)^T mu_i = src + outflow-side data (rte_adjoint_sweep)."""
+    return _sweep(lib().rte_adjoint_sweep, prob, dir_idx, src, want_psi, want_phi, mixed)
+
+
+def default_params(**kw):
+    d = dict(full_rank=0, adjoint=0, use_dsa=1, p=1, q=8, m_max=4, max_outer=100, max_rank=0,
+             eps_si=1e-6, eps_res=1e-7, eps_diff=1e-7, eps_svd=1e-8, eps_mgs=1e-10,
+             eps_dsa=1e-12, mixed=False)
+    d.update(kw)
+    return d
+
+
+def solve(prob, rand=None, replay=None, phi0=None, want_factors=False, checkpoints=False,
+          log_cap=1 << 16, **kw):
+    """SI-DSA (rte_lowrank_si_dsa_solve).  Returns a dict with phi and the report."""
+    o = default_params(**kw)
+    rand_arr = None if rand is None else np.ascontiguousarray(rand, dtype=np.uint64)
+    rep_arr = None
+    if replay is not None:
+        flat = []
+        for group in replay:
+            flat.append(len(group)); flat.extend(int(x) for x in group)
+        rep_arr = np.ascontiguousarray(flat, dtype=np.int32)
+    max_outer = int(o["max_outer"])
+    ck = torch.zeros((max_outer, prob.ny, prob.nx, 4), dtype=torch.float64, device=prob.device) if checkpoints else None
+    prm = Params_(int(o["full_rank"]), int(o["adjoint"]), int(o["use_dsa"]), int(o["p"]),
+                  int(o["q"]), int(o["m_max"]), max_outer, int(o["max_rank"]),
+                  o["eps_si"], o["eps_res"], o["eps_diff"], o["eps_svd"], o["eps_mgs"],
+                  o["eps_dsa"], RTE_MIXED if o["mixed"] else RTE_FP64,
+                  None if rand_arr is None else rand_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                  0 if rand_arr is None else rand_arr.size,
+                  None if rep_arr is None else rep_arr.ctypes.data_as(_I),
+                  0 if rep_arr is None else rep_arr.size, _dptr(ck))
+    hist = np.zeros(max_outer); ranks = np.zeros(max_outer, np.int32); swept = np.zeros(max_outer, np.int32)
+    slog = np.zeros(log_cap, np.int32); rlog = np.zeros(log_cap)
+    res = Result_()
+    res.history = hist.ctypes.data_as(_D); res.ranks = ranks.ctypes.data_as(_I)
+    res.swept = swept.ctypes.data_as(_I); res.sample_log = slog.ctypes.data_as(_I)
+    res.sample_log_cap = log_cap; res.resid_log = rlog.ctypes.data_as(_D); res.resid_log_cap = log_cap
+    phi = torch.empty((prob.ny, prob.nx, 4), dtype=torch.float64, device=prob.device)
+    X = S = V = None
+    if want_factors:
+        mr = int(o["max_rank"]) or prob.n_dirs
+        X = torch.zeros((mr, prob.ndof), dtype=torch.float64, device=prob.device)
+        S = torch.zeros(mr, dtype=torch.float64, device=prob.device)
+        V = torch.zeros((mr, prob.n_dirs), dtype=torch.float64, device=prob.device)
+    p0 = None if phi0 is None else phi0.to(torch.float64).contiguous()
+    cp = prob.c(G=kw.get("G_override", "self"), bc=kw.get("bc_override", "self"))
+    code = lib().rte_lowrank_si_dsa_solve(ctypes.byref(cp), ctypes.byref(prm), _dptr(p0),
+                                          _dptr(phi), _dptr(X), _dptr(S), _dptr(V),
+                                          ctypes.byref(res), _stream())
+    _check(code, allow_noconv=True)
+    n = res.outer_iters
+    out = dict(phi=phi, iters=n, converged=bool(res.converged), rank=res.rank,
+               n_swept=res.n_swept, mgs_failures=res.mgs_failures, breakdowns=res.breakdowns,
+               dsa_iters=res.dsa_iters, history=hist[:n].copy(), ranks=ranks[:n].copy(),
+               swept=swept[:n].copy(), sample_log=slog[:res.sample_log_len].copy(),
+               resid_log=rlog[:res.resid_log_len].copy(), ms_sweep=res.ms_sweep,
+               ms_lowrank=res.ms_lowrank, ms_dsa=res.ms_dsa, ms_total=res.ms_total, status=code)
+    if want_factors:
+        r = res.rank
+        out.update(X=X[:r], S=S[:r], V=V[:r])
+    if checkpoints:
+        out["checkpoints"] = ck[:n]
+    return out
+
+
+def exit_currents(prob, phi):
+    J = torch.zeros((4, max(prob.nx, prob.ny)), dtype=torch.float64, device=prob.device)
+    cp = prob.c()
+    _check(lib().rte_exit_currents(ctypes.byref(cp), _dptr(phi.contiguous()), _dptr(J), _stream()))
+    return J
+
+
+def cross_section_gradient(prob, phi, phi_adj, bc_adj):
+    ga = torch.zeros((prob.ny, prob.nx), dtype=torch.float64, device=prob.device)
+    gs = torch.zeros_like(ga)
+    cp = prob.c()
+    _check(lib().rte_cross_section_gradient(ctypes.byref(cp), _dptr(phi.contiguous()),
+                                            _dptr(phi_adj.contiguous()),
+                                            _dptr(bc_adj.contiguous()), _dptr(ga), _dptr(gs),
+                                            _stream()))
+    return ga, gs
