@@ -94,6 +94,26 @@ rte_status rte_adjoint_sweep(const rte_problem* prob, const int32_t* dir_idx,
                              int32_t n_sel, const void* src, void* psi, void* phi,
                              rte_precision prec, void* stream);
 
+/*
+ * Persistent sweep plan for repeated sweeps of the same ordinate list (e.g. one SI
+ * step per call): the direction table and the partial-sum workspace are built and
+ * uploaded once, so rte_sweep_execute only enqueues the sweep kernel (and, when phi
+ * is requested, the fixed-order reduction of the per-group partial sums).
+ *   rte_sweep_plan_create: arguments as rte_sweep (prob->dirs/wts/bc and the device
+ *     pointers in prob are captured and must stay valid for the plan's lifetime);
+ *     want_phi != 0 reserves the scalar-flux workspace; adjoint != 0 plans
+ *     rte_adjoint_sweep semantics.  *plan receives an opaque handle.
+ *   rte_sweep_execute: asynchronous on `stream`; src/psi/phi as in rte_sweep.
+ *   rte_sweep_plan_destroy: frees the plan (synchronises the device).
+ */
+typedef struct rte_sweep_plan_s* rte_sweep_plan;
+rte_status rte_sweep_plan_create(const rte_problem* prob, const int32_t* dir_idx,
+                                 int32_t n_sel, rte_precision prec, int32_t want_phi,
+                                 int32_t adjoint, rte_sweep_plan* plan);
+rte_status rte_sweep_execute(rte_sweep_plan plan, const void* src, void* psi, void* phi,
+                             void* stream);
+rte_status rte_sweep_plan_destroy(rte_sweep_plan plan);
+
 /* Solver settings (paper Sec. 2.2, Alg. 1, Sec. 3.2-3.4 and the settings of Sec. 4). */
 typedef struct {
   int32_t full_rank;     /* 1: full-rank SI-DSA (every ordinate swept per outer step) */
@@ -114,8 +134,10 @@ typedef struct {
   rte_precision prec;
   const uint64_t* rand;  /* HOST random stream consumed by the sampling (low rank)     */
   int64_t n_rand;
-  const int32_t* replay; /* HOST optional forced samples: groups "count, id, id, ..."
-                            consumed one group per inner iteration; NULL = greedy      */
+  const int32_t* replay; /* HOST optional forced samples (angle classes): for each outer
+                            iteration, groups "count, id, id, ..." (one per inner
+                            iteration) followed by a 0; when an outer iteration's
+                            groups run out the greedy choice is used; NULL = greedy    */
   int64_t n_replay;
   double* phi_checkpoints;  /* DEV [max_outer][ny][nx][4]: phi^{n,*} of every outer
                                iteration, or NULL                                     */
@@ -125,13 +147,13 @@ typedef struct {
 typedef struct {
   int32_t outer_iters;   /* SI steps taken, counting the last one                     */
   int32_t converged;
-  int32_t rank;          /* r' after the final truncation (low rank)                  */
+  int32_t rank;          /* r' after the single truncation of the last outer step    */
   int32_t n_swept;       /* angles swept over all outer iterations (low rank)         */
   int32_t mgs_failures;  /* Alg. 2 orthogonality failures                             */
   int32_t breakdowns;    /* snapshots already in span(X) (not appended)               */
   int32_t dsa_iters;     /* conjugate-gradient iterations over all DSA solves          */
   double* history;       /* [max_outer] ||phi^{n,*} - phi^{n-1}||_inf per outer step   */
-  int32_t* ranks;        /* [max_outer] r' per outer step (low rank)                   */
+  int32_t* ranks;        /* [max_outer] basis size r_k before truncation (low rank)    */
   int32_t* swept;        /* [max_outer] angles swept per outer step (low rank)         */
   int32_t* sample_log;   /* [sample_log_cap] angle classes in the order swept          */
   int32_t sample_log_cap, sample_log_len;

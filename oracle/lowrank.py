@@ -32,13 +32,20 @@ Readings (also implemented by the GPU library; each is listed in the design doc):
     swap index i + floor(u (n - i) / 2^64); candidates are all unsampled ordinates
     when fewer than q remain;
   * classes are numbered in the order of their smallest ordinate index; greedy order:
-    residual norm descending, class index ascending on ties;
+    residual norm descending, class index ascending on ties, where norms are compared
+    after rounding their binary mantissa to 30 bits (angles related by a symmetry of
+    the medium have residuals that are equal in exact arithmetic and differ only by
+    rounding; the paper does not say how ties are broken);
+  * a forced (replayed) sample sequence is given per outer iteration; if the inner
+    loop needs more groups than given, the greedy choice takes over;
   * the next samples are the top p of the current candidates, also after a failed
     phi-difference test; the inner loop also ends when every class is sampled;
   * MGS2-A breakdown (not specified by the paper): if alpha <= tol_break * ||psi||,
     the snapshot is not appended and the sampled class keeps the coefficient c;
   * truncation rank r' = smallest l with sum_{i>l} s_i <= eps_svd sum_i s_i.
 """
+import math
+
 import numpy as np
 import scipy.linalg as sla
 
@@ -60,6 +67,17 @@ class RandomStream:
         u = int(self.v[self.i])
         self.i += 1
         return u
+
+
+def order_key(res):
+    """Comparison key of a residual norm: (binary exponent, mantissa rounded to 30 bits)."""
+    if res <= 0.0:
+        return (-100000, 0)
+    m, e = math.frexp(res)              # res = m 2^e, 0.5 <= m < 1
+    q = int(math.floor(m * (1 << 30) + 0.5))
+    if q == (1 << 30):
+        return (e + 1, 1 << 29)
+    return (e, q)
 
 
 def draw(stream, pool, k):
@@ -240,7 +258,7 @@ class LowRankSI:
         log = []
         phi_old = phi_prev.copy()
         k = 0
-        samples = list(replay[0]) if replay is not None else draw(stream, range(K), self.p)
+        samples = list(replay[0]) if replay else draw(stream, range(K), self.p)
         while True:
             k += 1
             # 1. sweeps of the sampled angles, eq. (sampled-sweep)
@@ -266,7 +284,7 @@ class LowRankSI:
             cand = draw(stream, unsampled, self.q)
             res = {c: self.residual_norm(self.reps[c], self.galerkin(self.reps[c])) for c in cand}
             entry.update(candidates=list(cand), residuals=[res[c] for c in cand])
-            order = sorted(cand, key=lambda c: (-res[c], c))
+            order = sorted(cand, key=lambda c: (tuple(-x for x in order_key(res[c])), c))
             # 5. stopping test, Sec. 3.3
             stop = False
             if max(res.values()) < self.eps_res:
@@ -281,9 +299,7 @@ class LowRankSI:
             log.append(entry)
             if stop:
                 break
-            if replay is not None:
-                if k >= len(replay):
-                    raise RuntimeError("replay sequence exhausted")
+            if replay is not None and k < len(replay):
                 samples = list(replay[k])
             else:
                 samples = order[:self.p]
@@ -325,7 +341,8 @@ def lr_si_dsa(prob, eps_si, p, q, eps_res, eps_diff, eps_svd, rand, eps_mgs=1e-1
     phi_star = phi_prev
     for n in range(1, max_outer + 1):
         src = prob.sig_s4 * phi_prev + prob.G
-        phi_star = lr.run(src, phi_prev, stream, None if replay is None else replay[n - 1])
+        rep = None if replay is None or n - 1 >= len(replay) else replay[n - 1]
+        phi_star = lr.run(src, phi_prev, stream, rep)
         mgs_fail += lr.mgs_failures
         Xn, S, V, s_all = lr.truncate(eps_svd)
         ranks.append(S.size)

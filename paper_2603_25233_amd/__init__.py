@@ -4,10 +4,10 @@ steady first-order radiative transfer equation (Guo & Peng, arXiv 2603.25233).
 The computation lives in the HIP library librte.so (C ABI in include/rte.h); this
 package is its Python binding.  Build it with `python -m paper_2603_25233_amd.build`.
 """
-from .rte import (RTE_FP64, RTE_MIXED, SIDE_B, SIDE_L, SIDE_R, SIDE_T, Problem, RTEError,
+from .rte import (RTE_FP64, RTE_MIXED, SIDE_B, SIDE_L, SIDE_R, SIDE_T, Problem, RTEError, SweepPlan,
                   adjoint_sweep, box_source_moments, cl_quadrature, cross_section_gradient,
                   default_params, exit_currents, inflow_moments, lib, solve, sweep)
 
-__all__ = ["RTE_FP64", "RTE_MIXED", "SIDE_L", "SIDE_R", "SIDE_B", "SIDE_T", "Problem", "RTEError",
+__all__ = ["RTE_FP64", "RTE_MIXED", "SIDE_L", "SIDE_R", "SIDE_B", "SIDE_T", "Problem", "RTEError", "SweepPlan",
            "adjoint_sweep", "box_source_moments", "cl_quadrature", "cross_section_gradient",
            "default_params", "exit_currents", "inflow_moments", "lib", "solve", "sweep"]

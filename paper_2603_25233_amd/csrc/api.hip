@@ -229,6 +229,17 @@ static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w
 
 }  // namespace rte
 
+struct rte_sweep_plan_s {
+  rte::Geom g;
+  rte::SweepPlan pl;
+  rte::DevBuf<rte::SweepDir> dirs;
+  rte::DevBuf<unsigned char> part;
+  const double* sigma_t = nullptr;
+  const double* bc = nullptr;
+  rte_precision prec = RTE_FP64;
+  bool want_phi = false;
+};
+
 using namespace rte;
 
 extern "C" {
@@ -246,6 +257,65 @@ rte_status rte_adjoint_sweep(const rte_problem* prob, const int32_t* dir_idx, in
                              const void* src, void* psi, void* phi, rte_precision prec,
                              void* stream) {
   return sweep_common(prob, dir_idx, n_sel, src, psi, phi, prec, stream, true);
+}
+
+rte_status rte_sweep_plan_create(const rte_problem* prob, const int32_t* dir_idx, int32_t n_sel,
+                                 rte_precision prec, int32_t want_phi, int32_t adjoint,
+                                 rte_sweep_plan* plan) {
+  rte_sweep_plan_s* h = nullptr;
+  try {
+    RTE_REQUIRE(plan, "plan is NULL");
+    *plan = nullptr;
+    validate_problem(prob, false);
+    RTE_REQUIRE(dir_idx && n_sel >= 1, "dir_idx / n_sel");
+    RTE_REQUIRE(prec == RTE_FP64 || prec == RTE_MIXED, "unknown precision %d", (int)prec);
+    h = new rte_sweep_plan_s();
+    h->g = make_geom(prob);
+    std::vector<SweepDir> dirs = sweep_dirs(prob, h->g, dir_idx, n_sel, adjoint != 0);
+    const size_t eb = prec == RTE_FP64 ? sizeof(double) : sizeof(float);
+    h->pl = make_sweep_plan(h->g, dirs, want_phi != 0, eb);
+    h->dirs.alloc(h->pl.groups.size());
+    RTE_CHECK_HIP(hipMemcpy(h->dirs.get(), h->pl.groups.data(),
+                            h->pl.groups.size() * sizeof(SweepDir), hipMemcpyHostToDevice));
+    if (want_phi) h->part.alloc((size_t)h->pl.ngroups * h->g.ndof * eb);
+    h->sigma_t = prob->sigma_t;
+    h->bc = prob->bc;
+    h->prec = prec;
+    h->want_phi = want_phi != 0;
+    *plan = h;
+    return RTE_OK;
+  } catch (const Error& e) {
+    delete h;
+    return e.code;
+  }
+}
+
+rte_status rte_sweep_execute(rte_sweep_plan h, const void* src, void* psi, void* phi,
+                             void* stream) {
+  try {
+    RTE_REQUIRE(h, "plan is NULL");
+    RTE_REQUIRE(src, "src is NULL");
+    RTE_REQUIRE(psi || phi, "one of psi, phi is required");
+    RTE_REQUIRE(!phi || h->want_phi, "the plan was created without the scalar-flux workspace");
+    hipStream_t st = (hipStream_t)stream;
+    if (h->prec == RTE_FP64)
+      sweep_enqueue<double>(h->g, h->pl, h->dirs.get(), h->sigma_t, (const double*)src, h->bc,
+                            (double*)psi, (double*)phi, (double*)h->part.get(), st);
+    else
+      sweep_enqueue<float>(h->g, h->pl, h->dirs.get(), h->sigma_t, (const float*)src, h->bc,
+                           (float*)psi, (float*)phi, (float*)h->part.get(), st);
+    return RTE_OK;
+  } catch (const Error& e) {
+    return e.code;
+  }
+}
+
+rte_status rte_sweep_plan_destroy(rte_sweep_plan h) {
+  if (h) {
+    (void)hipDeviceSynchronize();
+    delete h;
+  }
+  return RTE_OK;
 }
 
 rte_status rte_cl_quadrature(int32_t n_theta, int32_t n_z, double* dirs, double* wts) {

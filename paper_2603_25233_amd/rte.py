@@ -71,6 +71,11 @@ SIGNATURES = {
     "rte_cl_quadrature": ([ctypes.c_int32, ctypes.c_int32, _D, _D], ctypes.c_int),
     "rte_box_source_moments": ([ctypes.c_int32, ctypes.c_int32] + [ctypes.c_double] * 9 + [_D],
                                ctypes.c_int),
+    "rte_sweep_plan_create": ([ctypes.POINTER(Problem_), _I, ctypes.c_int32, ctypes.c_int,
+                               ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)],
+                              ctypes.c_int),
+    "rte_sweep_execute": ([_P, _P, _P, _P, _P], ctypes.c_int),
+    "rte_sweep_plan_destroy": ([_P], ctypes.c_int),
     "rte_last_error": ([], ctypes.c_char_p),
     "rte_abi_version": ([], ctypes.c_int32),
 }
@@ -208,6 +213,36 @@ def adjoint_sweep(prob, dir_idx, src, want_psi=True, want_phi=False, mixed=False
     return _sweep(lib().rte_adjoint_sweep, prob, dir_idx, src, want_psi, want_phi, mixed)
 
 
+class SweepPlan:
+    """Persistent plan for repeated sweeps of one ordinate list (rte_sweep_plan_*)."""
+
+    def __init__(self, prob, dir_idx, mixed=False, want_phi=False, adjoint=False):
+        self.prob = prob
+        self.idx = np.ascontiguousarray(dir_idx, dtype=np.int32).reshape(-1)
+        self.mixed = mixed
+        self.dtype = torch.float32 if mixed else torch.float64
+        self._cp = prob.c()
+        h = ctypes.c_void_p()
+        _check(lib().rte_sweep_plan_create(ctypes.byref(self._cp), self.idx.ctypes.data_as(_I),
+                                           self.idx.size, RTE_MIXED if mixed else RTE_FP64,
+                                           int(want_phi), int(adjoint), ctypes.byref(h)))
+        self.h = h
+
+    def execute(self, src, psi=None, phi=None):
+        _check(lib().rte_sweep_execute(self.h, _dptr(src), _dptr(psi), _dptr(phi), _stream()))
+
+    def close(self):
+        if self.h:
+            lib().rte_sweep_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def default_params(**kw):
     d = dict(full_rank=0, adjoint=0, use_dsa=1, p=1, q=8, m_max=4, max_outer=100, max_rank=0,
              eps_si=1e-6, eps_res=1e-7, eps_diff=1e-7, eps_svd=1e-8, eps_mgs=1e-10,
@@ -223,9 +258,12 @@ def solve(prob, rand=None, replay=None, phi0=None, want_factors=False, checkpoin
     rand_arr = None if rand is None else np.ascontiguousarray(rand, dtype=np.uint64)
     rep_arr = None
     if replay is not None:
+        # replay: per outer iteration, a list of groups (angle class ids per inner iteration)
         flat = []
-        for group in replay:
-            flat.append(len(group)); flat.extend(int(x) for x in group)
+        for outer in replay:
+            for group in outer:
+                flat.append(len(group)); flat.extend(int(x) for x in group)
+            flat.append(0)
         rep_arr = np.ascontiguousarray(flat, dtype=np.int32)
     max_outer = int(o["max_outer"])
     ck = torch.zeros((max_outer, prob.ny, prob.nx, 4), dtype=torch.float64, device=prob.device) if checkpoints else None

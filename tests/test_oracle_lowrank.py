@@ -34,6 +34,20 @@ def test_draw_partial_fisher_yates():
         assert len(set(out)) == len(out) == min(7, len(pool)) and set(out) <= set(pool)
 
 
+def test_order_key_breaks_rounding_level_ties():
+    k = lowrank.order_key
+    a = 0.1234567
+    assert k(a) == k(a * (1 + 1e-15)) == k(a * (1 - 1e-15))     # rounding noise: tie
+    assert k(a * (1 + 1e-8)) > k(a) > k(a * (1 - 1e-8))          # real differences order
+    assert k(1.0) > k(0.9999999) and k(0.5) < k(0.5000001)
+    assert k(0.0) < k(1e-300)
+    m = 1.0 - 2.0 ** -40                                          # rounds up to the next binade
+    assert k(m) == k(1.0)
+    vals = np.random.default_rng(0).uniform(1e-8, 1.0, 2000)
+    keys = [k(v) for v in sorted(vals)]
+    assert keys == sorted(keys)
+
+
 def test_truncation_rank():
     s = np.array([10.0, 1.0, 1e-3, 1e-9, 1e-12])
     tot = s.sum()
