@@ -96,9 +96,12 @@ rte_status rte_adjoint_sweep(const rte_problem* prob, const int32_t* dir_idx,
 
 /*
  * Persistent sweep plan for repeated sweeps of the same ordinate list (e.g. one SI
- * step per call): the direction table and the partial-sum workspace are built and
- * uploaded once, so rte_sweep_execute only enqueues the sweep kernel (and, when phi
- * is requested, the fixed-order reduction of the per-group partial sums).
+ * step per call): the direction tables and the workspace (anti-diagonal copies of
+ * the source and cross section, per-group partial sums) are built and allocated
+ * once, so rte_sweep_execute only enqueues the sweep's kernels: the input reordering,
+ * the sweep and, when phi is requested, the fixed-order reduction of the per-group
+ * partial sums.  A call with psi == NULL uses a table that batches several ordinates
+ * per workgroup; a call that writes psi uses one ordinate per workgroup.
  *   rte_sweep_plan_create: arguments as rte_sweep (prob->dirs/wts/bc and the device
  *     pointers in prob are captured and must stay valid for the plan's lifetime);
  *     want_phi != 0 reserves the scalar-flux workspace; adjoint != 0 plans

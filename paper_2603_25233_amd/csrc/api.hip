@@ -1,5 +1,6 @@
 // C ABI entry points of the rte library: validation, set-up helpers (Appendix A/B)
 // and the sweep entry points.  The SI-DSA solver lives in solver.hip.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
@@ -231,9 +232,10 @@ static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w
 
 struct rte_sweep_plan_s {
   rte::Geom g;
-  rte::SweepPlan pl;
-  rte::DevBuf<rte::SweepDir> dirs;
-  rte::DevBuf<unsigned char> part;
+  rte::SweepPlan pl;                      // one direction per workgroup (psi written)
+  rte::SweepPlan plf;                     // scalar flux only (directions batched)
+  rte::DevBuf<rte::SweepDir> dirs, dirsf;
+  rte::DevBuf<unsigned char> work;
   const double* sigma_t = nullptr;
   const double* bc = nullptr;
   rte_precision prec = RTE_FP64;
@@ -273,11 +275,19 @@ rte_status rte_sweep_plan_create(const rte_problem* prob, const int32_t* dir_idx
     h->g = make_geom(prob);
     std::vector<SweepDir> dirs = sweep_dirs(prob, h->g, dir_idx, n_sel, adjoint != 0);
     const size_t eb = prec == RTE_FP64 ? sizeof(double) : sizeof(float);
-    h->pl = make_sweep_plan(h->g, dirs, want_phi != 0, eb);
+    h->pl = make_sweep_plan(h->g, dirs, want_phi != 0, true, eb);
     h->dirs.alloc(h->pl.groups.size());
     RTE_CHECK_HIP(hipMemcpy(h->dirs.get(), h->pl.groups.data(),
                             h->pl.groups.size() * sizeof(SweepDir), hipMemcpyHostToDevice));
-    if (want_phi) h->part.alloc((size_t)h->pl.ngroups * h->g.ndof * eb);
+    size_t work = sweep_work_elems(h->g, h->pl, want_phi != 0);
+    if (want_phi) {
+      h->plf = make_sweep_plan(h->g, dirs, true, false, eb);
+      h->dirsf.alloc(h->plf.groups.size());
+      RTE_CHECK_HIP(hipMemcpy(h->dirsf.get(), h->plf.groups.data(),
+                              h->plf.groups.size() * sizeof(SweepDir), hipMemcpyHostToDevice));
+      work = std::max(work, sweep_work_elems(h->g, h->plf, true));
+    }
+    h->work.alloc(work * eb);
     h->sigma_t = prob->sigma_t;
     h->bc = prob->bc;
     h->prec = prec;
@@ -298,12 +308,15 @@ rte_status rte_sweep_execute(rte_sweep_plan h, const void* src, void* psi, void*
     RTE_REQUIRE(psi || phi, "one of psi, phi is required");
     RTE_REQUIRE(!phi || h->want_phi, "the plan was created without the scalar-flux workspace");
     hipStream_t st = (hipStream_t)stream;
+    const bool batched = !psi;  // scalar flux only: the batched plan
+    const SweepPlan& pl = batched ? h->plf : h->pl;
+    const SweepDir* dd = batched ? h->dirsf.get() : h->dirs.get();
     if (h->prec == RTE_FP64)
-      sweep_enqueue<double>(h->g, h->pl, h->dirs.get(), h->sigma_t, (const double*)src, h->bc,
-                            (double*)psi, (double*)phi, (double*)h->part.get(), st);
+      sweep_enqueue<double>(h->g, pl, dd, h->sigma_t, (const double*)src, h->bc,
+                            (double*)psi, (double*)phi, (double*)h->work.get(), st);
     else
-      sweep_enqueue<float>(h->g, h->pl, h->dirs.get(), h->sigma_t, (const float*)src, h->bc,
-                           (float*)psi, (float*)phi, (float*)h->part.get(), st);
+      sweep_enqueue<float>(h->g, pl, dd, h->sigma_t, (const float*)src, h->bc,
+                           (float*)psi, (float*)phi, (float*)h->work.get(), st);
     return RTE_OK;
   } catch (const Error& e) {
     return e.code;

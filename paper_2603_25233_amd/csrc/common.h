@@ -86,15 +86,24 @@ struct SweepDir {
 // (padding entries have slot = -1).  `groups` is uploaded to the device by the caller.
 struct SweepPlan {
   std::vector<SweepDir> groups;
-  int D = 1, ngroups = 0, nt = 64;
+  int D = 1, ngroups = 0, nt = 64, rpt = 1;
+  int ch = 1;     // steps per store chunk (output ring of 2 ch steps in LDS)
+  int qmask = 0;  // quadrants swept (bit q = (sx < 0) + 2 (sy < 0))
 };
+// Directions are batched D > 1 per workgroup only for scalar-flux-only sweeps
+// (want_phi && !want_psi).
 SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool want_phi,
-                          size_t elem_bytes);
-// Enqueues the sweep (no synchronisation).  part: [ngroups][ndof] scratch when phi != null.
+                          bool want_psi, size_t elem_bytes);
+// Elements of T the sweep needs as workspace: the diagonal-major copies of the
+// source and cross section (5 ncell per quadrant) and, when phi is requested, the
+// per-group partial sums ([ngroups][ndof]).
+size_t sweep_work_elems(const Geom& g, const SweepPlan& pl, bool want_phi);
+// Enqueues the sweep (no synchronisation).  work: sweep_work_elems(g, pl, phi != null)
+// elements.  psi != null needs a plan with D == 1.
 template <typename T>
 void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
                    const double* sigma_t, const T* src, const double* bc, T* psi, T* phi,
-                   T* part, hipStream_t st);
+                   T* work, hipStream_t st);
 // One-shot sweep with its own temporaries; returns after completion on `st`.
 template <typename T>
 void launch_sweep(const Geom& g, const std::vector<SweepDir>& dirs, const double* sigma_t,

@@ -793,7 +793,7 @@ struct LowRank {
   DevBuf<int> d_cls_of, d_sampled, d_list;
   DevBuf<double> d_wc, d_mult;
   // fields
-  DevBuf<T> X, psi, srcT, Y, V;
+  DevBuf<T> X, psi, srcT, Y, V, swork;
   DevBuf<double> src, E, phi_k, phi_old, part, dvec, cvec, cw, dpart;
   // projected operators and factors
   DevBuf<double> Tm, Dx, Dy, bsrc, bside, Lt, U, yv, Cg, Rst, tsd, tsd2, tsd3;
@@ -869,6 +869,7 @@ struct LowRank {
     X.alloc((size_t)rcap * nd);
     psi.alloc((size_t)p * nd);
     srcT.alloc(nd);
+    swork.alloc(20 * (size_t)g.nx * g.ny);  // sweep workspace without the scalar flux
     Y.alloc((size_t)5 * p * nd);
     V.alloc((size_t)32 * nd);
     src.alloc(nd);
@@ -929,12 +930,12 @@ struct LowRank {
       d.pad = 0;
       dirs.push_back(d);
     }
-    SweepPlan pl = make_sweep_plan(g, dirs, false, sizeof(T));
+    SweepPlan pl = make_sweep_plan(g, dirs, false, true, sizeof(T));
     std::memcpy(h_dirs, pl.groups.data(), pl.groups.size() * sizeof(SweepDir));
     RTE_CHECK_HIP(hipMemcpyAsync(d_dirs.get(), h_dirs, pl.groups.size() * sizeof(SweepDir),
                                  hipMemcpyHostToDevice, st));
     sweep_enqueue<T>(g, pl, d_dirs.get(), prob->sigma_t, srcT.get(), prob->bc, psi.get(), nullptr,
-                     nullptr, st);
+                     swork.get(), st);
     RTE_CHECK_HIP(hipEventRecord(e1, st));
     sync();
     float ms = 0.f;

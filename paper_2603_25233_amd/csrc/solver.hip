@@ -108,11 +108,11 @@ static rte_status fr_solve(const rte_problem* prob, const rte_solve_params* prm,
   const auto t_start = std::chrono::steady_clock::now();
   const Geom g = make_geom(prob);
   const long nd = g.ndof;
-  SweepPlan plan = make_sweep_plan(g, all_dirs(prob, g, prm->adjoint != 0), true, sizeof(T));
+  SweepPlan plan = make_sweep_plan(g, all_dirs(prob, g, prm->adjoint != 0), true, false, sizeof(T));
   DevBuf<SweepDir> ddirs(plan.groups.size());
   RTE_CHECK_HIP(hipMemcpy(ddirs.get(), plan.groups.data(), plan.groups.size() * sizeof(SweepDir),
                           hipMemcpyHostToDevice));
-  DevBuf<T> part((size_t)plan.ngroups * nd), src(nd), phiT;
+  DevBuf<T> work(sweep_work_elems(g, plan, true)), src(nd), phiT;
   DevBuf<double> phi_prev(nd), phi_star(nd);
   if (sizeof(T) != sizeof(double)) phiT.alloc(nd);
   if (phi0)
@@ -133,7 +133,7 @@ static rte_status fr_solve(const rte_problem* prob, const rte_solve_params* prm,
     make_source<T>(g, prob->sigma_s, phi_prev.get(), G, src.get(), st);
     T* phi_sw = sizeof(T) == sizeof(double) ? (T*)phi_star.get() : phiT.get();
     sweep_enqueue<T>(g, plan, ddirs.get(), prob->sigma_t, src.get(), prob->bc, nullptr, phi_sw,
-                     part.get(), st);
+                     work.get(), st);
     if (sizeof(T) != sizeof(double))
       hipLaunchKernelGGL(to_double_kernel, dim3((nd + 255) / 256), dim3(256), 0, st,
                          (const float*)phiT.get(), phi_star.get(), nd);

@@ -75,7 +75,7 @@ def test_scalar_flux_accumulation(nx, ny, nt, nz):
     assert np.abs(got - ref).max() < 1e-13 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("nx,ny,nt,nz", [(37, 70, 8, 4), (64, 64, 16, 8)])
+@pytest.mark.parametrize("nx,ny,nt,nz", [(37, 70, 8, 4), (64, 64, 16, 8), (9, 40, 64, 32)])
 def test_sweep_fp32_within_mixed_tolerance(nx, ny, nt, nz):
     import paper_2603_25233_amd as R
     prob, m, do, wo, sig_t, src, bc = make(nx, ny, nt, nz, seed=11)
@@ -110,3 +110,26 @@ def test_rejects_bad_input():
     big = R.Problem(2, 1025, (0, 1, 0, 1), do, wo, np.ones((1025, 2)), np.zeros((1025, 2)))
     with pytest.raises(R.RTEError):
         R.sweep(big, [0], torch.zeros((1025, 2, 4), dtype=torch.float64, device="cuda"))
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_plan_matches_one_shot(mixed):
+    """A plan made with the scalar-flux workspace: psi-writing and phi-only executions
+    match the one-shot entry point bit for bit, repeated executions included."""
+    import paper_2603_25233_amd as R
+    prob, m, do, wo, sig_t, src, bc = make(23, 41, 32, 16, seed=13)
+    sel = np.arange(len(wo))
+    dt = torch.float32 if mixed else torch.float64
+    s = torch.as_tensor(src, device="cuda").to(dt).contiguous()
+    psi_ref, _ = R.sweep(prob, sel, s, mixed=mixed)
+    _, phi_ref = R.sweep(prob, sel, s, want_psi=False, want_phi=True, mixed=mixed)
+    plan = R.SweepPlan(prob, sel, mixed=mixed, want_phi=True)
+    psi = torch.empty_like(psi_ref)
+    phi = torch.empty_like(phi_ref)
+    for _ in range(2):
+        plan.execute(s, psi=psi)
+        plan.execute(s, phi=phi)
+        torch.cuda.synchronize()
+        assert torch.equal(psi, psi_ref)
+        assert torch.equal(phi, phi_ref)
+    plan.close()
