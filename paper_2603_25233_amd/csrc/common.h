@@ -86,8 +86,10 @@ struct SweepDir {
 // (padding entries have slot = -1).  `groups` is uploaded to the device by the caller.
 struct SweepPlan {
   std::vector<SweepDir> groups;
-  int D = 1, ngroups = 0, nt = 64, rpt = 1;
-  int ch = 1;     // steps per store chunk (output ring of 2 ch steps in LDS)
+  int D = 1, ngroups = 0;
+  int nt = 64;    // threads per workgroup: nc compute threads + staging wavefronts
+  int nc = 64;
+  int rpt = 1;    // rows per compute thread
   int qmask = 0;  // quadrants swept (bit q = (sx < 0) + 2 (sy < 0))
 };
 // Directions are batched D > 1 per workgroup only for scalar-flux-only sweeps

@@ -24,11 +24,11 @@
 // trace stays in registers; the y-inflow trace of row r comes from row r-1 of the
 // previous step through a double-buffered LDS slot, one barrier per step.  A small
 // kernel first copies the source and cross section into anti-diagonal order per
-// quadrant, so that the loads of one step are contiguous; the results leave through
-// an LDS ring written back by a dedicated store wavefront in row chunks (see
-// sweep_kernel).  D directions of the same quadrant are solved per thread in lock
-// step (ILP); their weighted sum is written once per cell when only the scalar flux
-// is requested.
+// quadrant; staging wavefronts of the sweep workgroup move each step's inputs from
+// there into LDS two steps ahead, so the compute wavefronts issue no global loads
+// and never wait for their own stores (see sweep_kernel).  D directions of the same
+// quadrant are solved per thread in lock step (ILP); their weighted sum is written
+// once per cell when only the scalar flux is requested.
 #include <algorithm>
 #include <cmath>
 
@@ -110,13 +110,6 @@ __device__ __forceinline__ void store4(T* p, const T v[4]) {
   }
 }
 
-// Raw source moments and cross section of one cell, fetched a superstep ahead.
-template <typename T>
-struct Slot {
-  T s[4];
-  T sig;
-};
-
 // Diagonal-major cell numbering of one quadrant.  In the canonical frame (cell
 // coordinates reflected so that the sweep runs towards +x, +y) the cell of row r and
 // column ap lies on anti-diagonal t = r + ap; anti-diagonals are stored one after the
@@ -156,107 +149,113 @@ __global__ void diag_layout_kernel(int nx, int ny, int qmask, const double* __re
   }
 }
 
+// Rows of one step that each staging wavefront lane carries (64 lanes x 4 = 256 rows).
+constexpr int kStageRows = 4;
+
 // One workgroup sweeps D directions (dirs[blockIdx.x*D + d]) of one quadrant.
 // psi: [slots][ndof] or null (D == 1 when psi is written).  part: [gridDim.x][ndof]
 // weighted partial sums or null.  dsrc/dsig: the diagonal-major inputs.
 //
-// Roles.  The first nc = blockDim.x - 64 threads compute; compute thread j owns the
-// canonical rows j + k nc, k < RPT (both on the current anti-diagonal, so they are
-// independent work).  The last wavefront only stores.  At step t the compute threads
-// solve the cells of canonical column t - r and leave one 4-vector per row in an LDS
-// ring of 2 ch steps (psi, or sum_d w_d psi_d when only the scalar flux is wanted).
-// While the compute threads fill one chunk of ch steps, the store wavefront writes the
-// previous chunk, a 1/ch share of its rows per step, each row as ch consecutive cells
-// (16 bytes per lane), so a store instruction touches few cache lines.  Compute
-// wavefronts issue no global stores, so waiting for their prefetched loads never
-// waits for store acknowledgements (one vector-memory counter covers both).
+// Roles.  The first nc threads compute; compute thread j owns the canonical rows
+// j + k nc, k < RPT (both on the current anti-diagonal, so they are independent
+// work).  The remaining wavefronts stage inputs: staging wavefront w carries rows
+// 256 w + lane + 64 i, i < 4.  Compute wavefronts read their inputs from LDS and
+// issue only global stores (psi, or the weighted partial sums), which they never
+// wait for; staging wavefronts issue only global loads, so their waits are exact.
 //
-// Prefetch.  Time is cut into supersteps of SS steps; consecutive rows of a step are
-// consecutive in the diagonal-major inputs.  The inputs of superstep K + 1 are
-// requested at the start of superstep K and waited for at its end.
+// Per step t: the compute threads solve the cells of canonical column t - r, taking
+// the source and sigma_t of step t from LDS slot t & 1 and the y-inflow trace from row
+// r - 1 of step t - 1 (double-buffered LDS, one barrier per step); the x-inflow trace
+// stays in registers.  Meanwhile the staging wavefronts move step t + 1 from registers
+// into slot (t + 1) & 1 and request step t + 3 from global memory (two register
+// buffers, so a load has two steps to arrive).  Slot (t + 1) & 1 was last read in
+// step t - 1, before the barrier that ended it.
 template <typename T, int D, int NTB, int RPT>
 __global__ __launch_bounds__(NTB) void sweep_kernel(
-    int nx, int ny, int mb, int ch, double shx, double shy, const SweepDir* __restrict__ dirs,
+    int nx, int ny, int mb, int nc, double shx, double shy, const SweepDir* __restrict__ dirs,
     const T* __restrict__ dsrc_all, const T* __restrict__ dsig_all,
     const double* __restrict__ bc, T* __restrict__ psi, T* __restrict__ part, long ndof) {
-  constexpr int SS = RPT == 1 ? 4 : 2;
   extern __shared__ unsigned char smem_raw[];
   const int tid = threadIdx.x;
-  const int nc = blockDim.x - 64;            // compute threads
   const int nr = nc * RPT;                   // padded rows
-  const int nsm = 2 * ch - 1;                // ring slot mask (ch is a power of two)
   T* vbuf = reinterpret_cast<T*>(smem_raw);  // [2][nr][D][2] y-inflow traces by row
-  T* vbnd = vbuf + 4L * nr * D;              // [nx][2] inflow of canonical row 0
-  T* ring = vbnd + 2L * nx;                  // [2 ch][nr][4] outputs by step and row
+  T* in_src = vbuf + 4L * nr * D;            // [2][nr + 1][4] source moments of the step
+  T* in_sig = in_src + 8L * (nr + 1);        // [2][nr + 1] sigma_t of the step
+  T* in_bnd = in_sig + 2L * (nr + 1);        // [2][2] y-inflow of canonical row 0
+  // (row nr of in_src / in_sig takes the staging writes of cells not on the step)
   const SweepDir* grp = dirs + (long)blockIdx.x * D;
   const int sx = grp[0].sx, sy = grp[0].sy;
   const T fx = T(sx), fy = T(sy), fxy = T(sx * sy);
   const long ncell = (long)nx * ny;
   const int q = (sx < 0 ? 1 : 0) + (sy < 0 ? 2 : 0);
-  {
-    const int yside = sy > 0 ? 2 : 3;
-    for (int i = tid; i < nx; i += blockDim.x) {
-      T g0 = T(0), g1 = T(0);
-      if (bc) {
-        g0 = T(bc[((long)yside * mb + i) * 2 + 0]);
-        g1 = T(bc[((long)yside * mb + i) * 2 + 1]);
-      }
-      vbnd[2 * i] = T(shy) * g0;
-      vbnd[2 * i + 1] = T(shy) * g1 * fx;
-    }
-  }
   const int nsteps = nx + ny - 1;
   if (tid >= nc) {
-    // ------------------------------------------------ store wavefront
-    const int lane = tid - nc;
-    constexpr int LPC = sizeof(T) * 4 / 16;  // lanes per cell (16 bytes per lane)
-    const int lpr = LPC * ch;                // lanes per row chunk
-    const int rpi = 64 / lpr;                // rows per store instruction
-    const int jrow = lane / lpr, ci = (lane % lpr) / LPC, half = lane % LPC;
-    const bool wpsi = psi && grp[0].slot >= 0;
-    T* pdst = wpsi ? psi + (long)grp[0].slot * ndof : nullptr;
-    const T w0 = T(grp[0].w);
-    T* pp = part ? part + (long)blockIdx.x * ndof : nullptr;
-    // rows j (mod rpi ch) = jrow + rpi * piece of the chunk starting at step t0
-    auto flush = [&](int t0, int piece) {
-      const int t = t0 + ci;  // the step of this lane's cell
-      if (t >= nsteps) return;
-      const T* slot = ring + (long)(t & nsm) * nr * 4;
-      for (int r = jrow + rpi * piece; r < ny; r += rpi * ch) {
-        const int ap = t - r;
-        if (ap >= 0 && ap < nx) {
-          const int brow = sy > 0 ? r : ny - 1 - r;
-          const long c = (long)brow * nx + (sx > 0 ? ap : nx - 1 - ap);
-          const T* e = slot + (long)r * 4 + half * (16 / sizeof(T));
-          if constexpr (sizeof(T) == 8) {
-            const double2 v = *reinterpret_cast<const double2*>(e);
-            if (wpsi) *reinterpret_cast<double2*>(pdst + 4 * c + 2 * half) = v;
-            if (pp) {
-              const double2 wv = D == 1 ? make_double2(w0 * v.x, w0 * v.y) : v;
-              *reinterpret_cast<double2*>(pp + 4 * c + 2 * half) = wv;
-            }
-          } else {
-            const float4 v = *reinterpret_cast<const float4*>(e);
-            if (wpsi) *reinterpret_cast<float4*>(pdst + 4 * c) = v;
-            if (pp) {
-              const float4 wv = D == 1 ? make_float4(w0 * v.x, w0 * v.y, w0 * v.z, w0 * v.w) : v;
-              *reinterpret_cast<float4*>(pp + 4 * c) = wv;
-            }
-          }
-        }
-      }
+    // ------------------------------------------------ staging wavefronts
+    const int lane = tid & 63;
+    const int rbase = ((tid - nc) >> 6) * 64 * kStageRows + lane;
+    const T* dsrc = dsrc_all + 4 * q * ncell;
+    const T* dsig = dsig_all + q * ncell;
+    const int yside = sy > 0 ? 2 : 3;
+    struct Buf {
+      Vec4<T> s[kStageRows];
+      T sig[kStageRows];
+      T g[2];
     };
-    __syncthreads();  // vbnd ready
-    for (int t = 0; t < nsteps; ++t) {
-      // steps t0 - ch .. t0 - 1 are complete: write one piece of them per step
-      const int t0 = t & ~(ch - 1);
-      if (t0 >= ch) flush(t0 - ch, t - t0);
-      __syncthreads();
+    // Loads of step t: unconditional and clamped in bounds, so the wait counts are
+    // static.  Every lane also reads the row-0 inflow of the step (one address).
+    const double* gsrc = bc ? bc : reinterpret_cast<const double*>(dsig_all);
+    auto load = [&](Buf& b, int t) {
+      const long f = diag_first(t, nx, ny) - (t >= nx ? t - nx + 1 : 0);
+#pragma unroll
+      for (int i = 0; i < kStageRows; ++i) {
+        const int r = rbase + 64 * i;
+        const bool ok = r < ny && t - r >= 0 && t - r < nx;
+        const long idx = ok ? f + r : 0;
+        b.s[i] = load4(dsrc + 4 * idx);
+        b.sig[i] = dsig[idx];
+      }
+      const int ap = t < nx ? t : nx - 1;
+      const int col = sx > 0 ? ap : nx - 1 - ap;
+      const long go = bc ? ((long)yside * mb + col) * 2 : 0;
+      const double g0 = gsrc[go], g1 = gsrc[go + 1];
+      b.g[0] = bc ? T(g0) : T(0);
+      b.g[1] = bc ? T(g1) : T(0);
+    };
+    // LDS writes of step t, branch-free: cells not on the step go to the junk row nr.
+    auto put = [&](const Buf& b, int t) {
+      const int sl = t & 1;
+#pragma unroll
+      for (int i = 0; i < kStageRows; ++i) {
+        const int r = rbase + 64 * i;
+        const bool ok = r < ny && t - r >= 0 && t - r < nx;
+        const long e = (long)sl * (nr + 1) + (ok ? r : nr);
+        store4(in_src + e * 4, b.s[i].v);
+        in_sig[e] = b.sig[i];
+      }
+      // every staging lane holds the same row-0 inflow; unused for t >= nx
+      in_bnd[2 * sl] = T(shy) * b.g[0];
+      in_bnd[2 * sl + 1] = T(shy) * b.g[1] * fx;
+    };
+    // Two register buffers: while step t is computed, step t + 1 goes from one
+    // buffer into LDS and step t + 3 is requested into the same buffer; the other
+    // holds step t + 2 in flight.  Loop bodies are straight-line, so every wait is
+    // for the older buffer only.
+    Buf b1, b2;
+    load(b1, 0);
+    load(b2, 1);
+    put(b1, 0);
+    load(b1, 2);
+    __syncthreads();  // step 0 staged
+    int t = 0;
+    for (; t + 1 < nsteps; t += 2) {
+      put(b2, t + 1);
+      load(b2, t + 3);
+      __syncthreads();  // end of step t
+      put(b1, t + 2);
+      load(b1, t + 4);
+      __syncthreads();  // end of step t + 1
     }
-    const int tl = (nsteps - 1) & ~(ch - 1);  // first step of the last chunk
-    if (tl >= ch)
-      for (int piece = nsteps - tl; piece < ch; ++piece) flush(tl - ch, piece);
-    for (int piece = 0; piece < ch; ++piece) flush(tl, piece);
+    if (t < nsteps) __syncthreads();  // end of the last step (odd step count)
     return;
   }
   // -------------------------------------------------- compute wavefronts
@@ -267,16 +266,19 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
     b[d] = T(grp[d].b);
     w[d] = T(grp[d].w);
   }
-  const T* dsrc = dsrc_all + 4 * q * ncell;
-  const T* dsig = dsig_all + q * ncell;
+  const bool wpsi = psi && grp[0].slot >= 0;
+  T* pdst = wpsi ? psi + (long)grp[0].slot * ndof : nullptr;
+  T* pp = part ? part + (long)blockIdx.x * ndof : nullptr;
   int row[RPT];
   bool row_ok[RPT];
+  long cell0[RPT];
   T u[RPT][D][2];
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     row[k] = tid + k * nc;
     row_ok[k] = row[k] < ny;
     const int brow = sy > 0 ? row[k] : ny - 1 - row[k];
+    cell0[k] = (long)brow * nx + (sx > 0 ? 0 : nx - 1);  // cell of canonical column 0
     T g0 = T(0), g1 = T(0);
     if (row_ok[k] && bc) {
       const int side = sx > 0 ? 0 : 1;
@@ -289,72 +291,39 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
       u[k][d][1] = T(shx) * g1 * fy;
     }
   }
-  auto fetch = [&](Slot<T> (&sl)[RPT][SS], int K) {
+  __syncthreads();  // step 0 staged
+  for (int t = 0; t < nsteps; ++t) {
+    const int sl = t & 1;
 #pragma unroll
-    for (int i = 0; i < SS; ++i) {
-      const int t = SS * K + i;
-      const long base = diag_first(t, nx, ny) - (t >= nx ? t - nx + 1 : 0);
+    for (int k = 0; k < RPT; ++k) {
+      const int r = row[k];
+      const int ap = t - r;
+      if (row_ok[k] && ap >= 0 && ap < nx) {
+        const T* rd = r == 0 ? in_bnd + 2 * sl : vbuf + ((long)(sl ^ 1) * nr + (r - 1)) * D * 2;
+        const int rstride = r == 0 ? 0 : 2;
+        T* wr = vbuf + ((long)sl * nr + r) * D * 2;
+        const Vec4<T> s4 = load4(in_src + ((long)sl * (nr + 1) + r) * 4);
+        const T sig = in_sig[(long)sl * (nr + 1) + r];
+        T acc[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int ap = t - row[k];
-        if (row_ok[k] && ap >= 0 && ap < nx) {
-          const long idx = base + row[k];
-          sl[k][i].sig = dsig[idx];
-          const Vec4<T> s4 = load4(dsrc + 4 * idx);
+        for (int d = 0; d < D; ++d) {
+          const T v[2] = {rd[rstride * d], rd[rstride * d + 1]};
+          Cell<T> cell;
+          solve_cell<T>(sig, a[d], b[d], s4.v, u[k][d], v, cell);
+          u[k][d][0] = cell.uo[0];
+          u[k][d][1] = cell.uo[1];
+          wr[2 * d] = cell.vo[0];
+          wr[2 * d + 1] = cell.vo[1];
+          const T ph[4] = {cell.p[0], fx * cell.p[1], fy * cell.p[2], fxy * cell.p[3]};
+          const T wd = D == 1 && !pp ? T(1) : w[d];
 #pragma unroll
-          for (int m = 0; m < 4; ++m) sl[k][i].s[m] = s4.v[m];
+          for (int m = 0; m < 4; ++m) acc[m] += wd * ph[m];
+          if (D == 1 && wpsi) store4(pdst + 4 * (cell0[k] + (sx > 0 ? ap : -ap)), ph);
         }
+        if (pp) store4(pp + 4 * (cell0[k] + (sx > 0 ? ap : -ap)), acc);
       }
     }
-  };
-  Slot<T> A[RPT][SS], B[RPT][SS];
-  fetch(A, 0);
-  __syncthreads();  // vbnd ready
-  for (int K = 0; SS * K < nsteps; ++K) {
-    fetch(B, K + 1);
-#pragma unroll
-    for (int i = 0; i < SS; ++i) {
-      const int t = SS * K + i;
-      if (t < nsteps) {
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-          const int r = row[k];
-          const int ap = t - r;
-          if (row_ok[k] && ap >= 0 && ap < nx) {
-            const T* rd = r == 0 ? vbnd + 2 * (sx > 0 ? ap : nx - 1 - ap)
-                                 : vbuf + ((long)((t + 1) & 1) * nr + (r - 1)) * D * 2;
-            const int rstride = r == 0 ? 0 : 2;
-            T* wr = vbuf + ((long)(t & 1) * nr + r) * D * 2;
-            const Slot<T>& in = A[k][i];
-            T acc[4] = {T(0), T(0), T(0), T(0)};
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-              const T v[2] = {rd[rstride * d], rd[rstride * d + 1]};
-              Cell<T> cell;
-              solve_cell<T>(in.sig, a[d], b[d], in.s, u[k][d], v, cell);
-              u[k][d][0] = cell.uo[0];
-              u[k][d][1] = cell.uo[1];
-              wr[2 * d] = cell.vo[0];
-              wr[2 * d + 1] = cell.vo[1];
-              const T ph[4] = {cell.p[0], fx * cell.p[1], fy * cell.p[2], fxy * cell.p[3]};
-              if (D == 1) {
-#pragma unroll
-                for (int m = 0; m < 4; ++m) acc[m] = ph[m];
-              } else {
-#pragma unroll
-                for (int m = 0; m < 4; ++m) acc[m] += w[d] * ph[m];
-              }
-            }
-            store4(ring + ((long)(t & nsm) * nr + r) * 4, acc);
-          }
-        }
-        __syncthreads();
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < RPT; ++k)
-#pragma unroll
-      for (int i = 0; i < SS; ++i) A[k][i] = B[k][i];
+    __syncthreads();
   }
 }
 
@@ -394,9 +363,10 @@ static std::vector<SweepDir> make_groups(const std::vector<SweepDir>& in, int D)
   return out;
 }
 
-// vbuf [2][nr][D][2] + vbnd [nx][2] + ring [2 ch][nr][4], nr = padded rows
-static size_t sweep_lds_bytes(const Geom& g, int nr, int D, int ch, size_t eb) {
-  return (4ull * nr * D + 2ull * g.nx + 8ull * ch * nr) * eb;
+// vbuf [2][nr][D][2] + in_src [2][nr + 1][4] + in_sig [2][nr + 1] + in_bnd [2][2],
+// nr = padded rows
+static size_t sweep_lds_bytes(int nr, int D, size_t eb) {
+  return (4ull * nr * D + 10ull * (nr + 1) + 4) * eb;
 }
 
 // LDS bytes one workgroup may use on the current device
@@ -408,11 +378,12 @@ static size_t max_lds_per_block() {
   return (size_t)v;
 }
 
-// compute threads and rows per compute thread for ny rows (one wavefront is added
-// for the stores; a workgroup holds at most 1024 threads)
-static void sweep_threads(int ny, int& nc, int& rpt) {
-  rpt = ny <= 960 ? 1 : 2;
+// compute threads, rows per compute thread and staging wavefronts for ny rows (a
+// workgroup holds at most 1024 threads; a staging wavefront carries 256 rows)
+static void sweep_threads(int ny, int& nc, int& rpt, int& nst) {
+  rpt = ny <= 768 ? 1 : 2;
   nc = ((ny + rpt - 1) / rpt + 63) / 64 * 64;
+  nst = (nc * rpt + 64 * kStageRows - 1) / (64 * kStageRows);
 }
 
 // LDS per workgroup that still lets two workgroups share a compute unit (160 KB)
@@ -421,12 +392,13 @@ constexpr size_t kLdsTwoPerCU = 80 * 1024;
 SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool want_phi,
                           bool want_psi, size_t elem_bytes) {
   RTE_REQUIRE(g.ny >= 1 && g.ny <= 1024, "sweep: ny = %d outside [1, 1024]", g.ny);
-  RTE_REQUIRE(g.nx >= 1 && g.nx <= 4096, "sweep: nx = %d outside [1, 4096]", g.nx);
+  RTE_REQUIRE(g.nx >= 1 && g.nx <= 1 << 20, "sweep: nx = %d outside [1, 2^20]", g.nx);
   RTE_REQUIRE(!dirs.empty(), "sweep: no directions");
   SweepPlan pl;
-  int nc, rpt;
-  sweep_threads(g.ny, nc, rpt);  // one more wavefront stores
-  pl.nt = nc + 64;
+  int nc, rpt, nst;
+  sweep_threads(g.ny, nc, rpt, nst);
+  pl.nc = nc;
+  pl.nt = nc + 64 * nst;
   pl.rpt = rpt;
   const int nr = nc * rpt;
   const size_t lmax = max_lds_per_block();
@@ -436,18 +408,13 @@ SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool
     // enough workgroups to cover the chip first, then fewer partial sums; D is bounded
     // by the register budget (FP64: 2, and 1 beyond 576 threads)
     const int dmax = elem_bytes == 8 ? (pl.nt <= 576 && rpt == 1 ? 2 : 1) : 4;
-    while (D < dmax && dirs.size() / (2 * D) >= 256 && sweep_lds_bytes(g, nr, 2 * D, 1, elem_bytes) <= lcap)
+    while (D < dmax && dirs.size() / (2 * D) >= 256 && sweep_lds_bytes(nr, 2 * D, elem_bytes) <= lcap)
       D *= 2;
   }
-  // store chunk: up to 128 bytes of one row per chunk (16 bytes per lane)
-  const int chmax = (int)(128 / (4 * elem_bytes));
-  int ch = 1;
-  while (ch < chmax && sweep_lds_bytes(g, nr, D, 2 * ch, elem_bytes) <= lcap) ch *= 2;
-  RTE_REQUIRE(sweep_lds_bytes(g, nr, D, ch, elem_bytes) <= lmax,
+  RTE_REQUIRE(sweep_lds_bytes(nr, D, elem_bytes) <= lmax,
               "sweep: %d x %d cells need %zu bytes of LDS per workgroup (device limit %zu)", g.nx,
-              g.ny, sweep_lds_bytes(g, nr, D, ch, elem_bytes), lmax);
+              g.ny, sweep_lds_bytes(nr, D, elem_bytes), lmax);
   pl.D = D;
-  pl.ch = ch;
   pl.groups = make_groups(dirs, D);
   pl.ngroups = (int)(pl.groups.size() / D);
   for (const auto& d : pl.groups) pl.qmask |= 1 << ((d.sx < 0 ? 1 : 0) + (d.sy < 0 ? 2 : 0));
@@ -473,12 +440,12 @@ void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
                        g.ny, pl.qmask, sigma_t, src, dsrc, dsig);
     RTE_CHECK_HIP(hipGetLastError());
   }
-  const size_t lds = sweep_lds_bytes(g, (pl.nt - 64) * pl.rpt, pl.D, pl.ch, sizeof(T));
+  const size_t lds = sweep_lds_bytes(pl.nc * pl.rpt, pl.D, sizeof(T));
   dim3 grid(pl.ngroups), block(pl.nt);
   const double shx = std::sqrt(g.hx), shy = std::sqrt(g.hy);
   T* pp = phi ? part : nullptr;
 #define RTE_SWEEP_CASE(DD, NTB, RP)                                                                \
-  hipLaunchKernelGGL((sweep_kernel<T, DD, NTB, RP>), grid, block, lds, st, g.nx, g.ny, g.mb, pl.ch, \
+  hipLaunchKernelGGL((sweep_kernel<T, DD, NTB, RP>), grid, block, lds, st, g.nx, g.ny, g.mb, pl.nc, \
                      shx, shy, dirs_dev, dsrc, dsig, bc, psi, pp, g.ndof)
   // FP64 plans use D = 2 only with at most 576 threads (register budget)
 #define RTE_SWEEP_D(NTB, RP)                                         \
@@ -488,14 +455,15 @@ void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
   else if constexpr (sizeof(T) == 8) bad();                          \
   else RTE_SWEEP_CASE(4, NTB, RP);
   auto bad = [&] { RTE_REQUIRE(false, "sweep: no kernel for D = %d, %d threads", pl.D, pl.nt); };
+  RTE_REQUIRE(pl.nt <= 1024, "sweep: %d threads", pl.nt);
   if (pl.rpt == 2) {
-    RTE_SWEEP_D(576, 2)
+    RTE_SWEEP_D(768, 2)
   } else if (pl.nt <= 320) {
     RTE_SWEEP_D(320, 1)
   } else if (pl.nt <= 576) {
     RTE_SWEEP_D(576, 1)
   } else {
-    RTE_SWEEP_D(1024, 1)
+    RTE_SWEEP_D(960, 1)
   }
 #undef RTE_SWEEP_D
 #undef RTE_SWEEP_CASE
