@@ -100,8 +100,9 @@ rte_status rte_adjoint_sweep(const rte_problem* prob, const int32_t* dir_idx,
  * the source and cross section, per-group partial sums) are built and allocated
  * once, so rte_sweep_execute only enqueues the sweep's kernels: the input reordering,
  * the sweep and, when phi is requested, the fixed-order reduction of the per-group
- * partial sums.  A call with psi == NULL uses a table that batches several ordinates
- * per workgroup; a call that writes psi uses one ordinate per workgroup.
+ * partial sums.  The plan keeps one direction table per output combination (psi
+ * only, phi only, both): large ordinate sets batch several ordinates of one quadrant
+ * per workgroup, except when psi and phi are both written.
  *   rte_sweep_plan_create: arguments as rte_sweep (prob->dirs/wts/bc and the device
  *     pointers in prob are captured and must stay valid for the plan's lifetime);
  *     want_phi != 0 reserves the scalar-flux workspace; adjoint != 0 plans

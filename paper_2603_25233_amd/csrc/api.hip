@@ -232,9 +232,10 @@ static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w
 
 struct rte_sweep_plan_s {
   rte::Geom g;
-  rte::SweepPlan pl;                      // one direction per workgroup (psi written)
-  rte::SweepPlan plf;                     // scalar flux only (directions batched)
-  rte::DevBuf<rte::SweepDir> dirs, dirsf;
+  rte::SweepPlan pl;                      // psi only
+  rte::SweepPlan plf;                     // scalar flux only
+  rte::SweepPlan plb;                     // psi and the scalar flux
+  rte::DevBuf<rte::SweepDir> dirs, dirsf, dirsb;
   rte::DevBuf<unsigned char> work;
   const double* sigma_t = nullptr;
   const double* bc = nullptr;
@@ -275,17 +276,21 @@ rte_status rte_sweep_plan_create(const rte_problem* prob, const int32_t* dir_idx
     h->g = make_geom(prob);
     std::vector<SweepDir> dirs = sweep_dirs(prob, h->g, dir_idx, n_sel, adjoint != 0);
     const size_t eb = prec == RTE_FP64 ? sizeof(double) : sizeof(float);
-    h->pl = make_sweep_plan(h->g, dirs, want_phi != 0, true, eb);
-    h->dirs.alloc(h->pl.groups.size());
-    RTE_CHECK_HIP(hipMemcpy(h->dirs.get(), h->pl.groups.data(),
-                            h->pl.groups.size() * sizeof(SweepDir), hipMemcpyHostToDevice));
-    size_t work = sweep_work_elems(h->g, h->pl, want_phi != 0);
+    auto upload = [&](const SweepPlan& p, DevBuf<SweepDir>& d) {
+      d.alloc(p.groups.size());
+      RTE_CHECK_HIP(hipMemcpy(d.get(), p.groups.data(), p.groups.size() * sizeof(SweepDir),
+                              hipMemcpyHostToDevice));
+    };
+    h->pl = make_sweep_plan(h->g, dirs, false, true, eb);
+    upload(h->pl, h->dirs);
+    size_t work = sweep_work_elems(h->g, h->pl, false);
     if (want_phi) {
       h->plf = make_sweep_plan(h->g, dirs, true, false, eb);
-      h->dirsf.alloc(h->plf.groups.size());
-      RTE_CHECK_HIP(hipMemcpy(h->dirsf.get(), h->plf.groups.data(),
-                              h->plf.groups.size() * sizeof(SweepDir), hipMemcpyHostToDevice));
+      upload(h->plf, h->dirsf);
+      h->plb = make_sweep_plan(h->g, dirs, true, true, eb);
+      upload(h->plb, h->dirsb);
       work = std::max(work, sweep_work_elems(h->g, h->plf, true));
+      work = std::max(work, sweep_work_elems(h->g, h->plb, true));
     }
     h->work.alloc(work * eb);
     h->sigma_t = prob->sigma_t;
@@ -308,9 +313,8 @@ rte_status rte_sweep_execute(rte_sweep_plan h, const void* src, void* psi, void*
     RTE_REQUIRE(psi || phi, "one of psi, phi is required");
     RTE_REQUIRE(!phi || h->want_phi, "the plan was created without the scalar-flux workspace");
     hipStream_t st = (hipStream_t)stream;
-    const bool batched = !psi;  // scalar flux only: the batched plan
-    const SweepPlan& pl = batched ? h->plf : h->pl;
-    const SweepDir* dd = batched ? h->dirsf.get() : h->dirs.get();
+    const SweepPlan& pl = !phi ? h->pl : !psi ? h->plf : h->plb;
+    const SweepDir* dd = !phi ? h->dirs.get() : !psi ? h->dirsf.get() : h->dirsb.get();
     if (h->prec == RTE_FP64)
       sweep_enqueue<double>(h->g, pl, dd, h->sigma_t, (const double*)src, h->bc,
                             (double*)psi, (double*)phi, (double*)h->work.get(), st);

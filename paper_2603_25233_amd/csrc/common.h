@@ -90,18 +90,21 @@ struct SweepPlan {
   int nt = 64;    // threads per workgroup: nc compute threads + staging wavefronts
   int nc = 64;
   int rpt = 1;    // rows per compute thread
+  int ring = 1;   // results leave through the LDS ring (else direct stores)
+  int psi = 1;    // planned for psi output (else the scalar flux only)
   int qmask = 0;  // quadrants swept (bit q = (sx < 0) + 2 (sy < 0))
 };
-// Directions are batched D > 1 per workgroup only for scalar-flux-only sweeps
-// (want_phi && !want_psi).
+// Plans for psi (want_psi) or for the scalar flux only; a psi plan also serves
+// calls that request both.
 SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool want_phi,
                           bool want_psi, size_t elem_bytes);
 // Elements of T the sweep needs as workspace: the diagonal-major copies of the
-// source and cross section (5 ncell per quadrant) and, when phi is requested, the
-// per-group partial sums ([ngroups][ndof]).
+// source and cross section (about 5 ncell per quadrant) and, when phi is requested,
+// the per-group partial sums ([ngroups][ndof]).
+size_t sweep_input_elems(const Geom& g);
 size_t sweep_work_elems(const Geom& g, const SweepPlan& pl, bool want_phi);
 // Enqueues the sweep (no synchronisation).  work: sweep_work_elems(g, pl, phi != null)
-// elements.  psi != null needs a plan with D == 1.
+// elements.  psi != null needs a plan made with want_psi.
 template <typename T>
 void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
                    const double* sigma_t, const T* src, const double* bc, T* psi, T* phi,

@@ -869,7 +869,7 @@ struct LowRank {
     X.alloc((size_t)rcap * nd);
     psi.alloc((size_t)p * nd);
     srcT.alloc(nd);
-    swork.alloc(20 * (size_t)g.nx * g.ny);  // sweep workspace without the scalar flux
+    swork.alloc(sweep_input_elems(g));  // sweep workspace without the scalar flux
     Y.alloc((size_t)5 * p * nd);
     V.alloc((size_t)32 * nd);
     src.alloc(nd);

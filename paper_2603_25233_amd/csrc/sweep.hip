@@ -122,9 +122,24 @@ __host__ __device__ __forceinline__ long diag_first(int t, int nx, int ny) {
   return a - u * (u + 1) / 2;
 }
 
+// Sigma_t of anti-diagonal t starts at sig_first(t) in its quadrant's array: the
+// diagonal-major position advanced by (CPS - 1) t and rounded up to a multiple of
+// CPS = 16 / sizeof(T) cells, so every diagonal's block starts on a 16-byte boundary
+// (and blocks never overlap).  sig_stride is the per-quadrant length.
+template <typename T>
+__host__ __device__ __forceinline__ long sig_first(int t, int nx, int ny) {
+  constexpr long CPS = 16 / sizeof(T);
+  return (diag_first(t, nx, ny) + (CPS - 1) * t + CPS - 1) / CPS * CPS;
+}
+template <typename T>
+__host__ __device__ __forceinline__ long sig_stride(int nx, int ny) {
+  constexpr long CPS = 16 / sizeof(T);
+  return ((long)nx * ny + (CPS - 1) * (long)(nx + ny) + 2 * CPS) / CPS * CPS;
+}
+
 // Diagonal-major copies of the sweep inputs for the quadrants in qmask: the source
 // moments (with the quadrant's reflections applied to the odd moments) and sigma_t,
-// converted to T.  dsrc: [4][ncell][4], dsig: [4][ncell].
+// converted to T.  dsrc: [4][ncell][4], dsig: [4][sig_stride].
 template <typename T>
 __global__ void diag_layout_kernel(int nx, int ny, int qmask, const double* __restrict__ sigma_t,
                                    const T* __restrict__ src, T* __restrict__ dsrc,
@@ -135,6 +150,7 @@ __global__ void diag_layout_kernel(int nx, int ny, int qmask, const double* __re
   const int acol = (int)(c % nx), brow = (int)(c / nx);
   const Vec4<T> s4 = load4(src + 4 * c);
   const T sg = T(sigma_t[c]);
+  const long qs = sig_stride<T>(nx, ny);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     if (!((qmask >> q) & 1)) continue;
@@ -142,47 +158,76 @@ __global__ void diag_layout_kernel(int nx, int ny, int qmask, const double* __re
     const int r = sy > 0 ? brow : ny - 1 - brow;
     const int ap = sx > 0 ? acol : nx - 1 - acol;
     const int t = r + ap;
-    const long k = q * ncell + diag_first(t, nx, ny) + r - (t >= nx ? t - nx + 1 : 0);
+    const int lo = t >= nx ? t - nx + 1 : 0;
+    const long k = q * ncell + diag_first(t, nx, ny) + r - lo;
     const T v[4] = {s4.v[0], T(sx) * s4.v[1], T(sy) * s4.v[2], T(sx * sy) * s4.v[3]};
     store4(dsrc + 4 * k, v);
-    dsig[k] = sg;
+    dsig[q * qs + sig_first<T>(t, nx, ny) + r - lo] = sg;
   }
 }
 
-// Rows of one step that each staging wavefront lane carries (64 lanes x 4 = 256 rows).
-constexpr int kStageRows = 4;
+// Rows of one step that each staging wavefront carries.
+constexpr int kStageRows = 256;
+
+// Output write-back geometry for element type T: a row's results leave in aligned
+// chunks of 128 bytes (kChunkCells cells), 16 bytes per lane, 8 rows per store
+// instruction; the LDS ring keeps the last kRingSlots steps.
+template <typename T>
+struct WriteBack {
+  static constexpr int kCellBytes = 4 * sizeof(T);
+  static constexpr int kChunkCells = 128 / kCellBytes;  // 4 (FP64) or 8 (FP32)
+  static constexpr int kLanesPerCell = kCellBytes / 16;  // 2 or 1
+  static constexpr int kRingSlots = kChunkCells + 1;
+  static constexpr int kInstr = 64 / kChunkCells / 8;    // store instructions per wave and step
+};
+
+typedef __attribute__((address_space(3))) void lds_void;
 
 // One workgroup sweeps D directions (dirs[blockIdx.x*D + d]) of one quadrant.
-// psi: [slots][ndof] or null (D == 1 when psi is written).  part: [gridDim.x][ndof]
-// weighted partial sums or null.  dsrc/dsig: the diagonal-major inputs.
+// psi: [slots][ndof] or null; part: [gridDim.x][ndof] weighted partial sums or null
+// (not both).  dsrc/dsig: the diagonal-major inputs.
 //
 // Roles.  The first nc threads compute; compute thread j owns the canonical rows
 // j + k nc, k < RPT (both on the current anti-diagonal, so they are independent
-// work).  The remaining wavefronts stage inputs: staging wavefront w carries rows
-// 256 w + lane + 64 i, i < 4.  Compute wavefronts read their inputs from LDS and
-// issue only global stores (psi, or the weighted partial sums), which they never
-// wait for; staging wavefronts issue only global loads, so their waits are exact.
+// work).  The remaining wavefronts stage inputs, 256 rows each, with direct
+// global-to-LDS loads.  Compute wavefronts read their inputs from LDS and issue only
+// global stores, which they never wait for.
 //
 // Per step t: the compute threads solve the cells of canonical column t - r, taking
 // the source and sigma_t of step t from LDS slot t & 1 and the y-inflow trace from row
 // r - 1 of step t - 1 (double-buffered LDS, one barrier per step); the x-inflow trace
-// stays in registers.  Meanwhile the staging wavefronts move step t + 1 from registers
-// into slot (t + 1) & 1 and request step t + 3 from global memory (two register
-// buffers, so a load has two steps to arrive).  Slot (t + 1) & 1 was last read in
-// step t - 1, before the barrier that ended it.
+// stays in registers.  Meanwhile the staging wavefronts copy exactly the cells of step
+// t + 1 into slot (t + 1) & 1 (last read in step t - 1) and wait for the copies before
+// the barrier that ends step t.
+//
+// Output.  With use_ring, step t leaves its results in LDS ring slot t mod kRingSlots
+// (per direction for psi, or the weighted sum over the group's directions for the
+// scalar flux).  A row's cells are grouped into aligned chunks of kChunkCells
+// physical columns; at the start of step t each compute wavefront writes back, from
+// the ring, the chunks of its rows whose last cell was solved at step t - 1 (one row
+// in kChunkCells, plus the short end chunk of one row when nx is not a multiple of
+// kChunkCells and the sweep runs towards +x), so every store instruction writes whole
+// 128-byte lines.  Without the ring (LDS too small) each thread stores its cell.
 template <typename T, int D, int NTB, int RPT>
 __global__ __launch_bounds__(NTB) void sweep_kernel(
-    int nx, int ny, int mb, int nc, double shx, double shy, const SweepDir* __restrict__ dirs,
-    const T* __restrict__ dsrc_all, const T* __restrict__ dsig_all,
-    const double* __restrict__ bc, T* __restrict__ psi, T* __restrict__ part, long ndof) {
+    int nx, int ny, int mb, int nc, int use_ring, double shx, double shy,
+    const SweepDir* __restrict__ dirs, const T* __restrict__ dsrc_all,
+    const T* __restrict__ dsig_all, const double* __restrict__ bc, T* __restrict__ psi,
+    T* __restrict__ part, long ndof) {
+  using WB = WriteBack<T>;
+  constexpr int CW = WB::kChunkCells, NS = WB::kRingSlots, LPC = WB::kLanesPerCell;
+  constexpr int CPC = 4 * (int)sizeof(T) / 16;  // 16-byte pieces per source cell
+  constexpr int CPS = 16 / (int)sizeof(T);      // sigma_t cells per 16-byte piece
   extern __shared__ unsigned char smem_raw[];
   const int tid = threadIdx.x;
-  const int nr = nc * RPT;                   // padded rows
-  T* vbuf = reinterpret_cast<T*>(smem_raw);  // [2][nr][D][2] y-inflow traces by row
-  T* in_src = vbuf + 4L * nr * D;            // [2][nr + 1][4] source moments of the step
-  T* in_sig = in_src + 8L * (nr + 1);        // [2][nr + 1] sigma_t of the step
-  T* in_bnd = in_sig + 2L * (nr + 1);        // [2][2] y-inflow of canonical row 0
-  // (row nr of in_src / in_sig takes the staging writes of cells not on the step)
+  const int nr = nc * RPT;                    // padded rows
+  const int nrs = nr + 2 * CPS;               // sigma_t slot length
+  const int RD = psi ? D : 1;                 // ring entries per row and step
+  T* vbuf = reinterpret_cast<T*>(smem_raw);   // [2][nr][D][2] y-inflow traces by row
+  T* in_src = vbuf + 4L * nr * D;             // [2][nr][4] source moments of the step
+  T* in_sig = in_src + 8L * nr;               // [2][nrs] sigma_t of the step (shifted)
+  T* in_bnd = in_sig + 2L * nrs;              // [2][2] y-inflow of canonical row 0
+  T* ring = in_bnd + 4;                       // [NS][nr][RD][4] outputs by step and row
   const SweepDir* grp = dirs + (long)blockIdx.x * D;
   const int sx = grp[0].sx, sy = grp[0].sy;
   const T fx = T(sx), fy = T(sy), fxy = T(sx * sy);
@@ -191,71 +236,60 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
   const int nsteps = nx + ny - 1;
   if (tid >= nc) {
     // ------------------------------------------------ staging wavefronts
+    // Step t's cells are rows lo..hi of anti-diagonal t, contiguous in the
+    // diagonal-major arrays.  Staging wavefront sw copies rows lo + 256 sw ..
+    // lo + 256 sw + 255 (16 bytes per lane, lanes past the step masked off): the
+    // source to in_src rows lo.., sigma_t to in_sig positions sh(t) + lo.., where
+    // sh(t) = -lo mod CPS keeps the copy 16-byte aligned on both sides.
     const int lane = tid & 63;
-    const int rbase = ((tid - nc) >> 6) * 64 * kStageRows + lane;
-    const T* dsrc = dsrc_all + 4 * q * ncell;
-    const T* dsig = dsig_all + q * ncell;
+    const int sw = (tid - nc) >> 6;
+    const float4* src16 = reinterpret_cast<const float4*>(dsrc_all + 4 * q * ncell);
+    const float4* sig16 = reinterpret_cast<const float4*>(dsig_all + q * sig_stride<T>(nx, ny));
     const int yside = sy > 0 ? 2 : 3;
-    struct Buf {
-      Vec4<T> s[kStageRows];
-      T sig[kStageRows];
-      T g[2];
-    };
-    // Loads of step t: unconditional and clamped in bounds, so the wait counts are
-    // static.  Every lane also reads the row-0 inflow of the step (one address).
-    const double* gsrc = bc ? bc : reinterpret_cast<const double*>(dsig_all);
-    auto load = [&](Buf& b, int t) {
-      const long f = diag_first(t, nx, ny) - (t >= nx ? t - nx + 1 : 0);
-#pragma unroll
-      for (int i = 0; i < kStageRows; ++i) {
-        const int r = rbase + 64 * i;
-        const bool ok = r < ny && t - r >= 0 && t - r < nx;
-        const long idx = ok ? f + r : 0;
-        b.s[i] = load4(dsrc + 4 * idx);
-        b.sig[i] = dsig[idx];
-      }
-      const int ap = t < nx ? t : nx - 1;
-      const int col = sx > 0 ? ap : nx - 1 - ap;
-      const long go = bc ? ((long)yside * mb + col) * 2 : 0;
-      const double g0 = gsrc[go], g1 = gsrc[go + 1];
-      b.g[0] = bc ? T(g0) : T(0);
-      b.g[1] = bc ? T(g1) : T(0);
-    };
-    // LDS writes of step t, branch-free: cells not on the step go to the junk row nr.
-    auto put = [&](const Buf& b, int t) {
+    auto stage = [&](int t) {
+      const int lo = t >= nx ? t - nx + 1 : 0;
+      const int hi = t < ny ? t : ny - 1;
       const int sl = t & 1;
-#pragma unroll
-      for (int i = 0; i < kStageRows; ++i) {
-        const int r = rbase + 64 * i;
-        const bool ok = r < ny && t - r >= 0 && t - r < nx;
-        const long e = (long)sl * (nr + 1) + (ok ? r : nr);
-        store4(in_src + e * 4, b.s[i].v);
-        in_sig[e] = b.sig[i];
+      const int c0 = sw * kStageRows;   // first cell of this wavefront
+      const int nce = hi - lo + 1 - c0;  // cells left for it
+      if (nce > 0) {
+        const int ncw = nce < kStageRows ? nce : kStageRows;
+        // source: ncw * CPC pieces
+        const float4* gs = src16 + (diag_first(t, nx, ny) + c0) * CPC;
+        float4* ls = reinterpret_cast<float4*>(in_src) + ((long)sl * nr + lo + c0) * CPC;
+        for (int i = 0; 64 * i < ncw * CPC; ++i)
+          if (64 * i + lane < ncw * CPC)
+            __builtin_amdgcn_global_load_lds((const void*)(gs + 64 * i + lane),
+                                             (lds_void*)(ls + 64 * i), 16, 0, 0);
+        // sigma_t: ceil(ncw / CPS) pieces
+        const int sh = (-lo) & (CPS - 1);
+        const float4* gg = sig16 + (sig_first<T>(t, nx, ny) + c0) / CPS;
+        float4* lg = reinterpret_cast<float4*>(in_sig + (long)sl * nrs + sh + lo + c0);
+        const int npg = (ncw + CPS - 1) / CPS;
+        for (int i = 0; 64 * i < npg; ++i)
+          if (64 * i + lane < npg)
+            __builtin_amdgcn_global_load_lds((const void*)(gg + 64 * i + lane),
+                                             (lds_void*)(lg + 64 * i), 16, 0, 0);
       }
-      // every staging lane holds the same row-0 inflow; unused for t >= nx
-      in_bnd[2 * sl] = T(shy) * b.g[0];
-      in_bnd[2 * sl + 1] = T(shy) * b.g[1] * fx;
+      if (sw == 0 && lane == 0 && t < nx) {
+        const int col = sx > 0 ? t : nx - 1 - t;
+        T g0 = T(0), g1 = T(0);
+        if (bc) {
+          g0 = T(bc[((long)yside * mb + col) * 2 + 0]);
+          g1 = T(bc[((long)yside * mb + col) * 2 + 1]);
+        }
+        in_bnd[2 * sl] = T(shy) * g0;
+        in_bnd[2 * sl + 1] = T(shy) * g1 * fx;
+      }
     };
-    // Two register buffers: while step t is computed, step t + 1 goes from one
-    // buffer into LDS and step t + 3 is requested into the same buffer; the other
-    // holds step t + 2 in flight.  Loop bodies are straight-line, so every wait is
-    // for the older buffer only.
-    Buf b1, b2;
-    load(b1, 0);
-    load(b2, 1);
-    put(b1, 0);
-    load(b1, 2);
+    stage(0);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();  // step 0 staged
-    int t = 0;
-    for (; t + 1 < nsteps; t += 2) {
-      put(b2, t + 1);
-      load(b2, t + 3);
-      __syncthreads();  // end of step t
-      put(b1, t + 2);
-      load(b1, t + 4);
-      __syncthreads();  // end of step t + 1
+    for (int t = 0; t < nsteps; ++t) {
+      if (t + 1 < nsteps) stage(t + 1);
+      __builtin_amdgcn_s_waitcnt(0);  // copies of step t + 1 landed
+      __syncthreads();                // end of step t
     }
-    if (t < nsteps) __syncthreads();  // end of the last step (odd step count)
     return;
   }
   // -------------------------------------------------- compute wavefronts
@@ -266,19 +300,14 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
     b[d] = T(grp[d].b);
     w[d] = T(grp[d].w);
   }
-  const bool wpsi = psi && grp[0].slot >= 0;
-  T* pdst = wpsi ? psi + (long)grp[0].slot * ndof : nullptr;
-  T* pp = part ? part + (long)blockIdx.x * ndof : nullptr;
   int row[RPT];
   bool row_ok[RPT];
-  long cell0[RPT];
   T u[RPT][D][2];
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     row[k] = tid + k * nc;
     row_ok[k] = row[k] < ny;
     const int brow = sy > 0 ? row[k] : ny - 1 - row[k];
-    cell0[k] = (long)brow * nx + (sx > 0 ? 0 : nx - 1);  // cell of canonical column 0
     T g0 = T(0), g1 = T(0);
     if (row_ok[k] && bc) {
       const int side = sx > 0 ? 0 : 1;
@@ -291,9 +320,94 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
       u[k][d][1] = T(shx) * g1 * fy;
     }
   }
+  // output bases per direction (null: padding direction or no psi)
+  T* pdst[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+    pdst[d] = psi && grp[d].slot >= 0 ? psi + (long)grp[d].slot * ndof : nullptr;
+  T* pp = part ? part + (long)blockIdx.x * ndof : nullptr;
+  const T w0 = T(grp[0].w);
+  // Write-back lanes: 8 per row (16 bytes each), 8 rows per store instruction;
+  // instruction i of block k covers rows wrow[k][i] + rho(t), rho(t) the residue
+  // (mod CW) of the rows whose last cell closed an aligned chunk.  The flat cell index
+  // of a lane's cell is affine in its row and the step: c = clane + (Cr rho + sx t),
+  // and the ring slot of the cell depends on the step and the lane's cell only.
+  const int lane = tid & 63, wbase = tid & ~63;
+  const int jrow = lane >> 3;
+  const int cc = (lane & 7) / LPC, half = lane % LPC;  // cell within the chunk, piece
+  const long Cr = (long)sy * nx - sx;
+  const long C0 = (sy > 0 ? 0 : (long)(ny - 1) * nx) + (sx > 0 ? -CW : nx);
+  int wrow[RPT][WB::kInstr];
+  long clane[RPT][WB::kInstr];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k)
+#pragma unroll
+    for (int i = 0; i < WB::kInstr; ++i) {
+      wrow[k][i] = wbase + k * nc + CW * (jrow + 8 * i);
+      clane[k][i] = C0 + Cr * wrow[k][i] + cc;
+    }
+  const int roff = sx > 0 ? 1 + cc : NS - 1 - cc;  // ring slot = (t + roff) mod NS
+  const int eoff = half * (16 / (int)sizeof(T));
+  auto put_cell = [&](long c, int slot, int r) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      if (d > 0 && !psi) break;
+      const T* e = ring + (((long)slot * nr + r) * RD + d) * 4 + eoff;
+      if constexpr (sizeof(T) == 8) {
+        const double2 v = *reinterpret_cast<const double2*>(e);
+        if (pdst[d]) *reinterpret_cast<double2*>(pdst[d] + 4 * c + eoff) = v;
+        if (pp) {
+          const double2 wv = D == 1 ? make_double2(w0 * v.x, w0 * v.y) : v;
+          *reinterpret_cast<double2*>(pp + 4 * c + eoff) = wv;
+        }
+      } else {
+        const float4 v = *reinterpret_cast<const float4*>(e);
+        if (pdst[d]) *reinterpret_cast<float4*>(pdst[d] + 4 * c) = v;
+        if (pp) {
+          const float4 wv = D == 1 ? make_float4(w0 * v.x, w0 * v.y, w0 * v.z, w0 * v.w) : v;
+          *reinterpret_cast<float4*>(pp + 4 * c) = wv;
+        }
+      }
+    }
+  };
+  const int endc = nx % CW;  // cells in the short end chunk of a row (0: none)
+  // Chunks closed by the cells solved at step t - 1 (st = t mod NS).
+  auto write_back = [&](int t, int st) {
+    const int rho = (sx > 0 ? t : t - nx) & (CW - 1);
+    const long cu = Cr * rho + (long)sx * t;
+    int slot = st + roff;
+    slot = slot >= NS ? slot - NS : slot;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k)
+#pragma unroll
+      for (int i = 0; i < WB::kInstr; ++i) {
+        const int r = wrow[k][i] + rho;
+        const int apl = t - 1 - r;  // canonical column solved at step t - 1
+        const bool ok = r < ny && (unsigned)apl < (unsigned)nx &&
+                        (sx > 0 || nx - 1 - apl + cc < nx);
+        if (ok) put_cell(clane[k][i] + cu, slot, r);
+      }
+    // the short end chunk of row t - nx (towards +x only)
+    if (sx > 0 && endc != 0) {
+      const int r = t - nx;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int j = r - wbase - k * nc;
+        if (r >= 0 && r < ny && j >= 0 && j < 64 && jrow == 0 && cc < endc) {
+          const int col = nx - endc + cc;
+          const int brow = sy > 0 ? r : ny - 1 - r;
+          put_cell((long)brow * nx + col, (r + col) % NS, r);
+        }
+      }
+    }
+  };
   __syncthreads();  // step 0 staged
+  int ns = 0;       // t mod NS
   for (int t = 0; t < nsteps; ++t) {
     const int sl = t & 1;
+    if (use_ring && t > 0) write_back(t, ns);
+    const int lo = t >= nx ? t - nx + 1 : 0;
+    const T* sigs = in_sig + (long)sl * nrs + ((-lo) & (CPS - 1));
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int r = row[k];
@@ -302,8 +416,9 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
         const T* rd = r == 0 ? in_bnd + 2 * sl : vbuf + ((long)(sl ^ 1) * nr + (r - 1)) * D * 2;
         const int rstride = r == 0 ? 0 : 2;
         T* wr = vbuf + ((long)sl * nr + r) * D * 2;
-        const Vec4<T> s4 = load4(in_src + ((long)sl * (nr + 1) + r) * 4);
-        const T sig = in_sig[(long)sl * (nr + 1) + r];
+        const Vec4<T> s4 = load4(in_src + ((long)sl * nr + r) * 4);
+        const T sig = sigs[r];
+        T* rg = ring + ((long)ns * nr + r) * RD * 4;
         T acc[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
         for (int d = 0; d < D; ++d) {
@@ -315,16 +430,42 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
           wr[2 * d] = cell.vo[0];
           wr[2 * d + 1] = cell.vo[1];
           const T ph[4] = {cell.p[0], fx * cell.p[1], fy * cell.p[2], fxy * cell.p[3]};
-          const T wd = D == 1 && !pp ? T(1) : w[d];
+          if (psi) {
+            if (use_ring) {
+              store4(rg + 4 * d, ph);
+            } else {
+              const int brow = sy > 0 ? r : ny - 1 - r;
+              const long c = (long)brow * nx + (sx > 0 ? ap : nx - 1 - ap);
+              if (pdst[d]) store4(pdst[d] + 4 * c, ph);
+              if (pp) {  // D == 1 here
+                T wv[4];
 #pragma unroll
-          for (int m = 0; m < 4; ++m) acc[m] += wd * ph[m];
-          if (D == 1 && wpsi) store4(pdst + 4 * (cell0[k] + (sx > 0 ? ap : -ap)), ph);
+                for (int m = 0; m < 4; ++m) wv[m] = w0 * ph[m];
+                store4(pp + 4 * c, wv);
+              }
+            }
+          } else {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) acc[m] = D == 1 ? ph[m] : acc[m] + w[d] * ph[m];
+          }
         }
-        if (pp) store4(pp + 4 * (cell0[k] + (sx > 0 ? ap : -ap)), acc);
+        if (!psi) {
+          if (use_ring) {
+            store4(rg, acc);
+          } else {
+            const int brow = sy > 0 ? r : ny - 1 - r;
+            T wv[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) wv[m] = D == 1 ? w0 * acc[m] : acc[m];
+            store4(pp + 4 * ((long)brow * nx + (sx > 0 ? ap : nx - 1 - ap)), wv);
+          }
+        }
       }
     }
     __syncthreads();
+    ns = ns + 1 == NS ? 0 : ns + 1;
   }
+  if (use_ring) write_back(nsteps, ns);  // chunks closed by the last step
 }
 
 // phi[i] = sum_g part[g][i] in group order (deterministic).
@@ -363,10 +504,13 @@ static std::vector<SweepDir> make_groups(const std::vector<SweepDir>& in, int D)
   return out;
 }
 
-// vbuf [2][nr][D][2] + in_src [2][nr + 1][4] + in_sig [2][nr + 1] + in_bnd [2][2],
-// nr = padded rows
-static size_t sweep_lds_bytes(int nr, int D, size_t eb) {
-  return (4ull * nr * D + 10ull * (nr + 1) + 4) * eb;
+// vbuf [2][nr][D][2] + in_src [2][nr][4] + in_sig [2][nr + 2 CPS] + in_bnd [2][2]
+// + ring [kRingSlots][nr][RD][4] (with the ring; RD = D for psi, 1 for the scalar
+// flux), nr = padded rows
+static size_t sweep_lds_bytes(int nr, int D, bool psi, bool ring, size_t eb) {
+  const size_t slots = ring ? (eb == 8 ? WriteBack<double>::kRingSlots : WriteBack<float>::kRingSlots) : 0;
+  const size_t cps = 16 / eb;
+  return (4ull * nr * D + 8ull * nr + 2 * (nr + 2 * cps) + 4 + 4ull * slots * nr * (psi ? D : 1)) * eb;
 }
 
 // LDS bytes one workgroup may use on the current device
@@ -383,7 +527,7 @@ static size_t max_lds_per_block() {
 static void sweep_threads(int ny, int& nc, int& rpt, int& nst) {
   rpt = ny <= 768 ? 1 : 2;
   nc = ((ny + rpt - 1) / rpt + 63) / 64 * 64;
-  nst = (nc * rpt + 64 * kStageRows - 1) / (64 * kStageRows);
+  nst = (nc * rpt + kStageRows - 1) / kStageRows;
 }
 
 // LDS per workgroup that still lets two workgroups share a compute unit (160 KB)
@@ -403,50 +547,63 @@ SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool
   const int nr = nc * rpt;
   const size_t lmax = max_lds_per_block();
   const size_t lcap = std::min(lmax, kLdsTwoPerCU);
+  // Directions per workgroup: enough workgroups to cover the chip first; then D > 1
+  // shares the staged inputs (and, for the scalar flux, the partial sums) among
+  // directions.  D is bounded by the register budget (FP64: 2, and 1 beyond 576
+  // threads; FP32: 4) and by LDS.
+  // (psi together with the scalar flux: one direction per workgroup)
+  const int dmax = want_psi && want_phi ? 1 : elem_bytes == 8 ? (pl.nt <= 576 && rpt == 1 ? 2 : 1) : 4;
   int D = 1;
-  if (want_phi && !want_psi) {
-    // enough workgroups to cover the chip first, then fewer partial sums; D is bounded
-    // by the register budget (FP64: 2, and 1 beyond 576 threads)
-    const int dmax = elem_bytes == 8 ? (pl.nt <= 576 && rpt == 1 ? 2 : 1) : 4;
-    while (D < dmax && dirs.size() / (2 * D) >= 256 && sweep_lds_bytes(nr, 2 * D, elem_bytes) <= lcap)
-      D *= 2;
-  }
-  RTE_REQUIRE(sweep_lds_bytes(nr, D, elem_bytes) <= lmax,
+  while (D < dmax && dirs.size() / (2 * D) >= 256 &&
+         sweep_lds_bytes(nr, 2 * D, want_psi, true, elem_bytes) <= lmax)
+    D *= 2;
+  // the output ring if it fits (else each thread stores its cells directly)
+  const bool ring = sweep_lds_bytes(nr, D, want_psi, true, elem_bytes) <= lmax;
+  RTE_REQUIRE(sweep_lds_bytes(nr, D, want_psi, ring, elem_bytes) <= lmax,
               "sweep: %d x %d cells need %zu bytes of LDS per workgroup (device limit %zu)", g.nx,
-              g.ny, sweep_lds_bytes(nr, D, elem_bytes), lmax);
+              g.ny, sweep_lds_bytes(nr, D, want_psi, ring, elem_bytes), lmax);
   pl.D = D;
+  pl.ring = ring ? 1 : 0;
+  pl.psi = want_psi ? 1 : 0;
   pl.groups = make_groups(dirs, D);
   pl.ngroups = (int)(pl.groups.size() / D);
   for (const auto& d : pl.groups) pl.qmask |= 1 << ((d.sx < 0 ? 1 : 0) + (d.sy < 0 ? 2 : 0));
   return pl;
 }
 
+size_t sweep_input_elems(const Geom& g) {
+  // both precisions use the larger of the two sigma_t strides
+  const size_t qs = std::max(sig_stride<double>(g.nx, g.ny), sig_stride<float>(g.nx, g.ny));
+  return 16ull * g.nx * g.ny + 4 * qs;
+}
+
 size_t sweep_work_elems(const Geom& g, const SweepPlan& pl, bool want_phi) {
-  return 20ull * g.nx * g.ny + (want_phi ? (size_t)pl.ngroups * g.ndof : 0);
+  return sweep_input_elems(g) + (want_phi ? (size_t)pl.ngroups * g.ndof : 0);
 }
 
 template <typename T>
 void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
                    const double* sigma_t, const T* src, const double* bc, T* psi, T* phi,
                    T* work, hipStream_t st) {
-  RTE_REQUIRE(!psi || pl.D == 1, "sweep: psi needs a plan with one direction per workgroup");
   const long ncell = (long)g.nx * g.ny;
-  T* dsrc = work;
-  T* dsig = work + 16 * ncell;
-  T* part = work + 20 * ncell;
+  RTE_REQUIRE(!psi || pl.psi, "sweep: the plan was made for the scalar flux only");
+  RTE_REQUIRE(!(psi && phi) || pl.D == 1, "sweep: psi with the scalar flux needs one direction per workgroup");
+  T* dsrc = work;              // [4][ncell][4]
+  T* dsig = work + 16 * ncell;  // [4][sig_stride]
+  T* part = work + sweep_input_elems(g);
   {
     const int tb = 256;
     hipLaunchKernelGGL((diag_layout_kernel<T>), dim3((ncell + tb - 1) / tb), dim3(tb), 0, st, g.nx,
                        g.ny, pl.qmask, sigma_t, src, dsrc, dsig);
     RTE_CHECK_HIP(hipGetLastError());
   }
-  const size_t lds = sweep_lds_bytes(pl.nc * pl.rpt, pl.D, sizeof(T));
+  const size_t lds = sweep_lds_bytes(pl.nc * pl.rpt, pl.D, psi != nullptr, pl.ring != 0, sizeof(T));
   dim3 grid(pl.ngroups), block(pl.nt);
   const double shx = std::sqrt(g.hx), shy = std::sqrt(g.hy);
   T* pp = phi ? part : nullptr;
 #define RTE_SWEEP_CASE(DD, NTB, RP)                                                                \
   hipLaunchKernelGGL((sweep_kernel<T, DD, NTB, RP>), grid, block, lds, st, g.nx, g.ny, g.mb, pl.nc, \
-                     shx, shy, dirs_dev, dsrc, dsig, bc, psi, pp, g.ndof)
+                     pl.ring, shx, shy, dirs_dev, dsrc, dsig, bc, psi, pp, g.ndof)
   // FP64 plans use D = 2 only with at most 576 threads (register budget)
 #define RTE_SWEEP_D(NTB, RP)                                         \
   if (pl.D == 1) RTE_SWEEP_CASE(1, NTB, RP);                         \
