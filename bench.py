@@ -190,8 +190,11 @@ def main():
                                "8x8 diffusive/absorbing blocks, p=4 q=32, eps_si=1e-6",
                    "only": args.only},
         "sweep_kernel": {"updates_per_s": k1_updates / (k1_ms * 1e-3), "ms": k1_ms,
-                         "launch": "1 workgroup per ordinate, 256 threads (one per row)"},
-        "roofline": {"kernel": "sweep_kernel (full-angle, psi written)", "bound": "hbm",
+                         "launch": "diag_layout_kernel, then sweep_kernel: 2 ordinates of one "
+                                   "quadrant per workgroup (256 workgroups), 256 compute threads "
+                                   "(one per row) + 1 staging wavefront"},
+        "roofline": {"kernel": "psi sweep (diag_layout_kernel + sweep_kernel), full angle set",
+                     "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": k1_bytes},
