@@ -68,78 +68,171 @@ __device__ __forceinline__ void block_sum_vec(const double* v, double* red) {
 }
 
 // ------------------------------------------------------------------ projections
-// Row chunk per block.  If r_upd > 0: v -= sum_{c<r_upd} X[c] dc[c] (written back).
-// Then part[blk][0..r_dot) = X[c]^T v (chunk), part[blk][r_dot] = v.v (after),
-// part[blk][r_dot+1] = v.v (before the update).
-template <typename T>
-__global__ __launch_bounds__(kTB) void proj_kernel(const T* __restrict__ X, long nd, int r_upd,
-                                                   int r_dot, T* __restrict__ v,
-                                                   const double* __restrict__ dc,
-                                                   double* __restrict__ part, long chunk) {
-  extern __shared__ double sm[];
-  double* sdc = sm;                  // [r_upd]
-  double* red = sm + r_upd;          // [(4+1)*8]
-  const long i0 = (long)blockIdx.x * chunk, i1 = min(nd, i0 + chunk);
-  for (int c = threadIdx.x; c < r_upd; c += kTB) sdc[c] = dc[c];
+// A block of kProjWaves wavefronts covers kProjRows consecutive rows; each lane owns
+// kProjRpt rows (lane-interleaved, so every column read is one contiguous run per
+// wavefront).
+//   If r_upd > 0: v -= sum_{c<r_upd} X[c] dc[c] (written back), one sum per row.
+//   Then part[blk][c] = X[c]^T v over the block's rows for c < r_dot, 16 columns at a
+//   time: each lane sums its rows, the 64 x 16 lane partials of a wavefront are
+//   transposed through LDS and summed in a fixed order, then the wavefronts' sums are
+//   added in wavefront order.
+//   part[blk][r_dot] = v.v after the update, part[blk][r_dot + 1] = v.v before.
+constexpr int kProjRpt = 2;
+constexpr int kProjWaves = 4;
+constexpr int kProjRows = 64 * kProjRpt * kProjWaves;
+constexpr int kProjCols = 16;
+constexpr int kProjRed = 64 * (kProjCols + 1) + 4 * kProjCols;  // LDS doubles per wavefront
+
+// Column sums over the block: every lane contributes kProjCols values; lane c <
+// kProjCols of wavefront 0 returns the block sum of column c.  red: kProjWaves *
+// kProjRed + kProjWaves * kProjCols doubles of LDS.
+__device__ __forceinline__ double block_colsum(const double (&p)[kProjCols], double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int LD = kProjCols + 1;
+  double* rw = red + wave * kProjRed;
+#pragma unroll
+  for (int j = 0; j < kProjCols; ++j) rw[lane * LD + j] = p[j];
   __syncthreads();
-  constexpr int R = 8;  // rows per thread at most (chunk <= 8 * kTB)
-  double vv[R];
+  const int col = lane % kProjCols, seg = lane / kProjCols;  // 4 segments of 16 lanes
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) s += rw[(seg * 16 + u) * LD + col];
+  double* r2 = rw + 64 * LD;
+  r2[seg * kProjCols + col] = s;
+  __syncthreads();
+  double* wsum = red + kProjWaves * kProjRed;
+  if (lane < kProjCols) {
+    double t = 0.0;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) t += r2[g * kProjCols + lane];
+    wsum[wave * kProjCols + lane] = t;
+  }
+  __syncthreads();
+  double t = 0.0;
+  if (wave == 0 && lane < kProjCols)
+#pragma unroll
+    for (int w = 0; w < kProjWaves; ++w) t += wsum[w * kProjCols + lane];
+  __syncthreads();
+  return t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(64 * kProjWaves) void proj_kernel(
+    const T* __restrict__ X, long nd, int r_upd, int r_dot, T* __restrict__ v,
+    const double* __restrict__ dc, double* __restrict__ part) {
+  extern __shared__ double sm[];
+  double* sdc = sm;            // [r_upd]
+  double* red = sm + r_upd;    // reduction buffers
+  const int tid = threadIdx.x;
+  const long i0 = (long)blockIdx.x * kProjRows + (tid >> 6) * (64 * kProjRpt) + (tid & 63);
+  for (int c = tid; c < r_upd; c += 64 * kProjWaves) sdc[c] = dc[c];
+  __syncthreads();
+  double x[kProjRpt];
+  bool ok[kProjRpt];
   double before = 0.0, after = 0.0;
 #pragma unroll
-  for (int t = 0; t < R; ++t) {
-    const long i = i0 + threadIdx.x + (long)t * kTB;
-    double x = 0.0;
-    if (i < i1) {
-      x = (double)v[i];
-      before += x * x;
-      if (r_upd > 0) {
-        double s = 0.0;
-        for (int c = 0; c < r_upd; ++c) s += (double)X[(long)c * nd + i] * sdc[c];
-        x -= s;
-        v[i] = (T)x;
-        x = (double)v[i];
-      }
-      after += x * x;
-    }
-    vv[t] = x;
+  for (int t = 0; t < kProjRpt; ++t) {
+    const long i = i0 + 64 * t;
+    ok[t] = i < nd;
+    x[t] = ok[t] ? (double)v[i] : 0.0;
+    before += x[t] * x[t];
   }
+  if (r_upd > 0) {
+    double s[kProjRpt];
+#pragma unroll
+    for (int t = 0; t < kProjRpt; ++t) s[t] = 0.0;
+    // 8 columns per round: all loads of a round are issued before its sums
+    int c = 0;
+    for (; c + 8 <= r_upd; c += 8) {
+      double xv[8][kProjRpt];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int t = 0; t < kProjRpt; ++t)
+          xv[u][t] = ok[t] ? (double)X[(long)(c + u) * nd + i0 + 64 * t] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double d = sdc[c + u];
+#pragma unroll
+        for (int t = 0; t < kProjRpt; ++t) s[t] += xv[u][t] * d;
+      }
+    }
+    for (; c < r_upd; ++c) {
+      const double d = sdc[c];
+#pragma unroll
+      for (int t = 0; t < kProjRpt; ++t)
+        if (ok[t]) s[t] += (double)X[(long)c * nd + i0 + 64 * t] * d;
+    }
+#pragma unroll
+    for (int t = 0; t < kProjRpt; ++t)
+      if (ok[t]) {
+        v[i0 + 64 * t] = (T)(x[t] - s[t]);
+        x[t] = (double)v[i0 + 64 * t];  // the stored (possibly rounded) value
+      }
+  }
+#pragma unroll
+  for (int t = 0; t < kProjRpt; ++t) after += x[t] * x[t];
   const int stride = r_dot + 2;
   double* out = part + (long)blockIdx.x * stride;
-  for (int c0 = 0; c0 < r_dot; c0 += 8) {
-    double acc[8];
+  for (int c0 = 0; c0 < r_dot; c0 += kProjCols) {
+    double p[kProjCols];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+    for (int j = 0; j < kProjCols; ++j) {
+      p[j] = 0.0;
+      if (c0 + j < r_dot) {
+        const T* xc = X + (long)(c0 + j) * nd;
 #pragma unroll
-    for (int t = 0; t < R; ++t) {
-      const long i = i0 + threadIdx.x + (long)t * kTB;
-      if (i < i1) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-          if (c0 + k < r_dot) acc[k] += (double)X[(long)(c0 + k) * nd + i] * vv[t];
+        for (int t = 0; t < kProjRpt; ++t)
+          if (ok[t]) p[j] += (double)xc[i0 + 64 * t] * x[t];
       }
     }
-    block_sum_vec<8>(acc, red);
-    if ((int)threadIdx.x < 8 && c0 + (int)threadIdx.x < r_dot)
-      out[c0 + threadIdx.x] = red[4 * 8 + threadIdx.x];
+    const double tot = block_colsum(p, red);
+    if (tid < kProjCols && c0 + tid < r_dot) out[c0 + tid] = tot;
+  }
+  double p[kProjCols];
+#pragma unroll
+  for (int j = 0; j < kProjCols; ++j) p[j] = j == 0 ? after : (j == 1 ? before : 0.0);
+  const double tot = block_colsum(p, red);
+  if (tid < 2) out[r_dot + tid] = tot;
+}
+
+// out[c] = sum_b part[b][c] for c < n (and acc_into[c] += out[c] for c < n_acc).  A block of
+// 256 threads handles 8 columns: 32 lanes per column take every 32nd partial (four
+// running sums, fixed assignment), then a fixed pairwise tree combines the lanes, so
+// the sum is the same on every run.
+__global__ __launch_bounds__(256) void reduce_cols_kernel(const double* __restrict__ part, int nblk,
+                                                          int stride, int n, double* __restrict__ out,
+                                                          double* __restrict__ acc_into, int n_acc) {
+  __shared__ double red[256];
+  const int c = blockIdx.x * 8 + (threadIdx.x >> 5);
+  const int l = threadIdx.x & 31;
+  double s4[4] = {0.0, 0.0, 0.0, 0.0};
+  if (c < n) {
+    int b = l;
+    for (; b + 96 < nblk; b += 128)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s4[u] += part[(long)(b + 32 * u) * stride + c];
+    if (b < nblk) s4[0] += part[(long)b * stride + c];
+    if (b + 32 < nblk) s4[1] += part[(long)(b + 32) * stride + c];
+    if (b + 64 < nblk) s4[2] += part[(long)(b + 64) * stride + c];
+  }
+  red[threadIdx.x] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+  __syncthreads();
+  for (int h = 16; h > 0; h >>= 1) {
+    if (l < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
-  double nn[2] = {after, before};
-  block_sum_vec<2>(nn, red);
-  if (threadIdx.x == 0) {
-    out[r_dot] = red[4 * 2 + 0];
-    out[r_dot + 1] = red[4 * 2 + 1];
+  if (l == 0 && c < n) {
+    const double v = red[threadIdx.x];
+    out[c] = v;
+    if (acc_into && c < n_acc) acc_into[c] += v;
   }
 }
 
-// out[c] (+)= sum_b part[b][c] for c < n, blocks in order.
-__global__ void reduce_cols_kernel(const double* __restrict__ part, int nblk, int stride, int n,
-                                   double* __restrict__ out, double* __restrict__ acc_into) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(long)b * stride + c];
-  out[c] = s;
-  if (acc_into) acc_into[c] += s;
+static void reduce_cols(const double* part, int nblk, int stride, int n, double* out,
+                        double* acc_into, hipStream_t st, int n_acc = 0) {
+  hipLaunchKernelGGL(reduce_cols_kernel, dim3((n + 7) / 8), dim3(256), 0, st, part, nblk, stride, n,
+                     out, acc_into, n_acc);
 }
 
 template <typename T>
@@ -319,29 +412,54 @@ __global__ void to_double_kernel(const T* __restrict__ a, double* __restrict__ b
 }
 
 // ------------------------------------------------------------------ tall-skinny A^T B
-// part[chunk][a][b] = sum over the chunk rows of A[a][.] B[b][.]  (a < na, b < nb <= 32)
+// part[chunk][a][b] = sum over the chunk rows of A[a][.] B[b][.]  (a < na, b < nb)
+// Block tile: 64 vectors of A (blockIdx.x) x 32 of B (blockIdx.z) over 32 rows at a
+// time, staged in LDS; the next 32 rows are fetched into registers while the current
+// ones are used.
 template <typename TA, typename TB>
 __global__ __launch_bounds__(256) void tsdot_kernel(const TA* __restrict__ A, int na,
                                                     const TB* __restrict__ B, int nb, long nd,
                                                     long kchunk, double* __restrict__ part) {
   __shared__ double As[32][65];
   __shared__ double Bs[32][33];
-  const int a0 = blockIdx.x * 64;
+  const int a0 = blockIdx.x * 64, b0 = blockIdx.z * 32;
   const long k0 = (long)blockIdx.y * kchunk, k1 = min(nd, k0 + kchunk);
   const int ta = threadIdx.x & 31, tb = threadIdx.x >> 5;  // tb in 0..7
+  // element e = threadIdx.x + 256 u of a tile: column e >> 5, row e & 31
+  double ra[8], rb[4];
+  auto fetch = [&](long kk) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = threadIdx.x + 256 * u, col = e >> 5;
+      const long k = kk + (e & 31);
+      ra[u] = (a0 + col < na && k < k1) ? (double)A[(long)(a0 + col) * nd + k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = threadIdx.x + 256 * u, col = e >> 5;
+      const long k = kk + (e & 31);
+      rb[u] = (b0 + col < nb && k < k1) ? (double)B[(long)(b0 + col) * nd + k] : 0.0;
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      As[e & 31][e >> 5] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      Bs[e & 31][e >> 5] = rb[u];
+    }
+  };
   double acc[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+  fetch(k0);
+  stash();
+  __syncthreads();
   for (long kk = k0; kk < k1; kk += 32) {
-    for (int e = threadIdx.x; e < 64 * 32; e += 256) {
-      const int col = e >> 5, row = e & 31;
-      const long k = kk + row;
-      As[row][col] = (a0 + col < na && k < k1) ? (double)A[(long)(a0 + col) * nd + k] : 0.0;
-    }
-    for (int e = threadIdx.x; e < 32 * 32; e += 256) {
-      const int col = e >> 5, row = e & 31;
-      const long k = kk + row;
-      Bs[row][col] = (col < nb && k < k1) ? (double)B[(long)col * nd + k] : 0.0;
-    }
-    __syncthreads();
+    const bool more = kk + 32 < k1;
+    if (more) fetch(kk + 32);
 #pragma unroll 8
     for (int k = 0; k < 32; ++k) {
       const double x0 = As[k][ta], x1 = As[k][ta + 32];
@@ -353,43 +471,57 @@ __global__ __launch_bounds__(256) void tsdot_kernel(const TA* __restrict__ A, in
       }
     }
     __syncthreads();
+    if (more) stash();
+    __syncthreads();
   }
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 4; ++j) {
-      const int a = a0 + ta + 32 * i, b = tb + 8 * j;
+      const int a = a0 + ta + 32 * i, b = b0 + tb + 8 * j;
       if (a < na && b < nb) part[((long)blockIdx.y * na + a) * nb + b] = acc[i][j];
     }
 }
 
 // ------------------------------------------------------------------ X C products
-// out[m][i] = sum_c X[c][i] C[c*ldc + m] for m < nm (<= 32), rows i; C staged in LDS.
-template <typename T, typename TO>
+// out[m][i] = sum_c X[c][i] C[c*ldc + m] for m < nm (<= NM), rows i; C staged in LDS.
+// Four columns of X are loaded per round before their products are summed.
+template <typename T, typename TO, int NM>
 __global__ __launch_bounds__(256) void xc_kernel(const T* __restrict__ X, int r, long nd,
                                                  const double* __restrict__ C, int ldc, int nm,
                                                  TO* __restrict__ out) {
-  __shared__ double Cs[64][32];
+  __shared__ double Cs[64][NM];
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  double acc[32];
+  const bool ok = i < nd;
+  double acc[NM];
 #pragma unroll
-  for (int m = 0; m < 32; ++m) acc[m] = 0.0;
+  for (int m = 0; m < NM; ++m) acc[m] = 0.0;
   for (int c0 = 0; c0 < r; c0 += 64) {
     const int cn = min(64, r - c0);
     __syncthreads();
-    for (int e = threadIdx.x; e < 64 * 32; e += 256) {
-      const int c = e >> 5, m = e & 31;
+    for (int e = threadIdx.x; e < 64 * NM; e += 256) {
+      const int c = e / NM, m = e % NM;
       Cs[c][m] = (c < cn && m < nm) ? C[(long)(c0 + c) * ldc + m] : 0.0;
     }
     __syncthreads();
-    if (i < nd) {
-      for (int c = 0; c < cn; ++c) {
-        const double x = (double)X[(long)(c0 + c) * nd + i];
+    int c = 0;
+    for (; c + 4 <= cn; c += 4) {
+      double x[4];
 #pragma unroll
-        for (int m = 0; m < 32; ++m) acc[m] += x * Cs[c][m];
-      }
+      for (int u = 0; u < 4; ++u) x[u] = ok ? (double)X[(long)(c0 + c + u) * nd + i] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int m = 0; m < NM; ++m) acc[m] += x[u] * Cs[c + u][m];
+    }
+    for (; c < cn; ++c) {
+      const double x = ok ? (double)X[(long)(c0 + c) * nd + i] : 0.0;
+#pragma unroll
+      for (int m = 0; m < NM; ++m) acc[m] += x * Cs[c][m];
     }
   }
-  if (i < nd)
-    for (int m = 0; m < nm; ++m) out[(long)m * nd + i] = (TO)acc[m];
+  if (ok)
+#pragma unroll
+    for (int m = 0; m < NM; ++m)
+      if (m < nm) out[(long)m * nd + i] = (TO)acc[m];
 }
 
 // Cm[i][m] = Cg[list[m]][i] for i < r, m < nm
@@ -449,7 +581,6 @@ __global__ __launch_bounds__(256) void residual_kernel(
 //   rowY [r0][2 pn]: X_old^T [(D_x^-)^T P, (D_y^-)^T P]
 //   ext  [5][pn]   : [s, g_L, g_R, g_B, g_T]^T P
 __global__ void scatter_border_kernel(int r0, int pn, int rcap, const double* __restrict__ colY,
-                                      const double* __restrict__ rowY,
                                       const double* __restrict__ ext, double* __restrict__ Tm,
                                       double* __restrict__ Dx, double* __restrict__ Dy,
                                       double* __restrict__ bsrc, double* __restrict__ bside) {
@@ -457,13 +588,13 @@ __global__ void scatter_border_kernel(int r0, int pn, int rcap, const double* __
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < r1 * pn) {
     const int i = t / pn, m = t % pn, j = r0 + m;
-    const double* row = colY + (long)i * 3 * pn;
+    const double* row = colY + (long)i * 5 * pn;
     Tm[(long)i * rcap + j] = row[m];
     Dx[(long)i * rcap + j] = row[pn + m];
     Dy[(long)i * rcap + j] = row[2 * pn + m];
     if (i < r0) {  // Sigma_t symmetric; D rows from the transposed products
       Tm[(long)j * rcap + i] = row[m];
-      const double* rw = rowY + (long)i * 2 * pn;
+      const double* rw = row + 3 * pn;
       Dx[(long)j * rcap + i] = rw[m];
       Dy[(long)j * rcap + i] = rw[pn + m];
     }
@@ -492,6 +623,8 @@ __device__ __forceinline__ double bvec(const double* bsrc, const double* bside, 
 //   Lt[rcap][rcap]: Lt[i][j] = L(j, i) (column i of the unit lower factor, j > i)
 //   U [rcap][rcap]: row-major upper factor;  y[rcap]: L^{-1} b.
 // Extends the factorisation of the leading r0 x r0 block by pn rows/columns.
+constexpr int kLuRows = 8;  // factor rows staged per round in lu_border_kernel
+
 __global__ __launch_bounds__(64) void lu_border_kernel(
     int r0, int pn, int rcap, const int* __restrict__ cls, const ClassDev* __restrict__ cd,
     const double* __restrict__ Tm, const double* __restrict__ Dx, const double* __restrict__ Dy,
@@ -514,27 +647,47 @@ __global__ __launch_bounds__(64) void lu_border_kernel(
       row[m * r0 + i] = amat(Tm, Dx, Dy, rcap, k, r0 + m, i);
     }
   __syncthreads();
+  // Rows of L^T and U are staged in LDS kLuRows at a time (columns from the block's
+  // first row on), so the sequential sweeps below wait for global memory once per
+  // kLuRows rows.
+  double* stg = sm + (size_t)2 * pn * r0;  // [kLuRows][r0]
   // U_12 = L_11^{-1} A_12 (unit lower, column sweeps)
-  for (int i = 0; i < r0; ++i) {
-    const double* li = Lt + (size_t)i * rcap;
-    for (int j = i + 1 + lane; j < r0; j += 64) {
-      const double l = li[j];
-      for (int m = 0; m < pn; ++m) col[m * r0 + j] -= l * col[m * r0 + i];
-    }
+  for (int i0 = 0; i0 < r0; i0 += kLuRows) {
+    const int nb = min(kLuRows, r0 - i0), w = r0 - i0;
     __syncthreads();
+    for (int ii = 0; ii < nb; ++ii)
+      for (int j = lane; j < w; j += 64) stg[ii * w + j] = Lt[(size_t)(i0 + ii) * rcap + i0 + j];
+    __syncthreads();
+    for (int ii = 0; ii < nb; ++ii) {
+      const int i = i0 + ii;
+      const int lb = ii * w - i0;  // stg[lb + j] = L^T(i, j)
+      for (int j = i + 1 + lane; j < r0; j += 64) {
+        const double l = stg[lb + j];
+        for (int m = 0; m < pn; ++m) col[m * r0 + j] -= l * col[m * r0 + i];
+      }
+      __syncthreads();
+    }
   }
   // L_21 = A_21 U_11^{-1}: x U = a, row sweeps of U
-  for (int i = 0; i < r0; ++i) {
-    const double* ui = U + (size_t)i * rcap;
-    const double piv = ui[i];
-    for (int m = 0; m < pn; ++m) {
-      // every lane reads the current a_i before lane 0 rescales it
-      const double xi = row[m * r0 + i] / piv;
-      for (int j = i + 1 + lane; j < r0; j += 64) row[m * r0 + j] -= xi * ui[j];
-      __syncthreads();
-      if (lane == 0) row[m * r0 + i] = xi;
-    }
+  for (int i0 = 0; i0 < r0; i0 += kLuRows) {
+    const int nb = min(kLuRows, r0 - i0), w = r0 - i0;
     __syncthreads();
+    for (int ii = 0; ii < nb; ++ii)
+      for (int j = lane; j < w; j += 64) stg[ii * w + j] = U[(size_t)(i0 + ii) * rcap + i0 + j];
+    __syncthreads();
+    for (int ii = 0; ii < nb; ++ii) {
+      const int i = i0 + ii;
+      const int ub = ii * w - i0;  // stg[ub + j] = U(i, j)
+      const double piv = stg[ub + i];
+      for (int m = 0; m < pn; ++m) {
+        // every lane reads the current a_i before lane 0 rescales it
+        const double xi = row[m * r0 + i] / piv;
+        for (int j = i + 1 + lane; j < r0; j += 64) row[m * r0 + j] -= xi * stg[ub + j];
+        __syncthreads();
+        if (lane == 0) row[m * r0 + i] = xi;
+      }
+      __syncthreads();
+    }
   }
   // S = A_22 - L_21 U_12 and the new entries of y
   for (int m = 0; m < pn; ++m)
@@ -853,7 +1006,7 @@ struct LowRank {
     const bool mixed = sizeof(T) == sizeof(float);
     eps_mgs = mixed ? std::max(prm->eps_mgs, 1e-6) : prm->eps_mgs;
     tol_break = mixed ? 1e-6 : 1e-12;
-    chunk = 4 * kTB;
+    chunk = kProjRows;
     nblk = (int)((nd + chunk - 1) / chunk);
     // device buffers
     d_cd.alloc(K);
@@ -893,8 +1046,8 @@ struct LowRank {
     Cm.alloc((size_t)rcap * 32);
     rpart.alloc((size_t)rblk * 32);
     rsums.alloc(32);
-    tsd.alloc((size_t)65536 * 3 * kMaxP);
-    tsd2.alloc((size_t)rcap * 3 * kMaxP);
+    tsd.alloc((size_t)65536 * 5 * kMaxP);  // nch * na <= 65536 (see tsdot), nb <= 5 kMaxP
+    tsd2.alloc((size_t)rcap * 5 * kMaxP);
     tsd3.alloc((size_t)rcap * 2 * kMaxP + 5 * kMaxP);
     RTE_CHECK_HIP(hipEventCreate(&e0));
     RTE_CHECK_HIP(hipEventCreate(&e1));
@@ -948,15 +1101,12 @@ struct LowRank {
   // ------------------------------------------------------------ projections
   // part <- proj_kernel(...); then dvec[0..r_dot+2) = column sums; if acc, cvec += dots
   void proj(T* v, int r_upd, const double* dc, int r_dot, bool acc) {
-    const size_t sm = (size_t)(r_upd + 5 * 8) * sizeof(double);
-    hipLaunchKernelGGL((proj_kernel<T>), dim3(nblk), dim3(kTB), sm, st, X.get(), nd, r_upd, r_dot,
-                       v, dc, part.get(), chunk);
+    const size_t sm = (size_t)(r_upd + kProjWaves * (kProjRed + kProjCols)) * sizeof(double);
+    hipLaunchKernelGGL((proj_kernel<T>), dim3(nblk), dim3(64 * kProjWaves), sm, st, X.get(), nd,
+                       r_upd, r_dot, v, dc, part.get());
     const int n = r_dot + 2;
-    hipLaunchKernelGGL(reduce_cols_kernel, dim3((n + 127) / 128), dim3(128), 0, st, part.get(), nblk,
-                       n, n, dvec.get(), nullptr);
-    if (acc && r_dot > 0)
-      hipLaunchKernelGGL(reduce_cols_kernel, dim3((r_dot + 127) / 128), dim3(128), 0, st,
-                         part.get(), nblk, n, r_dot, dvec.get(), cvec.get());
+    // the column sums, and c += the dot products when accumulating
+    reduce_cols(part.get(), nblk, n, n, dvec.get(), acc ? cvec.get() : nullptr, st, acc ? r_dot : 0);
     RTE_CHECK_HIP(hipGetLastError());
   }
 
@@ -1036,7 +1186,7 @@ struct LowRank {
     nch = (nd + kchunk - 1) / kchunk;
     DevBuf<double>& buf = tsd;
     RTE_REQUIRE(buf.n >= (size_t)nch * na * nb, "internal: tsdot scratch too small");
-    dim3 grid(gx, (unsigned)nch);
+    dim3 grid(gx, (unsigned)nch, (unsigned)((nb + 31) / 32));
     if (a_double && b_double)
       hipLaunchKernelGGL((tsdot_kernel<double, double>), grid, dim3(256), 0, st, (const double*)A, na,
                          (const double*)B, nb, nd, kchunk, buf.get());
@@ -1050,8 +1200,7 @@ struct LowRank {
       hipLaunchKernelGGL((tsdot_kernel<T, double>), grid, dim3(256), 0, st, (const T*)A, na,
                          (const double*)B, nb, nd, kchunk, buf.get());
     const int n = na * nb;
-    hipLaunchKernelGGL(reduce_cols_kernel, dim3((n + 127) / 128), dim3(128), 0, st, buf.get(),
-                       (int)nch, n, n, out, nullptr);
+    reduce_cols(buf.get(), (int)nch, n, n, out, nullptr, st);
     RTE_CHECK_HIP(hipGetLastError());
   }
 
@@ -1061,15 +1210,14 @@ struct LowRank {
                        g.nx, g.ny, 1.0 / g.hx, 1.0 / g.hy, prob->sigma_t, P, pn, nd, Y.get());
     RTE_CHECK_HIP(hipGetLastError());
     const int r1 = r0 + pn;
-    tsdot(X.get(), sizeof(T) == 8, r1, Y.get(), sizeof(T) == 8, 3 * pn, tsd2.get());
-    if (r0 > 0)
-      tsdot(X.get(), sizeof(T) == 8, r0, Y.get() + (size_t)3 * pn * nd, sizeof(T) == 8, 2 * pn,
-            tsd3.get());
-    double* ext = tsd3.get() + (size_t)rcap * 2 * kMaxP;
+    // X^T [Sigma_t P, D_x^- P, D_y^- P, (D_x^-)^T P, (D_y^-)^T P] in one pass over X
+    // (the last two blocks are used for the old rows only)
+    tsdot(X.get(), sizeof(T) == 8, r1, Y.get(), sizeof(T) == 8, 5 * pn, tsd2.get());
+    double* ext = tsd3.get();
     tsdot(E.get(), true, 5, P, sizeof(T) == 8, pn, ext);
     const int nt = std::max(r1 * pn, 5);
     hipLaunchKernelGGL(scatter_border_kernel, dim3((nt + 127) / 128), dim3(128), 0, st, r0, pn,
-                       rcap, tsd2.get(), tsd3.get(), ext, Tm.get(), Dx.get(), Dy.get(), bsrc.get(),
+                       rcap, tsd2.get(), ext, Tm.get(), Dx.get(), Dy.get(), bsrc.get(),
                        bside.get());
     RTE_CHECK_HIP(hipGetLastError());
   }
@@ -1084,7 +1232,7 @@ struct LowRank {
   void lu_border(int r0, int pn, const std::vector<int>& classes) {
     if (classes.empty() || pn == 0) return;
     upload_list(classes);
-    const size_t sm = (size_t)2 * pn * r0 * sizeof(double);
+    const size_t sm = ((size_t)2 * pn * r0 + (size_t)kLuRows * r0) * sizeof(double);
     hipLaunchKernelGGL(lu_border_kernel, dim3((unsigned)classes.size()), dim3(64), sm, st, r0, pn,
                        rcap, d_list.get(), d_cd.get(), Tm.get(), Dx.get(), Dy.get(), bsrc.get(),
                        bside.get(), Lt.get(), U.get(), yv.get());
@@ -1110,7 +1258,7 @@ struct LowRank {
     if (r > 0) {
       hipLaunchKernelGGL(gather_cg_kernel, dim3((r * nm + 255) / 256), dim3(256), 0, st, Cg.get(),
                          rcap, d_list.get(), nm, r, Cm.get());
-      hipLaunchKernelGGL((xc_kernel<T, T>), dim3((nd + 255) / 256), dim3(256), 0, st, X.get(), r,
+      hipLaunchKernelGGL((xc_kernel<T, T, 32>), dim3((nd + 255) / 256), dim3(256), 0, st, X.get(), r,
                          nd, Cm.get(), nm, nm, V.get());
     } else {
       RTE_CHECK_HIP(hipMemsetAsync(V.get(), 0, (size_t)nm * nd * sizeof(T), st));
@@ -1118,8 +1266,7 @@ struct LowRank {
     hipLaunchKernelGGL((residual_kernel<T>), dim3(rblk, nm), dim3(256), 0, st, g.nx, g.ny,
                        1.0 / g.hx, 1.0 / g.hy, prob->sigma_t, src.get(), E.get(), nd, V.get(), nm,
                        d_list.get(), d_cd.get(), rpart.get());
-    hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(64), 0, st, rpart.get(), rblk, nm, nm,
-                       rsums.get(), nullptr);
+    reduce_cols(rpart.get(), rblk, nm, nm, rsums.get(), nullptr, st);
     RTE_CHECK_HIP(hipGetLastError());
     RTE_CHECK_HIP(hipMemcpyAsync(out.data(), rsums.get(), nm * sizeof(double), hipMemcpyDeviceToHost, st));
     sync();
@@ -1138,7 +1285,7 @@ struct LowRank {
     }
     hipLaunchKernelGGL(cw_kernel, dim3((r + 63) / 64), dim3(64), 0, st, r, rcap, K, d_sampled.get(),
                        Rst.get(), Cg.get(), d_wc.get(), d_mult.get(), cw.get(), Bsvd);
-    hipLaunchKernelGGL((xc_kernel<T, double>), dim3((nd + 255) / 256), dim3(256), 0, st, X.get(), r,
+    hipLaunchKernelGGL((xc_kernel<T, double, 1>), dim3((nd + 255) / 256), dim3(256), 0, st, X.get(), r,
                        nd, cw.get(), 1, 1, phi_k.get());
     RTE_CHECK_HIP(hipGetLastError());
   }
@@ -1147,7 +1294,7 @@ struct LowRank {
     const int nb = 1024;
     hipLaunchKernelGGL(diff2_kernel, dim3(nb), dim3(256), 0, st, a, b, nd, dpart.get());
     double* out = dpart.get() + 2048;
-    hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(64), 0, st, dpart.get(), nb, 1, 1, out, nullptr);
+    reduce_cols(dpart.get(), nb, 1, 1, out, nullptr, st);
     RTE_CHECK_HIP(hipGetLastError());
     double h = 0.0;
     RTE_CHECK_HIP(hipMemcpyAsync(&h, out, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1319,7 +1466,7 @@ struct LowRank {
         hipLaunchKernelGGL(gather_u_kernel, dim3((r * rp + 255) / 256), dim3(256), 0, st, Qt.get(), r,
                            dord.get(), rp, Csel.get());
         for (int m0 = 0; m0 < rp; m0 += 32)
-          hipLaunchKernelGGL((xc_kernel<T, double>), dim3((nd + 255) / 256), dim3(256), 0, st, X.get(),
+          hipLaunchKernelGGL((xc_kernel<T, double, 32>), dim3((nd + 255) / 256), dim3(256), 0, st, X.get(),
                              r, nd, Csel.get() + m0, rp, std::min(32, rp - m0), Xo + (size_t)m0 * nd);
         RTE_CHECK_HIP(hipGetLastError());
         sync();
