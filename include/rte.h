@@ -194,6 +194,18 @@ rte_status rte_exit_currents(const rte_problem* prob, const double* phi, double*
                              void* stream);
 
 /*
+ * Boundary-detector misfit of exit currents (project addition, the functional whose
+ * gradient rte_cross_section_gradient returns): L = 1/2 sum_e (J_e - J_obs,e)^2 over
+ * every boundary face, and the adjoint boundary data it induces, an isotropic inflow
+ * (J_e - J_obs,e) / |e| on face e, as face moments bc_adj[e] = ((J_e - J_obs,e) /
+ * sqrt|e|, 0).
+ *   J, J_obs DEV [4][max(nx,ny)] (tail entries ignored); bc_adj DEV [4][max(nx,ny)][2]
+ *   (written; tail entries 0); loss HOST (written).  Synchronous on `stream`.
+ */
+rte_status rte_detector_misfit(const rte_problem* prob, const double* J, const double* J_obs,
+                               double* bc_adj, double* loss, void* stream);
+
+/*
  * Cross-section gradients by the discrete adjoint.  With psi_j regenerated from
  * the forward flux phi and mu_j from the adjoint flux phi_adj (adjoint sweeps with
  * boundary data bc_adj), per cell c:

@@ -56,6 +56,35 @@ __global__ void exit_current_kernel(int nx, int ny, int mb, double hx, double hy
   J[f] = acc * scale;
 }
 
+// Detector misfit L = 1/2 sum_e (J_e - J_obs,e)^2 over the boundary faces and the
+// adjoint inflow it induces: on face e the isotropic inflow (J_e - J_obs,e)/|e|, whose
+// face moments are ((J_e - J_obs,e)/sqrt|e|, 0).  One block; part of L per thread
+// summed in a fixed order.
+__global__ __launch_bounds__(256) void misfit_kernel(int nx, int ny, int mb, double hx, double hy,
+                                                     const double* __restrict__ J,
+                                                     const double* __restrict__ J_obs,
+                                                     double* __restrict__ bc_adj,
+                                                     double* __restrict__ loss) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int f = threadIdx.x; f < 4 * mb; f += 256) {
+    const int side = f / mb, i = f % mb;
+    const bool valid = i < (side < 2 ? ny : nx);
+    const double len = side < 2 ? hy : hx;
+    const double d = valid ? J[f] - J_obs[f] : 0.0;
+    s += 0.5 * d * d;
+    bc_adj[2 * f] = valid ? d / sqrt(len) : 0.0;
+    bc_adj[2 * f + 1] = 0.0;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = red[0];
+}
+
 // grad_a[c] = -sum_j w_j <mu_j, psi_j>_c ; grad_s[c] = grad_a[c] + <phi_adj, phi>_c
 __global__ void gradient_kernel(long ncell, int n_dirs, const double* __restrict__ w,
                                 const double* __restrict__ psi, const double* __restrict__ mu,
@@ -257,6 +286,25 @@ rte_status rte_exit_currents(const rte_problem* prob, const double* phi, double*
                        g.mb, g.hx, g.hy, prob->n_dirs, dox.get(), doy.get(), dw.get(), psi.get(),
                        g.ndof, J);
     RTE_CHECK_HIP(hipGetLastError());
+    RTE_CHECK_HIP(hipStreamSynchronize(st));
+    return RTE_OK;
+  } catch (const Error& e) {
+    return e.code;
+  }
+}
+
+rte_status rte_detector_misfit(const rte_problem* prob, const double* J, const double* J_obs,
+                               double* bc_adj, double* loss, void* stream) {
+  try {
+    validate_problem(prob, true);
+    RTE_REQUIRE(J && J_obs && bc_adj && loss, "missing array");
+    hipStream_t st = (hipStream_t)stream;
+    const Geom g = make_geom(prob);
+    DevBuf<double> dl(1);
+    hipLaunchKernelGGL(misfit_kernel, dim3(1), dim3(256), 0, st, g.nx, g.ny, g.mb, g.hx, g.hy, J,
+                       J_obs, bc_adj, dl.get());
+    RTE_CHECK_HIP(hipGetLastError());
+    RTE_CHECK_HIP(hipMemcpyAsync(loss, dl.get(), sizeof(double), hipMemcpyDeviceToHost, st));
     RTE_CHECK_HIP(hipStreamSynchronize(st));
     return RTE_OK;
   } catch (const Error& e) {

@@ -68,6 +68,8 @@ SIGNATURES = {
     "rte_exit_currents": ([ctypes.POINTER(Problem_), _P, _P, _P], ctypes.c_int),
     "rte_cross_section_gradient": ([ctypes.POINTER(Problem_), _P, _P, _P, _P, _P, _P],
                                    ctypes.c_int),
+    "rte_detector_misfit": ([ctypes.POINTER(Problem_), _P, _P, _P, ctypes.POINTER(ctypes.c_double),
+                             _P], ctypes.c_int),
     "rte_cl_quadrature": ([ctypes.c_int32, ctypes.c_int32, _D, _D], ctypes.c_int),
     "rte_box_source_moments": ([ctypes.c_int32, ctypes.c_int32] + [ctypes.c_double] * 9 + [_D],
                                ctypes.c_int),
@@ -164,10 +166,14 @@ class Problem:
         self.wts = np.ascontiguousarray(wts, dtype=np.float64)
         dev = torch.device(device)
         f64 = dict(dtype=torch.float64, device=dev)
-        self.sigma_t = torch.as_tensor(np.asarray(sigma_t, dtype=np.float64).reshape(ny, nx), **f64).contiguous()
-        self.sigma_s = torch.as_tensor(np.asarray(sigma_s, dtype=np.float64).reshape(ny, nx), **f64).contiguous()
-        self.G = None if G is None else torch.as_tensor(np.asarray(G, dtype=np.float64).reshape(ny, nx, 4), **f64).contiguous()
-        self.bc = None if bc is None else torch.as_tensor(np.asarray(bc, dtype=np.float64).reshape(4, max(nx, ny), 2), **f64).contiguous()
+        def todev(a, shape):  # host arrays are copied; device tensors are used as they are
+            if isinstance(a, torch.Tensor):
+                return a.detach().to(**f64).reshape(shape).contiguous()
+            return torch.as_tensor(np.asarray(a, dtype=np.float64).reshape(shape), **f64).contiguous()
+        self.sigma_t = todev(sigma_t, (ny, nx))
+        self.sigma_s = todev(sigma_s, (ny, nx))
+        self.G = None if G is None else todev(G, (ny, nx, 4))
+        self.bc = None if bc is None else todev(bc, (4, max(nx, ny), 2))
         self.device = dev
 
     @property
@@ -314,6 +320,16 @@ def exit_currents(prob, phi):
     cp = prob.c()
     _check(lib().rte_exit_currents(ctypes.byref(cp), _dptr(phi.contiguous()), _dptr(J), _stream()))
     return J
+
+
+def detector_misfit(prob, J, J_obs):
+    """L = 1/2 sum (J - J_obs)^2 and the adjoint boundary data (rte_detector_misfit)."""
+    bc_adj = torch.zeros((4, max(prob.nx, prob.ny), 2), dtype=torch.float64, device=prob.device)
+    loss = ctypes.c_double(0.0)
+    J_obs = torch.as_tensor(J_obs, dtype=torch.float64, device=prob.device).contiguous()
+    _check(lib().rte_detector_misfit(ctypes.byref(prob.c()), _dptr(J.contiguous()), _dptr(J_obs),
+                                     _dptr(bc_adj), ctypes.byref(loss), _stream()))
+    return loss.value, bc_adj
 
 
 def cross_section_gradient(prob, phi, phi_adj, bc_adj):
