@@ -190,8 +190,8 @@ def main():
                                "8x8 diffusive/absorbing blocks, p=4 q=32, eps_si=1e-6",
                    "only": args.only},
         "sweep_kernel": {"updates_per_s": k1_updates / (k1_ms * 1e-3), "ms": k1_ms,
-                         "launch": "diag_layout_kernel, then sweep_kernel: 2 ordinates of one "
-                                   "quadrant per workgroup (256 workgroups), 256 compute threads "
+                         "launch": "diag_layout_kernel, then sweep_kernel: 1 ordinate per "
+                                   "workgroup (512 workgroups, 2 per CU), 256 compute threads "
                                    "(one per row) + 1 staging wavefront"},
         "roofline": {"kernel": "psi sweep (diag_layout_kernel + sweep_kernel), full angle set",
                      "bound": "hbm",

@@ -60,7 +60,7 @@ typedef struct {
   int32_t n_dirs;              /* number of ordinates N_Omega                         */
   const double* dirs;          /* HOST [n_dirs][3] unit vectors Omega_j               */
   const double* wts;           /* HOST [n_dirs] weights, sum within 1e-12 of 1        */
-  const double* sigma_t;       /* DEV [ny][nx] total cross section, > 0               */
+  const double* sigma_t;       /* DEV [ny][nx] total cross section, in [1e-30, 1e30]  */
   const double* sigma_s;       /* DEV [ny][nx] scattering, 0 <= sigma_s <= sigma_t    */
   const double* G;             /* DEV [ny][nx][4] moments int_cell G eta_k, or NULL   */
   const double* bc;            /* DEV [4][max(nx,ny)][2] inflow face moments, or NULL */

@@ -47,6 +47,22 @@ struct Cell {
   T vo[2];  // outflow trace on the downstream y face (index p)
 };
 
+// 1/x for a positive normal x: the hardware reciprocal refined by Newton steps
+// (r <- r + r (1 - x r)), two in FP64 and one in FP32, to working precision.
+template <typename T>
+__device__ __forceinline__ T recip(T x) {
+  if constexpr (sizeof(T) == 8) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+  } else {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void solve_cell(T sig, T a, T b, const T s[4], const T u[2],
                                            const T v[2], Cell<T>& out) {
@@ -66,7 +82,7 @@ __device__ __forceinline__ void solve_cell(T sig, T a, T b, const T s[4], const 
   const T d0 = sig * sig + T(4) * b * sig + T(6) * (b * b - a * a);
   const T d1 = T(2) * a * (sig + T(2) * (a + b));
   const T det = d0 * d0 + T(4) * d0 * d1 + T(6) * d1 * d1;
-  const T inv = T(1) / det;
+  const T inv = recip(det);  // det >= sigma^4 > 0 (sigma_t in [1e-30, 1e30])
   const T e0 = (d0 + T(4) * d1) * inv, e1 = -d1 * inv;
   const T m0 = y00 + r3 * y01, m1 = T(3) * y01 - r3 * y00;
   const T n0 = y10 + r3 * y11, n1 = T(3) * y11 - r3 * y10;
@@ -547,12 +563,12 @@ SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool
   const int nr = nc * rpt;
   const size_t lmax = max_lds_per_block();
   const size_t lcap = std::min(lmax, kLdsTwoPerCU);
-  // Directions per workgroup: enough workgroups to cover the chip first; then D > 1
-  // shares the staged inputs (and, for the scalar flux, the partial sums) among
-  // directions.  D is bounded by the register budget (FP64: 2, and 1 beyond 576
+  // Directions per workgroup (scalar flux only): enough workgroups to cover the chip
+  // first; then D > 1 shares the staged inputs and the partial sums among directions.  D is bounded by the register budget (FP64: 2, and 1 beyond 576
   // threads; FP32: 4) and by LDS.
   // (psi together with the scalar flux: one direction per workgroup)
-  const int dmax = want_psi && want_phi ? 1 : elem_bytes == 8 ? (pl.nt <= 576 && rpt == 1 ? 2 : 1) : 4;
+  // (psi: one direction per workgroup measured faster, two workgroups sharing a CU)
+  const int dmax = want_psi ? 1 : elem_bytes == 8 ? (pl.nt <= 576 && rpt == 1 ? 2 : 1) : 4;
   int D = 1;
   while (D < dmax && dirs.size() / (2 * D) >= 256 &&
          sweep_lds_bytes(nr, 2 * D, want_psi, true, elem_bytes) <= lmax)
