@@ -12,16 +12,41 @@
 // x-degrees p through a 2x2 matrix and leaves the y-degree q alone (and vice
 // versa), with traces l_p(+-1) = (1, +-sqrt3)/sqrt(h) and d/dx l_p = (0, 2 sqrt3/h^1.5).
 // The 4x4 blocks are built on the host in closed form; the SPD system is solved by
-// conjugate gradients with the inverse 4x4 diagonal blocks as preconditioner, all
-// scalars kept on the device and every reduction done in a fixed order.
+// conjugate gradients, all scalars kept on the device and every reduction done in a
+// fixed order.  Preconditioner (additive two-level, symmetric positive definite):
+//   M^{-1} r = B^{-1} r + P V P^T r,
+// B the 4x4 diagonal blocks, P the embedding of continuous bilinear functions (nodal
+// values at the cell corners) in the DG-Q1 space, V one V-cycle of geometric multigrid
+// on the Galerkin operator P^T A P (9-point stencils; bilinear interpolation, full
+// weighting, Galerkin coarse operators, l1-Jacobi smoothing, exact solve on the
+// coarsest grid).  The continuous coarse space carries the smooth error that block
+// Jacobi alone removes only in O(1/h) iterations.
 #include <cmath>
 #include <cstring>
+#include <memory>
+#include <vector>
 
 #include "common.h"
 
 namespace rte {
 
 static constexpr double kCip = 8.0;
+
+// one grid of the multigrid hierarchy on the continuous Q1 space (mx x my nodes)
+struct MgLevel {
+  int mx = 0, my = 0;
+  DevBuf<double> A9;    // [node][9] stencil, entry (dj + 1) 3 + (di + 1)
+  DevBuf<double> dinv;  // l1-Jacobi: 1 / (a_ii + sum_{j != i} |a_ij|)
+  DevBuf<double> x, b, t;
+};
+
+// device view of a level (for the single-workgroup V-cycle of the small grids)
+struct MgDev {
+  int mx, my;
+  const double* A9;
+  const double* dinv;
+  double *x, *b, *t;
+};
 
 struct DSA {
   Geom g;
@@ -30,6 +55,11 @@ struct DSA {
   DevBuf<double> part1, part2;                 // per-block partial sums
   DevBuf<double> scal;                         // device scalars (see Sc below)
   int nblk = 0;
+  std::vector<std::unique_ptr<MgLevel>> mg;    // mg[0]: the nodes of the DG mesh
+  DevBuf<double> cinv;                         // dense inverse on the coarsest grid
+  int ncoarse = 0;                             // its size (0: smoothing only)
+  int lsmall = 0;                              // first level of the one-workgroup V-cycle
+  DevBuf<MgDev> mgdev;                         // device views of every level
 };
 
 // layout of the device scalar block
@@ -159,41 +189,6 @@ __global__ void alpha_kernel(double* sc) {
   sc[S_ALPHA] = sc[S_RHO] / sc[S_PQ];
 }
 
-// x += alpha p, r -= alpha q, z = Minv r, part1 = r.z, part2 = r.r
-__global__ __launch_bounds__(256) void update_kernel(
-    long ncell, const double* __restrict__ minv, const double* __restrict__ p,
-    const double* __restrict__ q, double* __restrict__ x, double* __restrict__ r,
-    double* __restrict__ z, double* __restrict__ part1, double* __restrict__ part2,
-    const double* __restrict__ sc) {
-  __shared__ double red[256];
-  if (sc[S_DONE] != 0.0) return;
-  const double alpha = sc[S_ALPHA];
-  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  double rz = 0.0, rr = 0.0;
-  if (c < ncell) {
-    double rv[4], zv[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      x[4 * c + k] += alpha * p[4 * c + k];
-      rv[k] = r[4 * c + k] - alpha * q[4 * c + k];
-      r[4 * c + k] = rv[k];
-    }
-    mv4(minv + 16 * c, rv, zv);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      z[4 * c + k] = zv[k];
-      rz += rv[k] * zv[k];
-      rr += rv[k] * rv[k];
-    }
-  }
-  const double s1 = block_sum(rz, red);
-  const double s2 = block_sum(rr, red);
-  if (threadIdx.x == 0) {
-    part1[blockIdx.x] = s1;
-    part2[blockIdx.x] = s2;
-  }
-}
-
 // after reductions of r.z into sc[S_PQ] (reused as scratch) and r.r into sc[S_RR]
 __global__ void beta_kernel(double* sc, double rz_new_unused) {
   if (sc[S_DONE] != 0.0) return;
@@ -204,41 +199,6 @@ __global__ void beta_kernel(double* sc, double rz_new_unused) {
   }
   sc[S_BETA] = sc[S_PQ] / sc[S_RHO];
   sc[S_RHO] = sc[S_PQ];
-}
-
-// r = b = sigma_s (phi* - phi_prev); z = Minv r; x = 0; p_old = 0; part1 = r.z; part2 = r.r
-__global__ __launch_bounds__(256) void init_kernel(
-    long ncell, const double* __restrict__ sig_s, const double* __restrict__ phis,
-    const double* __restrict__ phip, const double* __restrict__ minv, double* __restrict__ x,
-    double* __restrict__ r, double* __restrict__ z, double* __restrict__ pold,
-    double* __restrict__ part1, double* __restrict__ part2) {
-  __shared__ double red[256];
-  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  double rz = 0.0, rr = 0.0;
-  if (c < ncell) {
-    double rv[4], zv[4] = {0, 0, 0, 0};
-    const double s = sig_s[c];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      rv[k] = s * (phis[4 * c + k] - phip[4 * c + k]);
-      r[4 * c + k] = rv[k];
-      x[4 * c + k] = 0.0;
-      pold[4 * c + k] = 0.0;
-    }
-    mv4(minv + 16 * c, rv, zv);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      z[4 * c + k] = zv[k];
-      rz += rv[k] * zv[k];
-      rr += rv[k] * rv[k];
-    }
-  }
-  const double s1 = block_sum(rz, red);
-  const double s2 = block_sum(rr, red);
-  if (threadIdx.x == 0) {
-    part1[blockIdx.x] = s1;
-    part2[blockIdx.x] = s2;
-  }
 }
 
 // rho = r.z, rr = r.r, tol2 = tol^2 * rr, beta = 0
@@ -253,6 +213,543 @@ __global__ void axpy_out_kernel(long n, const double* __restrict__ a, const doub
                                 double* __restrict__ out) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = a[i] + x[i];
+}
+
+// ------------------------------------------------------------ two-level preconditioner
+// Bilinear nodal function -> DG-Q1 coefficients on a cell: coefficient k = 2q + p of the
+// nodal basis function of corner (i, j) is ap(p, i) aq(q, j) with
+//   ap(0, i) = sqrt(hx)/2,  ap(1, i) = (2i - 1) sqrt(hx) / (2 sqrt3)   (same in y).
+struct Emb {
+  double x0, x1, y0, y1;  // ap(0,.), |ap(1,.)|, aq(0,.), |aq(1,.)|
+  __host__ __device__ double w(int k, int i, int j) const {
+    const int p = k & 1, q = k >> 1;
+    const double wx = p ? (i ? x1 : -x1) : x0;
+    const double wy = q ? (j ? y1 : -y1) : y0;
+    return wx * wy;
+  }
+};
+
+__device__ __forceinline__ double stencil9(const double* __restrict__ A9,
+                                           const double* __restrict__ x, int mx, int my, int i,
+                                           int j) {
+  const double* a = A9 + 9L * ((long)j * mx + i);
+  double s = 0.0;
+#pragma unroll
+  for (int dj = -1; dj <= 1; ++dj) {
+    const int jj = j + dj;
+    if (jj < 0 || jj >= my) continue;
+#pragma unroll
+    for (int di = -1; di <= 1; ++di) {
+      const int ii = i + di;
+      if (ii < 0 || ii >= mx) continue;
+      s += a[(dj + 1) * 3 + di + 1] * x[(long)jj * mx + ii];
+    }
+  }
+  return s;
+}
+
+// xout = x + dinv (b - A x)   (x == nullptr: x = 0)
+__global__ __launch_bounds__(256) void mg_jacobi_kernel(int mx, int my,
+                                                       const double* __restrict__ A9,
+                                                       const double* __restrict__ dinv,
+                                                       const double* __restrict__ b,
+                                                       const double* __restrict__ x,
+                                                       double* __restrict__ xout,
+                                                       const double* __restrict__ sc) {
+  if (sc[S_DONE] != 0.0) return;
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= (long)mx * my) return;
+  const int i = (int)(n % mx), j = (int)(n / mx);
+  if (x) xout[n] = x[n] + dinv[n] * (b[n] - stencil9(A9, x, mx, my, i, j));
+  else xout[n] = dinv[n] * b[n];
+}
+
+// the first two sweeps from x = 0: x = y + dinv (b - A y) with y = dinv b
+__global__ __launch_bounds__(256) void mg_pre_kernel(int mx, int my, const double* __restrict__ A9,
+                                                    const double* __restrict__ dinv,
+                                                    const double* __restrict__ b,
+                                                    double* __restrict__ x,
+                                                    const double* __restrict__ sc) {
+  if (sc[S_DONE] != 0.0) return;
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= (long)mx * my) return;
+  const int i = (int)(n % mx), j = (int)(n / mx);
+  const double* a = A9 + 9 * n;
+  double s = 0.0;
+#pragma unroll
+  for (int dj = -1; dj <= 1; ++dj) {
+    const int jj = j + dj;
+    if (jj < 0 || jj >= my) continue;
+#pragma unroll
+    for (int di = -1; di <= 1; ++di) {
+      const int ii = i + di;
+      if (ii < 0 || ii >= mx) continue;
+      const long m = (long)jj * mx + ii;
+      s += a[(dj + 1) * 3 + di + 1] * (dinv[m] * b[m]);
+    }
+  }
+  x[n] = dinv[n] * b[n] + dinv[n] * (b[n] - s);
+}
+
+// prolongation and the first post-smoothing sweep: t = y + dinv (b - A y), y = x + P xc
+__global__ __launch_bounds__(256) void mg_post_kernel(int mx, int my, const double* __restrict__ A9,
+                                                     const double* __restrict__ dinv,
+                                                     const double* __restrict__ b,
+                                                     const double* __restrict__ x, int mxc,
+                                                     const double* __restrict__ xc,
+                                                     double* __restrict__ t,
+                                                     const double* __restrict__ sc) {
+  if (sc[S_DONE] != 0.0) return;
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= (long)mx * my) return;
+  const int i = (int)(n % mx), j = (int)(n / mx);
+  auto y = [&](int ii, int jj) {
+    const int i0 = ii >> 1, i1 = (ii + 1) >> 1, j0 = jj >> 1, j1 = (jj + 1) >> 1;
+    return x[(long)jj * mx + ii] + 0.25 * (xc[(long)j0 * mxc + i0] + xc[(long)j0 * mxc + i1] +
+                                           xc[(long)j1 * mxc + i0] + xc[(long)j1 * mxc + i1]);
+  };
+  const double* a = A9 + 9 * n;
+  double s = 0.0;
+#pragma unroll
+  for (int dj = -1; dj <= 1; ++dj) {
+    const int jj = j + dj;
+    if (jj < 0 || jj >= my) continue;
+#pragma unroll
+    for (int di = -1; di <= 1; ++di) {
+      const int ii = i + di;
+      if (ii < 0 || ii >= mx) continue;
+      s += a[(dj + 1) * 3 + di + 1] * y(ii, jj);
+    }
+  }
+  t[n] = y(i, j) + dinv[n] * (b[n] - s);
+}
+
+// r = b - A x
+__global__ __launch_bounds__(256) void mg_residual_kernel(int mx, int my,
+                                                         const double* __restrict__ A9,
+                                                         const double* __restrict__ b,
+                                                         const double* __restrict__ x,
+                                                         double* __restrict__ r,
+                                                         const double* __restrict__ sc) {
+  if (sc[S_DONE] != 0.0) return;
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= (long)mx * my) return;
+  const int i = (int)(n % mx), j = (int)(n / mx);
+  r[n] = b[n] - stencil9(A9, x, mx, my, i, j);
+}
+
+// full weighting (transpose of bilinear interpolation): fine node (2I + di, 2J + dj) has
+// weight (1 - |di|/2)(1 - |dj|/2) in coarse node (I, J)
+__global__ __launch_bounds__(256) void mg_restrict_kernel(int mxf, int myf,
+                                                         const double* __restrict__ rf, int mxc,
+                                                         int myc, double* __restrict__ bc,
+                                                         const double* __restrict__ sc) {
+  if (sc[S_DONE] != 0.0) return;
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= (long)mxc * myc) return;
+  const int I = (int)(n % mxc), J = (int)(n / mxc);
+  double s = 0.0;
+#pragma unroll
+  for (int dj = -1; dj <= 1; ++dj) {
+    const int j = 2 * J + dj;
+    if (j < 0 || j >= myf) continue;
+#pragma unroll
+    for (int di = -1; di <= 1; ++di) {
+      const int i = 2 * I + di;
+      if (i < 0 || i >= mxf) continue;
+      s += (di ? 0.5 : 1.0) * (dj ? 0.5 : 1.0) * rf[(long)j * mxf + i];
+    }
+  }
+  bc[n] = s;
+}
+
+// V-cycle of the levels l0 .. nlev-1 by one workgroup (the small grids, whose data stay
+// in L2): the same steps as the multi-kernel cycle, separated by workgroup barriers.
+constexpr int kSmallThreads = 1024;
+constexpr long kSmallNodes = 1100;  // grids this small run inside the one workgroup
+
+__device__ void sm_jacobi(const MgDev& L, const double* x, double* out) {
+  const long n = (long)L.mx * L.my;
+  for (long k = threadIdx.x; k < n; k += blockDim.x) {
+    const int i = (int)(k % L.mx), j = (int)(k / L.mx);
+    out[k] = x ? x[k] + L.dinv[k] * (L.b[k] - stencil9(L.A9, x, L.mx, L.my, i, j))
+               : L.dinv[k] * L.b[k];
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kSmallThreads) void mg_small_kernel(const MgDev* __restrict__ lv,
+                                                                 int l0, int nlev,
+                                                                 const double* __restrict__ cinv,
+                                                                 int nc, int coarse_sweeps,
+                                                                 const double* __restrict__ sc) {
+  if (sc[S_DONE] != 0.0) return;
+  // down: pre-smoothing, residual, restriction
+  for (int l = l0; l + 1 < nlev; ++l) {
+    const MgDev L = lv[l], C = lv[l + 1];
+    sm_jacobi(L, nullptr, L.t);
+    sm_jacobi(L, L.t, L.x);
+    const long n = (long)L.mx * L.my;
+    for (long k = threadIdx.x; k < n; k += blockDim.x) {
+      const int i = (int)(k % L.mx), j = (int)(k / L.mx);
+      L.t[k] = L.b[k] - stencil9(L.A9, L.x, L.mx, L.my, i, j);
+    }
+    __syncthreads();
+    const long nc2 = (long)C.mx * C.my;
+    for (long k = threadIdx.x; k < nc2; k += blockDim.x) {
+      const int I = (int)(k % C.mx), J = (int)(k / C.mx);
+      double s = 0.0;
+      for (int dj = -1; dj <= 1; ++dj) {
+        const int j = 2 * J + dj;
+        if (j < 0 || j >= L.my) continue;
+        for (int di = -1; di <= 1; ++di) {
+          const int i = 2 * I + di;
+          if (i < 0 || i >= L.mx) continue;
+          s += (di ? 0.5 : 1.0) * (dj ? 0.5 : 1.0) * L.t[(long)j * L.mx + i];
+        }
+      }
+      C.b[k] = s;
+    }
+    __syncthreads();
+  }
+  // coarsest grid
+  {
+    const MgDev C = lv[nlev - 1];
+    if (nc > 0) {
+      for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+        double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int j = 0;
+        for (; j + 8 <= nc; j += 8)
+#pragma unroll
+          for (int u = 0; u < 8; ++u) s[u] += cinv[(long)(j + u) * nc + i] * C.b[j + u];
+        for (; j < nc; ++j) s[0] += cinv[(long)j * nc + i] * C.b[j];
+        C.x[i] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+      }
+      __syncthreads();
+    } else {
+      sm_jacobi(C, nullptr, C.t);
+      for (int s = 1; s < coarse_sweeps; s += 2) {
+        sm_jacobi(C, C.t, C.x);
+        if (s + 1 < coarse_sweeps) sm_jacobi(C, C.x, C.t);
+      }
+    }
+  }
+  // up: prolongation, post-smoothing
+  for (int l = nlev - 2; l >= l0; --l) {
+    const MgDev L = lv[l], C = lv[l + 1];
+    const long n = (long)L.mx * L.my;
+    for (long k = threadIdx.x; k < n; k += blockDim.x) {
+      const int i = (int)(k % L.mx), j = (int)(k / L.mx);
+      const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1;
+      L.x[k] += 0.25 * (C.x[(long)j0 * C.mx + i0] + C.x[(long)j0 * C.mx + i1] +
+                        C.x[(long)j1 * C.mx + i0] + C.x[(long)j1 * C.mx + i1]);
+    }
+    __syncthreads();
+    sm_jacobi(L, L.x, L.t);
+    sm_jacobi(L, L.t, L.x);
+  }
+}
+
+// b0 = P^T r: node (i, j) collects corner (i - a, j - b) of each adjacent cell (a, b)
+__global__ __launch_bounds__(256) void dg_restrict_kernel(int nx, int ny, Emb em,
+                                                         const double* __restrict__ r,
+                                                         double* __restrict__ b0,
+                                                         const double* __restrict__ sc) {
+  if (sc[S_DONE] != 0.0) return;
+  const int mx = nx + 1, my = ny + 1;
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= (long)mx * my) return;
+  const int i = (int)(n % mx), j = (int)(n / mx);
+  double s = 0.0;
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb) {
+    const int b = j - 1 + cb;
+    if (b < 0 || b >= ny) continue;
+#pragma unroll
+    for (int ca = 0; ca < 2; ++ca) {
+      const int a = i - 1 + ca;
+      if (a < 0 || a >= nx) continue;
+      const double* rc = r + 4 * ((long)b * nx + a);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s += em.w(k, i - a, j - b) * rc[k];
+    }
+  }
+  b0[n] = s;
+}
+
+// z = B^{-1} r + P x0 on every cell; part1 = r.z per block
+__global__ __launch_bounds__(256) void dg_precond_kernel(int nx, int ny, Emb em,
+                                                        const double* __restrict__ minv,
+                                                        const double* __restrict__ r,
+                                                        const double* __restrict__ x0,
+                                                        double* __restrict__ z,
+                                                        double* __restrict__ part1,
+                                                        const double* __restrict__ sc) {
+  __shared__ double red[256];
+  if (sc[S_DONE] != 0.0) return;
+  const long ncell = (long)nx * ny;
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double rz = 0.0;
+  if (c < ncell) {
+    const int a = (int)(c % nx), b = (int)(c / nx), mx = nx + 1;
+    double rv[4], zv[4] = {0, 0, 0, 0}, u[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) rv[k] = r[4 * c + k];
+    mv4(minv + 16 * c, rv, zv);
+#pragma unroll
+    for (int cj = 0; cj < 2; ++cj)
+#pragma unroll
+      for (int ci = 0; ci < 2; ++ci) u[2 * cj + ci] = x0[(long)(b + cj) * mx + a + ci];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) zv[k] += em.w(k, m & 1, m >> 1) * u[m];
+      z[4 * c + k] = zv[k];
+      rz += rv[k] * zv[k];
+    }
+  }
+  const double s = block_sum(rz, red);
+  if (threadIdx.x == 0) part1[blockIdx.x] = s;
+}
+
+// x += alpha p, r -= alpha q, part2 = r.r
+__global__ __launch_bounds__(256) void update_r_kernel(long ncell, const double* __restrict__ p,
+                                                      const double* __restrict__ q,
+                                                      double* __restrict__ x,
+                                                      double* __restrict__ r,
+                                                      double* __restrict__ part2,
+                                                      const double* __restrict__ sc) {
+  __shared__ double red[256];
+  if (sc[S_DONE] != 0.0) return;
+  const double alpha = sc[S_ALPHA];
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double rr = 0.0;
+  if (c < ncell) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      x[4 * c + k] += alpha * p[4 * c + k];
+      const double rv = r[4 * c + k] - alpha * q[4 * c + k];
+      r[4 * c + k] = rv;
+      rr += rv * rv;
+    }
+  }
+  const double s = block_sum(rr, red);
+  if (threadIdx.x == 0) part2[blockIdx.x] = s;
+}
+
+// r = b = sigma_s (phi* - phi_prev); x = 0; p_old = 0; part2 = r.r
+__global__ __launch_bounds__(256) void init_r_kernel(
+    long ncell, const double* __restrict__ sig_s, const double* __restrict__ phis,
+    const double* __restrict__ phip, double* __restrict__ x, double* __restrict__ r,
+    double* __restrict__ pold, double* __restrict__ part2) {
+  __shared__ double red[256];
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double rr = 0.0;
+  if (c < ncell) {
+    const double s = sig_s[c];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double rv = s * (phis[4 * c + k] - phip[4 * c + k]);
+      r[4 * c + k] = rv;
+      x[4 * c + k] = 0.0;
+      pold[4 * c + k] = 0.0;
+      rr += rv * rv;
+    }
+  }
+  const double s = block_sum(rr, red);
+  if (threadIdx.x == 0) part2[blockIdx.x] = s;
+}
+
+// clears the done flag before the first application of the preconditioner
+__global__ void clear_done_kernel(double* sc) { sc[S_DONE] = 0.0; }
+
+// ------------------------------------------------------------ multigrid setup (host)
+constexpr int kCoarseDense = 100;  // largest grid solved by its dense inverse
+constexpr int kCoarseSweeps = 20;  // l1-Jacobi sweeps on a coarsest grid that is larger
+
+Emb embedding(const Geom& g) {
+  const double r3 = std::sqrt(3.0);
+  return Emb{std::sqrt(g.hx) / 2, std::sqrt(g.hx) / (2 * r3), std::sqrt(g.hy) / 2,
+             std::sqrt(g.hy) / (2 * r3)};
+}
+
+// Galerkin coarse operator R A P for bilinear P (vertex-centred, fine node 2I <-> coarse I)
+std::vector<double> galerkin_coarse(const std::vector<double>& A, int mx, int my, int mxc, int myc) {
+  std::vector<double> Ac((size_t)9 * mxc * myc, 0.0);
+  auto parents = [](int i, int* I, double* w) {
+    if ((i & 1) == 0) {
+      I[0] = i / 2;
+      w[0] = 1.0;
+      return 1;
+    }
+    I[0] = (i - 1) / 2;
+    I[1] = (i + 1) / 2;
+    w[0] = w[1] = 0.5;
+    return 2;
+  };
+  for (int j = 0; j < my; ++j)
+    for (int i = 0; i < mx; ++i) {
+      int Ia[2], Ja[2];
+      double wIa[2], wJa[2];
+      const int nI = parents(i, Ia, wIa), nJ = parents(j, Ja, wJa);
+      const double* a = &A[9 * ((size_t)j * mx + i)];
+      for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di) {
+          const double v = a[(dj + 1) * 3 + di + 1];
+          const int i2 = i + di, j2 = j + dj;
+          if (v == 0.0 || i2 < 0 || i2 >= mx || j2 < 0 || j2 >= my) continue;
+          int Ib[2], Jb[2];
+          double wIb[2], wJb[2];
+          const int nI2 = parents(i2, Ib, wIb), nJ2 = parents(j2, Jb, wJb);
+          for (int u = 0; u < nJ; ++u)
+            for (int t = 0; t < nI; ++t)
+              for (int u2 = 0; u2 < nJ2; ++u2)
+                for (int t2 = 0; t2 < nI2; ++t2) {
+                  const int oi = Ib[t2] - Ia[t], oj = Jb[u2] - Ja[u];
+                  Ac[9 * ((size_t)Ja[u] * mxc + Ia[t]) + (oj + 1) * 3 + oi + 1] +=
+                      wJa[u] * wIa[t] * v * wJb[u2] * wIb[t2];
+                }
+        }
+    }
+  return Ac;
+}
+
+void upload(DevBuf<double>& b, const std::vector<double>& h) {
+  b.alloc(h.size());
+  RTE_CHECK_HIP(hipMemcpy(b.get(), h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+}
+
+void build_multigrid(DSA* d, const std::vector<double>& diag, const std::vector<double>& ax,
+                     const std::vector<double>& ay) {
+  const Geom& g = d->g;
+  const Emb em = embedding(g);
+  const int nx = g.nx, ny = g.ny, mx0 = nx + 1, my0 = ny + 1;
+  // P^T A P on the nodes: per block (test cell c1, trial cell c2) the 4 x 4 corner matrix
+  // P^T B P; couplings of corners two nodes apart vanish for continuous functions and
+  // are dropped.
+  std::vector<double> A0((size_t)9 * mx0 * my0, 0.0);
+  auto add = [&](int a1, int b1, int a2, int b2, const double* B, bool tr) {
+    for (int m = 0; m < 4; ++m)
+      for (int mm = 0; mm < 4; ++mm) {
+        const int i1 = a1 + (m & 1), j1 = b1 + (m >> 1), i2 = a2 + (mm & 1), j2 = b2 + (mm >> 1);
+        const int di = i2 - i1, dj = j2 - j1;
+        if (di < -1 || di > 1 || dj < -1 || dj > 1) continue;
+        double v = 0.0;
+        for (int k = 0; k < 4; ++k)
+          for (int kk = 0; kk < 4; ++kk)
+            v += em.w(k, m & 1, m >> 1) * (tr ? B[4 * kk + k] : B[4 * k + kk]) *
+                 em.w(kk, mm & 1, mm >> 1);
+        A0[9 * ((size_t)j1 * mx0 + i1) + (dj + 1) * 3 + di + 1] += v;
+      }
+  };
+  for (int b = 0; b < ny; ++b)
+    for (int a = 0; a < nx; ++a) {
+      const long c = (long)b * nx + a;
+      add(a, b, a, b, &diag[16 * c], false);
+      if (a + 1 < nx) {
+        add(a, b, a + 1, b, &ax[16 * c], false);
+        add(a + 1, b, a, b, &ax[16 * c], true);
+      }
+      if (b + 1 < ny) {
+        add(a, b, a, b + 1, &ay[16 * c], false);
+        add(a, b + 1, a, b, &ay[16 * c], true);
+      }
+    }
+  std::vector<std::vector<double>> As{std::move(A0)};
+  std::vector<std::pair<int, int>> dims{{mx0, my0}};
+  while (true) {
+    const int mx = dims.back().first, my = dims.back().second;
+    if ((long)mx * my <= kCoarseDense) break;
+    if ((mx - 1) % 2 || (my - 1) % 2 || mx < 5 || my < 5) break;
+    const int mxc = (mx + 1) / 2, myc = (my + 1) / 2;
+    As.push_back(galerkin_coarse(As.back(), mx, my, mxc, myc));
+    dims.push_back({mxc, myc});
+  }
+  for (size_t l = 0; l < As.size(); ++l) {
+    d->mg.push_back(std::make_unique<MgLevel>());
+    MgLevel& L = *d->mg[l];
+    L.mx = dims[l].first;
+    L.my = dims[l].second;
+    const size_t n = (size_t)L.mx * L.my;
+    std::vector<double> dinv(n);
+    for (size_t i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int k = 0; k < 9; ++k) s += k == 4 ? As[l][9 * i + k] : std::fabs(As[l][9 * i + k]);
+      RTE_REQUIRE(As[l][9 * i + 4] > 0.0 && s > 0.0, "DSA: non-positive coarse diagonal");
+      dinv[i] = 1.0 / s;
+    }
+    upload(L.A9, As[l]);
+    upload(L.dinv, dinv);
+    L.x.alloc(n);
+    L.b.alloc(n);
+    L.t.alloc(n);
+  }
+  // dense inverse on the coarsest grid (Cholesky, then the inverse column by column)
+  const MgLevel& Lc = *d->mg.back();
+  const int nc = Lc.mx * Lc.my;
+  d->ncoarse = 0;
+  if (nc <= kCoarseDense) {
+    const std::vector<double>& A = As.back();
+    std::vector<double> M((size_t)nc * nc, 0.0);
+    for (int j = 0; j < Lc.my; ++j)
+      for (int i = 0; i < Lc.mx; ++i)
+        for (int dj = -1; dj <= 1; ++dj)
+          for (int di = -1; di <= 1; ++di) {
+            const int i2 = i + di, j2 = j + dj;
+            if (i2 < 0 || i2 >= Lc.mx || j2 < 0 || j2 >= Lc.my) continue;
+            M[(size_t)(j * Lc.mx + i) * nc + j2 * Lc.mx + i2] =
+                A[9 * ((size_t)j * Lc.mx + i) + (dj + 1) * 3 + di + 1];
+          }
+    // symmetrise (the assembled entries agree to rounding)
+    for (int i = 0; i < nc; ++i)
+      for (int j = 0; j < i; ++j) {
+        const double v = 0.5 * (M[(size_t)i * nc + j] + M[(size_t)j * nc + i]);
+        M[(size_t)i * nc + j] = M[(size_t)j * nc + i] = v;
+      }
+    std::vector<double> L((size_t)nc * nc, 0.0);  // lower Cholesky factor
+    for (int j = 0; j < nc; ++j) {
+      double s = M[(size_t)j * nc + j];
+      for (int k = 0; k < j; ++k) s -= L[(size_t)j * nc + k] * L[(size_t)j * nc + k];
+      RTE_REQUIRE(s > 0.0, "DSA: coarse operator not positive definite");
+      const double ljj = std::sqrt(s);
+      L[(size_t)j * nc + j] = ljj;
+      for (int i = j + 1; i < nc; ++i) {
+        double t = M[(size_t)i * nc + j];
+        for (int k = 0; k < j; ++k) t -= L[(size_t)i * nc + k] * L[(size_t)j * nc + k];
+        L[(size_t)i * nc + j] = t / ljj;
+      }
+    }
+    std::vector<double> inv((size_t)nc * nc), y(nc);
+    for (int e = 0; e < nc; ++e) {
+      for (int i = 0; i < nc; ++i) {  // L y = e_e
+        double t = i == e ? 1.0 : 0.0;
+        for (int k = 0; k < i; ++k) t -= L[(size_t)i * nc + k] * y[k];
+        y[i] = t / L[(size_t)i * nc + i];
+      }
+      for (int i = nc - 1; i >= 0; --i) {  // L^T x = y
+        double t = y[i];
+        for (int k = i + 1; k < nc; ++k) t -= L[(size_t)k * nc + i] * inv[(size_t)k * nc + e];
+        inv[(size_t)i * nc + e] = t / L[(size_t)i * nc + i];
+      }
+    }
+    for (int i = 0; i < nc; ++i)  // exact symmetry for the column reads on the device
+      for (int j = 0; j < i; ++j) {
+        const double v = 0.5 * (inv[(size_t)i * nc + j] + inv[(size_t)j * nc + i]);
+        inv[(size_t)i * nc + j] = inv[(size_t)j * nc + i] = v;
+      }
+    upload(d->cinv, inv);
+    d->ncoarse = nc;
+  }
+  // the one-workgroup cycle takes over from the first level that is small enough
+  d->lsmall = (int)d->mg.size() - 1;
+  while (d->lsmall > 0 && (long)d->mg[d->lsmall - 1]->mx * d->mg[d->lsmall - 1]->my <= kSmallNodes)
+    --d->lsmall;
+  std::vector<MgDev> views;
+  for (auto& L : d->mg)
+    views.push_back(MgDev{L->mx, L->my, L->A9.get(), L->dinv.get(), L->x.get(), L->b.get(), L->t.get()});
+  d->mgdev.alloc(views.size());
+  RTE_CHECK_HIP(hipMemcpy(d->mgdev.get(), views.data(), views.size() * sizeof(MgDev),
+                          hipMemcpyHostToDevice));
 }
 
 }  // namespace
@@ -359,6 +856,7 @@ DSA* dsa_create(const Geom& g, const double* sigma_t_dev, const double* sigma_s_
         }
         RTE_REQUIRE(inv4(B, &minv[16 * c]), "DSA: singular diagonal block at cell %ld", c);
       }
+    build_multigrid(d, diag, ax, ay);
     d->diag.alloc(16 * n); d->ax.alloc(16 * n); d->ay.alloc(16 * n); d->minv.alloc(16 * n);
     RTE_CHECK_HIP(hipMemcpy(d->diag.get(), diag.data(), 16 * n * sizeof(double), hipMemcpyHostToDevice));
     RTE_CHECK_HIP(hipMemcpy(d->ax.get(), ax.data(), 16 * n * sizeof(double), hipMemcpyHostToDevice));
@@ -382,22 +880,70 @@ DSA* dsa_create(const Geom& g, const double* sigma_t_dev, const double* sigma_s_
 
 void dsa_destroy(DSA* d) { delete d; }
 
+namespace {
+
+unsigned nblocks(long n) { return (unsigned)((n + 255) / 256); }
+
+// one V-cycle on level l (x = V b), two l1-Jacobi sweeps before and after
+void vcycle(DSA* d, int l, hipStream_t st) {
+  MgLevel& L = *d->mg[l];
+  const double* sc = d->scal.get();
+  if (l == d->lsmall) {
+    hipLaunchKernelGGL(mg_small_kernel, dim3(1), dim3(kSmallThreads), 0, st, d->mgdev.get(), l,
+                       (int)d->mg.size(), d->cinv.get(), d->ncoarse, kCoarseSweeps, sc);
+    return;
+  }
+  const long n = (long)L.mx * L.my;
+  const unsigned nb = nblocks(n);
+  auto jac = [&](const double* x, double* out) {
+    hipLaunchKernelGGL(mg_jacobi_kernel, dim3(nb), dim3(256), 0, st, L.mx, L.my, L.A9.get(),
+                       L.dinv.get(), L.b.get(), x, out, sc);
+  };
+  MgLevel& C = *d->mg[l + 1];
+  hipLaunchKernelGGL(mg_pre_kernel, dim3(nb), dim3(256), 0, st, L.mx, L.my, L.A9.get(),
+                     L.dinv.get(), L.b.get(), L.x.get(), sc);
+  hipLaunchKernelGGL(mg_residual_kernel, dim3(nb), dim3(256), 0, st, L.mx, L.my, L.A9.get(),
+                     L.b.get(), L.x.get(), L.t.get(), sc);
+  hipLaunchKernelGGL(mg_restrict_kernel, dim3(nblocks((long)C.mx * C.my)), dim3(256), 0, st, L.mx,
+                     L.my, L.t.get(), C.mx, C.my, C.b.get(), sc);
+  vcycle(d, l + 1, st);
+  hipLaunchKernelGGL(mg_post_kernel, dim3(nb), dim3(256), 0, st, L.mx, L.my, L.A9.get(),
+                     L.dinv.get(), L.b.get(), L.x.get(), C.mx, C.x.get(), L.t.get(), sc);
+  jac(L.t.get(), L.x.get());
+}
+
+// z = M^{-1} r, part1 = r.z per block
+void precondition(DSA* d, const double* r, double* z, hipStream_t st) {
+  const Geom& g = d->g;
+  const Emb em = embedding(g);
+  const double* sc = d->scal.get();
+  MgLevel& L0 = *d->mg[0];
+  hipLaunchKernelGGL(dg_restrict_kernel, dim3(nblocks((long)L0.mx * L0.my)), dim3(256), 0, st, g.nx,
+                     g.ny, em, r, L0.b.get(), sc);
+  vcycle(d, 0, st);
+  hipLaunchKernelGGL(dg_precond_kernel, dim3(d->nblk), dim3(256), 0, st, g.nx, g.ny, em,
+                     d->minv.get(), r, L0.x.get(), z, d->part1.get(), sc);
+}
+
+}  // namespace
+
 int dsa_apply(DSA* d, const double* phi_star, const double* phi_prev, double* phi_next,
               double rel_tol, hipStream_t st) {
   const Geom& g = d->g;
   const long n = g.ncell;
   const int nb = d->nblk;
   double* sc = d->scal.get();
-  hipLaunchKernelGGL(init_kernel, dim3(nb), dim3(256), 0, st, n, d->sig_s.get(), phi_star,
-                     phi_prev, d->minv.get(), d->x.get(), d->r.get(), d->z.get(), d->p0.get(),
-                     d->part1.get(), d->part2.get());
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part1.get(), nb, sc + S_RHO);
+  hipLaunchKernelGGL(init_r_kernel, dim3(nb), dim3(256), 0, st, n, d->sig_s.get(), phi_star,
+                     phi_prev, d->x.get(), d->r.get(), d->p0.get(), d->part2.get());
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part2.get(), nb, sc + S_RR);
+  hipLaunchKernelGGL(clear_done_kernel, dim3(1), dim3(1), 0, st, sc);
+  precondition(d, d->r.get(), d->z.get(), st);
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part1.get(), nb, sc + S_RHO);
   hipLaunchKernelGGL(start_kernel, dim3(1), dim3(1), 0, st, sc, rel_tol);
   RTE_CHECK_HIP(hipGetLastError());
   double* pold = d->p0.get();
   double* pnew = d->p1.get();
-  const int chunk = 16, max_iter = 40000;
+  const int chunk = 4, max_iter = 40000;
   double hsc[S_N];
   int it = 0;
   for (; it < max_iter; it += chunk) {
@@ -407,11 +953,11 @@ int dsa_apply(DSA* d, const double* phi_star, const double* phi_prev, double* ph
                          d->part1.get(), sc);
       hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part1.get(), nb, sc + S_PQ);
       hipLaunchKernelGGL(alpha_kernel, dim3(1), dim3(1), 0, st, sc);
-      hipLaunchKernelGGL(update_kernel, dim3(nb), dim3(256), 0, st, n, d->minv.get(), pnew,
-                         d->q.get(), d->x.get(), d->r.get(), d->z.get(), d->part1.get(),
-                         d->part2.get(), sc);
-      hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part1.get(), nb, sc + S_PQ);
+      hipLaunchKernelGGL(update_r_kernel, dim3(nb), dim3(256), 0, st, n, pnew, d->q.get(),
+                         d->x.get(), d->r.get(), d->part2.get(), sc);
       hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part2.get(), nb, sc + S_RR);
+      precondition(d, d->r.get(), d->z.get(), st);
+      hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part1.get(), nb, sc + S_PQ);
       hipLaunchKernelGGL(beta_kernel, dim3(1), dim3(1), 0, st, sc, 0.0);
       std::swap(pold, pnew);
     }

@@ -68,134 +68,179 @@ __device__ __forceinline__ void block_sum_vec(const double* v, double* red) {
 }
 
 // ------------------------------------------------------------------ projections
-// A block of kProjWaves wavefronts covers kProjRows consecutive rows; each lane owns
-// kProjRpt rows (lane-interleaved, so every column read is one contiguous run per
-// wavefront).
-//   If r_upd > 0: v -= sum_{c<r_upd} X[c] dc[c] (written back), one sum per row.
-//   Then part[blk][c] = X[c]^T v over the block's rows for c < r_dot, 16 columns at a
-//   time: each lane sums its rows, the 64 x 16 lane partials of a wavefront are
-//   transposed through LDS and summed in a fixed order, then the wavefronts' sums are
-//   added in wavefront order.
-//   part[blk][r_dot] = v.v after the update, part[blk][r_dot + 1] = v.v before.
-constexpr int kProjRpt = 2;
-constexpr int kProjWaves = 4;
-constexpr int kProjRows = 64 * kProjRpt * kProjWaves;
-constexpr int kProjCols = 16;
-constexpr int kProjRed = 64 * (kProjCols + 1) + 4 * kProjCols;  // LDS doubles per wavefront
+// Batched projection of NV vectors W[l] (stride nd) against columns of the basis.  A
+// wavefront covers PjCfg<NV>::rows consecutive rows, rpt rows per lane, lane-interleaved
+// (every column read is one contiguous 512-byte run per wavefront); a block holds
+// kPjWaves wavefronts.
+//   If r_upd > 0: W[l] -= sum_{c < r_upd} Xu[c] C[c NV + l] (written back).
+//   Then, per wavefront wf: part[wf][c NV + l] = Xd[c]^T W[l] over its rows (c < r_dot),
+//   part[wf][r_dot NV + l] = W[l].W[l] after the update and part[wf][r_dot NV + NV + l]
+//   before it.
+// The lane sums are reduced over the wavefront 16 values at a time by a transpose
+// through the wavefront's own LDS rows and a fixed-order sum, so nothing but the C
+// staging waits on a block-wide barrier; the columns of the next round are fetched
+// before the current round is reduced.
+constexpr int kPjWaves = 4;
+constexpr int kPjVals = 16;          // values reduced per round
+constexpr int kPjLd = kPjVals + 1;   // LDS row stride (doubles) of the transpose
+constexpr int kPjRed = 64 * kPjLd;   // LDS doubles per wavefront
 
-// Column sums over the block: every lane contributes kProjCols values; lane c <
-// kProjCols of wavefront 0 returns the block sum of column c.  red: kProjWaves *
-// kProjRed + kProjWaves * kProjCols doubles of LDS.
-__device__ __forceinline__ double block_colsum(const double (&p)[kProjCols], double* red) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  constexpr int LD = kProjCols + 1;
-  double* rw = red + wave * kProjRed;
+template <int NV>
+struct PjCfg {
+  static constexpr int rpt = NV == 3 || NV == 4 ? 4 : 2;  // rows per lane (NV rpt <= 16)
+  static constexpr int rows = 64 * rpt;                   // rows per wavefront
+  static constexpr int g = kPjVals / NV < 8 ? kPjVals / NV : 8;  // dot columns per round
+  static constexpr int u = 16 / rpt;                      // update columns per round
+};
+
+__device__ __forceinline__ void lds_fence_wave() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
+}
+
+// Sum of 16 values over the 64 lanes of a wavefront; lane j < 16 returns the sum of value
+// j (fixed order: four 16-lane segments summed in lane order, then two xor shuffles).
+// rw: 64 * kPjLd doubles of LDS owned by this wavefront.
+__device__ __forceinline__ double wave_colsum16(const double (&p)[kPjVals], double* rw) {
+  const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int j = 0; j < kProjCols; ++j) rw[lane * LD + j] = p[j];
-  __syncthreads();
-  const int col = lane % kProjCols, seg = lane / kProjCols;  // 4 segments of 16 lanes
+  for (int j = 0; j < kPjVals; ++j) rw[lane * kPjLd + j] = p[j];
+  lds_fence_wave();
+  const int col = lane & 15, seg = lane >> 4;
   double s = 0.0;
 #pragma unroll
-  for (int u = 0; u < 16; ++u) s += rw[(seg * 16 + u) * LD + col];
-  double* r2 = rw + 64 * LD;
-  r2[seg * kProjCols + col] = s;
-  __syncthreads();
-  double* wsum = red + kProjWaves * kProjRed;
-  if (lane < kProjCols) {
-    double t = 0.0;
-#pragma unroll
-    for (int g = 0; g < 4; ++g) t += r2[g * kProjCols + lane];
-    wsum[wave * kProjCols + lane] = t;
-  }
-  __syncthreads();
-  double t = 0.0;
-  if (wave == 0 && lane < kProjCols)
-#pragma unroll
-    for (int w = 0; w < kProjWaves; ++w) t += wsum[w * kProjCols + lane];
-  __syncthreads();
-  return t;
+  for (int u = 0; u < 16; ++u) s += rw[(seg * 16 + u) * kPjLd + col];
+  lds_fence_wave();
+  s += __shfl_xor(s, 16, 64);
+  s += __shfl_xor(s, 32, 64);
+  return s;
 }
 
-template <typename T>
-__global__ __launch_bounds__(64 * kProjWaves) void proj_kernel(
-    const T* __restrict__ X, long nd, int r_upd, int r_dot, T* __restrict__ v,
-    const double* __restrict__ dc, double* __restrict__ part) {
+template <typename T, int NV>
+__global__ __launch_bounds__(64 * kPjWaves, 2) void bproj_kernel(
+    const T* __restrict__ Xu, int r_upd, const double* __restrict__ C, const T* __restrict__ Xd,
+    int r_dot, T* __restrict__ W, long nd, double* __restrict__ part) {
+  using Cfg = PjCfg<NV>;
+  constexpr int RPT = Cfg::rpt, G = Cfg::g, U = Cfg::u;
   extern __shared__ double sm[];
-  double* sdc = sm;            // [r_upd]
-  double* red = sm + r_upd;    // reduction buffers
-  const int tid = threadIdx.x;
-  const long i0 = (long)blockIdx.x * kProjRows + (tid >> 6) * (64 * kProjRpt) + (tid & 63);
-  for (int c = tid; c < r_upd; c += 64 * kProjWaves) sdc[c] = dc[c];
+  double* sC = sm;  // [r_upd NV]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* rw = sm + r_upd * NV + wave * kPjRed;
+  const long wf = (long)blockIdx.x * kPjWaves + wave;
+  const long i0 = wf * Cfg::rows + lane;
+  for (int c = threadIdx.x; c < r_upd * NV; c += 64 * kPjWaves) sC[c] = C[c];
   __syncthreads();
-  double x[kProjRpt];
-  bool ok[kProjRpt];
-  double before = 0.0, after = 0.0;
+  bool ok[RPT];
+  double w[NV][RPT], before[NV], after[NV];
 #pragma unroll
-  for (int t = 0; t < kProjRpt; ++t) {
-    const long i = i0 + 64 * t;
-    ok[t] = i < nd;
-    x[t] = ok[t] ? (double)v[i] : 0.0;
-    before += x[t] * x[t];
+  for (int t = 0; t < RPT; ++t) ok[t] = i0 + 64 * t < nd;
+#pragma unroll
+  for (int l = 0; l < NV; ++l) {
+    before[l] = 0.0;
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) {
+      w[l][t] = ok[t] ? (double)W[(long)l * nd + i0 + 64 * t] : 0.0;
+      before[l] += w[l][t] * w[l][t];
+    }
   }
   if (r_upd > 0) {
-    double s[kProjRpt];
+    double s[NV][RPT];
 #pragma unroll
-    for (int t = 0; t < kProjRpt; ++t) s[t] = 0.0;
-    // 8 columns per round: all loads of a round are issued before its sums
+    for (int l = 0; l < NV; ++l)
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) s[l][t] = 0.0;
+    // U columns per round: all loads of a round are issued before its products
     int c = 0;
-    for (; c + 8 <= r_upd; c += 8) {
-      double xv[8][kProjRpt];
+    for (; c + U <= r_upd; c += U) {
+      double xv[U][RPT];
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
+      for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int t = 0; t < kProjRpt; ++t)
-          xv[u][t] = ok[t] ? (double)X[(long)(c + u) * nd + i0 + 64 * t] : 0.0;
+        for (int t = 0; t < RPT; ++t)
+          xv[u][t] = ok[t] ? (double)Xu[(long)(c + u) * nd + i0 + 64 * t] : 0.0;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const double d = sdc[c + u];
+      for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int t = 0; t < kProjRpt; ++t) s[t] += xv[u][t] * d;
-      }
+        for (int l = 0; l < NV; ++l) {
+          const double d = sC[(c + u) * NV + l];
+#pragma unroll
+          for (int t = 0; t < RPT; ++t) s[l][t] += xv[u][t] * d;
+        }
     }
     for (; c < r_upd; ++c) {
-      const double d = sdc[c];
+      double xv[RPT];
 #pragma unroll
-      for (int t = 0; t < kProjRpt; ++t)
-        if (ok[t]) s[t] += (double)X[(long)c * nd + i0 + 64 * t] * d;
+      for (int t = 0; t < RPT; ++t) xv[t] = ok[t] ? (double)Xu[(long)c * nd + i0 + 64 * t] : 0.0;
+#pragma unroll
+      for (int l = 0; l < NV; ++l) {
+        const double d = sC[c * NV + l];
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) s[l][t] += xv[t] * d;
+      }
     }
 #pragma unroll
-    for (int t = 0; t < kProjRpt; ++t)
-      if (ok[t]) {
-        v[i0 + 64 * t] = (T)(x[t] - s[t]);
-        x[t] = (double)v[i0 + 64 * t];  // the stored (possibly rounded) value
+    for (int l = 0; l < NV; ++l)
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) {
+        const T nv = (T)(w[l][t] - s[l][t]);
+        w[l][t] = ok[t] ? (double)nv : 0.0;  // the stored (possibly rounded) value
+        if (ok[t]) W[(long)l * nd + i0 + 64 * t] = nv;
       }
   }
 #pragma unroll
-  for (int t = 0; t < kProjRpt; ++t) after += x[t] * x[t];
-  const int stride = r_dot + 2;
-  double* out = part + (long)blockIdx.x * stride;
-  for (int c0 = 0; c0 < r_dot; c0 += kProjCols) {
-    double p[kProjCols];
+  for (int l = 0; l < NV; ++l) {
+    after[l] = 0.0;
 #pragma unroll
-    for (int j = 0; j < kProjCols; ++j) {
-      p[j] = 0.0;
-      if (c0 + j < r_dot) {
-        const T* xc = X + (long)(c0 + j) * nd;
-#pragma unroll
-        for (int t = 0; t < kProjRpt; ++t)
-          if (ok[t]) p[j] += (double)xc[i0 + 64 * t] * x[t];
-      }
-    }
-    const double tot = block_colsum(p, red);
-    if (tid < kProjCols && c0 + tid < r_dot) out[c0 + tid] = tot;
+    for (int t = 0; t < RPT; ++t) after[l] += w[l][t] * w[l][t];
   }
-  double p[kProjCols];
+  const int stride = r_dot * NV + 2 * NV;
+  double* out = part + wf * stride;
+  if (r_dot > 0) {
+    double xc[G][RPT], xn[G][RPT];
+    auto fetch = [&](double (&x)[G][RPT], int c0) {
 #pragma unroll
-  for (int j = 0; j < kProjCols; ++j) p[j] = j == 0 ? after : (j == 1 ? before : 0.0);
-  const double tot = block_colsum(p, red);
-  if (tid < 2) out[r_dot + tid] = tot;
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int t = 0; t < RPT; ++t)
+          x[g][t] = (ok[t] && c0 + g < r_dot) ? (double)Xd[(long)(c0 + g) * nd + i0 + 64 * t] : 0.0;
+    };
+    fetch(xc, 0);
+    for (int c0 = 0; c0 < r_dot; c0 += G) {
+      if (c0 + G < r_dot) fetch(xn, c0 + G);
+      double p[kPjVals];
+#pragma unroll
+      for (int j = 0; j < kPjVals; ++j) p[j] = 0.0;
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int l = 0; l < NV; ++l)
+#pragma unroll
+          for (int t = 0; t < RPT; ++t) p[g * NV + l] += xc[g][t] * w[l][t];
+      const double tot = wave_colsum16(p, rw);
+      if (lane < G * NV && c0 + lane / NV < r_dot) out[c0 * NV + lane] = tot;
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) xc[g][t] = xn[g][t];
+    }
+  }
+  double p[kPjVals];
+#pragma unroll
+  for (int j = 0; j < kPjVals; ++j) p[j] = 0.0;
+#pragma unroll
+  for (int l = 0; l < NV; ++l) {
+    p[l] = after[l];
+    p[NV + l] = before[l];
+  }
+  const double tot = wave_colsum16(p, rw);
+  if (lane < 2 * NV) out[r_dot * NV + lane] = tot;
 }
 
+// cvec[i] = cb[i pn + l] for i < r0, 0 for r0 <= i < n
+__global__ void coef_col_kernel(const double* __restrict__ cb, int pn, int l, int r0,
+                                double* __restrict__ cvec, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) cvec[i] = i < r0 ? cb[(long)i * pn + l] : 0.0;
+}
 // out[c] = sum_b part[b][c] for c < n (and acc_into[c] += out[c] for c < n_acc).  A block of
 // 256 threads handles 8 columns: 32 lanes per column take every 32nd partial (four
 // running sums, fixed assignment), then a fixed pairwise tree combines the lanes, so
@@ -411,74 +456,129 @@ __global__ void to_double_kernel(const T* __restrict__ a, double* __restrict__ b
   if (i < n) b[i] = (double)a[i];
 }
 
-// ------------------------------------------------------------------ tall-skinny A^T B
-// part[chunk][a][b] = sum over the chunk rows of A[a][.] B[b][.]  (a < na, b < nb)
-// Block tile: 64 vectors of A (blockIdx.x) x 32 of B (blockIdx.z) over 32 rows at a
-// time, staged in LDS; the next 32 rows are fetched into registers while the current
-// ones are used.
-template <typename TA, typename TB>
-__global__ __launch_bounds__(256) void tsdot_kernel(const TA* __restrict__ A, int na,
-                                                    const TB* __restrict__ B, int nb, long nd,
-                                                    long kchunk, double* __restrict__ part) {
-  __shared__ double As[32][65];
-  __shared__ double Bs[32][33];
-  const int a0 = blockIdx.x * 64, b0 = blockIdx.z * 32;
-  const long k0 = (long)blockIdx.y * kchunk, k1 = min(nd, k0 + kchunk);
-  const int ta = threadIdx.x & 31, tb = threadIdx.x >> 5;  // tb in 0..7
-  // element e = threadIdx.x + 256 u of a tile: column e >> 5, row e & 31
-  double ra[8], rb[4];
-  auto fetch = [&](long kk) {
+// ------------------------------------------------------------------ E^T P
+// part[blk][e PN + m] = sum over the block's rows of E[e][k] P[m][k]  (e < 5, m < PN): the
+// projections of the source and boundary vectors on the new columns.  Threads stride
+// over the rows; one block reduction at the end.
+template <typename T, int PN>
+__global__ __launch_bounds__(256) void edot_kernel(const double* __restrict__ E,
+                                                  const T* __restrict__ P, long nd,
+                                                  double* __restrict__ part) {
+  constexpr int NV = 5 * PN;
+  __shared__ double red[(kTB / 64 + 1) * NV];
+  double acc[NV];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = threadIdx.x + 256 * u, col = e >> 5;
-      const long k = kk + (e & 31);
-      ra[u] = (a0 + col < na && k < k1) ? (double)A[(long)(a0 + col) * nd + k] : 0.0;
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < nd; k += (long)gridDim.x * blockDim.x) {
+    double pm[PN];
+#pragma unroll
+    for (int m = 0; m < PN; ++m) pm[m] = (double)P[(long)m * nd + k];
+#pragma unroll
+    for (int e = 0; e < 5; ++e) {
+      const double ev = E[(long)e * nd + k];
+#pragma unroll
+      for (int m = 0; m < PN; ++m) acc[e * PN + m] += ev * pm[m];
     }
+  }
+  block_sum_vec<NV>(acc, red);
+  if ((int)threadIdx.x < NV) part[(long)blockIdx.x * NV + threadIdx.x] = red[(kTB / 64) * NV + threadIdx.x];
+}
+
+// ------------------------------------------------------------------ X^T W, lanes over columns
+// part[blk][c NV + l] = sum over the block's rows k of X[c][k] W[l][k]  (c < r, l < NV).
+// Each lane owns one column of X and reads it in 16-byte runs (X is column-major), so the
+// sums need no cross-lane reduction.  The NV vectors of W are staged per kXwRows-row chunk
+// in LDS as [row][vector] (double-buffered: the next chunk is fetched into registers while
+// the current one is used) and read as broadcasts.  A block of 256 threads covers 256
+// columns (blockIdx.y selects the tile) and `nch` consecutive chunks.
+constexpr int kXwRows = 128;
+
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int n = 2;
+  __device__ static double at(const double2& v, int i) { return i == 0 ? v.x : v.y; }
+};
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int n = 4;
+  __device__ static double at(const float4& v, int i) {
+    return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+  }
+};
+
+template <typename T, int NV>
+__global__ __launch_bounds__(256) void xtw_kernel(const T* __restrict__ X, int r,
+                                                 const T* __restrict__ W, long nd, int nch,
+                                                 double* __restrict__ part) {
+  constexpr int NVP = (NV + 1) & ~1;                // even row stride: 16-byte pairs
+  constexpr int PT = (NV * kXwRows + 255) / 256;     // staged values per thread
+  constexpr int E = Vec16<T>::n;
+  using V = typename Vec16<T>::type;
+  __shared__ __align__(16) double Ws[2][kXwRows * NVP];
+  const int c = blockIdx.y * 256 + threadIdx.x;
+  const bool on = c < r;
+  const V* xc = reinterpret_cast<const V*>(X + (long)(on ? c : 0) * nd);
+  const long kb = (long)blockIdx.x * nch * kXwRows;
+  const int nq = (int)std::min<long>(nch, (nd - kb + kXwRows - 1) / kXwRows);
+  double wpf[PT];
+  auto wfetch = [&](long k0) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = threadIdx.x + 256 * u, col = e >> 5;
-      const long k = kk + (e & 31);
-      rb[u] = (b0 + col < nb && k < k1) ? (double)B[(long)(b0 + col) * nd + k] : 0.0;
+    for (int i = 0; i < PT; ++i) {
+      const int e = threadIdx.x + 256 * i, l = e / kXwRows, k = e % kXwRows;
+      wpf[i] = (e < NV * kXwRows && k0 + k < nd) ? (double)W[(long)l * nd + k0 + k] : 0.0;
     }
   };
-  auto stash = [&]() {
+  auto wstash = [&](double* ws) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      As[e & 31][e >> 5] = ra[u];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      Bs[e & 31][e >> 5] = rb[u];
+    for (int i = 0; i < PT; ++i) {
+      const int e = threadIdx.x + 256 * i, l = e / kXwRows, k = e % kXwRows;
+      if (e < NV * kXwRows) ws[k * NVP + l] = wpf[i];
     }
   };
-  double acc[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
-  fetch(k0);
-  stash();
+  double acc[NV];
+#pragma unroll
+  for (int l = 0; l < NV; ++l) acc[l] = 0.0;
+  wfetch(kb);
+  wstash(Ws[0]);
   __syncthreads();
-  for (long kk = k0; kk < k1; kk += 32) {
-    const bool more = kk + 32 < k1;
-    if (more) fetch(kk + 32);
-#pragma unroll 8
-    for (int k = 0; k < 32; ++k) {
-      const double x0 = As[k][ta], x1 = As[k][ta + 32];
+  for (int q = 0; q < nq; ++q) {
+    const long k0 = kb + (long)q * kXwRows;
+    if (q + 1 < nq) wfetch(k0 + kXwRows);
+    const double* ws = Ws[q & 1];
+    if (on) {
+      // rows past nd (last chunk only) read a clamped in-range address; their staged W is 0
+      auto xload = [&](V (&xv)[8], int kk) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const double y = Bs[k][tb + 8 * j];
-        acc[0][j] += x0 * y;
-        acc[1][j] += x1 * y;
+        for (int u = 0; u < 8; ++u) xv[u] = xc[std::min<long>(k0 + kk + u * E, nd - E) / E];
+      };
+      auto madd = [&](const V (&xv)[8], int kk) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const double x = Vec16<T>::at(xv[u], e);
+            const double* wr = ws + (kk + u * E + e) * NVP;
+#pragma unroll
+            for (int l = 0; l < NV; ++l) acc[l] += x * wr[l];
+          }
+      };
+#pragma unroll 1
+      for (int kk = 0; kk < kXwRows; kk += 8 * E) {
+        V xv[8];
+        xload(xv, kk);
+        madd(xv, kk);
       }
     }
-    __syncthreads();
-    if (more) stash();
+    if (q + 1 < nq) wstash(Ws[(q + 1) & 1]);
     __syncthreads();
   }
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 4; ++j) {
-      const int a = a0 + ta + 32 * i, b = b0 + tb + 8 * j;
-      if (a < na && b < nb) part[((long)blockIdx.y * na + a) * nb + b] = acc[i][j];
-    }
+  if (on)
+#pragma unroll
+    for (int l = 0; l < NV; ++l) part[((long)blockIdx.x * r + c) * NV + l] = acc[l];
 }
 
 // ------------------------------------------------------------------ X C products
@@ -576,7 +676,7 @@ __global__ __launch_bounds__(256) void residual_kernel(
 }
 
 // ------------------------------------------------------------------ projected operators
-// Scatter the border blocks computed by tsdot into the projected matrices.
+// Scatter the border blocks into the projected matrices.
 //   colY [r1][3 pn]: X^T [Sigma_t P, D_x^- P, D_y^- P]
 //   rowY [r0][2 pn]: X_old^T [(D_x^-)^T P, (D_y^-)^T P]
 //   ext  [5][pn]   : [s, g_L, g_R, g_B, g_T]^T P
@@ -619,20 +719,102 @@ __device__ __forceinline__ double bvec(const double* bsrc, const double* bside, 
 }
 
 // ------------------------------------------------------------------ bordered LU
-// One 64-thread workgroup per class in cls[].  Factor storage per class:
+// One 256-thread workgroup per class in cls[].  Factor storage per class:
 //   Lt[rcap][rcap]: Lt[i][j] = L(j, i) (column i of the unit lower factor, j > i)
 //   U [rcap][rcap]: row-major upper factor;  y[rcap]: L^{-1} b.
 // Extends the factorisation of the leading r0 x r0 block by pn rows/columns.
-constexpr int kLuRows = 8;  // factor rows staged per round in lu_border_kernel
+// The triangular solves are blocked by 64 rows: the 64 x 64 diagonal block is staged
+// in LDS and solved by one wavefront with the unknowns in registers (one row per
+// lane, values broadcast with readlane); the rows below are then updated by the whole
+// workgroup, reading the factor columns with coalesced loads.
+constexpr int kLuThreads = 256;
+constexpr int kLuB = 64;           // block of the triangular solves
+constexpr int kLuLd = kLuB + 1;    // LDS row stride of a staged diagonal block
 
-__global__ __launch_bounds__(64) void lu_border_kernel(
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// X[m][0..n) <- T^{-1} X[m][0..n) for m < pn (X in LDS, row stride n), T lower
+// triangular with column i stored contiguously: T(j, i) = M[i rcap + j] for j >= i;
+// unit diagonal if `unit`, else T(i, i) = M[i rcap + i].  Dg: kLuB * kLuLd doubles of LDS.
+__device__ void lu_lower_solve(const double* __restrict__ M, int rcap, bool unit, int n, double* X,
+                               int pn, double* Dg) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int b0 = 0; b0 < n; b0 += kLuB) {
+    const int nb = min(kLuB, n - b0);
+    // Dg[i][j] = T(b0 + j, b0 + i)  (column i of the block); all loads issued first
+    {
+      constexpr int NE = kLuB * kLuB / kLuThreads;
+      double t[NE];
+#pragma unroll
+      for (int u = 0; u < NE; ++u) {
+        const int e = tid + kLuThreads * u, i = e / kLuB, j = e % kLuB;
+        t[u] = (i < nb && j < nb) ? M[(long)(b0 + i) * rcap + b0 + j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < NE; ++u) {
+        const int e = tid + kLuThreads * u;
+        Dg[(e / kLuB) * kLuLd + e % kLuB] = t[u];
+      }
+    }
+    __syncthreads();
+    if (wave == 0) {
+      double v[kMaxP];
+#pragma unroll
+      for (int m = 0; m < kMaxP; ++m) v[m] = (m < pn && lane < nb) ? X[m * n + b0 + lane] : 0.0;
+      const double rd = (!unit && lane < nb) ? 1.0 / Dg[lane * kLuLd + lane] : 1.0;
+      for (int i = 0; i < nb; ++i) {
+        const double t = lane > i ? Dg[i * kLuLd + lane] : 0.0;
+        const double ri = unit ? 1.0 : readlane_d(rd, i);
+#pragma unroll
+        for (int m = 0; m < kMaxP; ++m) {
+          if (m >= pn) break;
+          const double zi = readlane_d(v[m], i) * ri;
+          v[m] = lane == i ? zi : v[m] - t * zi;
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < kMaxP; ++m)
+        if (m < pn && lane < nb) X[m * n + b0 + lane] = v[m];
+    }
+    __syncthreads();
+    // rows below the block (16 factor entries in flight per thread)
+    for (int j = b0 + nb + tid; j < n; j += kLuThreads) {
+      double acc[kMaxP];
+#pragma unroll
+      for (int m = 0; m < kMaxP; ++m) acc[m] = 0.0;
+      for (int i0 = 0; i0 < nb; i0 += 16) {
+        double t[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          t[u] = i0 + u < nb ? M[(long)(b0 + i0 + u) * rcap + j] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+#pragma unroll
+          for (int m = 0; m < kMaxP; ++m)
+            if (m < pn && i0 + u < nb) acc[m] += t[u] * X[m * n + b0 + i0 + u];
+      }
+#pragma unroll
+      for (int m = 0; m < kMaxP; ++m)
+        if (m < pn) X[m * n + j] -= acc[m];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kLuThreads) void lu_border_kernel(
     int r0, int pn, int rcap, const int* __restrict__ cls, const ClassDev* __restrict__ cd,
     const double* __restrict__ Tm, const double* __restrict__ Dx, const double* __restrict__ Dy,
     const double* __restrict__ bsrc, const double* __restrict__ bside, double* __restrict__ Lt_all,
     double* __restrict__ U_all, double* __restrict__ y_all) {
   extern __shared__ double sm[];
   double* col = sm;                       // [pn][r0]: A_12 -> U_12
-  double* row = sm + (long)pn * r0;       // [pn][r0]: A_21 -> L_21
+  double* row = sm + (long)pn * r0;       // [pn][r0]: A_21 -> L_21^T
+  double* Dg = row + (long)pn * r0;       // [kLuB][kLuLd]
   __shared__ double S[kMaxP][kMaxP], yn[kMaxP];
   const int cl = cls[blockIdx.x];
   const ClassDev k = cd[cl];
@@ -640,71 +822,30 @@ __global__ __launch_bounds__(64) void lu_border_kernel(
   double* Lt = Lt_all + fsz * cl;
   double* U = U_all + fsz * cl;
   double* y = y_all + (size_t)rcap * cl;
-  const int lane = threadIdx.x;
-  for (int m = 0; m < pn; ++m)
-    for (int i = lane; i < r0; i += 64) {
-      col[m * r0 + i] = amat(Tm, Dx, Dy, rcap, k, i, r0 + m);
-      row[m * r0 + i] = amat(Tm, Dx, Dy, rcap, k, r0 + m, i);
-    }
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < pn * r0; e += kLuThreads) {
+    const int m = e / r0, i = e % r0;
+    col[e] = amat(Tm, Dx, Dy, rcap, k, i, r0 + m);
+    row[e] = amat(Tm, Dx, Dy, rcap, k, r0 + m, i);
+  }
   __syncthreads();
-  // Rows of L^T and U are staged in LDS kLuRows at a time (columns from the block's
-  // first row on), so the sequential sweeps below wait for global memory once per
-  // kLuRows rows.
-  double* stg = sm + (size_t)2 * pn * r0;  // [kLuRows][r0]
-  // U_12 = L_11^{-1} A_12 (unit lower, column sweeps)
-  for (int i0 = 0; i0 < r0; i0 += kLuRows) {
-    const int nb = min(kLuRows, r0 - i0), w = r0 - i0;
-    __syncthreads();
-    for (int ii = 0; ii < nb; ++ii)
-      for (int j = lane; j < w; j += 64) stg[ii * w + j] = Lt[(size_t)(i0 + ii) * rcap + i0 + j];
-    __syncthreads();
-    for (int ii = 0; ii < nb; ++ii) {
-      const int i = i0 + ii;
-      const int lb = ii * w - i0;  // stg[lb + j] = L^T(i, j)
-      for (int j = i + 1 + lane; j < r0; j += 64) {
-        const double l = stg[lb + j];
-        for (int m = 0; m < pn; ++m) col[m * r0 + j] -= l * col[m * r0 + i];
-      }
-      __syncthreads();
-    }
-  }
-  // L_21 = A_21 U_11^{-1}: x U = a, row sweeps of U
-  for (int i0 = 0; i0 < r0; i0 += kLuRows) {
-    const int nb = min(kLuRows, r0 - i0), w = r0 - i0;
-    __syncthreads();
-    for (int ii = 0; ii < nb; ++ii)
-      for (int j = lane; j < w; j += 64) stg[ii * w + j] = U[(size_t)(i0 + ii) * rcap + i0 + j];
-    __syncthreads();
-    for (int ii = 0; ii < nb; ++ii) {
-      const int i = i0 + ii;
-      const int ub = ii * w - i0;  // stg[ub + j] = U(i, j)
-      const double piv = stg[ub + i];
-      for (int m = 0; m < pn; ++m) {
-        // every lane reads the current a_i before lane 0 rescales it
-        const double xi = row[m * r0 + i] / piv;
-        for (int j = i + 1 + lane; j < r0; j += 64) row[m * r0 + j] -= xi * stg[ub + j];
-        __syncthreads();
-        if (lane == 0) row[m * r0 + i] = xi;
-      }
-      __syncthreads();
-    }
-  }
-  // S = A_22 - L_21 U_12 and the new entries of y
-  for (int m = 0; m < pn; ++m)
-    for (int mm = 0; mm < pn; ++mm) {
-      double s = 0.0;
-      for (int i = lane; i < r0; i += 64) s += row[m * r0 + i] * col[mm * r0 + i];
-      s = wave_sum(s);
-      if (lane == 0) S[m][mm] = amat(Tm, Dx, Dy, rcap, k, r0 + m, r0 + mm) - s;
-    }
-  for (int m = 0; m < pn; ++m) {
+  // U_12 = L_11^{-1} A_12;  L_21 = A_21 U_11^{-1}, i.e. U_11^T L_21^T = A_21^T
+  lu_lower_solve(Lt, rcap, true, r0, col, pn, Dg);
+  lu_lower_solve(U, rcap, false, r0, row, pn, Dg);
+  // S = A_22 - L_21 U_12 and the new entries of y (one wavefront per dot product)
+  for (int d = wave; d < pn * pn + pn; d += kLuThreads / 64) {
+    const bool isy = d >= pn * pn;
+    const int m = isy ? d - pn * pn : d / pn, mm = d % pn;
     double s = 0.0;
-    for (int i = lane; i < r0; i += 64) s += row[m * r0 + i] * y[i];
+    for (int i = lane; i < r0; i += 64) s += row[m * r0 + i] * (isy ? y[i] : col[mm * r0 + i]);
     s = wave_sum(s);
-    if (lane == 0) yn[m] = bvec(bsrc, bside, rcap, k, r0 + m) - s;
+    if (lane == 0) {
+      if (isy) yn[m] = bvec(bsrc, bside, rcap, k, r0 + m) - s;
+      else S[m][mm] = amat(Tm, Dx, Dy, rcap, k, r0 + m, r0 + mm) - s;
+    }
   }
   __syncthreads();
-  if (lane == 0) {
+  if (tid == 0) {
     // LU of S without pivoting (in place), then finish y
     for (int c = 0; c < pn; ++c)
       for (int i = c + 1; i < pn; ++i) {
@@ -724,33 +865,78 @@ __global__ __launch_bounds__(64) void lu_border_kernel(
         else Lt[(size_t)(r0 + mm) * rcap + r0 + m] = S[m][mm];
       }
   }
-  for (int m = 0; m < pn; ++m)
-    for (int i = lane; i < r0; i += 64) {
-      U[(size_t)i * rcap + r0 + m] = col[m * r0 + i];
-      Lt[(size_t)i * rcap + r0 + m] = row[m * r0 + i];
-    }
+  for (int e = tid; e < pn * r0; e += kLuThreads) {
+    const int m = e / r0, i = e % r0;
+    U[(size_t)i * rcap + r0 + m] = col[e];
+    Lt[(size_t)i * rcap + r0 + m] = row[e];
+  }
 }
 
-// c = U^{-1} y for each class in cls[] (row-oriented back substitution) -> Cg[cl][.]
-__global__ __launch_bounds__(64) void backsub_kernel(int r, int rcap, const int* __restrict__ cls,
-                                                     const double* __restrict__ U_all,
-                                                     const double* __restrict__ y_all,
-                                                     double* __restrict__ Cg) {
-  extern __shared__ double x[];
+// c = U^{-1} y for each class in cls[] -> Cg[cl][.], blocked by 64 rows from the bottom:
+// the contributions of the solved rows (one wavefront per row dot product), then the
+// diagonal block by one wavefront with the unknowns in registers.
+__global__ __launch_bounds__(kLuThreads) void backsub_kernel(int r, int rcap,
+                                                             const int* __restrict__ cls,
+                                                             const double* __restrict__ U_all,
+                                                             const double* __restrict__ y_all,
+                                                             double* __restrict__ Cg) {
+  extern __shared__ double sm[];
+  double* x = sm;            // [r]
+  double* Dg = sm + r;       // [kLuB][kLuLd]: Dg[k][i] = U(b0 + k, b0 + i)
   const int cl = cls[blockIdx.x];
   const double* U = U_all + (size_t)rcap * rcap * cl;
   const double* y = y_all + (size_t)rcap * cl;
-  const int lane = threadIdx.x;
-  for (int i = r - 1; i >= 0; --i) {
-    const double* ui = U + (size_t)i * rcap;
-    double s = 0.0;
-    for (int j = i + 1 + lane; j < r; j += 64) s += ui[j] * x[j];
-    s = wave_sum(s);
-    if (lane == 0) x[i] = (y[i] - s) / ui[i];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < r; i += kLuThreads) x[i] = y[i];
+  const int nblk = (r + kLuB - 1) / kLuB;
+  for (int bb = nblk - 1; bb >= 0; --bb) {
+    const int b0 = bb * kLuB, nb = min(kLuB, r - b0), e0 = b0 + nb;
+    {
+      constexpr int NE = kLuB * kLuB / kLuThreads;
+      double t[NE];
+#pragma unroll
+      for (int u = 0; u < NE; ++u) {
+        const int e = tid + kLuThreads * u, kk = e / kLuB, i = e % kLuB;
+        t[u] = (kk < nb && i < nb) ? U[(long)(b0 + kk) * rcap + b0 + i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < NE; ++u) {
+        const int e = tid + kLuThreads * u;
+        Dg[(e / kLuB) * kLuLd + e % kLuB] = t[u];
+      }
+    }
+    // x[b0 + kk] -= U(b0 + kk, e0 ..) x[e0 ..]: each wavefront takes 4 rows at a time
+    for (int k0 = 4 * wave; k0 < nb; k0 += 4 * (kLuThreads / 64)) {
+      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int j = e0 + lane; j < r; j += 64) {
+        const double xj = x[j];
+        double u4[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) u4[q] = k0 + q < nb ? U[(long)(b0 + k0 + q) * rcap + j] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s4[q] += u4[q] * xj;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double sq = wave_sum(s4[q]);
+        if (lane == 0 && k0 + q < nb) x[b0 + k0 + q] -= sq;
+      }
+    }
+    __syncthreads();
+    if (wave == 0) {
+      double v = lane < nb ? x[b0 + lane] : 0.0;
+      const double rd = lane < nb ? 1.0 / Dg[lane * kLuLd + lane] : 1.0;
+      for (int i = nb - 1; i >= 0; --i) {
+        const double t = lane < i ? Dg[lane * kLuLd + i] : 0.0;
+        const double ci = readlane_d(v, i) * readlane_d(rd, i);
+        v = lane == i ? ci : v - t * ci;
+      }
+      if (lane < nb) x[b0 + lane] = v;
+    }
     __syncthreads();
   }
   double* out = Cg + (size_t)rcap * cl;
-  for (int i = lane; i < rcap; i += 64) out[i] = i < r ? x[i] : 0.0;
+  for (int i = tid; i < rcap; i += kLuThreads) out[i] = i < r ? x[i] : 0.0;
 }
 
 // cw[i] = sum_c wc[c] C(i, c), C(:, c) = R column if sampled else Galerkin; also
@@ -935,8 +1121,7 @@ struct LowRank {
   hipStream_t st;
   Geom g;
   long nd;
-  int K = 0, rcap = 0, nblk = 0;
-  long chunk = 0;
+  int K = 0, rcap = 0;
   double eps_mgs = 0.0, tol_break = 0.0;
   // classes
   std::vector<int> cls_of, reps;
@@ -947,9 +1132,9 @@ struct LowRank {
   DevBuf<double> d_wc, d_mult;
   // fields
   DevBuf<T> X, psi, srcT, Y, V, swork;
-  DevBuf<double> src, E, phi_k, phi_old, part, dvec, cvec, cw, dpart;
+  DevBuf<double> src, E, phi_k, phi_old, part, cvec, cw, dpart, cb, d1, d2, d3;
   // projected operators and factors
-  DevBuf<double> Tm, Dx, Dy, bsrc, bside, Lt, U, yv, Cg, Rst, tsd, tsd2, tsd3;
+  DevBuf<double> Tm, Dx, Dy, bsrc, bside, Lt, U, yv, Cg, Rst, tsd, tsd2, tsd3, xwp;
   DevBuf<SweepDir> d_dirs;
   DevBuf<double> Cm, rpart, rsums;
   SweepDir* h_dirs = nullptr;  // pinned staging
@@ -1006,8 +1191,6 @@ struct LowRank {
     const bool mixed = sizeof(T) == sizeof(float);
     eps_mgs = mixed ? std::max(prm->eps_mgs, 1e-6) : prm->eps_mgs;
     tol_break = mixed ? 1e-6 : 1e-12;
-    chunk = kProjRows;
-    nblk = (int)((nd + chunk - 1) / chunk);
     // device buffers
     d_cd.alloc(K);
     RTE_CHECK_HIP(hipMemcpy(d_cd.get(), cd.data(), K * sizeof(ClassDev), hipMemcpyHostToDevice));
@@ -1029,8 +1212,13 @@ struct LowRank {
     E.alloc((size_t)5 * nd);
     phi_k.alloc(nd);
     phi_old.alloc(nd);
-    part.alloc((size_t)nblk * (rcap + 2) + 64);
-    dvec.alloc(rcap + 2);
+    // projection partials: one row per wavefront (at least 128 rows each), rcap kMaxP dot
+    // products and 2 kMaxP norms per row
+    part.alloc((size_t)((nd + 127) / 128 + kPjWaves) * ((size_t)rcap * kMaxP + 2 * kMaxP));
+    cb.alloc((size_t)rcap * kMaxP);
+    d1.alloc((size_t)rcap * kMaxP + 2 * kMaxP);
+    d2.alloc((size_t)rcap * kMaxP + 2 * kMaxP);
+    d3.alloc((size_t)rcap * kMaxP + 2 * kMaxP);
     cvec.alloc(rcap + 2);
     cw.alloc(rcap);
     dpart.alloc(4096);
@@ -1046,8 +1234,13 @@ struct LowRank {
     Cm.alloc((size_t)rcap * 32);
     rpart.alloc((size_t)rblk * 32);
     rsums.alloc(32);
-    tsd.alloc((size_t)65536 * 5 * kMaxP);  // nch * na <= 65536 (see tsdot), nb <= 5 kMaxP
+    tsd.alloc((size_t)512 * 5 * kMaxP);
     tsd2.alloc((size_t)rcap * 5 * kMaxP);
+    {
+      const long nchunk = (nd + kXwRows - 1) / kXwRows;
+      const long nch = std::max<long>(1, nchunk / 512);
+      xwp.alloc((size_t)((nchunk + nch - 1) / nch) * rcap * 5 * kMaxP);
+    }
     tsd3.alloc((size_t)rcap * 2 * kMaxP + 5 * kMaxP);
     RTE_CHECK_HIP(hipEventCreate(&e0));
     RTE_CHECK_HIP(hipEventCreate(&e1));
@@ -1099,47 +1292,97 @@ struct LowRank {
   }
 
   // ------------------------------------------------------------ projections
-  // part <- proj_kernel(...); then dvec[0..r_dot+2) = column sums; if acc, cvec += dots
-  void proj(T* v, int r_upd, const double* dc, int r_dot, bool acc) {
-    const size_t sm = (size_t)(r_upd + kProjWaves * (kProjRed + kProjCols)) * sizeof(double);
-    hipLaunchKernelGGL((proj_kernel<T>), dim3(nblk), dim3(64 * kProjWaves), sm, st, X.get(), nd,
-                       r_upd, r_dot, v, dc, part.get());
-    const int n = r_dot + 2;
-    // the column sums, and c += the dot products when accumulating
-    reduce_cols(part.get(), nblk, n, n, dvec.get(), acc ? cvec.get() : nullptr, st, acc ? r_dot : 0);
+  template <int NV>
+  void bproj_n(T* W, const T* Xu, int r_upd, const double* C, const T* Xd, int r_dot,
+               double* out, double* acc_into) {
+    const long nwf = (nd + PjCfg<NV>::rows - 1) / PjCfg<NV>::rows;
+    const int nb = (int)((nwf + kPjWaves - 1) / kPjWaves);
+    const size_t sm = (size_t)(r_upd * NV + kPjWaves * kPjRed) * sizeof(double);
+    const int n = r_dot * NV + 2 * NV;
+    RTE_REQUIRE(part.n >= (size_t)nb * kPjWaves * n, "internal: projection scratch too small");
+    hipLaunchKernelGGL((bproj_kernel<T, NV>), dim3(nb), dim3(64 * kPjWaves), sm, st, Xu, r_upd, C,
+                       Xd, r_dot, W, nd, part.get());
+    reduce_cols(part.get(), nb * kPjWaves, n, n, out, acc_into, st, acc_into ? r_dot * NV : 0);
     RTE_CHECK_HIP(hipGetLastError());
   }
-
-  void read_tail(int r_dot, double out[2]) {
-    RTE_CHECK_HIP(hipMemcpyAsync(out, dvec.get() + r_dot, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-    sync();
+  // W: nv vectors (stride nd).  If r_upd > 0, W -= Xu C (C: [r_upd][nv]); then
+  // out[c nv + l] = Xd[c]^T W[l] for c < r_dot, out[r_dot nv + l] = ||W[l]||^2 after the
+  // update, out[r_dot nv + nv + l] = ||W[l]||^2 before it; acc_into[j] += out[j] for the
+  // dot products when acc_into is given.
+  void bproj(T* W, int nv, const T* Xu, int r_upd, const double* C, const T* Xd, int r_dot,
+             double* out, double* acc_into) {
+    switch (nv) {
+      case 1: bproj_n<1>(W, Xu, r_upd, C, Xd, r_dot, out, acc_into); break;
+      case 2: bproj_n<2>(W, Xu, r_upd, C, Xd, r_dot, out, acc_into); break;
+      case 3: bproj_n<3>(W, Xu, r_upd, C, Xd, r_dot, out, acc_into); break;
+      case 4: bproj_n<4>(W, Xu, r_upd, C, Xd, r_dot, out, acc_into); break;
+      case 5: bproj_n<5>(W, Xu, r_upd, C, Xd, r_dot, out, acc_into); break;
+      case 6: bproj_n<6>(W, Xu, r_upd, C, Xd, r_dot, out, acc_into); break;
+      case 7: bproj_n<7>(W, Xu, r_upd, C, Xd, r_dot, out, acc_into); break;
+      case 8: bproj_n<8>(W, Xu, r_upd, C, Xd, r_dot, out, acc_into); break;
+      default: RTE_REQUIRE(false, "internal: projection batch of %d vectors", nv);
+    }
   }
 
-  // MGS2-A (Alg. 2) for snapshot v of class cl; returns true if appended.
-  bool mgs2a(T* v, int cl) {
-    RTE_CHECK_HIP(hipMemsetAsync(cvec.get(), 0, (rcap + 2) * sizeof(double), st));
-    double tail[2];
-    double x1dot = 0.0, nrm2 = 0.0, orig2 = 0.0;
-    if (r == 0) {
-      proj(v, 0, nullptr, 0, false);
-      read_tail(0, tail);
-      nrm2 = tail[0];
-      orig2 = tail[1];
+  void to_host(double* h, const double* d, int n) {
+    RTE_CHECK_HIP(hipMemcpyAsync(h, d, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+
+  // MGS2-A (Alg. 2) for the sampled snapshots psi[0 .. pn) of classes cls[0 .. pn).
+  // Alg. 2 takes the snapshots one after the other, each against the basis including the
+  // columns appended before it in the same batch.  Here the two projections against the
+  // basis as it stood before the batch are made for all snapshots together (one pass over
+  // X serves the whole batch); then, snapshot by snapshot in batch order, two projections
+  // against the columns appended earlier in the batch, the normalisation, the clean-up
+  // projections and the append.  The appended columns are orthogonal to the old basis,
+  // so both orders give the same snapshots and coefficients in exact arithmetic.
+  void mgs_batch(const std::vector<int>& cls) {
+    const int pn = (int)cls.size();
+    const int r0 = r;
+    double h_orig[kMaxP], h_nrm[kMaxP], h_x1[kMaxP];
+    if (r0 > 0) {
+      device_fill(cb.get(), 0.0, (long)r0 * pn, st);
+      const T* X0 = X.get();
+      // pass 1: C1 = X^T psi;  pass 2: psi -= X C1, C2 = X^T psi;  pass 3: psi -= X C2
+      bproj(psi.get(), pn, nullptr, 0, nullptr, X0, r0, d1.get(), cb.get());
+      bproj(psi.get(), pn, X0, r0, d1.get(), X0, r0, d2.get(), cb.get());
+      bproj(psi.get(), pn, X0, r0, d2.get(), X0, 1, d3.get(), nullptr);
+      to_host(h_orig, d1.get() + (size_t)r0 * pn + pn, pn);
+      to_host(h_x1, d3.get(), pn);
+      to_host(h_nrm, d3.get() + pn, pn);
     } else {
-      // projection 1: dc = X^T v   (also ||v_orig||^2)
-      proj(v, 0, nullptr, r, true);
-      RTE_CHECK_HIP(hipMemcpyAsync(&orig2, dvec.get() + r + 1, sizeof(double), hipMemcpyDeviceToHost, st));
-      // v -= X dc ; projection 2: dc = X^T v  (the update reads a copy of dc)
-      copy_dc();
-      proj(v, r, dcsave.get(), r, true);
-      // v -= X dc ; ||v||^2, X(:,1)^T v
-      copy_dc();
-      proj(v, r, dcsave.get(), 1, false);
-      read_tail(1, tail);
-      RTE_CHECK_HIP(hipMemcpyAsync(&x1dot, dvec.get(), sizeof(double), hipMemcpyDeviceToHost, st));
-      sync();
-      nrm2 = tail[0];
+      bproj(psi.get(), pn, nullptr, 0, nullptr, nullptr, 0, d3.get(), nullptr);
+      to_host(h_nrm, d3.get(), pn);
+      to_host(h_orig, d3.get() + pn, pn);
+      for (int l = 0; l < pn; ++l) h_x1[l] = 0.0;
     }
+    sync();
+    for (int l = 0; l < pn; ++l) {
+      T* v = psi.get() + (size_t)l * nd;
+      hipLaunchKernelGGL(coef_col_kernel, dim3((rcap + 2 + 127) / 128), dim3(128), 0, st, cb.get(),
+                         pn, l, r0, cvec.get(), rcap + 2);
+      RTE_CHECK_HIP(hipGetLastError());
+      double nrm2 = h_nrm[l], x1dot = h_x1[l];
+      const int nnew = r - r0;
+      if (nnew > 0) {
+        const T* Xn = X.get() + (size_t)r0 * nd;
+        double tail[2];
+        bproj(v, 1, nullptr, 0, nullptr, Xn, nnew, d1.get(), cvec.get() + r0);
+        bproj(v, 1, Xn, nnew, d1.get(), Xn, nnew, d2.get(), cvec.get() + r0);
+        bproj(v, 1, Xn, nnew, d2.get(), X.get(), 1, d3.get(), nullptr);
+        to_host(tail, d3.get(), 2);
+        sync();
+        x1dot = tail[0];
+        nrm2 = tail[1];
+      }
+      finish(v, cls[l], nrm2, h_orig[l], x1dot);
+    }
+  }
+
+  // Normalisation, clean-up projections and append of one snapshot whose coefficients
+  // against the current basis are in cvec (Alg. 2); a snapshot that vanishes against
+  // the basis (breakdown) keeps its coefficients and adds no column.
+  bool finish(T* v, int cl, double nrm2, double orig2, double x1dot) {
     double alpha = std::sqrt(nrm2);
     if (alpha <= tol_break * std::sqrt(orig2) || alpha == 0.0) {
       ++breakdowns;
@@ -1151,14 +1394,13 @@ struct LowRank {
     if (r > 0) {
       double t = std::fabs(x1dot) / alpha;
       for (int m = 0; m < prm->m_max && t > eps_mgs; ++m) {
-        proj(v, 0, nullptr, r, true);
-        copy_dc();
-        proj(v, r, dcsave.get(), 1, false);
-        read_tail(1, tail);
-        RTE_CHECK_HIP(hipMemcpyAsync(&x1dot, dvec.get(), sizeof(double), hipMemcpyDeviceToHost, st));
+        double tail[2];
+        bproj(v, 1, nullptr, 0, nullptr, X.get(), r, d1.get(), cvec.get());
+        bproj(v, 1, X.get(), r, d1.get(), X.get(), 1, d3.get(), nullptr);
+        to_host(tail, d3.get(), 2);
         sync();
-        alpha = std::sqrt(tail[0]);
-        t = std::fabs(x1dot) / alpha;
+        alpha = std::sqrt(tail[1]);
+        t = std::fabs(tail[0]) / alpha;
       }
       if (t > eps_mgs) ++mgs_failures;
     }
@@ -1171,36 +1413,53 @@ struct LowRank {
     ++r;
     return true;
   }
-  DevBuf<double> dcsave;
-  void copy_dc() {
-    RTE_CHECK_HIP(hipMemcpyAsync(dcsave.get(), dvec.get(), (size_t)r * sizeof(double),
-                                 hipMemcpyDeviceToDevice, st));
-  }
 
   // ------------------------------------------------------------ bordering
-  void tsdot(const void* A, bool a_double, int na, const void* B, bool b_double, int nb,
-             double* out) {
-    const int gx = (na + 63) / 64;
-    long nch = std::max<long>(1, std::min<long>((nd + 2047) / 2048, std::max(1, 1024 / gx)));
-    const long kchunk = ((nd + nch - 1) / nch + 31) / 32 * 32;
-    nch = (nd + kchunk - 1) / kchunk;
-    DevBuf<double>& buf = tsd;
-    RTE_REQUIRE(buf.n >= (size_t)nch * na * nb, "internal: tsdot scratch too small");
-    dim3 grid(gx, (unsigned)nch, (unsigned)((nb + 31) / 32));
-    if (a_double && b_double)
-      hipLaunchKernelGGL((tsdot_kernel<double, double>), grid, dim3(256), 0, st, (const double*)A, na,
-                         (const double*)B, nb, nd, kchunk, buf.get());
-    else if (!a_double && !b_double)
-      hipLaunchKernelGGL((tsdot_kernel<T, T>), grid, dim3(256), 0, st, (const T*)A, na,
-                         (const T*)B, nb, nd, kchunk, buf.get());
-    else if (a_double)
-      hipLaunchKernelGGL((tsdot_kernel<double, T>), grid, dim3(256), 0, st, (const double*)A, na,
-                         (const T*)B, nb, nd, kchunk, buf.get());
-    else
-      hipLaunchKernelGGL((tsdot_kernel<T, double>), grid, dim3(256), 0, st, (const T*)A, na,
-                         (const double*)B, nb, nd, kchunk, buf.get());
-    const int n = na * nb;
-    reduce_cols(buf.get(), (int)nch, n, n, out, nullptr, st);
+  // out[e pn + m] = E[e]^T P[m] for the 5 vectors of E and the pn new columns P
+  template <int PN>
+  void edot_n(const T* P, int nbk) {
+    hipLaunchKernelGGL((edot_kernel<T, PN>), dim3(nbk), dim3(kTB), 0, st, E.get(), P, nd, tsd.get());
+  }
+  void edot(const T* P, int pn, double* out) {
+    const int nbk = 512;
+    switch (pn) {
+      case 1: edot_n<1>(P, nbk); break;
+      case 2: edot_n<2>(P, nbk); break;
+      case 3: edot_n<3>(P, nbk); break;
+      case 4: edot_n<4>(P, nbk); break;
+      case 5: edot_n<5>(P, nbk); break;
+      case 6: edot_n<6>(P, nbk); break;
+      case 7: edot_n<7>(P, nbk); break;
+      case 8: edot_n<8>(P, nbk); break;
+      default: RTE_REQUIRE(false, "internal: %d new columns", pn);
+    }
+    reduce_cols(tsd.get(), nbk, 5 * pn, 5 * pn, out, nullptr, st);
+    RTE_CHECK_HIP(hipGetLastError());
+  }
+
+  template <int NV>
+  void xtw_n(const T* A, int na, const T* B, dim3 grid, int nch) {
+    hipLaunchKernelGGL((xtw_kernel<T, NV>), grid, dim3(256), 0, st, A, na, B, nd, nch, xwp.get());
+  }
+  // out[a nb + b] = A[a]^T B[b] for a < na columns of A, b < nb = 5 pn vectors of B
+  void xtw(const T* A, int na, const T* B, int nb, double* out) {
+    const long nchunk = (nd + kXwRows - 1) / kXwRows;
+    const int nch = (int)std::max<long>(1, nchunk / 512);
+    const int nbk = (int)((nchunk + nch - 1) / nch);
+    RTE_REQUIRE(xwp.n >= (size_t)nbk * na * nb, "internal: X^T W scratch too small");
+    const dim3 grid(nbk, (na + 255) / 256);
+    switch (nb) {
+      case 5: xtw_n<5>(A, na, B, grid, nch); break;
+      case 10: xtw_n<10>(A, na, B, grid, nch); break;
+      case 15: xtw_n<15>(A, na, B, grid, nch); break;
+      case 20: xtw_n<20>(A, na, B, grid, nch); break;
+      case 25: xtw_n<25>(A, na, B, grid, nch); break;
+      case 30: xtw_n<30>(A, na, B, grid, nch); break;
+      case 35: xtw_n<35>(A, na, B, grid, nch); break;
+      case 40: xtw_n<40>(A, na, B, grid, nch); break;
+      default: RTE_REQUIRE(false, "internal: X^T W with %d vectors", nb);
+    }
+    reduce_cols(xwp.get(), nbk, na * nb, na * nb, out, nullptr, st);
     RTE_CHECK_HIP(hipGetLastError());
   }
 
@@ -1212,9 +1471,9 @@ struct LowRank {
     const int r1 = r0 + pn;
     // X^T [Sigma_t P, D_x^- P, D_y^- P, (D_x^-)^T P, (D_y^-)^T P] in one pass over X
     // (the last two blocks are used for the old rows only)
-    tsdot(X.get(), sizeof(T) == 8, r1, Y.get(), sizeof(T) == 8, 5 * pn, tsd2.get());
+    xtw(X.get(), r1, Y.get(), 5 * pn, tsd2.get());
     double* ext = tsd3.get();
-    tsdot(E.get(), true, 5, P, sizeof(T) == 8, pn, ext);
+    edot(P, pn, ext);
     const int nt = std::max(r1 * pn, 5);
     hipLaunchKernelGGL(scatter_border_kernel, dim3((nt + 127) / 128), dim3(128), 0, st, r0, pn,
                        rcap, tsd2.get(), ext, Tm.get(), Dx.get(), Dy.get(), bsrc.get(),
@@ -1232,8 +1491,8 @@ struct LowRank {
   void lu_border(int r0, int pn, const std::vector<int>& classes) {
     if (classes.empty() || pn == 0) return;
     upload_list(classes);
-    const size_t sm = ((size_t)2 * pn * r0 + (size_t)kLuRows * r0) * sizeof(double);
-    hipLaunchKernelGGL(lu_border_kernel, dim3((unsigned)classes.size()), dim3(64), sm, st, r0, pn,
+    const size_t sm = ((size_t)2 * pn * r0 + (size_t)kLuB * kLuLd) * sizeof(double);
+    hipLaunchKernelGGL(lu_border_kernel, dim3((unsigned)classes.size()), dim3(kLuThreads), sm, st, r0, pn,
                        rcap, d_list.get(), d_cd.get(), Tm.get(), Dx.get(), Dy.get(), bsrc.get(),
                        bside.get(), Lt.get(), U.get(), yv.get());
     RTE_CHECK_HIP(hipGetLastError());
@@ -1243,9 +1502,9 @@ struct LowRank {
   void galerkin(const std::vector<int>& classes) {
     if (classes.empty() || r == 0) return;
     upload_list(classes);
-    hipLaunchKernelGGL(backsub_kernel, dim3((unsigned)classes.size()), dim3(64),
-                       (size_t)rcap * sizeof(double), st, r, rcap, d_list.get(), U.get(), yv.get(),
-                       Cg.get());
+    hipLaunchKernelGGL(backsub_kernel, dim3((unsigned)classes.size()), dim3(kLuThreads),
+                       ((size_t)r + (size_t)kLuB * kLuLd) * sizeof(double), st, r, rcap,
+                       d_list.get(), U.get(), yv.get(), Cg.get());
     RTE_CHECK_HIP(hipGetLastError());
     sync();
   }
@@ -1349,10 +1608,10 @@ struct LowRank {
     while (true) {
       sweep_classes(samples);
       const int r0 = r;
-      for (size_t l = 0; l < samples.size(); ++l) {
-        mgs2a(psi.get() + (size_t)l * nd, samples[l]);
-        sampled[samples[l]] = 1;
-        log_sample(samples[l]);
+      mgs_batch(samples);
+      for (int c : samples) {
+        sampled[c] = 1;
+        log_sample(c);
       }
       const int pn = r - r0;
       std::vector<int> uns;
@@ -1496,7 +1755,6 @@ static rte_status run_lowrank(const rte_problem* prob, const rte_solve_params* p
   lr.st = st;
   lr.res = res;
   lr.setup();
-  lr.dcsave.alloc(lr.rcap + 2);
   const long nd = lr.nd;
   const Geom& g = lr.g;
   DevBuf<double> phi_prev(nd);
