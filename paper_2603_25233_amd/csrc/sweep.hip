@@ -153,15 +153,42 @@ __host__ __device__ __forceinline__ long sig_stride(int nx, int ny) {
   return ((long)nx * ny + (CPS - 1) * (long)(nx + ny) + 2 * CPS) / CPS * CPS;
 }
 
+// Elements of T in one 16-byte piece.
+template <typename T>
+constexpr int kPiece = 16 / (int)sizeof(T);
+
 // Diagonal-major copies of the sweep inputs for the quadrants in qmask: the source
 // moments (with the quadrant's reflections applied to the odd moments) and sigma_t,
-// converted to T.  dsrc: [4][ncell][4], dsig: [4][sig_stride].
+// converted to T, and per step t the y-inflow trace of canonical row 0 (the boundary
+// data of column t, zero for t >= nx) in a 16-byte piece.
+// dsrc: [4][ncell][4], dsig: [4][sig_stride], dbnd: [4][nx + ny - 1][kPiece].
 template <typename T>
 __global__ void diag_layout_kernel(int nx, int ny, int qmask, const double* __restrict__ sigma_t,
-                                   const T* __restrict__ src, T* __restrict__ dsrc,
-                                   T* __restrict__ dsig) {
+                                   const T* __restrict__ src, const double* __restrict__ bc,
+                                   int mb, double shy, T* __restrict__ dsrc,
+                                   T* __restrict__ dsig, T* __restrict__ dbnd) {
   const long ncell = (long)nx * ny;
   const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nsteps = nx + ny - 1;
+  if (c < nsteps) {
+    const int t = (int)c;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (!((qmask >> q) & 1)) continue;
+      const int sx = (q & 1) ? -1 : 1, sy = (q & 2) ? -1 : 1;
+      T v[kPiece<T>];
+#pragma unroll
+      for (int i = 0; i < kPiece<T>; ++i) v[i] = T(0);
+      if (bc && t < nx) {
+        const int col = sx > 0 ? t : nx - 1 - t;
+        const int yside = sy > 0 ? 2 : 3;
+        v[0] = T(shy * bc[((long)yside * mb + col) * 2 + 0]);
+        v[1] = T(shy * bc[((long)yside * mb + col) * 2 + 1] * sx);
+      }
+#pragma unroll
+      for (int i = 0; i < kPiece<T>; ++i) dbnd[((long)q * nsteps + t) * kPiece<T> + i] = v[i];
+    }
+  }
   if (c >= ncell) return;
   const int acol = (int)(c % nx), brow = (int)(c / nx);
   const Vec4<T> s4 = load4(src + 4 * c);
@@ -184,6 +211,20 @@ __global__ void diag_layout_kernel(int nx, int ny, int qmask, const double* __re
 
 // Rows of one step that each staging wavefront carries.
 constexpr int kStageRows = 256;
+// Input slots in LDS: the staging wavefronts fill step t + 2 while step t is solved.
+constexpr int kInSlots = 3;
+
+// s_waitcnt vmcnt(n) (expcnt and lgkmcnt not waited for); n > 15 waits for everything.
+__device__ __forceinline__ void wait_vmcnt(int n) {
+  switch (n) {
+#define RTE_VM(k) \
+  case k: __builtin_amdgcn_s_waitcnt(0xF70 | k); break;
+    RTE_VM(0) RTE_VM(1) RTE_VM(2) RTE_VM(3) RTE_VM(4) RTE_VM(5) RTE_VM(6) RTE_VM(7)
+    RTE_VM(8) RTE_VM(9) RTE_VM(10) RTE_VM(11) RTE_VM(12) RTE_VM(13) RTE_VM(14) RTE_VM(15)
+#undef RTE_VM
+    default: __builtin_amdgcn_s_waitcnt(0xF70); break;
+  }
+}
 
 // Output write-back geometry for element type T: a row's results leave in aligned
 // chunks of 128 bytes (kChunkCells cells), 16 bytes per lane, 8 rows per store
@@ -210,11 +251,13 @@ typedef __attribute__((address_space(3))) void lds_void;
 // global stores, which they never wait for.
 //
 // Per step t: the compute threads solve the cells of canonical column t - r, taking
-// the source and sigma_t of step t from LDS slot t & 1 and the y-inflow trace from row
-// r - 1 of step t - 1 (double-buffered LDS, one barrier per step); the x-inflow trace
-// stays in registers.  Meanwhile the staging wavefronts copy exactly the cells of step
-// t + 1 into slot (t + 1) & 1 (last read in step t - 1) and wait for the copies before
-// the barrier that ends step t.
+// the source and sigma_t of step t from LDS input slot t mod 3 and the y-inflow trace
+// from row r - 1 of step t - 1 (double-buffered LDS, one barrier per step); the
+// x-inflow trace stays in registers.  Meanwhile the staging wavefronts copy exactly the
+// cells of step t + 2 into slot (t + 2) mod 3 (last read in step t - 1) and, before the
+// barrier that ends step t, wait only for the copies of step t + 1 (issued one step
+// earlier): vector memory counts complete in issue order, so waiting until no more
+// than this step's copies are outstanding suffices, and a copy has a whole step to land.
 //
 // Output.  With use_ring, step t leaves its results in LDS ring slot t mod kRingSlots
 // (per direction for psi, or the weighted sum over the group's directions for the
@@ -228,8 +271,8 @@ template <typename T, int D, int NTB, int RPT>
 __global__ __launch_bounds__(NTB) void sweep_kernel(
     int nx, int ny, int mb, int nc, int use_ring, double shx, double shy,
     const SweepDir* __restrict__ dirs, const T* __restrict__ dsrc_all,
-    const T* __restrict__ dsig_all, const double* __restrict__ bc, T* __restrict__ psi,
-    T* __restrict__ part, long ndof) {
+    const T* __restrict__ dsig_all, const T* __restrict__ dbnd_all, const double* __restrict__ bc,
+    T* __restrict__ psi, T* __restrict__ part, long ndof) {
   using WB = WriteBack<T>;
   constexpr int CW = WB::kChunkCells, NS = WB::kRingSlots, LPC = WB::kLanesPerCell;
   constexpr int CPC = 4 * (int)sizeof(T) / 16;  // 16-byte pieces per source cell
@@ -239,11 +282,12 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
   const int nr = nc * RPT;                    // padded rows
   const int nrs = nr + 2 * CPS;               // sigma_t slot length
   const int RD = psi ? D : 1;                 // ring entries per row and step
+  constexpr int BS = kPiece<T>;                // elements of a 16-byte piece
   T* vbuf = reinterpret_cast<T*>(smem_raw);   // [2][nr][D][2] y-inflow traces by row
-  T* in_src = vbuf + 4L * nr * D;             // [2][nr][4] source moments of the step
-  T* in_sig = in_src + 8L * nr;               // [2][nrs] sigma_t of the step (shifted)
-  T* in_bnd = in_sig + 2L * nrs;              // [2][2] y-inflow of canonical row 0
-  T* ring = in_bnd + 4;                       // [NS][nr][RD][4] outputs by step and row
+  T* in_src = vbuf + 4L * nr * D;             // [3][nr][4] source moments of the step
+  T* in_sig = in_src + 4L * kInSlots * nr;    // [3][nrs] sigma_t of the step (shifted)
+  T* in_bnd = in_sig + (long)kInSlots * nrs;  // [3][BS] y-inflow of canonical row 0
+  T* ring = in_bnd + kInSlots * BS;           // [NS][nr][RD][4] outputs by step and row
   const SweepDir* grp = dirs + (long)blockIdx.x * D;
   const int sx = grp[0].sx, sy = grp[0].sy;
   const T fx = T(sx), fy = T(sy), fxy = T(sx * sy);
@@ -261,19 +305,20 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
     const int sw = (tid - nc) >> 6;
     const float4* src16 = reinterpret_cast<const float4*>(dsrc_all + 4 * q * ncell);
     const float4* sig16 = reinterpret_cast<const float4*>(dsig_all + q * sig_stride<T>(nx, ny));
-    const int yside = sy > 0 ? 2 : 3;
-    auto stage = [&](int t) {
+    const float4* bnd16 = reinterpret_cast<const float4*>(dbnd_all) + (long)q * nsteps;
+    // issues the copies of step t into slot sl; returns the number of copy instructions
+    auto stage = [&](int t, int sl) {
       const int lo = t >= nx ? t - nx + 1 : 0;
       const int hi = t < ny ? t : ny - 1;
-      const int sl = t & 1;
       const int c0 = sw * kStageRows;   // first cell of this wavefront
       const int nce = hi - lo + 1 - c0;  // cells left for it
+      int n = 0;
       if (nce > 0) {
         const int ncw = nce < kStageRows ? nce : kStageRows;
         // source: ncw * CPC pieces
         const float4* gs = src16 + (diag_first(t, nx, ny) + c0) * CPC;
         float4* ls = reinterpret_cast<float4*>(in_src) + ((long)sl * nr + lo + c0) * CPC;
-        for (int i = 0; 64 * i < ncw * CPC; ++i)
+        for (int i = 0; 64 * i < ncw * CPC; ++i, ++n)
           if (64 * i + lane < ncw * CPC)
             __builtin_amdgcn_global_load_lds((const void*)(gs + 64 * i + lane),
                                              (lds_void*)(ls + 64 * i), 16, 0, 0);
@@ -282,30 +327,32 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
         const float4* gg = sig16 + (sig_first<T>(t, nx, ny) + c0) / CPS;
         float4* lg = reinterpret_cast<float4*>(in_sig + (long)sl * nrs + sh + lo + c0);
         const int npg = (ncw + CPS - 1) / CPS;
-        for (int i = 0; 64 * i < npg; ++i)
+        for (int i = 0; 64 * i < npg; ++i, ++n)
           if (64 * i + lane < npg)
             __builtin_amdgcn_global_load_lds((const void*)(gg + 64 * i + lane),
                                              (lds_void*)(lg + 64 * i), 16, 0, 0);
       }
-      if (sw == 0 && lane == 0 && t < nx) {
-        const int col = sx > 0 ? t : nx - 1 - t;
-        T g0 = T(0), g1 = T(0);
-        if (bc) {
-          g0 = T(bc[((long)yside * mb + col) * 2 + 0]);
-          g1 = T(bc[((long)yside * mb + col) * 2 + 1]);
-        }
-        in_bnd[2 * sl] = T(shy) * g0;
-        in_bnd[2 * sl + 1] = T(shy) * g1 * fx;
+      if (sw == 0) {  // the y-inflow piece of row 0
+        if (lane == 0)
+          __builtin_amdgcn_global_load_lds((const void*)(bnd16 + t),
+                                           (lds_void*)(in_bnd + BS * sl), 16, 0, 0);
+        ++n;
       }
+      return n;
     };
-    stage(0);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();  // step 0 staged
+    // Plain barriers: the copies are waited for explicitly, with counts.
+    stage(0, 0);
+    const int n1 = nsteps > 1 ? stage(1, 1) : 0;
+    wait_vmcnt(n1);
+    __builtin_amdgcn_s_barrier();  // step 0 staged
+    int sl2 = 2;                   // (t + 2) mod 3
     for (int t = 0; t < nsteps; ++t) {
-      if (t + 1 < nsteps) stage(t + 1);
-      __builtin_amdgcn_s_waitcnt(0);  // copies of step t + 1 landed
-      __syncthreads();                // end of step t
+      const int n2 = t + 2 < nsteps ? stage(t + 2, sl2) : 0;
+      wait_vmcnt(n2);                // copies of step t + 1 landed
+      __builtin_amdgcn_s_barrier();  // end of step t
+      sl2 = sl2 == kInSlots - 1 ? 0 : sl2 + 1;
     }
+    __builtin_amdgcn_s_waitcnt(0);
     return;
   }
   // -------------------------------------------------- compute wavefronts
@@ -419,20 +466,21 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
   };
   __syncthreads();  // step 0 staged
   int ns = 0;       // t mod NS
+  int si = 0;       // t mod 3: input slot
   for (int t = 0; t < nsteps; ++t) {
     const int sl = t & 1;
     if (use_ring && t > 0) write_back(t, ns);
     const int lo = t >= nx ? t - nx + 1 : 0;
-    const T* sigs = in_sig + (long)sl * nrs + ((-lo) & (CPS - 1));
+    const T* sigs = in_sig + (long)si * nrs + ((-lo) & (CPS - 1));
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int r = row[k];
       const int ap = t - r;
       if (row_ok[k] && ap >= 0 && ap < nx) {
-        const T* rd = r == 0 ? in_bnd + 2 * sl : vbuf + ((long)(sl ^ 1) * nr + (r - 1)) * D * 2;
+        const T* rd = r == 0 ? in_bnd + BS * si : vbuf + ((long)(sl ^ 1) * nr + (r - 1)) * D * 2;
         const int rstride = r == 0 ? 0 : 2;
         T* wr = vbuf + ((long)sl * nr + r) * D * 2;
-        const Vec4<T> s4 = load4(in_src + ((long)sl * nr + r) * 4);
+        const Vec4<T> s4 = load4(in_src + ((long)si * nr + r) * 4);
         const T sig = sigs[r];
         T* rg = ring + ((long)ns * nr + r) * RD * 4;
         T acc[4] = {T(0), T(0), T(0), T(0)};
@@ -480,6 +528,7 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
     }
     __syncthreads();
     ns = ns + 1 == NS ? 0 : ns + 1;
+    si = si + 1 == kInSlots ? 0 : si + 1;
   }
   if (use_ring) write_back(nsteps, ns);  // chunks closed by the last step
 }
@@ -526,7 +575,8 @@ static std::vector<SweepDir> make_groups(const std::vector<SweepDir>& in, int D)
 static size_t sweep_lds_bytes(int nr, int D, bool psi, bool ring, size_t eb) {
   const size_t slots = ring ? (eb == 8 ? WriteBack<double>::kRingSlots : WriteBack<float>::kRingSlots) : 0;
   const size_t cps = 16 / eb;
-  return (4ull * nr * D + 8ull * nr + 2 * (nr + 2 * cps) + 4 + 4ull * slots * nr * (psi ? D : 1)) * eb;
+  return (4ull * nr * D + 4ull * kInSlots * nr + kInSlots * (nr + 2 * cps) + kInSlots * cps +
+          4ull * slots * nr * (psi ? D : 1)) * eb;
 }
 
 // LDS bytes one workgroup may use on the current device
@@ -564,17 +614,18 @@ SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool
   const size_t lmax = max_lds_per_block();
   const size_t lcap = std::min(lmax, kLdsTwoPerCU);
   // Directions per workgroup (scalar flux only): enough workgroups to cover the chip
-  // first; then D > 1 shares the staged inputs and the partial sums among directions.  D is bounded by the register budget (FP64: 2, and 1 beyond 576
-  // threads; FP32: 4) and by LDS.
-  // (psi together with the scalar flux: one direction per workgroup)
-  // (psi: one direction per workgroup measured faster, two workgroups sharing a CU)
+  // first; then D > 1 shares the staged inputs and the partial sums among directions.
+  // D is bounded by the register budget (FP64: 2, and 1 beyond 576 threads; FP32: 4)
+  // and by LDS.  With psi, one direction per workgroup (measured faster: two
+  // workgroups share a compute unit).
   const int dmax = want_psi ? 1 : elem_bytes == 8 ? (pl.nt <= 576 && rpt == 1 ? 2 : 1) : 4;
   int D = 1;
   while (D < dmax && dirs.size() / (2 * D) >= 256 &&
          sweep_lds_bytes(nr, 2 * D, want_psi, true, elem_bytes) <= lmax)
     D *= 2;
-  // the output ring if it fits (else each thread stores its cells directly)
-  const bool ring = sweep_lds_bytes(nr, D, want_psi, true, elem_bytes) <= lmax;
+  // the output ring if it fits and the plan is large enough for the store bandwidth to
+  // matter (else each thread stores its cells directly, which is shorter per step)
+  const bool ring = dirs.size() >= 64 && sweep_lds_bytes(nr, D, want_psi, true, elem_bytes) <= lmax;
   RTE_REQUIRE(sweep_lds_bytes(nr, D, want_psi, ring, elem_bytes) <= lmax,
               "sweep: %d x %d cells need %zu bytes of LDS per workgroup (device limit %zu)", g.nx,
               g.ny, sweep_lds_bytes(nr, D, want_psi, ring, elem_bytes), lmax);
@@ -590,7 +641,7 @@ SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool
 size_t sweep_input_elems(const Geom& g) {
   // both precisions use the larger of the two sigma_t strides
   const size_t qs = std::max(sig_stride<double>(g.nx, g.ny), sig_stride<float>(g.nx, g.ny));
-  return 16ull * g.nx * g.ny + 4 * qs;
+  return 16ull * g.nx * g.ny + 4 * qs + 4ull * kPiece<float> * (g.nx + g.ny - 1);
 }
 
 size_t sweep_work_elems(const Geom& g, const SweepPlan& pl, bool want_phi) {
@@ -606,20 +657,21 @@ void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
   RTE_REQUIRE(!(psi && phi) || pl.D == 1, "sweep: psi with the scalar flux needs one direction per workgroup");
   T* dsrc = work;              // [4][ncell][4]
   T* dsig = work + 16 * ncell;  // [4][sig_stride]
+  T* dbnd = dsig + 4 * sig_stride<T>(g.nx, g.ny);  // [4][nsteps][kPiece]
   T* part = work + sweep_input_elems(g);
+  const double shx = std::sqrt(g.hx), shy = std::sqrt(g.hy);
   {
     const int tb = 256;
     hipLaunchKernelGGL((diag_layout_kernel<T>), dim3((ncell + tb - 1) / tb), dim3(tb), 0, st, g.nx,
-                       g.ny, pl.qmask, sigma_t, src, dsrc, dsig);
+                       g.ny, pl.qmask, sigma_t, src, bc, g.mb, shy, dsrc, dsig, dbnd);
     RTE_CHECK_HIP(hipGetLastError());
   }
   const size_t lds = sweep_lds_bytes(pl.nc * pl.rpt, pl.D, psi != nullptr, pl.ring != 0, sizeof(T));
   dim3 grid(pl.ngroups), block(pl.nt);
-  const double shx = std::sqrt(g.hx), shy = std::sqrt(g.hy);
   T* pp = phi ? part : nullptr;
 #define RTE_SWEEP_CASE(DD, NTB, RP)                                                                \
   hipLaunchKernelGGL((sweep_kernel<T, DD, NTB, RP>), grid, block, lds, st, g.nx, g.ny, g.mb, pl.nc, \
-                     pl.ring, shx, shy, dirs_dev, dsrc, dsig, bc, psi, pp, g.ndof)
+                     pl.ring, shx, shy, dirs_dev, dsrc, dsig, dbnd, bc, psi, pp, g.ndof)
   // FP64 plans use D = 2 only with at most 576 threads (register budget)
 #define RTE_SWEEP_D(NTB, RP)                                         \
   if (pl.D == 1) RTE_SWEEP_CASE(1, NTB, RP);                         \

@@ -5,7 +5,8 @@ relative, the precision target for the mixed path; the per-cell closed-form solv
 loses at most ~2e-6 in FP32 over sigma, a, b in [1e-3, 1e4] (checked on the host),
 and errors do not grow along the sweep for a contractive upwind transmission.
 Grids span several 64-row waves with ragged tails; every quadrant, heterogeneous
-cross sections, linear inflow data and both directions-per-workgroup paths.
+cross sections, linear inflow data, both directions-per-workgroup paths, and both output
+paths (the LDS write-back ring for plans of 64 or more ordinates, direct stores below).
 """
 import numpy as np
 import pytest
