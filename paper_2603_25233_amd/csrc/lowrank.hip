@@ -235,6 +235,48 @@ __global__ __launch_bounds__(64 * kPjWaves, 2) void bproj_kernel(
   if (lane < 2 * NV) out[r_dot * NV + lane] = tot;
 }
 
+// Per-snapshot statistics of a batch, mstat[l] = (|psi|^2 now, |psi|^2 at the start,
+// X(:,1)^T psi): from the batch projections (d1: pass 1, d3: pass 3 or the norms-only
+// pass when the basis is empty) ...
+__global__ void mstat_init_kernel(int pn, int r0, const double* __restrict__ d1,
+                                  const double* __restrict__ d3, double* __restrict__ mstat) {
+  const int l = threadIdx.x;
+  if (l >= pn) return;
+  double* m = mstat + 4 * l;
+  if (r0 > 0) {
+    m[0] = d3[pn + l];
+    m[1] = d1[(long)r0 * pn + pn + l];
+    m[2] = d3[l];
+  } else {
+    m[0] = d3[l];
+    m[1] = d3[pn + l];
+    m[2] = 0.0;
+  }
+}
+// ... and after the projections against the columns appended earlier in the batch
+__global__ void mstat_set_kernel(const double* __restrict__ d3, double* __restrict__ m) {
+  m[0] = d3[1];
+  m[2] = d3[0];
+}
+
+// col = v / |v| (|v|^2 = m[0]; a vanishing v gives a zero column, discarded by the host)
+template <typename T>
+__global__ void append_dev_kernel(const T* __restrict__ v, const double* __restrict__ m,
+                                  T* __restrict__ col, long nd) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const double a = sqrt(m[0]);
+  if (i < nd) col[i] = a > 0.0 ? (T)((double)v[i] / a) : T(0);
+}
+
+// dst = (cvec[0 .. r), |v|, 0 ...) with |v|^2 = m[0]
+__global__ void store_coef_dev_kernel(const double* __restrict__ cvec, int r,
+                                      const double* __restrict__ m, double* __restrict__ dst,
+                                      int rcap) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rcap) return;
+  dst[i] = i < r ? cvec[i] : (i == r ? sqrt(m[0]) : 0.0);
+}
+
 // cvec[i] = cb[i pn + l] for i < r0, 0 for r0 <= i < n
 __global__ void coef_col_kernel(const double* __restrict__ cb, int pn, int l, int r0,
                                 double* __restrict__ cvec, int n) {
@@ -1128,17 +1170,19 @@ struct LowRank {
   std::vector<double> wc, mult;
   std::vector<ClassDev> cd;
   DevBuf<ClassDev> d_cd;
-  DevBuf<int> d_cls_of, d_sampled, d_list;
+  DevBuf<int> d_cls_of, d_sampled, d_list[3];
   DevBuf<double> d_wc, d_mult;
   // fields
   DevBuf<T> X, psi, srcT, Y, V, swork;
-  DevBuf<double> src, E, phi_k, phi_old, part, cvec, cw, dpart, cb, d1, d2, d3;
+  DevBuf<double> src, E, phi_k, phi_old, part, cvec, cw, dpart, cb, d1, d2, d3, mstat;
+  DevBuf<T> psi_save;          // snapshots after the batch projections (roll-back copy)
+  double* h_mstat = nullptr;   // pinned copy of mstat
   // projected operators and factors
   DevBuf<double> Tm, Dx, Dy, bsrc, bside, Lt, U, yv, Cg, Rst, tsd, tsd2, tsd3, xwp;
   DevBuf<SweepDir> d_dirs;
   DevBuf<double> Cm, rpart, rsums;
   SweepDir* h_dirs = nullptr;  // pinned staging
-  int* h_list = nullptr;       // pinned staging for class lists
+  int* h_list[3] = {nullptr, nullptr, nullptr};  // pinned staging for class lists
   int* h_flags = nullptr;      // pinned staging for the sampled flags
   int rblk = 0;
   // bookkeeping
@@ -1152,7 +1196,17 @@ struct LowRank {
   double ms_sweep = 0.0, ms_lr = 0.0;
   hipEvent_t e0, e1;
 
-  void sync() { RTE_CHECK_HIP(hipStreamSynchronize(st)); }
+  bool sweep_pending = false;
+  // waits for the stream; adds the time of a sweep enqueued since the last wait
+  void sync() {
+    RTE_CHECK_HIP(hipStreamSynchronize(st));
+    if (sweep_pending) {
+      float ms = 0.f;
+      RTE_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+      ms_sweep += ms;
+      sweep_pending = false;
+    }
+  }
 
   void setup() {
     g = make_geom(prob);
@@ -1201,7 +1255,7 @@ struct LowRank {
     d_mult.alloc(K);
     RTE_CHECK_HIP(hipMemcpy(d_mult.get(), mult.data(), K * sizeof(double), hipMemcpyHostToDevice));
     d_sampled.alloc(K);
-    d_list.alloc(K);
+    for (int i = 0; i < 3; ++i) d_list[i].alloc(K);
     X.alloc((size_t)rcap * nd);
     psi.alloc((size_t)p * nd);
     srcT.alloc(nd);
@@ -1216,6 +1270,9 @@ struct LowRank {
     // products and 2 kMaxP norms per row
     part.alloc((size_t)((nd + 127) / 128 + kPjWaves) * ((size_t)rcap * kMaxP + 2 * kMaxP));
     cb.alloc((size_t)rcap * kMaxP);
+    mstat.alloc(4 * kMaxP);
+    psi_save.alloc((size_t)p * nd);
+    RTE_CHECK_HIP(hipHostMalloc((void**)&h_mstat, 4 * kMaxP * sizeof(double), hipHostMallocDefault));
     d1.alloc((size_t)rcap * kMaxP + 2 * kMaxP);
     d2.alloc((size_t)rcap * kMaxP + 2 * kMaxP);
     d3.alloc((size_t)rcap * kMaxP + 2 * kMaxP);
@@ -1228,7 +1285,8 @@ struct LowRank {
     yv.alloc((size_t)K * rcap); Cg.alloc((size_t)K * rcap); Rst.alloc((size_t)K * rcap);
     d_dirs.alloc(kMaxP);
     RTE_CHECK_HIP(hipHostMalloc((void**)&h_dirs, kMaxP * sizeof(SweepDir), hipHostMallocDefault));
-    RTE_CHECK_HIP(hipHostMalloc((void**)&h_list, (size_t)K * sizeof(int), hipHostMallocDefault));
+    for (int i = 0; i < 3; ++i)
+      RTE_CHECK_HIP(hipHostMalloc((void**)&h_list[i], (size_t)K * sizeof(int), hipHostMallocDefault));
     RTE_CHECK_HIP(hipHostMalloc((void**)&h_flags, (size_t)K * sizeof(int), hipHostMallocDefault));
     rblk = (int)((g.ncell + 255) / 256);
     Cm.alloc((size_t)rcap * 32);
@@ -1256,7 +1314,9 @@ struct LowRank {
 
   ~LowRank() {
     if (h_dirs) (void)hipHostFree(h_dirs);
-    if (h_list) (void)hipHostFree(h_list);
+    for (int i = 0; i < 3; ++i)
+      if (h_list[i]) (void)hipHostFree(h_list[i]);
+    if (h_mstat) (void)hipHostFree(h_mstat);
     if (h_flags) (void)hipHostFree(h_flags);
   }
 
@@ -1283,10 +1343,7 @@ struct LowRank {
     sweep_enqueue<T>(g, pl, d_dirs.get(), prob->sigma_t, srcT.get(), prob->bc, psi.get(), nullptr,
                      swork.get(), st);
     RTE_CHECK_HIP(hipEventRecord(e1, st));
-    sync();
-    float ms = 0.f;
-    RTE_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
-    ms_sweep += ms;
+    sweep_pending = true;  // timed at the next synchronisation (see sync)
     swept += (int)cl.size();
     swept_total += (int)cl.size();
   }
@@ -1336,10 +1393,15 @@ struct LowRank {
   // against the columns appended earlier in the batch, the normalisation, the clean-up
   // projections and the append.  The appended columns are orthogonal to the old basis,
   // so both orders give the same snapshots and coefficients in exact arithmetic.
+  //
+  // The per-snapshot steps first run on the device without waiting for the host, on the
+  // assumption that no snapshot breaks down and none needs a clean-up projection (the
+  // usual case); the host then checks the statistics of every snapshot in order and, from
+  // the first one that fails, rolls back (basis size, snapshots restored from a copy taken
+  // after the batch projections) and takes the decisions one snapshot at a time.
   void mgs_batch(const std::vector<int>& cls) {
     const int pn = (int)cls.size();
     const int r0 = r;
-    double h_orig[kMaxP], h_nrm[kMaxP], h_x1[kMaxP];
     if (r0 > 0) {
       device_fill(cb.get(), 0.0, (long)r0 * pn, st);
       const T* X0 = X.get();
@@ -1347,36 +1409,80 @@ struct LowRank {
       bproj(psi.get(), pn, nullptr, 0, nullptr, X0, r0, d1.get(), cb.get());
       bproj(psi.get(), pn, X0, r0, d1.get(), X0, r0, d2.get(), cb.get());
       bproj(psi.get(), pn, X0, r0, d2.get(), X0, 1, d3.get(), nullptr);
-      to_host(h_orig, d1.get() + (size_t)r0 * pn + pn, pn);
-      to_host(h_x1, d3.get(), pn);
-      to_host(h_nrm, d3.get() + pn, pn);
     } else {
       bproj(psi.get(), pn, nullptr, 0, nullptr, nullptr, 0, d3.get(), nullptr);
-      to_host(h_nrm, d3.get(), pn);
-      to_host(h_orig, d3.get() + pn, pn);
-      for (int l = 0; l < pn; ++l) h_x1[l] = 0.0;
     }
-    sync();
-    for (int l = 0; l < pn; ++l) {
+    hipLaunchKernelGGL(mstat_init_kernel, dim3(1), dim3(64), 0, st, pn, r0, d1.get(), d3.get(),
+                       mstat.get());
+    RTE_CHECK_HIP(hipGetLastError());
+    int lseq = 0;  // first snapshot taken with host decisions
+    if (r0 + pn <= rcap) {
+      RTE_CHECK_HIP(hipMemcpyAsync(psi_save.get(), psi.get(), (size_t)pn * nd * sizeof(T),
+                                   hipMemcpyDeviceToDevice, st));
+      for (int l = 0; l < pn; ++l) {
+        T* v = psi.get() + (size_t)l * nd;
+        coef_col(l, pn, r0);
+        if (l > 0) {
+          intra_passes(v, r0, l);
+          hipLaunchKernelGGL(mstat_set_kernel, dim3(1), dim3(1), 0, st, d3.get(),
+                             mstat.get() + 4 * l);
+        }
+        hipLaunchKernelGGL((append_dev_kernel<T>), dim3((nd + 255) / 256), dim3(256), 0, st, v,
+                           mstat.get() + 4 * l, X.get() + (size_t)(r0 + l) * nd, nd);
+        hipLaunchKernelGGL(store_coef_dev_kernel, dim3((rcap + 127) / 128), dim3(128), 0, st,
+                           cvec.get(), r0 + l, mstat.get() + 4 * l,
+                           Rst.get() + (size_t)rcap * cls[l], rcap);
+        RTE_CHECK_HIP(hipGetLastError());
+      }
+      to_host(h_mstat, mstat.get(), 4 * pn);
+      sync();
+      lseq = pn;
+      for (int l = 0; l < pn && lseq == pn; ++l) {
+        const double* m = h_mstat + 4 * l;
+        const double alpha = std::sqrt(m[0]);
+        if (alpha <= tol_break * std::sqrt(m[1]) || alpha == 0.0 ||
+            (r0 + l > 0 && std::fabs(m[2]) / alpha > eps_mgs))
+          lseq = l;
+      }
+      r = r0 + lseq;
+      if (lseq == pn) return;
+      RTE_CHECK_HIP(hipMemcpyAsync(psi.get() + (size_t)lseq * nd, psi_save.get() + (size_t)lseq * nd,
+                                   (size_t)(pn - lseq) * nd * sizeof(T), hipMemcpyDeviceToDevice, st));
+    } else {
+      to_host(h_mstat, mstat.get(), 4 * pn);
+      sync();
+    }
+    for (int l = lseq; l < pn; ++l) {
       T* v = psi.get() + (size_t)l * nd;
-      hipLaunchKernelGGL(coef_col_kernel, dim3((rcap + 2 + 127) / 128), dim3(128), 0, st, cb.get(),
-                         pn, l, r0, cvec.get(), rcap + 2);
-      RTE_CHECK_HIP(hipGetLastError());
-      double nrm2 = h_nrm[l], x1dot = h_x1[l];
+      coef_col(l, pn, r0);
+      double nrm2 = h_mstat[4 * l], x1dot = h_mstat[4 * l + 2];
       const int nnew = r - r0;
       if (nnew > 0) {
-        const T* Xn = X.get() + (size_t)r0 * nd;
         double tail[2];
-        bproj(v, 1, nullptr, 0, nullptr, Xn, nnew, d1.get(), cvec.get() + r0);
-        bproj(v, 1, Xn, nnew, d1.get(), Xn, nnew, d2.get(), cvec.get() + r0);
-        bproj(v, 1, Xn, nnew, d2.get(), X.get(), 1, d3.get(), nullptr);
+        intra_passes(v, r0, nnew);
         to_host(tail, d3.get(), 2);
         sync();
         x1dot = tail[0];
         nrm2 = tail[1];
       }
-      finish(v, cls[l], nrm2, h_orig[l], x1dot);
+      finish(v, cls[l], nrm2, h_mstat[4 * l + 1], x1dot);
     }
+  }
+
+  // cvec = (coefficients of snapshot l against the old basis, zeros)
+  void coef_col(int l, int pn, int r0) {
+    hipLaunchKernelGGL(coef_col_kernel, dim3((rcap + 2 + 127) / 128), dim3(128), 0, st, cb.get(),
+                       pn, l, r0, cvec.get(), rcap + 2);
+    RTE_CHECK_HIP(hipGetLastError());
+  }
+
+  // two projections of v against the nnew columns appended after r0 (coefficients into
+  // cvec[r0 ..]); the last pass leaves X(:,1)^T v and |v|^2 in d3[0], d3[1]
+  void intra_passes(T* v, int r0, int nnew) {
+    const T* Xn = X.get() + (size_t)r0 * nd;
+    bproj(v, 1, nullptr, 0, nullptr, Xn, nnew, d1.get(), cvec.get() + r0);
+    bproj(v, 1, Xn, nnew, d1.get(), Xn, nnew, d2.get(), cvec.get() + r0);
+    bproj(v, 1, Xn, nnew, d2.get(), X.get(), 1, d3.get(), nullptr);
   }
 
   // Normalisation, clean-up projections and append of one snapshot whose coefficients
@@ -1481,42 +1587,48 @@ struct LowRank {
     RTE_CHECK_HIP(hipGetLastError());
   }
 
-  // every caller synchronises before the staging buffer is reused
-  void upload_list(const std::vector<int>& l) {
-    std::memcpy(h_list, l.data(), l.size() * sizeof(int));
-    RTE_CHECK_HIP(hipMemcpyAsync(d_list.get(), h_list, l.size() * sizeof(int),
+  // Class lists: 0 for the bordered factorisations, 1 for the candidates, 2 for the
+  // unsampled classes at a convergence check or the truncation.  Each kind is uploaded
+  // at most once between two synchronisations of the inner loop, so its staging buffer
+  // is free again when it is next written.
+  const int* upload_list(int kind, const std::vector<int>& l) {
+    std::memcpy(h_list[kind], l.data(), l.size() * sizeof(int));
+    RTE_CHECK_HIP(hipMemcpyAsync(d_list[kind].get(), h_list[kind], l.size() * sizeof(int),
                                  hipMemcpyHostToDevice, st));
+    return d_list[kind].get();
   }
 
   void lu_border(int r0, int pn, const std::vector<int>& classes) {
     if (classes.empty() || pn == 0) return;
-    upload_list(classes);
+    const int* dl = upload_list(0, classes);
     const size_t sm = ((size_t)2 * pn * r0 + (size_t)kLuB * kLuLd) * sizeof(double);
     hipLaunchKernelGGL(lu_border_kernel, dim3((unsigned)classes.size()), dim3(kLuThreads), sm, st, r0, pn,
-                       rcap, d_list.get(), d_cd.get(), Tm.get(), Dx.get(), Dy.get(), bsrc.get(),
+                       rcap, dl, d_cd.get(), Tm.get(), Dx.get(), Dy.get(), bsrc.get(),
                        bside.get(), Lt.get(), U.get(), yv.get());
     RTE_CHECK_HIP(hipGetLastError());
-    sync();  // the class list is reused by the next call
   }
 
-  void galerkin(const std::vector<int>& classes) {
+  // Galerkin coefficients of the classes (list kind `kind`, see upload_list)
+  void galerkin(const std::vector<int>& classes, int kind) {
     if (classes.empty() || r == 0) return;
-    upload_list(classes);
+    const int* dl = upload_list(kind, classes);
     hipLaunchKernelGGL(backsub_kernel, dim3((unsigned)classes.size()), dim3(kLuThreads),
-                       ((size_t)r + (size_t)kLuB * kLuLd) * sizeof(double), st, r, rcap,
-                       d_list.get(), U.get(), yv.get(), Cg.get());
+                       ((size_t)r + (size_t)kLuB * kLuLd) * sizeof(double), st, r, rcap, dl,
+                       U.get(), yv.get(), Cg.get());
     RTE_CHECK_HIP(hipGetLastError());
-    sync();
   }
 
-  // candidate residual norms (host values in draw order)
+  // Galerkin solves and residual norms of the candidates (host values in draw order)
   std::vector<double> residuals(const std::vector<int>& cand) {
     const int nm = (int)cand.size();
     std::vector<double> out(nm, 0.0);
-    upload_list(cand);
+    const int* dl = upload_list(1, cand);
     if (r > 0) {
+      hipLaunchKernelGGL(backsub_kernel, dim3((unsigned)nm), dim3(kLuThreads),
+                         ((size_t)r + (size_t)kLuB * kLuLd) * sizeof(double), st, r, rcap, dl,
+                         U.get(), yv.get(), Cg.get());
       hipLaunchKernelGGL(gather_cg_kernel, dim3((r * nm + 255) / 256), dim3(256), 0, st, Cg.get(),
-                         rcap, d_list.get(), nm, r, Cm.get());
+                         rcap, dl, nm, r, Cm.get());
       hipLaunchKernelGGL((xc_kernel<T, T, 32>), dim3((nd + 255) / 256), dim3(256), 0, st, X.get(), r,
                          nd, Cm.get(), nm, nm, V.get());
     } else {
@@ -1524,7 +1636,7 @@ struct LowRank {
     }
     hipLaunchKernelGGL((residual_kernel<T>), dim3(rblk, nm), dim3(256), 0, st, g.nx, g.ny,
                        1.0 / g.hx, 1.0 / g.hy, prob->sigma_t, src.get(), E.get(), nd, V.get(), nm,
-                       d_list.get(), d_cd.get(), rpart.get());
+                       dl, d_cd.get(), rpart.get());
     reduce_cols(rpart.get(), rblk, nm, nm, rsums.get(), nullptr, st);
     RTE_CHECK_HIP(hipGetLastError());
     RTE_CHECK_HIP(hipMemcpyAsync(out.data(), rsums.get(), nm * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1626,14 +1738,13 @@ struct LowRank {
         break;
       }
       std::vector<int> cand = draw(rs, uns, prm->q);
-      galerkin(cand);
       std::vector<double> rn = residuals(cand);
       for (double v : rn) log_resid(v);
       double mx = 0.0;
       for (double v : rn) mx = std::max(mx, v);
       bool stop = false;
       if (mx < prm->eps_res) {
-        galerkin(uns);
+        galerkin(uns, 2);
         scalar_flux(nullptr);
         const double d = diff_norm(phi_k.get(), phi_old.get());
         if (d <= prm->eps_diff) stop = true;
@@ -1669,7 +1780,7 @@ struct LowRank {
     std::vector<int> uns;
     for (int c = 0; c < K; ++c)
       if (!sampled[c]) uns.push_back(c);
-    galerkin(uns);
+    galerkin(uns, 2);
     scalar_flux(B.get());
     hipLaunchKernelGGL(identity_kernel, dim3((r * r + 255) / 256), dim3(256), 0, st, Qt.get(), r);
     // round-robin pairs
