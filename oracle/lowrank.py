@@ -336,7 +336,7 @@ def lr_si_dsa(prob, eps_si, p, q, eps_res, eps_diff, eps_svd, rand, eps_mgs=1e-1
     phi_prev = np.zeros(prob.mesh.ndof) if phi0 is None else np.asarray(phi0, dtype=np.float64).copy()
     hist, logs, ranks, sampled = [], [], [], []
     lr = LowRankSI(prob, ops, p, q, eps_res, eps_diff, eps_mgs, m_max, tol_break, nthreads)
-    mgs_fail = 0
+    mgs_fail = breakdowns = 0
     out = None
     phi_star = phi_prev
     for n in range(1, max_outer + 1):
@@ -344,6 +344,7 @@ def lr_si_dsa(prob, eps_si, p, q, eps_res, eps_diff, eps_svd, rand, eps_mgs=1e-1
         rep = None if replay is None or n - 1 >= len(replay) else replay[n - 1]
         phi_star = lr.run(src, phi_prev, stream, rep)
         mgs_fail += lr.mgs_failures
+        breakdowns += lr.breakdowns
         Xn, S, V, s_all = lr.truncate(eps_svd)
         ranks.append(S.size)
         sampled.append(lr.n_swept)
@@ -357,7 +358,7 @@ def lr_si_dsa(prob, eps_si, p, q, eps_res, eps_diff, eps_svd, rand, eps_mgs=1e-1
     if out is None:
         out = dict(phi=phi_star, iters=max_outer, converged=False)
     out.update(history=hist, logs=logs, ranks=ranks, n_sampled=sampled, mgs_failures=mgs_fail,
-               rand_used=stream.i)
+               breakdowns=breakdowns, rand_used=stream.i)
     if keep_factors:
         out.update(X=Xn, S=S, V=V, singular_values=s_all, C=lr.C, Xfull=lr.X)
     return out

@@ -259,13 +259,15 @@ __global__ void mstat_set_kernel(const double* __restrict__ d3, double* __restri
   m[2] = d3[0];
 }
 
-// col = v / |v| (|v|^2 = m[0]; a vanishing v gives a zero column, discarded by the host)
+// col = v (1 / |v|) with |v|^2 = m[0], rounded as append_kernel with the host's 1 / |v|;
+// a vanishing v gives a zero column, discarded by the host
 template <typename T>
 __global__ void append_dev_kernel(const T* __restrict__ v, const double* __restrict__ m,
                                   T* __restrict__ col, long nd) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const double a = sqrt(m[0]);
-  if (i < nd) col[i] = a > 0.0 ? (T)((double)v[i] / a) : T(0);
+  const double ia = a > 0.0 ? 1.0 / a : 0.0;
+  if (i < nd) col[i] = (T)((double)v[i] * ia);
 }
 
 // dst = (cvec[0 .. r), |v|, 0 ...) with |v|^2 = m[0]
