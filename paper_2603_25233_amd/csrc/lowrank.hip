@@ -530,11 +530,13 @@ __global__ __launch_bounds__(256) void edot_kernel(const double* __restrict__ E,
 
 // ------------------------------------------------------------------ X^T W, lanes over columns
 // part[blk][c NV + l] = sum over the block's rows k of X[c][k] W[l][k]  (c < r, l < NV).
-// Each lane owns one column of X and reads it in 16-byte runs (X is column-major), so the
-// sums need no cross-lane reduction.  The NV vectors of W are staged per kXwRows-row chunk
-// in LDS as [row][vector] (double-buffered: the next chunk is fetched into registers while
-// the current one is used) and read as broadcasts.  A block of 256 threads covers 256
-// columns (blockIdx.y selects the tile) and `nch` consecutive chunks.
+// Each lane owns one column of X, so the sums need no cross-lane reduction.  A wavefront
+// covers 64 columns and reads them in sub-tiles of 128 bytes per column (8 columns per
+// load instruction, whole cache lines), transposes each sub-tile through its own LDS
+// rows, and then every lane walks down its column.  The NV vectors of W are staged per
+// kXwRows-row chunk in LDS as [row][vector] (double-buffered: the next chunk is fetched
+// into registers while the current one is used) and read as broadcasts.  A block of 256
+// threads covers 256 columns (blockIdx.y selects the tile) and `nch` consecutive chunks.
 constexpr int kXwRows = 128;
 
 template <typename T>
@@ -560,12 +562,27 @@ __global__ __launch_bounds__(256) void xtw_kernel(const T* __restrict__ X, int r
                                                  double* __restrict__ part) {
   constexpr int NVP = (NV + 1) & ~1;                // even row stride: 16-byte pairs
   constexpr int PT = (NV * kXwRows + 255) / 256;     // staged values per thread
-  constexpr int E = Vec16<T>::n;
+  constexpr int E = Vec16<T>::n;                     // elements per 16-byte load
+  constexpr int SUB = 128 / (int)sizeof(T);          // rows of a sub-tile (128 B per column)
+  constexpr int NSUB = kXwRows / SUB;                // sub-tiles per chunk
+  constexpr int LDX = SUB + 1;                       // LDS row stride of the transpose
   using V = typename Vec16<T>::type;
   __shared__ __align__(16) double Ws[2][kXwRows * NVP];
+  __shared__ T Xs[4][64 * LDX];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c = blockIdx.y * 256 + threadIdx.x;
   const bool on = c < r;
-  const V* xc = reinterpret_cast<const V*>(X + (long)(on ? c : 0) * nd);
+  // load lane roles: column cw + 8 i + (lane >> 3), elements (lane & 7) E .. of the sub-tile
+  const int cw = blockIdx.y * 256 + wave * 64;
+  const bool won = cw < r;  // wavefronts past the last column only help with the staging
+  const V* xcol[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int col = min(cw + 8 * i + (lane >> 3), r - 1);  // columns past r: any valid one
+    xcol[i] = reinterpret_cast<const V*>(X + (long)col * nd);
+  }
+  const int eoff = (lane & 7) * E;
+  T* xs = Xs[wave];
   const long kb = (long)blockIdx.x * nch * kXwRows;
   const int nq = (int)std::min<long>(nch, (nd - kb + kXwRows - 1) / kXwRows);
   double wpf[PT];
@@ -583,39 +600,45 @@ __global__ __launch_bounds__(256) void xtw_kernel(const T* __restrict__ X, int r
       if (e < NV * kXwRows) ws[k * NVP + l] = wpf[i];
     }
   };
+  // rows past nd (last chunk only) read a clamped in-range address; their staged W is 0
+  auto xload = [&](V (&xv)[8], long k0) {
+    const long k = std::min<long>(k0 + eoff, nd - E) / E;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) xv[i] = xcol[i][k];
+  };
   double acc[NV];
 #pragma unroll
   for (int l = 0; l < NV; ++l) acc[l] = 0.0;
   wfetch(kb);
   wstash(Ws[0]);
+  V xv[8];
+  if (won) xload(xv, kb);
   __syncthreads();
   for (int q = 0; q < nq; ++q) {
     const long k0 = kb + (long)q * kXwRows;
     if (q + 1 < nq) wfetch(k0 + kXwRows);
     const double* ws = Ws[q & 1];
-    if (on) {
-      // rows past nd (last chunk only) read a clamped in-range address; their staged W is 0
-      auto xload = [&](V (&xv)[8], int kk) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) xv[u] = xc[std::min<long>(k0 + kk + u * E, nd - E) / E];
-      };
-      auto madd = [&](const V (&xv)[8], int kk) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-#pragma unroll
-          for (int e = 0; e < E; ++e) {
-            const double x = Vec16<T>::at(xv[u], e);
-            const double* wr = ws + (kk + u * E + e) * NVP;
-#pragma unroll
-            for (int l = 0; l < NV; ++l) acc[l] += x * wr[l];
-          }
-      };
 #pragma unroll 1
-      for (int kk = 0; kk < kXwRows; kk += 8 * E) {
-        V xv[8];
-        xload(xv, kk);
-        madd(xv, kk);
+    for (int sb = 0; won && sb < NSUB; ++sb) {
+      // transpose the sub-tile: column 8 i + (lane >> 3), rows eoff .. eoff + E - 1
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          xs[(8 * i + (lane >> 3)) * LDX + eoff + e] = (T)Vec16<T>::at(xv[i], e);
+      lds_fence_wave();
+      // next sub-tile (or the first of the next chunk) in flight during the products
+      if (sb + 1 < NSUB) xload(xv, k0 + (sb + 1) * SUB);
+      else if (q + 1 < nq) xload(xv, k0 + kXwRows);
+      const T* xr = xs + lane * LDX;
+      const double* wr = ws + sb * SUB * NVP;
+#pragma unroll 4
+      for (int kk = 0; kk < SUB; ++kk) {
+        const double x = (double)xr[kk];
+#pragma unroll
+        for (int l = 0; l < NV; ++l) acc[l] += x * wr[kk * NVP + l];
       }
+      lds_fence_wave();
     }
     if (q + 1 < nq) wstash(Ws[(q + 1) & 1]);
     __syncthreads();
