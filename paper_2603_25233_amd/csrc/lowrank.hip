@@ -536,7 +536,9 @@ __global__ __launch_bounds__(256) void edot_kernel(const double* __restrict__ E,
 // rows, and then every lane walks down its column.  The NV vectors of W are staged per
 // kXwRows-row chunk in LDS as [row][vector] (double-buffered: the next chunk is fetched
 // into registers while the current one is used) and read as broadcasts.  A block of 256
-// threads covers 256 columns (blockIdx.y selects the tile) and `nch` consecutive chunks.
+// threads covers 256 columns (blockIdx.y selects the tile) and `nch` consecutive chunks;
+// with fewer columns than 256, the wavefronts of a block split the sub-tiles of each chunk
+// between them (row groups) and add their sums in a fixed order at the end.
 constexpr int kXwRows = 128;
 
 template <typename T>
@@ -570,10 +572,14 @@ __global__ __launch_bounds__(256) void xtw_kernel(const T* __restrict__ X, int r
   __shared__ __align__(16) double Ws[2][kXwRows * NVP];
   __shared__ T Xs[4][64 * LDX];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int c = blockIdx.y * 256 + threadIdx.x;
+  // column tiles of 64 in this block (1, 2 or 4) and row groups (4, 2 or 1)
+  const int ncol = min(256, r - (int)blockIdx.y * 256);
+  const int ntile = ncol <= 64 ? 1 : (ncol <= 128 ? 2 : 4);
+  const int ngrp = 4 / ntile, tile = wave % ntile, grp = wave / ntile;
+  const int c = blockIdx.y * 256 + tile * 64 + lane;
   const bool on = c < r;
   // load lane roles: column cw + 8 i + (lane >> 3), elements (lane & 7) E .. of the sub-tile
-  const int cw = blockIdx.y * 256 + wave * 64;
+  const int cw = blockIdx.y * 256 + tile * 64;
   const bool won = cw < r;  // wavefronts past the last column only help with the staging
   const V* xcol[8];
 #pragma unroll
@@ -612,14 +618,14 @@ __global__ __launch_bounds__(256) void xtw_kernel(const T* __restrict__ X, int r
   wfetch(kb);
   wstash(Ws[0]);
   V xv[8];
-  if (won) xload(xv, kb);
+  if (won) xload(xv, kb + grp * SUB);
   __syncthreads();
   for (int q = 0; q < nq; ++q) {
     const long k0 = kb + (long)q * kXwRows;
     if (q + 1 < nq) wfetch(k0 + kXwRows);
     const double* ws = Ws[q & 1];
 #pragma unroll 1
-    for (int sb = 0; won && sb < NSUB; ++sb) {
+    for (int sb = grp; won && sb < NSUB; sb += ngrp) {
       // transpose the sub-tile: column 8 i + (lane >> 3), rows eoff .. eoff + E - 1
 #pragma unroll
       for (int i = 0; i < 8; ++i)
@@ -628,8 +634,8 @@ __global__ __launch_bounds__(256) void xtw_kernel(const T* __restrict__ X, int r
           xs[(8 * i + (lane >> 3)) * LDX + eoff + e] = (T)Vec16<T>::at(xv[i], e);
       lds_fence_wave();
       // next sub-tile (or the first of the next chunk) in flight during the products
-      if (sb + 1 < NSUB) xload(xv, k0 + (sb + 1) * SUB);
-      else if (q + 1 < nq) xload(xv, k0 + kXwRows);
+      if (sb + ngrp < NSUB) xload(xv, k0 + (sb + ngrp) * SUB);
+      else if (q + 1 < nq) xload(xv, k0 + kXwRows + grp * SUB);
       const T* xr = xs + lane * LDX;
       const double* wr = ws + sb * SUB * NVP;
 #pragma unroll 4
@@ -643,7 +649,19 @@ __global__ __launch_bounds__(256) void xtw_kernel(const T* __restrict__ X, int r
     if (q + 1 < nq) wstash(Ws[(q + 1) & 1]);
     __syncthreads();
   }
-  if (on)
+  // row groups 1 .. ngrp-1 hand their sums to group 0 through LDS (reusing Ws)
+  if (ngrp > 1) {
+    double* red = &Ws[0][0];  // [ngrp - 1][64 ntile][NV] <= 3 * 64 * NV doubles
+    if (grp > 0)
+#pragma unroll
+      for (int l = 0; l < NV; ++l) red[(((grp - 1) * ntile + tile) * 64 + lane) * NV + l] = acc[l];
+    __syncthreads();
+    if (grp == 0)
+      for (int g = 1; g < ngrp; ++g)
+#pragma unroll
+        for (int l = 0; l < NV; ++l) acc[l] += red[(((g - 1) * ntile + tile) * 64 + lane) * NV + l];
+  }
+  if (on && grp == 0)
 #pragma unroll
     for (int l = 0; l < NV; ++l) part[((long)blockIdx.x * r + c) * NV + l] = acc[l];
 }
