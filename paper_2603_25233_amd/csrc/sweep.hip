@@ -215,8 +215,10 @@ constexpr int kStageRows = 256;
 constexpr int kInSlots = 3;
 
 // s_waitcnt vmcnt(n) (expcnt and lgkmcnt not waited for); n > 15 waits for everything.
+// n must be the same in every lane: it is made a scalar first, so that exactly one case
+// runs (a per-lane switch would pass through the wait of every case).
 __device__ __forceinline__ void wait_vmcnt(int n) {
-  switch (n) {
+  switch (__builtin_amdgcn_readfirstlane(n)) {
 #define RTE_VM(k) \
   case k: __builtin_amdgcn_s_waitcnt(0xF70 | k); break;
     RTE_VM(0) RTE_VM(1) RTE_VM(2) RTE_VM(3) RTE_VM(4) RTE_VM(5) RTE_VM(6) RTE_VM(7)
