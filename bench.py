@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=10)
     ap.add_argument("--mixed", action="store_true", help="mixed-precision solvers and sweep")
+    ap.add_argument("--no-mixed-report", action="store_true",
+                    help="skip the untimed mixed-precision solves reported next to the FP64 ones")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only (the method runs on one MI355X here); "
@@ -200,6 +202,24 @@ def main():
                      "algorithmic_bytes_per_launch": k1_bytes},
     }
     line.update(res)
+    if args.only == "step" and not args.mixed and not args.no_mixed_report:
+        # the mixed-precision form (FP32 sweeps and basis, FP64 reductions, Galerkin, SVD,
+        # DSA) once each, after the timed region, against this step's FP64 results
+        mkw = dict(solve_kw, mixed=True)
+        frm = R.solve(prob, full_rank=1, **mkw)
+        lrm = R.solve(prob, rand=W.random_stream(wl["seed"]), full_rank=0, p=wl["p"], q=wl["q"],
+                      eps_res=wl["eps_res"], eps_diff=wl["eps_diff"], eps_svd=wl["eps_svd"],
+                      eps_mgs=wl["eps_mgs"], m_max=wl["m_max"], **mkw)
+        fr, lr = outs[-1]["fr"], outs[-1]["lr"]
+        nrm = lambda a, b: float((a.double() - b.double()).norm() / b.double().norm())
+        line["mixed"] = {
+            "fr_time_to_tol_s": frm["ms_total"] / 1e3, "lr_time_to_tol_s": lrm["ms_total"] / 1e3,
+            "fr_outer_iters": frm["iters"], "lr_outer_iters": lrm["iters"], "lr_rank": lrm["rank"],
+            "fr_phi_vs_fp64_fr_rel_l2": nrm(frm["phi"], fr["phi"]),
+            "lr_phi_vs_fp64_lr_rel_l2": nrm(lrm["phi"], lr["phi"]),
+            "lr_phi_vs_fp64_fr_rel_l2": nrm(lrm["phi"], fr["phi"]),
+            "target_rel_l2": 1e-5,
+        }
     if not args.no_cpu_baseline and args.only == "step":
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_sweeps)
     plan.close()

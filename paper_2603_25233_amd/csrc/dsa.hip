@@ -71,36 +71,40 @@ namespace {
 using M4 = double[16];
 
 // Kronecker placement of a 2x2 matrix P acting on the x-degree (k = 2q + p)
-void put_p(double* B, const double P[2][2], double scale) {
+__host__ __device__ void put_p(double* B, const double P[2][2], double scale) {
   for (int q = 0; q < 2; ++q)
     for (int p = 0; p < 2; ++p)
       for (int pp = 0; pp < 2; ++pp) B[(2 * q + p) * 4 + (2 * q + pp)] += scale * P[p][pp];
 }
 // ... acting on the y-degree
-void put_q(double* B, const double Q[2][2], double scale) {
+__host__ __device__ void put_q(double* B, const double Q[2][2], double scale) {
   for (int p = 0; p < 2; ++p)
     for (int q = 0; q < 2; ++q)
       for (int qq = 0; qq < 2; ++qq) B[(2 * q + p) * 4 + (2 * qq + p)] += scale * Q[q][qq];
 }
 
 // P = k jX jY^T + jX aY^T + aX jY^T
-void face2(double P[2][2], double k, const double jX[2], const double jY[2], const double aX[2],
+__host__ __device__ void face2(double P[2][2], double k, const double jX[2], const double jY[2], const double aX[2],
            const double aY[2]) {
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) P[i][j] = k * jX[i] * jY[j] + jX[i] * aY[j] + aX[i] * jY[j];
 }
 
-bool inv4(const double* A, double* out) {
+__host__ __device__ bool inv4(const double* A, double* out) {
   double m[4][8];
   for (int i = 0; i < 4; ++i)
     for (int j = 0; j < 8; ++j) m[i][j] = j < 4 ? A[4 * i + j] : (j - 4 == i ? 1.0 : 0.0);
   for (int c = 0; c < 4; ++c) {
     int piv = c;
     for (int i = c + 1; i < 4; ++i)
-      if (std::fabs(m[i][c]) > std::fabs(m[piv][c])) piv = i;
+      if (fabs(m[i][c]) > fabs(m[piv][c])) piv = i;
     if (m[piv][c] == 0.0) return false;
     if (piv != c)
-      for (int j = 0; j < 8; ++j) std::swap(m[c][j], m[piv][j]);
+      for (int j = 0; j < 8; ++j) {
+        const double t = m[c][j];
+        m[c][j] = m[piv][j];
+        m[piv][j] = t;
+      }
     const double iv = 1.0 / m[c][c];
     for (int j = 0; j < 8; ++j) m[c][j] *= iv;
     for (int i = 0; i < 4; ++i)
@@ -563,7 +567,220 @@ __global__ __launch_bounds__(256) void init_r_kernel(
 // clears the done flag before the first application of the preconditioner
 __global__ void clear_done_kernel(double* sc) { sc[S_DONE] = 0.0; }
 
-// ------------------------------------------------------------ multigrid setup (host)
+// One thread per cell: the diagonal block, the couplings to the right and top neighbours
+// (zero on the boundary) and the inverse diagonal block, in closed form.  bad[0] = 1 if
+// a diagonal block is singular.
+__global__ __launch_bounds__(256) void dsa_blocks_kernel(int nx, int ny, double hx, double hy,
+                                                        const double* __restrict__ sigma_t,
+                                                        const double* __restrict__ sigma_s,
+                                                        double* __restrict__ diag,
+                                                        double* __restrict__ ax,
+                                                        double* __restrict__ ay,
+                                                        double* __restrict__ minv,
+                                                        int* __restrict__ bad) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (long)nx * ny) return;
+  const int a = (int)(c % nx), b = (int)(c / nx);
+  const double r3 = sqrt(3.0);
+  const double eRx[2] = {1 / sqrt(hx), r3 / sqrt(hx)};
+  const double eLx[2] = {1 / sqrt(hx), -r3 / sqrt(hx)};
+  const double dx[2] = {0.0, 2.0 * r3 / (hx * sqrt(hx))};
+  const double eRy[2] = {1 / sqrt(hy), r3 / sqrt(hy)};
+  const double eLy[2] = {1 / sqrt(hy), -r3 / sqrt(hy)};
+  const double dy[2] = {0.0, 2.0 * r3 / (hy * sqrt(hy))};
+  auto Dc = [&](long cc) { return 1.0 / (3.0 * sigma_t[cc]); };
+  double B[16], AX[16], AY[16];
+  for (int k = 0; k < 16; ++k) B[k] = AX[k] = AY[k] = 0.0;
+  const double D = Dc(c), sa = sigma_t[c] - sigma_s[c];
+  // volume: D (12/hx^2 on p = 1, 12/hy^2 on q = 1) + sigma_a I
+  for (int k = 0; k < 4; ++k) {
+    const int p = k & 1, q = k >> 1;
+    B[5 * k] += sa + D * (p ? 12.0 / (hx * hx) : 0.0) + D * (q ? 12.0 / (hy * hy) : 0.0);
+  }
+  double P[2][2];
+  // x faces: this cell is "-" of its right face and "+" of its left face
+  for (int side = 0; side < 2; ++side) {
+    const bool right = side == 1;
+    const int an = right ? a + 1 : a - 1;
+    const double* e = right ? eRx : eLx;
+    if (an >= 0 && an < nx) {
+      const long cn = (long)b * nx + an;
+      const double Dn = Dc(cn);
+      const double kap = fmax(0.25, 0.5 * kCip * (D / hx + Dn / hx));
+      // jump and average seen from this cell
+      double j[2], av[2];
+      for (int i = 0; i < 2; ++i) {
+        j[i] = right ? -e[i] : e[i];
+        av[i] = 0.5 * D * dx[i];
+      }
+      face2(P, kap, j, j, av, av);
+      put_p(B, P, 1.0);
+      if (right) {  // coupling (test here, trial in the right neighbour)
+        double jn[2], an2[2];
+        for (int i = 0; i < 2; ++i) {
+          jn[i] = eLx[i];
+          an2[i] = 0.5 * Dn * dx[i];
+        }
+        face2(P, kap, j, jn, av, an2);
+        put_p(AX, P, 1.0);
+      }
+    } else {
+      const double kap = fmax(0.25, kCip * D / hx);
+      double dn[2];
+      for (int i = 0; i < 2; ++i) dn[i] = (right ? 1.0 : -1.0) * D * dx[i];
+      for (int i = 0; i < 2; ++i)
+        for (int jj = 0; jj < 2; ++jj)
+          P[i][jj] = kap * e[i] * e[jj] - 0.5 * e[i] * dn[jj] - 0.5 * dn[i] * e[jj];
+      put_p(B, P, 1.0);
+    }
+  }
+  // y faces
+  for (int side = 0; side < 2; ++side) {
+    const bool top = side == 1;
+    const int bn = top ? b + 1 : b - 1;
+    const double* e = top ? eRy : eLy;
+    if (bn >= 0 && bn < ny) {
+      const long cn = (long)bn * nx + a;
+      const double Dn = Dc(cn);
+      const double kap = fmax(0.25, 0.5 * kCip * (D / hy + Dn / hy));
+      double j[2], av[2];
+      for (int i = 0; i < 2; ++i) {
+        j[i] = top ? -e[i] : e[i];
+        av[i] = 0.5 * D * dy[i];
+      }
+      face2(P, kap, j, j, av, av);
+      put_q(B, P, 1.0);
+      if (top) {
+        double jn[2], an2[2];
+        for (int i = 0; i < 2; ++i) {
+          jn[i] = eLy[i];
+          an2[i] = 0.5 * Dn * dy[i];
+        }
+        face2(P, kap, j, jn, av, an2);
+        put_q(AY, P, 1.0);
+      }
+    } else {
+      const double kap = fmax(0.25, kCip * D / hy);
+      double dn[2];
+      for (int i = 0; i < 2; ++i) dn[i] = (top ? 1.0 : -1.0) * D * dy[i];
+      for (int i = 0; i < 2; ++i)
+        for (int jj = 0; jj < 2; ++jj)
+          P[i][jj] = kap * e[i] * e[jj] - 0.5 * e[i] * dn[jj] - 0.5 * dn[i] * e[jj];
+      put_q(B, P, 1.0);
+    }
+  }
+  double Mi[16];
+  if (!inv4(B, Mi)) atomicOr(bad, 1);
+  for (int k = 0; k < 16; ++k) {
+    diag[16 * c + k] = B[k];
+    ax[16 * c + k] = AX[k];
+    ay[16 * c + k] = AY[k];
+    minv[16 * c + k] = Mi[k];
+  }
+}
+
+// Row of P^T A P at node (i, j) of the (nx + 1) x (ny + 1) nodal grid: the blocks whose
+// test cell has the node as a corner (the diagonal blocks of the up to four cells around
+// it and their couplings to the left / right / lower / upper neighbours), each projected
+// on the bilinear corner functions.  Couplings of nodes two apart vanish for continuous
+// functions and are not stored.  Fixed summation order.
+__global__ __launch_bounds__(256) void mg_fine_kernel(int nx, int ny, Emb em,
+                                                     const double* __restrict__ diag,
+                                                     const double* __restrict__ ax,
+                                                     const double* __restrict__ ay,
+                                                     double* __restrict__ A9) {
+  const int mx = nx + 1, my = ny + 1;
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= (long)mx * my) return;
+  const int i = (int)(n % mx), j = (int)(n / mx);
+  double row[9];
+  for (int k = 0; k < 9; ++k) row[k] = 0.0;
+  // block B (or B^T) between test cell (a, b), corner (mi, mj) = node, and trial cell (a2, b2)
+  auto add = [&](const double* B, bool tr, int mi, int mj, int a2, int b2) {
+    for (int mm = 0; mm < 4; ++mm) {
+      const int di = a2 + (mm & 1) - i, dj = b2 + (mm >> 1) - j;
+      if (di < -1 || di > 1 || dj < -1 || dj > 1) continue;
+      double v = 0.0;
+      for (int k = 0; k < 4; ++k) {
+        const double wk = em.w(k, mi, mj);
+        for (int kk = 0; kk < 4; ++kk)
+          v += wk * (tr ? B[4 * kk + k] : B[4 * k + kk]) * em.w(kk, mm & 1, mm >> 1);
+      }
+      row[(dj + 1) * 3 + di + 1] += v;
+    }
+  };
+  for (int cb = 0; cb < 2; ++cb) {
+    const int b = j - 1 + cb;
+    if (b < 0 || b >= ny) continue;
+    for (int ca = 0; ca < 2; ++ca) {
+      const int a = i - 1 + ca;
+      if (a < 0 || a >= nx) continue;
+      const long c = (long)b * nx + a;
+      const int mi = i - a, mj = j - b;
+      add(diag + 16 * c, false, mi, mj, a, b);
+      if (a + 1 < nx) add(ax + 16 * c, false, mi, mj, a + 1, b);
+      if (a > 0) add(ax + 16 * (c - 1), true, mi, mj, a - 1, b);
+      if (b + 1 < ny) add(ay + 16 * c, false, mi, mj, a, b + 1);
+      if (b > 0) add(ay + 16 * (c - nx), true, mi, mj, a, b - 1);
+    }
+  }
+  for (int k = 0; k < 9; ++k) A9[9 * n + k] = row[k];
+}
+
+// Galerkin coarse operator R A P at coarse node (I, J): bilinear interpolation (fine
+// node 2I <-> coarse I, weight 1/2 to the two coarse neighbours of an odd fine node),
+// gathered over the 3 x 3 fine nodes that interpolate from (I, J).
+__global__ __launch_bounds__(256) void mg_rap_kernel(int mx, int my,
+                                                    const double* __restrict__ Af, int mxc,
+                                                    int myc, double* __restrict__ Ac) {
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= (long)mxc * myc) return;
+  const int I = (int)(n % mxc), J = (int)(n / mxc);
+  double row[9];
+  for (int k = 0; k < 9; ++k) row[k] = 0.0;
+  for (int fj = -1; fj <= 1; ++fj) {
+    const int j = 2 * J + fj;
+    if (j < 0 || j >= my) continue;
+    for (int fi = -1; fi <= 1; ++fi) {
+      const int i = 2 * I + fi;
+      if (i < 0 || i >= mx) continue;
+      const double wi = (fi ? 0.5 : 1.0) * (fj ? 0.5 : 1.0);  // P[(i, j)][(I, J)]
+      const double* a = Af + 9 * ((long)j * mx + i);
+      for (int dj = -1; dj <= 1; ++dj) {
+        const int j2 = j + dj;
+        if (j2 < 0 || j2 >= my) continue;
+        for (int di = -1; di <= 1; ++di) {
+          const int i2 = i + di;
+          if (i2 < 0 || i2 >= mx) continue;
+          const double v = wi * a[(dj + 1) * 3 + di + 1];
+          // coarse parents of (i2, j2)
+          const int i0 = i2 >> 1, i1 = (i2 + 1) >> 1, j0 = j2 >> 1, j1 = (j2 + 1) >> 1;
+          const double wx = i0 == i1 ? 1.0 : 0.5, wy = j0 == j1 ? 1.0 : 0.5;
+          for (int pj = 0; pj < (j0 == j1 ? 1 : 2); ++pj)
+            for (int pi = 0; pi < (i0 == i1 ? 1 : 2); ++pi) {
+              const int oi = (pi ? i1 : i0) - I, oj = (pj ? j1 : j0) - J;
+              row[(oj + 1) * 3 + oi + 1] += v * wx * wy;
+            }
+        }
+      }
+    }
+  }
+  for (int k = 0; k < 9; ++k) Ac[9 * n + k] = row[k];
+}
+
+// l1-Jacobi: dinv = 1 / (a_ii + sum_{j != i} |a_ij|); bad |= 2 for a non-positive diagonal
+__global__ __launch_bounds__(256) void mg_dinv_kernel(long n, const double* __restrict__ A9,
+                                                     double* __restrict__ dinv,
+                                                     int* __restrict__ bad) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < 9; ++k) s += k == 4 ? A9[9 * i + k] : fabs(A9[9 * i + k]);
+  if (!(A9[9 * i + 4] > 0.0) || !(s > 0.0)) atomicOr(bad, 2);
+  dinv[i] = s > 0.0 ? 1.0 / s : 0.0;
+}
+
+// ------------------------------------------------------------ set-up
 constexpr int kCoarseDense = 100;  // largest grid solved by its dense inverse
 constexpr int kCoarseSweeps = 20;  // l1-Jacobi sweeps on a coarsest grid that is larger
 
@@ -573,304 +790,147 @@ Emb embedding(const Geom& g) {
              std::sqrt(g.hy) / (2 * r3)};
 }
 
-// Galerkin coarse operator R A P for bilinear P (vertex-centred, fine node 2I <-> coarse I)
-std::vector<double> galerkin_coarse(const std::vector<double>& A, int mx, int my, int mxc, int myc) {
-  std::vector<double> Ac((size_t)9 * mxc * myc, 0.0);
-  auto parents = [](int i, int* I, double* w) {
-    if ((i & 1) == 0) {
-      I[0] = i / 2;
-      w[0] = 1.0;
-      return 1;
-    }
-    I[0] = (i - 1) / 2;
-    I[1] = (i + 1) / 2;
-    w[0] = w[1] = 0.5;
-    return 2;
-  };
+unsigned nblocks(long n) { return (unsigned)((n + 255) / 256); }
+
+// Dense inverse of the coarsest operator (Cholesky, then the inverse column by column),
+// symmetrised so that the device can read columns as rows.
+std::vector<double> coarse_inverse(const std::vector<double>& A, int mx, int my) {
+  const int nc = mx * my;
+  std::vector<double> M((size_t)nc * nc, 0.0);
   for (int j = 0; j < my; ++j)
-    for (int i = 0; i < mx; ++i) {
-      int Ia[2], Ja[2];
-      double wIa[2], wJa[2];
-      const int nI = parents(i, Ia, wIa), nJ = parents(j, Ja, wJa);
-      const double* a = &A[9 * ((size_t)j * mx + i)];
+    for (int i = 0; i < mx; ++i)
       for (int dj = -1; dj <= 1; ++dj)
         for (int di = -1; di <= 1; ++di) {
-          const double v = a[(dj + 1) * 3 + di + 1];
           const int i2 = i + di, j2 = j + dj;
-          if (v == 0.0 || i2 < 0 || i2 >= mx || j2 < 0 || j2 >= my) continue;
-          int Ib[2], Jb[2];
-          double wIb[2], wJb[2];
-          const int nI2 = parents(i2, Ib, wIb), nJ2 = parents(j2, Jb, wJb);
-          for (int u = 0; u < nJ; ++u)
-            for (int t = 0; t < nI; ++t)
-              for (int u2 = 0; u2 < nJ2; ++u2)
-                for (int t2 = 0; t2 < nI2; ++t2) {
-                  const int oi = Ib[t2] - Ia[t], oj = Jb[u2] - Ja[u];
-                  Ac[9 * ((size_t)Ja[u] * mxc + Ia[t]) + (oj + 1) * 3 + oi + 1] +=
-                      wJa[u] * wIa[t] * v * wJb[u2] * wIb[t2];
-                }
+          if (i2 < 0 || i2 >= mx || j2 < 0 || j2 >= my) continue;
+          M[(size_t)(j * mx + i) * nc + j2 * mx + i2] = A[9 * ((size_t)j * mx + i) + (dj + 1) * 3 + di + 1];
         }
+  for (int i = 0; i < nc; ++i)  // the assembled entries agree to rounding
+    for (int j = 0; j < i; ++j) {
+      const double v = 0.5 * (M[(size_t)i * nc + j] + M[(size_t)j * nc + i]);
+      M[(size_t)i * nc + j] = M[(size_t)j * nc + i] = v;
     }
-  return Ac;
-}
-
-void upload(DevBuf<double>& b, const std::vector<double>& h) {
-  b.alloc(h.size());
-  RTE_CHECK_HIP(hipMemcpy(b.get(), h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
-}
-
-void build_multigrid(DSA* d, const std::vector<double>& diag, const std::vector<double>& ax,
-                     const std::vector<double>& ay) {
-  const Geom& g = d->g;
-  const Emb em = embedding(g);
-  const int nx = g.nx, ny = g.ny, mx0 = nx + 1, my0 = ny + 1;
-  // P^T A P on the nodes: per block (test cell c1, trial cell c2) the 4 x 4 corner matrix
-  // P^T B P; couplings of corners two nodes apart vanish for continuous functions and
-  // are dropped.
-  std::vector<double> A0((size_t)9 * mx0 * my0, 0.0);
-  auto add = [&](int a1, int b1, int a2, int b2, const double* B, bool tr) {
-    for (int m = 0; m < 4; ++m)
-      for (int mm = 0; mm < 4; ++mm) {
-        const int i1 = a1 + (m & 1), j1 = b1 + (m >> 1), i2 = a2 + (mm & 1), j2 = b2 + (mm >> 1);
-        const int di = i2 - i1, dj = j2 - j1;
-        if (di < -1 || di > 1 || dj < -1 || dj > 1) continue;
-        double v = 0.0;
-        for (int k = 0; k < 4; ++k)
-          for (int kk = 0; kk < 4; ++kk)
-            v += em.w(k, m & 1, m >> 1) * (tr ? B[4 * kk + k] : B[4 * k + kk]) *
-                 em.w(kk, mm & 1, mm >> 1);
-        A0[9 * ((size_t)j1 * mx0 + i1) + (dj + 1) * 3 + di + 1] += v;
-      }
-  };
-  for (int b = 0; b < ny; ++b)
-    for (int a = 0; a < nx; ++a) {
-      const long c = (long)b * nx + a;
-      add(a, b, a, b, &diag[16 * c], false);
-      if (a + 1 < nx) {
-        add(a, b, a + 1, b, &ax[16 * c], false);
-        add(a + 1, b, a, b, &ax[16 * c], true);
-      }
-      if (b + 1 < ny) {
-        add(a, b, a, b + 1, &ay[16 * c], false);
-        add(a, b + 1, a, b, &ay[16 * c], true);
-      }
+  std::vector<double> L((size_t)nc * nc, 0.0);
+  for (int j = 0; j < nc; ++j) {
+    double sjj = M[(size_t)j * nc + j];
+    for (int k = 0; k < j; ++k) sjj -= L[(size_t)j * nc + k] * L[(size_t)j * nc + k];
+    RTE_REQUIRE(sjj > 0.0, "DSA: coarse operator not positive definite");
+    const double ljj = std::sqrt(sjj);
+    L[(size_t)j * nc + j] = ljj;
+    for (int i = j + 1; i < nc; ++i) {
+      double t = M[(size_t)i * nc + j];
+      for (int k = 0; k < j; ++k) t -= L[(size_t)i * nc + k] * L[(size_t)j * nc + k];
+      L[(size_t)i * nc + j] = t / ljj;
     }
-  std::vector<std::vector<double>> As{std::move(A0)};
-  std::vector<std::pair<int, int>> dims{{mx0, my0}};
-  while (true) {
-    const int mx = dims.back().first, my = dims.back().second;
-    if ((long)mx * my <= kCoarseDense) break;
-    if ((mx - 1) % 2 || (my - 1) % 2 || mx < 5 || my < 5) break;
-    const int mxc = (mx + 1) / 2, myc = (my + 1) / 2;
-    As.push_back(galerkin_coarse(As.back(), mx, my, mxc, myc));
-    dims.push_back({mxc, myc});
   }
-  for (size_t l = 0; l < As.size(); ++l) {
-    d->mg.push_back(std::make_unique<MgLevel>());
-    MgLevel& L = *d->mg[l];
-    L.mx = dims[l].first;
-    L.my = dims[l].second;
-    const size_t n = (size_t)L.mx * L.my;
-    std::vector<double> dinv(n);
-    for (size_t i = 0; i < n; ++i) {
-      double s = 0.0;
-      for (int k = 0; k < 9; ++k) s += k == 4 ? As[l][9 * i + k] : std::fabs(As[l][9 * i + k]);
-      RTE_REQUIRE(As[l][9 * i + 4] > 0.0 && s > 0.0, "DSA: non-positive coarse diagonal");
-      dinv[i] = 1.0 / s;
+  std::vector<double> inv((size_t)nc * nc), y(nc);
+  for (int e = 0; e < nc; ++e) {
+    for (int i = 0; i < nc; ++i) {  // L y = e_e
+      double t = i == e ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) t -= L[(size_t)i * nc + k] * y[k];
+      y[i] = t / L[(size_t)i * nc + i];
     }
-    upload(L.A9, As[l]);
-    upload(L.dinv, dinv);
-    L.x.alloc(n);
-    L.b.alloc(n);
-    L.t.alloc(n);
+    for (int i = nc - 1; i >= 0; --i) {  // L^T x = y
+      double t = y[i];
+      for (int k = i + 1; k < nc; ++k) t -= L[(size_t)k * nc + i] * inv[(size_t)k * nc + e];
+      inv[(size_t)i * nc + e] = t / L[(size_t)i * nc + i];
+    }
   }
-  // dense inverse on the coarsest grid (Cholesky, then the inverse column by column)
-  const MgLevel& Lc = *d->mg.back();
-  const int nc = Lc.mx * Lc.my;
-  d->ncoarse = 0;
-  if (nc <= kCoarseDense) {
-    const std::vector<double>& A = As.back();
-    std::vector<double> M((size_t)nc * nc, 0.0);
-    for (int j = 0; j < Lc.my; ++j)
-      for (int i = 0; i < Lc.mx; ++i)
-        for (int dj = -1; dj <= 1; ++dj)
-          for (int di = -1; di <= 1; ++di) {
-            const int i2 = i + di, j2 = j + dj;
-            if (i2 < 0 || i2 >= Lc.mx || j2 < 0 || j2 >= Lc.my) continue;
-            M[(size_t)(j * Lc.mx + i) * nc + j2 * Lc.mx + i2] =
-                A[9 * ((size_t)j * Lc.mx + i) + (dj + 1) * 3 + di + 1];
-          }
-    // symmetrise (the assembled entries agree to rounding)
-    for (int i = 0; i < nc; ++i)
-      for (int j = 0; j < i; ++j) {
-        const double v = 0.5 * (M[(size_t)i * nc + j] + M[(size_t)j * nc + i]);
-        M[(size_t)i * nc + j] = M[(size_t)j * nc + i] = v;
-      }
-    std::vector<double> L((size_t)nc * nc, 0.0);  // lower Cholesky factor
-    for (int j = 0; j < nc; ++j) {
-      double s = M[(size_t)j * nc + j];
-      for (int k = 0; k < j; ++k) s -= L[(size_t)j * nc + k] * L[(size_t)j * nc + k];
-      RTE_REQUIRE(s > 0.0, "DSA: coarse operator not positive definite");
-      const double ljj = std::sqrt(s);
-      L[(size_t)j * nc + j] = ljj;
-      for (int i = j + 1; i < nc; ++i) {
-        double t = M[(size_t)i * nc + j];
-        for (int k = 0; k < j; ++k) t -= L[(size_t)i * nc + k] * L[(size_t)j * nc + k];
-        L[(size_t)i * nc + j] = t / ljj;
-      }
+  for (int i = 0; i < nc; ++i)
+    for (int j = 0; j < i; ++j) {
+      const double v = 0.5 * (inv[(size_t)i * nc + j] + inv[(size_t)j * nc + i]);
+      inv[(size_t)i * nc + j] = inv[(size_t)j * nc + i] = v;
     }
-    std::vector<double> inv((size_t)nc * nc), y(nc);
-    for (int e = 0; e < nc; ++e) {
-      for (int i = 0; i < nc; ++i) {  // L y = e_e
-        double t = i == e ? 1.0 : 0.0;
-        for (int k = 0; k < i; ++k) t -= L[(size_t)i * nc + k] * y[k];
-        y[i] = t / L[(size_t)i * nc + i];
-      }
-      for (int i = nc - 1; i >= 0; --i) {  // L^T x = y
-        double t = y[i];
-        for (int k = i + 1; k < nc; ++k) t -= L[(size_t)k * nc + i] * inv[(size_t)k * nc + e];
-        inv[(size_t)i * nc + e] = t / L[(size_t)i * nc + i];
-      }
-    }
-    for (int i = 0; i < nc; ++i)  // exact symmetry for the column reads on the device
-      for (int j = 0; j < i; ++j) {
-        const double v = 0.5 * (inv[(size_t)i * nc + j] + inv[(size_t)j * nc + i]);
-        inv[(size_t)i * nc + j] = inv[(size_t)j * nc + i] = v;
-      }
-    upload(d->cinv, inv);
-    d->ncoarse = nc;
-  }
-  // the one-workgroup cycle takes over from the first level that is small enough
-  d->lsmall = (int)d->mg.size() - 1;
-  while (d->lsmall > 0 && (long)d->mg[d->lsmall - 1]->mx * d->mg[d->lsmall - 1]->my <= kSmallNodes)
-    --d->lsmall;
-  std::vector<MgDev> views;
-  for (auto& L : d->mg)
-    views.push_back(MgDev{L->mx, L->my, L->A9.get(), L->dinv.get(), L->x.get(), L->b.get(), L->t.get()});
-  d->mgdev.alloc(views.size());
-  RTE_CHECK_HIP(hipMemcpy(d->mgdev.get(), views.data(), views.size() * sizeof(MgDev),
-                          hipMemcpyHostToDevice));
+  return inv;
 }
 
 }  // namespace
 
+// The blocks, the nodal hierarchy and its smoothers are assembled on the device; only
+// the coarsest grid (at most kCoarseDense nodes) is inverted on the host.
 DSA* dsa_create(const Geom& g, const double* sigma_t_dev, const double* sigma_s_dev,
                 hipStream_t st) {
   DSA* d = new DSA();
   try {
     d->g = g;
     const long n = g.ncell;
-    std::vector<double> st_h(n), ss_h(n);
-    RTE_CHECK_HIP(hipMemcpy(st_h.data(), sigma_t_dev, n * sizeof(double), hipMemcpyDeviceToHost));
-    RTE_CHECK_HIP(hipMemcpy(ss_h.data(), sigma_s_dev, n * sizeof(double), hipMemcpyDeviceToHost));
-    std::vector<double> diag(16 * n, 0.0), ax(16 * n, 0.0), ay(16 * n, 0.0), minv(16 * n, 0.0);
-    const double hx = g.hx, hy = g.hy, r3 = std::sqrt(3.0);
-    const double eRx[2] = {1 / std::sqrt(hx), r3 / std::sqrt(hx)};
-    const double eLx[2] = {1 / std::sqrt(hx), -r3 / std::sqrt(hx)};
-    const double dx[2] = {0.0, 2.0 * r3 / (hx * std::sqrt(hx))};
-    const double eRy[2] = {1 / std::sqrt(hy), r3 / std::sqrt(hy)};
-    const double eLy[2] = {1 / std::sqrt(hy), -r3 / std::sqrt(hy)};
-    const double dy[2] = {0.0, 2.0 * r3 / (hy * std::sqrt(hy))};
-    auto Dc = [&](long c) { return 1.0 / (3.0 * st_h[c]); };
-    for (int b = 0; b < g.ny; ++b)
-      for (int a = 0; a < g.nx; ++a) {
-        const long c = (long)b * g.nx + a;
-        double* B = &diag[16 * c];
-        const double D = Dc(c), sa = st_h[c] - ss_h[c];
-        // volume: D (12/hx^2 on p = 1, 12/hy^2 on q = 1) + sigma_a I
-        for (int k = 0; k < 4; ++k) {
-          const int p = k & 1, q = k >> 1;
-          B[5 * k] += sa + D * (p ? 12.0 / (hx * hx) : 0.0) + D * (q ? 12.0 / (hy * hy) : 0.0);
-        }
-        double P[2][2];
-        // x faces: this cell is "-" of its right face and "+" of its left face
-        for (int side = 0; side < 2; ++side) {
-          const bool right = side == 1;
-          const int an = right ? a + 1 : a - 1;
-          const double* e = right ? eRx : eLx;
-          if (an >= 0 && an < g.nx) {
-            const long cn = (long)b * g.nx + an;
-            const double Dn = Dc(cn);
-            const double kap = std::max(0.25, 0.5 * kCip * (D / hx + Dn / hx));
-            // jump and average seen from this cell
-            double j[2], av[2];
-            for (int i = 0; i < 2; ++i) {
-              j[i] = right ? -e[i] : e[i];
-              av[i] = 0.5 * D * dx[i];
-            }
-            face2(P, kap, j, j, av, av);
-            put_p(B, P, 1.0);
-            if (right) {  // coupling (test here, trial in the right neighbour)
-              double jn[2], an2[2];
-              for (int i = 0; i < 2; ++i) {
-                jn[i] = eLx[i];
-                an2[i] = 0.5 * Dn * dx[i];
-              }
-              face2(P, kap, j, jn, av, an2);
-              put_p(&ax[16 * c], P, 1.0);
-            }
-          } else {
-            const double kap = std::max(0.25, kCip * D / hx);
-            double dn[2];
-            for (int i = 0; i < 2; ++i) dn[i] = (right ? 1.0 : -1.0) * D * dx[i];
-            for (int i = 0; i < 2; ++i)
-              for (int jj = 0; jj < 2; ++jj)
-                P[i][jj] = kap * e[i] * e[jj] - 0.5 * e[i] * dn[jj] - 0.5 * dn[i] * e[jj];
-            put_p(B, P, 1.0);
-          }
-        }
-        // y faces
-        for (int side = 0; side < 2; ++side) {
-          const bool top = side == 1;
-          const int bn = top ? b + 1 : b - 1;
-          const double* e = top ? eRy : eLy;
-          if (bn >= 0 && bn < g.ny) {
-            const long cn = (long)bn * g.nx + a;
-            const double Dn = Dc(cn);
-            const double kap = std::max(0.25, 0.5 * kCip * (D / hy + Dn / hy));
-            double j[2], av[2];
-            for (int i = 0; i < 2; ++i) {
-              j[i] = top ? -e[i] : e[i];
-              av[i] = 0.5 * D * dy[i];
-            }
-            face2(P, kap, j, j, av, av);
-            put_q(B, P, 1.0);
-            if (top) {
-              double jn[2], an2[2];
-              for (int i = 0; i < 2; ++i) {
-                jn[i] = eLy[i];
-                an2[i] = 0.5 * Dn * dy[i];
-              }
-              face2(P, kap, j, jn, av, an2);
-              put_q(&ay[16 * c], P, 1.0);
-            }
-          } else {
-            const double kap = std::max(0.25, kCip * D / hy);
-            double dn[2];
-            for (int i = 0; i < 2; ++i) dn[i] = (top ? 1.0 : -1.0) * D * dy[i];
-            for (int i = 0; i < 2; ++i)
-              for (int jj = 0; jj < 2; ++jj)
-                P[i][jj] = kap * e[i] * e[jj] - 0.5 * e[i] * dn[jj] - 0.5 * dn[i] * e[jj];
-            put_q(B, P, 1.0);
-          }
-        }
-        RTE_REQUIRE(inv4(B, &minv[16 * c]), "DSA: singular diagonal block at cell %ld", c);
-      }
-    build_multigrid(d, diag, ax, ay);
+    DevBuf<int> bad(1);
+    RTE_CHECK_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), st));
     d->diag.alloc(16 * n); d->ax.alloc(16 * n); d->ay.alloc(16 * n); d->minv.alloc(16 * n);
-    RTE_CHECK_HIP(hipMemcpy(d->diag.get(), diag.data(), 16 * n * sizeof(double), hipMemcpyHostToDevice));
-    RTE_CHECK_HIP(hipMemcpy(d->ax.get(), ax.data(), 16 * n * sizeof(double), hipMemcpyHostToDevice));
-    RTE_CHECK_HIP(hipMemcpy(d->ay.get(), ay.data(), 16 * n * sizeof(double), hipMemcpyHostToDevice));
-    RTE_CHECK_HIP(hipMemcpy(d->minv.get(), minv.data(), 16 * n * sizeof(double), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(dsa_blocks_kernel, dim3(nblocks(n)), dim3(256), 0, st, g.nx, g.ny, g.hx,
+                       g.hy, sigma_t_dev, sigma_s_dev, d->diag.get(), d->ax.get(), d->ay.get(),
+                       d->minv.get(), bad.get());
+    // grid hierarchy: vertex-centred halving while both node counts allow it
+    std::vector<std::pair<int, int>> dims{{g.nx + 1, g.ny + 1}};
+    while (true) {
+      const int mx = dims.back().first, my = dims.back().second;
+      if ((long)mx * my <= kCoarseDense) break;
+      if ((mx - 1) % 2 || (my - 1) % 2 || mx < 5 || my < 5) break;
+      dims.push_back({(mx + 1) / 2, (my + 1) / 2});
+    }
+    for (size_t l = 0; l < dims.size(); ++l) {
+      d->mg.push_back(std::make_unique<MgLevel>());
+      MgLevel& L = *d->mg[l];
+      L.mx = dims[l].first;
+      L.my = dims[l].second;
+      const long nn = (long)L.mx * L.my;
+      L.A9.alloc(9 * nn);
+      L.dinv.alloc(nn);
+      L.x.alloc(nn);
+      L.b.alloc(nn);
+      L.t.alloc(nn);
+      if (l == 0)
+        hipLaunchKernelGGL(mg_fine_kernel, dim3(nblocks(nn)), dim3(256), 0, st, g.nx, g.ny,
+                           embedding(g), d->diag.get(), d->ax.get(), d->ay.get(), L.A9.get());
+      else {
+        const MgLevel& F = *d->mg[l - 1];
+        hipLaunchKernelGGL(mg_rap_kernel, dim3(nblocks(nn)), dim3(256), 0, st, F.mx, F.my,
+                           F.A9.get(), L.mx, L.my, L.A9.get());
+      }
+      hipLaunchKernelGGL(mg_dinv_kernel, dim3(nblocks(nn)), dim3(256), 0, st, nn, L.A9.get(),
+                         L.dinv.get(), bad.get());
+      RTE_CHECK_HIP(hipGetLastError());
+    }
+    const MgLevel& Lc = *d->mg.back();
+    const int nc = Lc.mx * Lc.my;
+    std::vector<double> Ac;
+    if (nc <= kCoarseDense) {
+      Ac.resize((size_t)9 * nc);
+      RTE_CHECK_HIP(hipMemcpyAsync(Ac.data(), Lc.A9.get(), Ac.size() * sizeof(double),
+                                   hipMemcpyDeviceToHost, st));
+    }
+    int hbad = 0;
+    RTE_CHECK_HIP(hipMemcpyAsync(&hbad, bad.get(), sizeof(int), hipMemcpyDeviceToHost, st));
+    RTE_CHECK_HIP(hipStreamSynchronize(st));
+    RTE_REQUIRE(!(hbad & 1), "DSA: singular diagonal block");
+    RTE_REQUIRE(!(hbad & 2), "DSA: non-positive diagonal in the multigrid hierarchy");
+    d->ncoarse = 0;
+    if (nc <= kCoarseDense) {
+      const std::vector<double> inv = coarse_inverse(Ac, Lc.mx, Lc.my);
+      d->cinv.alloc(inv.size());
+      RTE_CHECK_HIP(hipMemcpy(d->cinv.get(), inv.data(), inv.size() * sizeof(double),
+                              hipMemcpyHostToDevice));
+      d->ncoarse = nc;
+    }
+    // the one-workgroup cycle takes over from the first level that is small enough
+    d->lsmall = (int)d->mg.size() - 1;
+    while (d->lsmall > 0 && (long)d->mg[d->lsmall - 1]->mx * d->mg[d->lsmall - 1]->my <= kSmallNodes)
+      --d->lsmall;
+    std::vector<MgDev> views;
+    for (auto& L : d->mg)
+      views.push_back(MgDev{L->mx, L->my, L->A9.get(), L->dinv.get(), L->x.get(), L->b.get(), L->t.get()});
+    d->mgdev.alloc(views.size());
+    RTE_CHECK_HIP(hipMemcpy(d->mgdev.get(), views.data(), views.size() * sizeof(MgDev),
+                            hipMemcpyHostToDevice));
     d->sig_s.alloc(n);
-    RTE_CHECK_HIP(hipMemcpy(d->sig_s.get(), sigma_s_dev, n * sizeof(double), hipMemcpyDeviceToDevice));
+    RTE_CHECK_HIP(hipMemcpyAsync(d->sig_s.get(), sigma_s_dev, n * sizeof(double),
+                                 hipMemcpyDeviceToDevice, st));
     const long nd = g.ndof;
     d->x.alloc(nd); d->r.alloc(nd); d->z.alloc(nd); d->p0.alloc(nd); d->p1.alloc(nd); d->q.alloc(nd);
     d->nblk = (int)((n + 255) / 256);
     d->part1.alloc(d->nblk); d->part2.alloc(d->nblk);
     d->scal.alloc(S_N);
-    RTE_CHECK_HIP(hipMemset(d->scal.get(), 0, S_N * sizeof(double)));
-    (void)st;
+    RTE_CHECK_HIP(hipMemsetAsync(d->scal.get(), 0, S_N * sizeof(double), st));
     return d;
   } catch (...) {
     delete d;
@@ -881,8 +941,6 @@ DSA* dsa_create(const Geom& g, const double* sigma_t_dev, const double* sigma_s_
 void dsa_destroy(DSA* d) { delete d; }
 
 namespace {
-
-unsigned nblocks(long n) { return (unsigned)((n + 255) / 256); }
 
 // one V-cycle on level l (x = V b), two l1-Jacobi sweeps before and after
 void vcycle(DSA* d, int l, hipStream_t st) {
