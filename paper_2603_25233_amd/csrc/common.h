@@ -93,6 +93,7 @@ struct SweepPlan {
   int ring = 1;   // results leave through the LDS ring (else direct stores)
   int psi = 1;    // planned for psi output (else the scalar flux only)
   int qmask = 0;  // quadrants swept (bit q = (sx < 0) + 2 (sy < 0))
+  int srows = 256;  // rows of a step that each staging wavefront copies
 };
 // Plans for psi (want_psi) or for the scalar flux only; a psi plan also serves
 // calls that request both.

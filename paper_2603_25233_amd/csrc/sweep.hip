@@ -209,7 +209,8 @@ __global__ void diag_layout_kernel(int nx, int ny, int qmask, const double* __re
   }
 }
 
-// Rows of one step that each staging wavefront carries.
+// Rows of one step that a staging wavefront carries at most (plans may use fewer, with
+// more staging wavefronts, when the issue of the copies bounds the step).
 constexpr int kStageRows = 256;
 // Input slots in LDS: the staging wavefronts fill step t + 2 while step t is solved.
 constexpr int kInSlots = 3;
@@ -269,7 +270,7 @@ typedef __attribute__((address_space(3))) void lds_void;
 // in kChunkCells, plus the short end chunk of one row when nx is not a multiple of
 // kChunkCells and the sweep runs towards +x), so every store instruction writes whole
 // 128-byte lines.  Without the ring (LDS too small) each thread stores its cell.
-template <typename T, int D, int NTB, int RPT>
+template <typename T, int D, int NTB, int RPT, int SR>
 __global__ __launch_bounds__(NTB) void sweep_kernel(
     int nx, int ny, int mb, int nc, int use_ring, double shx, double shy,
     const SweepDir* __restrict__ dirs, const T* __restrict__ dsrc_all,
@@ -312,27 +313,37 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
     auto stage = [&](int t, int sl) {
       const int lo = t >= nx ? t - nx + 1 : 0;
       const int hi = t < ny ? t : ny - 1;
-      const int c0 = sw * kStageRows;   // first cell of this wavefront
+      const int c0 = sw * SR;            // first cell of this wavefront
       const int nce = hi - lo + 1 - c0;  // cells left for it
       int n = 0;
       if (nce > 0) {
-        const int ncw = nce < kStageRows ? nce : kStageRows;
+        const int ncw = nce < SR ? nce : SR;
         // source: ncw * CPC pieces
         const float4* gs = src16 + (diag_first(t, nx, ny) + c0) * CPC;
         float4* ls = reinterpret_cast<float4*>(in_src) + ((long)sl * nr + lo + c0) * CPC;
-        for (int i = 0; 64 * i < ncw * CPC; ++i, ++n)
-          if (64 * i + lane < ncw * CPC)
-            __builtin_amdgcn_global_load_lds((const void*)(gs + 64 * i + lane),
-                                             (lds_void*)(ls + 64 * i), 16, 0, 0);
+        constexpr int NIS = SR * CPC / 64;  // instructions for a full wavefront
+#pragma unroll
+        for (int i = 0; i < NIS; ++i)
+          if (64 * i < ncw * CPC) {
+            ++n;
+            if (64 * i + lane < ncw * CPC)
+              __builtin_amdgcn_global_load_lds((const void*)(gs + 64 * i + lane),
+                                               (lds_void*)(ls + 64 * i), 16, 0, 0);
+          }
         // sigma_t: ceil(ncw / CPS) pieces
         const int sh = (-lo) & (CPS - 1);
         const float4* gg = sig16 + (sig_first<T>(t, nx, ny) + c0) / CPS;
         float4* lg = reinterpret_cast<float4*>(in_sig + (long)sl * nrs + sh + lo + c0);
         const int npg = (ncw + CPS - 1) / CPS;
-        for (int i = 0; 64 * i < npg; ++i, ++n)
-          if (64 * i + lane < npg)
-            __builtin_amdgcn_global_load_lds((const void*)(gg + 64 * i + lane),
-                                             (lds_void*)(lg + 64 * i), 16, 0, 0);
+        constexpr int NIG = (SR / CPS + 63) / 64;
+#pragma unroll
+        for (int i = 0; i < NIG; ++i)
+          if (64 * i < npg) {
+            ++n;
+            if (64 * i + lane < npg)
+              __builtin_amdgcn_global_load_lds((const void*)(gg + 64 * i + lane),
+                                               (lds_void*)(lg + 64 * i), 16, 0, 0);
+          }
       }
       if (sw == 0) {  // the y-inflow piece of row 0
         if (lane == 0)
@@ -590,12 +601,16 @@ static size_t max_lds_per_block() {
   return (size_t)v;
 }
 
-// compute threads, rows per compute thread and staging wavefronts for ny rows (a
-// workgroup holds at most 1024 threads; a staging wavefront carries 256 rows)
-static void sweep_threads(int ny, int& nc, int& rpt, int& nst) {
+// compute threads, rows per compute thread and staging wavefronts for ny rows: a
+// staging wavefront carries srows rows, 64 (when requested and nc <= 256), 128 (when
+// requested and nc <= 640) or 256, so that the workgroup fits the kernels' thread counts
+// (960, or 768 with two rows per thread)
+static void sweep_threads(int ny, bool few_rows, int& nc, int& rpt, int& nst, int& srows) {
   rpt = ny <= 768 ? 1 : 2;
   nc = ((ny + rpt - 1) / rpt + 63) / 64 * 64;
-  nst = (nc * rpt + kStageRows - 1) / kStageRows;
+  srows = kStageRows;
+  if (few_rows && rpt == 1) srows = nc <= 256 ? 64 : (nc <= 640 ? 128 : kStageRows);
+  nst = (nc * rpt + srows - 1) / srows;
 }
 
 // LDS per workgroup that still lets two workgroups share a compute unit (160 KB)
@@ -607,11 +622,15 @@ SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool
   RTE_REQUIRE(g.nx >= 1 && g.nx <= 1 << 20, "sweep: nx = %d outside [1, 2^20]", g.nx);
   RTE_REQUIRE(!dirs.empty(), "sweep: no directions");
   SweepPlan pl;
-  int nc, rpt, nst;
-  sweep_threads(g.ny, nc, rpt, nst);
+  // Staging wavefronts: the issue of a step's copies bounds the step when few workgroups
+  // run (small plans) and for FP64 psi; there a wavefront copies 64 rows, else 256.
+  const bool small = dirs.size() < 64;
+  int nc, rpt, nst, srows;
+  sweep_threads(g.ny, small || (want_psi && elem_bytes == 8), nc, rpt, nst, srows);
   pl.nc = nc;
   pl.nt = nc + 64 * nst;
   pl.rpt = rpt;
+  pl.srows = srows;
   const int nr = nc * rpt;
   const size_t lmax = max_lds_per_block();
   const size_t lcap = std::min(lmax, kLdsTwoPerCU);
@@ -671,26 +690,39 @@ void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
   const size_t lds = sweep_lds_bytes(pl.nc * pl.rpt, pl.D, psi != nullptr, pl.ring != 0, sizeof(T));
   dim3 grid(pl.ngroups), block(pl.nt);
   T* pp = phi ? part : nullptr;
-#define RTE_SWEEP_CASE(DD, NTB, RP)                                                                \
-  hipLaunchKernelGGL((sweep_kernel<T, DD, NTB, RP>), grid, block, lds, st, g.nx, g.ny, g.mb, pl.nc, \
-                     pl.ring, shx, shy, dirs_dev, dsrc, dsig, dbnd, bc, psi, pp, g.ndof)
+#define RTE_SWEEP_CASE(DD, NTB, RP, SR)                                                        \
+  hipLaunchKernelGGL((sweep_kernel<T, DD, NTB, RP, SR>), grid, block, lds, st, g.nx, g.ny, g.mb,  \
+                     pl.nc, pl.ring, shx, shy, dirs_dev, dsrc, dsig, dbnd, bc, psi, pp, g.ndof)
   // FP64 plans use D = 2 only with at most 576 threads (register budget)
-#define RTE_SWEEP_D(NTB, RP)                                         \
-  if (pl.D == 1) RTE_SWEEP_CASE(1, NTB, RP);                         \
+#define RTE_SWEEP_D(NTB, RP, SR)                                     \
+  if (pl.D == 1) RTE_SWEEP_CASE(1, NTB, RP, SR);                     \
   else if constexpr (sizeof(T) == 8 && (NTB > 576 || RP > 1)) bad(); \
-  else if (pl.D == 2) RTE_SWEEP_CASE(2, NTB, RP);                    \
+  else if (pl.D == 2) RTE_SWEEP_CASE(2, NTB, RP, SR);                \
   else if constexpr (sizeof(T) == 8) bad();                          \
-  else RTE_SWEEP_CASE(4, NTB, RP);
+  else RTE_SWEEP_CASE(4, NTB, RP, SR);
   auto bad = [&] { RTE_REQUIRE(false, "sweep: no kernel for D = %d, %d threads", pl.D, pl.nt); };
   RTE_REQUIRE(pl.nt <= 1024, "sweep: %d threads", pl.nt);
   if (pl.rpt == 2) {
-    RTE_SWEEP_D(768, 2)
+    RTE_REQUIRE(pl.srows == 256, "internal: staging rows %d", pl.srows);
+    RTE_SWEEP_D(768, 2, 256)
+  } else if (pl.srows == 64) {
+    if (pl.nt <= 320) {
+      RTE_SWEEP_D(320, 1, 64)
+    } else {
+      RTE_SWEEP_D(576, 1, 64)
+    }
+  } else if (pl.srows == 128) {
+    if (pl.nt <= 576) {
+      RTE_SWEEP_D(576, 1, 128)
+    } else {
+      RTE_SWEEP_D(960, 1, 128)
+    }
   } else if (pl.nt <= 320) {
-    RTE_SWEEP_D(320, 1)
+    RTE_SWEEP_D(320, 1, 256)
   } else if (pl.nt <= 576) {
-    RTE_SWEEP_D(576, 1)
+    RTE_SWEEP_D(576, 1, 256)
   } else {
-    RTE_SWEEP_D(960, 1)
+    RTE_SWEEP_D(960, 1, 256)
   }
 #undef RTE_SWEEP_D
 #undef RTE_SWEEP_CASE
