@@ -891,15 +891,45 @@ __device__ void lu_lower_solve(const double* __restrict__ M, int rcap, bool unit
   }
 }
 
-__global__ __launch_bounds__(kLuThreads) void lu_border_kernel(
+// Two workgroups per class (blockIdx.y): 0 solves U_12 = L_11^{-1} A_12 into the new
+// columns of U, 1 solves L_21 = A_21 U_11^{-1} (U_11^T L_21^T = A_21^T) into the new
+// columns of L^T.  The two touch disjoint parts of the factors.
+__global__ __launch_bounds__(kLuThreads, 2) void lu_border_kernel(
+    int r0, int pn, int rcap, const int* __restrict__ cls, const ClassDev* __restrict__ cd,
+    const double* __restrict__ Tm, const double* __restrict__ Dx, const double* __restrict__ Dy,
+    double* __restrict__ Lt_all, double* __restrict__ U_all) {
+  extern __shared__ double sm[];
+  double* vec = sm;                       // [pn][r0]
+  double* Dg = sm + (long)pn * r0;        // [kLuB][kLuLd]
+  const int cl = cls[blockIdx.x];
+  const bool lower = blockIdx.y == 1;
+  const ClassDev k = cd[cl];
+  const size_t fsz = (size_t)rcap * rcap;
+  double* Lt = Lt_all + fsz * cl;
+  double* U = U_all + fsz * cl;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < pn * r0; e += kLuThreads) {
+    const int m = e / r0, i = e % r0;
+    vec[e] = lower ? amat(Tm, Dx, Dy, rcap, k, r0 + m, i) : amat(Tm, Dx, Dy, rcap, k, i, r0 + m);
+  }
+  __syncthreads();
+  if (lower) lu_lower_solve(U, rcap, false, r0, vec, pn, Dg);
+  else lu_lower_solve(Lt, rcap, true, r0, vec, pn, Dg);
+  double* dst = lower ? Lt : U;
+  for (int e = tid; e < pn * r0; e += kLuThreads) {
+    const int m = e / r0, i = e % r0;
+    dst[(size_t)i * rcap + r0 + m] = vec[e];
+  }
+}
+
+// The corner of the bordered factorisation, one workgroup per class:
+// S = A_22 - L_21 U_12 (no pivoting, as for the leading block), its LU, and the new
+// entries of y = L^{-1} b.
+__global__ __launch_bounds__(kLuThreads) void lu_corner_kernel(
     int r0, int pn, int rcap, const int* __restrict__ cls, const ClassDev* __restrict__ cd,
     const double* __restrict__ Tm, const double* __restrict__ Dx, const double* __restrict__ Dy,
     const double* __restrict__ bsrc, const double* __restrict__ bside, double* __restrict__ Lt_all,
     double* __restrict__ U_all, double* __restrict__ y_all) {
-  extern __shared__ double sm[];
-  double* col = sm;                       // [pn][r0]: A_12 -> U_12
-  double* row = sm + (long)pn * r0;       // [pn][r0]: A_21 -> L_21^T
-  double* Dg = row + (long)pn * r0;       // [kLuB][kLuLd]
   __shared__ double S[kMaxP][kMaxP], yn[kMaxP];
   const int cl = cls[blockIdx.x];
   const ClassDev k = cd[cl];
@@ -908,21 +938,13 @@ __global__ __launch_bounds__(kLuThreads) void lu_border_kernel(
   double* U = U_all + fsz * cl;
   double* y = y_all + (size_t)rcap * cl;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < pn * r0; e += kLuThreads) {
-    const int m = e / r0, i = e % r0;
-    col[e] = amat(Tm, Dx, Dy, rcap, k, i, r0 + m);
-    row[e] = amat(Tm, Dx, Dy, rcap, k, r0 + m, i);
-  }
-  __syncthreads();
-  // U_12 = L_11^{-1} A_12;  L_21 = A_21 U_11^{-1}, i.e. U_11^T L_21^T = A_21^T
-  lu_lower_solve(Lt, rcap, true, r0, col, pn, Dg);
-  lu_lower_solve(U, rcap, false, r0, row, pn, Dg);
-  // S = A_22 - L_21 U_12 and the new entries of y (one wavefront per dot product)
+  // one wavefront per dot product
   for (int d = wave; d < pn * pn + pn; d += kLuThreads / 64) {
     const bool isy = d >= pn * pn;
     const int m = isy ? d - pn * pn : d / pn, mm = d % pn;
     double s = 0.0;
-    for (int i = lane; i < r0; i += 64) s += row[m * r0 + i] * (isy ? y[i] : col[mm * r0 + i]);
+    for (int i = lane; i < r0; i += 64)
+      s += Lt[(size_t)i * rcap + r0 + m] * (isy ? y[i] : U[(size_t)i * rcap + r0 + mm]);
     s = wave_sum(s);
     if (lane == 0) {
       if (isy) yn[m] = bvec(bsrc, bside, rcap, k, r0 + m) - s;
@@ -949,11 +971,6 @@ __global__ __launch_bounds__(kLuThreads) void lu_border_kernel(
         if (mm >= m) U[(size_t)(r0 + m) * rcap + r0 + mm] = S[m][mm];
         else Lt[(size_t)(r0 + mm) * rcap + r0 + m] = S[m][mm];
       }
-  }
-  for (int e = tid; e < pn * r0; e += kLuThreads) {
-    const int m = e / r0, i = e % r0;
-    U[(size_t)i * rcap + r0 + m] = col[e];
-    Lt[(size_t)i * rcap + r0 + m] = row[e];
   }
 }
 
@@ -1644,9 +1661,13 @@ struct LowRank {
   void lu_border(int r0, int pn, const std::vector<int>& classes) {
     if (classes.empty() || pn == 0) return;
     const int* dl = upload_list(0, classes);
-    const size_t sm = ((size_t)2 * pn * r0 + (size_t)kLuB * kLuLd) * sizeof(double);
-    hipLaunchKernelGGL(lu_border_kernel, dim3((unsigned)classes.size()), dim3(kLuThreads), sm, st, r0, pn,
-                       rcap, dl, d_cd.get(), Tm.get(), Dx.get(), Dy.get(), bsrc.get(),
+    const size_t sm = ((size_t)pn * r0 + (size_t)kLuB * kLuLd) * sizeof(double);
+    if (r0 > 0)
+      hipLaunchKernelGGL(lu_border_kernel, dim3((unsigned)classes.size(), 2), dim3(kLuThreads), sm,
+                         st, r0, pn, rcap, dl, d_cd.get(), Tm.get(), Dx.get(), Dy.get(), Lt.get(),
+                         U.get());
+    hipLaunchKernelGGL(lu_corner_kernel, dim3((unsigned)classes.size()), dim3(kLuThreads), 0, st,
+                       r0, pn, rcap, dl, d_cd.get(), Tm.get(), Dx.get(), Dy.get(), bsrc.get(),
                        bside.get(), Lt.get(), U.get(), yv.get());
     RTE_CHECK_HIP(hipGetLastError());
   }
