@@ -129,17 +129,31 @@ __global__ __launch_bounds__(64 * kPjWaves, 2) void bproj_kernel(
   const long i0 = wf * Cfg::rows + lane;
   for (int c = threadIdx.x; c < r_upd * NV; c += 64 * kPjWaves) sC[c] = C[c];
   __syncthreads();
+  // Rows past nd read row 0 of their column (every load is unconditional, so none of them
+  // waits inside a branch) and are zeroed in w; the basis values of such rows then only
+  // ever meet w = 0 or results that are discarded.
   bool ok[RPT];
+  long ix[RPT];
   double w[NV][RPT], before[NV], after[NV];
 #pragma unroll
-  for (int t = 0; t < RPT; ++t) ok[t] = i0 + 64 * t < nd;
+  for (int t = 0; t < RPT; ++t) {
+    ok[t] = i0 + 64 * t < nd;
+    ix[t] = ok[t] ? i0 + 64 * t : 0;
+  }
+  {
+    T wr[NV][RPT];
 #pragma unroll
-  for (int l = 0; l < NV; ++l) {
-    before[l] = 0.0;
+    for (int l = 0; l < NV; ++l)
 #pragma unroll
-    for (int t = 0; t < RPT; ++t) {
-      w[l][t] = ok[t] ? (double)W[(long)l * nd + i0 + 64 * t] : 0.0;
-      before[l] += w[l][t] * w[l][t];
+      for (int t = 0; t < RPT; ++t) wr[l][t] = W[(long)l * nd + ix[t]];
+#pragma unroll
+    for (int l = 0; l < NV; ++l) {
+      before[l] = 0.0;
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) {
+        w[l][t] = ok[t] ? (double)wr[l][t] : 0.0;
+        before[l] += w[l][t] * w[l][t];
+      }
     }
   }
   if (r_upd > 0) {
@@ -151,30 +165,29 @@ __global__ __launch_bounds__(64 * kPjWaves, 2) void bproj_kernel(
     // U columns per round: all loads of a round are issued before its products
     int c = 0;
     for (; c + U <= r_upd; c += U) {
-      double xv[U][RPT];
+      T xv[U][RPT];
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int t = 0; t < RPT; ++t)
-          xv[u][t] = ok[t] ? (double)Xu[(long)(c + u) * nd + i0 + 64 * t] : 0.0;
+        for (int t = 0; t < RPT; ++t) xv[u][t] = Xu[(long)(c + u) * nd + ix[t]];
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int l = 0; l < NV; ++l) {
           const double d = sC[(c + u) * NV + l];
 #pragma unroll
-          for (int t = 0; t < RPT; ++t) s[l][t] += xv[u][t] * d;
+          for (int t = 0; t < RPT; ++t) s[l][t] += (double)xv[u][t] * d;
         }
     }
     for (; c < r_upd; ++c) {
-      double xv[RPT];
+      T xv[RPT];
 #pragma unroll
-      for (int t = 0; t < RPT; ++t) xv[t] = ok[t] ? (double)Xu[(long)c * nd + i0 + 64 * t] : 0.0;
+      for (int t = 0; t < RPT; ++t) xv[t] = Xu[(long)c * nd + ix[t]];
 #pragma unroll
       for (int l = 0; l < NV; ++l) {
         const double d = sC[c * NV + l];
 #pragma unroll
-        for (int t = 0; t < RPT; ++t) s[l][t] += xv[t] * d;
+        for (int t = 0; t < RPT; ++t) s[l][t] += (double)xv[t] * d;
       }
     }
 #pragma unroll
@@ -195,13 +208,15 @@ __global__ __launch_bounds__(64 * kPjWaves, 2) void bproj_kernel(
   const int stride = r_dot * NV + 2 * NV;
   double* out = part + wf * stride;
   if (r_dot > 0) {
-    double xc[G][RPT], xn[G][RPT];
-    auto fetch = [&](double (&x)[G][RPT], int c0) {
+    // columns past r_dot read column r_dot - 1; their sums are not stored
+    T xc[G][RPT], xn[G][RPT];
+    auto fetch = [&](T (&x)[G][RPT], int c0) {
 #pragma unroll
-      for (int g = 0; g < G; ++g)
+      for (int g = 0; g < G; ++g) {
+        const long col = c0 + g < r_dot ? c0 + g : r_dot - 1;
 #pragma unroll
-        for (int t = 0; t < RPT; ++t)
-          x[g][t] = (ok[t] && c0 + g < r_dot) ? (double)Xd[(long)(c0 + g) * nd + i0 + 64 * t] : 0.0;
+        for (int t = 0; t < RPT; ++t) x[g][t] = Xd[col * nd + ix[t]];
+      }
     };
     fetch(xc, 0);
     for (int c0 = 0; c0 < r_dot; c0 += G) {
@@ -214,7 +229,7 @@ __global__ __launch_bounds__(64 * kPjWaves, 2) void bproj_kernel(
 #pragma unroll
         for (int l = 0; l < NV; ++l)
 #pragma unroll
-          for (int t = 0; t < RPT; ++t) p[g * NV + l] += xc[g][t] * w[l][t];
+          for (int t = 0; t < RPT; ++t) p[g * NV + l] += (double)xc[g][t] * w[l][t];
       const double tot = wave_colsum16(p, rw);
       if (lane < G * NV && c0 + lane / NV < r_dot) out[c0 * NV + lane] = tot;
 #pragma unroll
@@ -591,19 +606,22 @@ __global__ __launch_bounds__(256) void xtw_kernel(const T* __restrict__ X, int r
   T* xs = Xs[wave];
   const long kb = (long)blockIdx.x * nch * kXwRows;
   const int nq = (int)std::min<long>(nch, (nd - kb + kXwRows - 1) / kXwRows);
-  double wpf[PT];
+  // W staging: raw values are fetched a chunk ahead (unconditional loads from a clamped
+  // address) and converted, with rows past nd zeroed, when they are stashed in LDS
+  T wpf[PT];
   auto wfetch = [&](long k0) {
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
       const int e = threadIdx.x + 256 * i, l = e / kXwRows, k = e % kXwRows;
-      wpf[i] = (e < NV * kXwRows && k0 + k < nd) ? (double)W[(long)l * nd + k0 + k] : 0.0;
+      const bool in = e < NV * kXwRows && k0 + k < nd;
+      wpf[i] = W[in ? (long)l * nd + k0 + k : 0];
     }
   };
-  auto wstash = [&](double* ws) {
+  auto wstash = [&](double* ws, long k0) {
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
       const int e = threadIdx.x + 256 * i, l = e / kXwRows, k = e % kXwRows;
-      if (e < NV * kXwRows) ws[k * NVP + l] = wpf[i];
+      if (e < NV * kXwRows) ws[k * NVP + l] = k0 + k < nd ? (double)wpf[i] : 0.0;
     }
   };
   // rows past nd (last chunk only) read a clamped in-range address; their staged W is 0
@@ -616,7 +634,7 @@ __global__ __launch_bounds__(256) void xtw_kernel(const T* __restrict__ X, int r
 #pragma unroll
   for (int l = 0; l < NV; ++l) acc[l] = 0.0;
   wfetch(kb);
-  wstash(Ws[0]);
+  wstash(Ws[0], kb);
   V xv[8];
   if (won) xload(xv, kb + grp * SUB);
   __syncthreads();
@@ -646,7 +664,7 @@ __global__ __launch_bounds__(256) void xtw_kernel(const T* __restrict__ X, int r
       }
       lds_fence_wave();
     }
-    if (q + 1 < nq) wstash(Ws[(q + 1) & 1]);
+    if (q + 1 < nq) wstash(Ws[(q + 1) & 1], k0 + kXwRows);
     __syncthreads();
   }
   // row groups 1 .. ngrp-1 hand their sums to group 0 through LDS (reusing Ws)
@@ -676,6 +694,7 @@ __global__ __launch_bounds__(256) void xc_kernel(const T* __restrict__ X, int r,
   __shared__ double Cs[64][NM];
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const bool ok = i < nd;
+  const long il = ok ? i : 0;  // rows past nd read row 0 (unconditional loads); not stored
   double acc[NM];
 #pragma unroll
   for (int m = 0; m < NM; ++m) acc[m] = 0.0;
@@ -689,16 +708,16 @@ __global__ __launch_bounds__(256) void xc_kernel(const T* __restrict__ X, int r,
     __syncthreads();
     int c = 0;
     for (; c + 4 <= cn; c += 4) {
-      double x[4];
+      T x[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) x[u] = ok ? (double)X[(long)(c0 + c + u) * nd + i] : 0.0;
+      for (int u = 0; u < 4; ++u) x[u] = X[(long)(c0 + c + u) * nd + il];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int m = 0; m < NM; ++m) acc[m] += x[u] * Cs[c + u][m];
+        for (int m = 0; m < NM; ++m) acc[m] += (double)x[u] * Cs[c + u][m];
     }
     for (; c < cn; ++c) {
-      const double x = ok ? (double)X[(long)(c0 + c) * nd + i] : 0.0;
+      const double x = (double)X[(long)(c0 + c) * nd + il];
 #pragma unroll
       for (int m = 0; m < NM; ++m) acc[m] += x * Cs[c][m];
     }

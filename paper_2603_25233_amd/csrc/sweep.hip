@@ -215,19 +215,9 @@ constexpr int kStageRows = 256;
 // Input slots in LDS: the staging wavefronts fill step t + 2 while step t is solved.
 constexpr int kInSlots = 3;
 
-// s_waitcnt vmcnt(n) (expcnt and lgkmcnt not waited for); n > 15 waits for everything.
-// n must be the same in every lane: it is made a scalar first, so that exactly one case
-// runs (a per-lane switch would pass through the wait of every case).
-__device__ __forceinline__ void wait_vmcnt(int n) {
-  switch (__builtin_amdgcn_readfirstlane(n)) {
-#define RTE_VM(k) \
-  case k: __builtin_amdgcn_s_waitcnt(0xF70 | k); break;
-    RTE_VM(0) RTE_VM(1) RTE_VM(2) RTE_VM(3) RTE_VM(4) RTE_VM(5) RTE_VM(6) RTE_VM(7)
-    RTE_VM(8) RTE_VM(9) RTE_VM(10) RTE_VM(11) RTE_VM(12) RTE_VM(13) RTE_VM(14) RTE_VM(15)
-#undef RTE_VM
-    default: __builtin_amdgcn_s_waitcnt(0xF70); break;
-  }
-}
+// s_waitcnt immediate for vmcnt(n), n <= 63 (the 6-bit counter: bits 3:0 and 15:14),
+// with expcnt and lgkmcnt not waited for.
+constexpr int vmcnt_imm(int n) { return 0xF70 | (n & 15) | ((n >> 4) << 14); }
 
 // Output write-back geometry for element type T: a row's results leave in aligned
 // chunks of 128 bytes (kChunkCells cells), 16 bytes per lane, 8 rows per store
@@ -256,11 +246,14 @@ typedef __attribute__((address_space(3))) void lds_void;
 // Per step t: the compute threads solve the cells of canonical column t - r, taking
 // the source and sigma_t of step t from LDS input slot t mod 3 and the y-inflow trace
 // from row r - 1 of step t - 1 (double-buffered LDS, one barrier per step); the
-// x-inflow trace stays in registers.  Meanwhile the staging wavefronts copy exactly the
-// cells of step t + 2 into slot (t + 2) mod 3 (last read in step t - 1) and, before the
+// x-inflow trace stays in registers.  Meanwhile the staging wavefronts copy the cells
+// of step t + 2 into slot (t + 2) mod 3 (last read in step t - 1) and, before the
 // barrier that ends step t, wait only for the copies of step t + 1 (issued one step
 // earlier): vector memory counts complete in issue order, so waiting until no more
 // than this step's copies are outstanding suffices, and a copy has a whole step to land.
+// A staging wavefront issues the same number of copies in every step in which it has
+// cells (none in the others), so that the counts waited for are constants of the kernel
+// and the staging loop keeps no per-step tallies.
 //
 // Output.  With use_ring, step t leaves its results in LDS ring slot t mod kRingSlots
 // (per direction for psi, or the weighted sum over the group's directions for the
@@ -287,10 +280,12 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
   const int RD = psi ? D : 1;                 // ring entries per row and step
   constexpr int BS = kPiece<T>;                // elements of a 16-byte piece
   T* vbuf = reinterpret_cast<T*>(smem_raw);   // [2][nr][D][2] y-inflow traces by row
-  T* in_src = vbuf + 4L * nr * D;             // [3][nr][4] source moments of the step
-  T* in_sig = in_src + 4L * kInSlots * nr;    // [3][nrs] sigma_t of the step (shifted)
-  T* in_bnd = in_sig + (long)kInSlots * nrs;  // [3][BS] y-inflow of canonical row 0
-  T* ring = in_bnd + kInSlots * BS;           // [NS][nr][RD][4] outputs by step and row
+  constexpr int S = kInSlots;
+  T* in_src = vbuf + 4L * nr * D;             // [S][nr][4] source moments of the step
+  T* in_sig = in_src + 4L * S * nr;           // [S][nrs] sigma_t of the step (shifted)
+  T* in_bnd = in_sig + (long)S * nrs;         // [S][BS] y-inflow of canonical row 0
+                                              // + [BS] pad (dummy copies)
+  T* ring = in_bnd + (S + 1) * BS;            // [NS][nr][RD][4] outputs by step and row
   const SweepDir* grp = dirs + (long)blockIdx.x * D;
   const int sx = grp[0].sx, sy = grp[0].sy;
   const T fx = T(sx), fy = T(sy), fxy = T(sx * sy);
@@ -306,64 +301,92 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
     // sh(t) = -lo mod CPS keeps the copy 16-byte aligned on both sides.
     const int lane = tid & 63;
     const int sw = (tid - nc) >> 6;
+    const int c0 = sw * SR;  // first cell of this wavefront within a step
     const float4* src16 = reinterpret_cast<const float4*>(dsrc_all + 4 * q * ncell);
     const float4* sig16 = reinterpret_cast<const float4*>(dsig_all + q * sig_stride<T>(nx, ny));
     const float4* bnd16 = reinterpret_cast<const float4*>(dbnd_all) + (long)q * nsteps;
-    // issues the copies of step t into slot sl; returns the number of copy instructions
-    auto stage = [&](int t, int sl) {
-      const int lo = t >= nx ? t - nx + 1 : 0;
-      const int hi = t < ny ? t : ny - 1;
-      const int c0 = sw * SR;            // first cell of this wavefront
-      const int nce = hi - lo + 1 - c0;  // cells left for it
-      int n = 0;
-      if (nce > 0) {
-        const int ncw = nce < SR ? nce : SR;
-        // source: ncw * CPC pieces
-        const float4* gs = src16 + (diag_first(t, nx, ny) + c0) * CPC;
-        float4* ls = reinterpret_cast<float4*>(in_src) + ((long)sl * nr + lo + c0) * CPC;
-        constexpr int NIS = SR * CPC / 64;  // instructions for a full wavefront
-#pragma unroll
-        for (int i = 0; i < NIS; ++i)
-          if (64 * i < ncw * CPC) {
-            ++n;
-            if (64 * i + lane < ncw * CPC)
-              __builtin_amdgcn_global_load_lds((const void*)(gs + 64 * i + lane),
-                                               (lds_void*)(ls + 64 * i), 16, 0, 0);
-          }
-        // sigma_t: ceil(ncw / CPS) pieces
-        const int sh = (-lo) & (CPS - 1);
-        const float4* gg = sig16 + (sig_first<T>(t, nx, ny) + c0) / CPS;
-        float4* lg = reinterpret_cast<float4*>(in_sig + (long)sl * nrs + sh + lo + c0);
-        const int npg = (ncw + CPS - 1) / CPS;
-        constexpr int NIG = (SR / CPS + 63) / 64;
-#pragma unroll
-        for (int i = 0; i < NIG; ++i)
-          if (64 * i < npg) {
-            ++n;
-            if (64 * i + lane < npg)
-              __builtin_amdgcn_global_load_lds((const void*)(gg + 64 * i + lane),
-                                               (lds_void*)(lg + 64 * i), 16, 0, 0);
-          }
-      }
-      if (sw == 0) {  // the y-inflow piece of row 0
-        if (lane == 0)
-          __builtin_amdgcn_global_load_lds((const void*)(bnd16 + t),
-                                           (lds_void*)(in_bnd + BS * sl), 16, 0, 0);
-        ++n;
-      }
-      return n;
+    float4* pad = reinterpret_cast<float4*>(in_bnd + S * BS);
+    // A wavefront with cells in a step issues the same number of copies (K, and one
+    // more, the y-inflow piece of row 0, in wavefront 0, which always has cells), so
+    // that the waits are constants: a copy with no cells left for it moves one 16-byte
+    // piece (lane 0, from a valid address) into the LDS pad, which nothing reads.  A
+    // wavefront without cells in step t + 2 issues nothing and waits for all its copies.
+    constexpr int NIS = SR * CPC / 64;         // source copies
+    constexpr int NIG = (SR / CPS + 63) / 64;  // sigma_t copies
+    constexpr int K = NIS + NIG;
+    static_assert(kInSlots == 3 && K + 1 <= 63, "outstanding copies exceed the vmcnt range");
+    const bool w0 = sw == 0;
+    // after the copies of step t + 2 (any: whether it had cells for this wavefront), those
+    // of step t + 1 have landed
+    auto wait_next = [&](bool any) {
+      if (!any) __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+      else if (w0) __builtin_amdgcn_s_waitcnt(vmcnt_imm(K + 1));
+      else __builtin_amdgcn_s_waitcnt(vmcnt_imm(K));
     };
-    // Plain barriers: the copies are waited for explicitly, with counts.
-    stage(0, 0);
-    const int n1 = nsteps > 1 ? stage(1, 1) : 0;
-    wait_vmcnt(n1);
+    // copies of step t (first row lo, first diagonal-major position df) into slot sl;
+    // false if the step has no cells for this wavefront (then nothing is issued)
+    auto stage = [&](int t, int lo, long df, int sl) {
+      const int hi = t < ny ? t : ny - 1;
+      const int nce = hi - lo + 1 - c0;  // cells left for this wavefront
+      if (nce <= 0) return false;
+      const int ncw = nce < SR ? nce : SR;
+      const float4* gs = src16 + (df + c0) * CPC;
+      float4* ls = reinterpret_cast<float4*>(in_src) + ((long)sl * nr + lo + c0) * CPC;
+#pragma unroll
+      for (int i = 0; i < NIS; ++i) {
+        const bool mine = 64 * i + lane < ncw * CPC;
+        if (mine || lane == 0)
+          __builtin_amdgcn_global_load_lds((const void*)(mine ? gs + 64 * i + lane : bnd16),
+                                           (lds_void*)(64 * i < ncw * CPC ? ls + 64 * i : pad),
+                                           16, 0, 0);
+      }
+      // sigma_t: ceil(ncw / CPS) pieces, at sig_first(t) (diagonal-major position
+      // advanced by (CPS - 1) t, rounded up to a multiple of CPS)
+      const long sf = (df + (CPS - 1) * (long)t + CPS - 1) / CPS * CPS;
+      const int sh = (-lo) & (CPS - 1);
+      const float4* gg = sig16 + (sf + c0) / CPS;
+      float4* lg = reinterpret_cast<float4*>(in_sig + (long)sl * nrs + sh + lo + c0);
+      const int npg = (ncw + CPS - 1) / CPS;
+#pragma unroll
+      for (int i = 0; i < NIG; ++i) {
+        const bool mine = 64 * i + lane < npg;
+        if (mine || lane == 0)
+          __builtin_amdgcn_global_load_lds((const void*)(mine ? gg + 64 * i + lane : bnd16),
+                                           (lds_void*)(64 * i < npg ? lg + 64 * i : pad), 16, 0,
+                                           0);
+      }
+      if (w0 && lane == 0)  // the y-inflow piece of row 0
+        __builtin_amdgcn_global_load_lds((const void*)(bnd16 + t),
+                                         (lds_void*)(in_bnd + BS * sl), 16, 0, 0);
+      return true;
+    };
+    // (lo, df) of the next step to stage, advanced one step at a time
+    int lo = 0;
+    long df = 0;
+    auto advance = [&](int t) {
+      df += (t < ny ? t : ny - 1) - lo + 1;
+      lo += t + 1 >= nx ? 1 : 0;
+    };
+    // Plain barriers: the copies are waited for explicitly.
+    stage(0, lo, df, 0);
+    advance(0);
+    bool any = false;
+    if (nsteps > 1) {
+      any = stage(1, lo, df, 1);
+      advance(1);
+    }
+    wait_next(any);                // step 0 landed
     __builtin_amdgcn_s_barrier();  // step 0 staged
     int sl2 = 2;                   // (t + 2) mod 3
     for (int t = 0; t < nsteps; ++t) {
-      const int n2 = t + 2 < nsteps ? stage(t + 2, sl2) : 0;
-      wait_vmcnt(n2);                // copies of step t + 1 landed
+      any = false;
+      if (t + 2 < nsteps) {
+        any = stage(t + 2, lo, df, sl2);
+        advance(t + 2);
+      }
+      wait_next(any);                // copies of step t + 1 landed
       __builtin_amdgcn_s_barrier();  // end of step t
-      sl2 = sl2 == kInSlots - 1 ? 0 : sl2 + 1;
+      sl2 = sl2 == S - 1 ? 0 : sl2 + 1;
     }
     __builtin_amdgcn_s_waitcnt(0);
     return;
@@ -541,7 +564,7 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
     }
     __syncthreads();
     ns = ns + 1 == NS ? 0 : ns + 1;
-    si = si + 1 == kInSlots ? 0 : si + 1;
+    si = si + 1 == S ? 0 : si + 1;
   }
   if (use_ring) write_back(nsteps, ns);  // chunks closed by the last step
 }
@@ -582,13 +605,14 @@ static std::vector<SweepDir> make_groups(const std::vector<SweepDir>& in, int D)
   return out;
 }
 
-// vbuf [2][nr][D][2] + in_src [2][nr][4] + in_sig [2][nr + 2 CPS] + in_bnd [2][2]
+// vbuf [2][nr][D][2] + in_src [S][nr][4] + in_sig [S][nr + 2 CPS] + in_bnd [S + 1][CPS]
 // + ring [kRingSlots][nr][RD][4] (with the ring; RD = D for psi, 1 for the scalar
-// flux), nr = padded rows
+// flux), nr = padded rows, S = kInSlots
 static size_t sweep_lds_bytes(int nr, int D, bool psi, bool ring, size_t eb) {
+  constexpr size_t S = kInSlots;
   const size_t slots = ring ? (eb == 8 ? WriteBack<double>::kRingSlots : WriteBack<float>::kRingSlots) : 0;
   const size_t cps = 16 / eb;
-  return (4ull * nr * D + 4ull * kInSlots * nr + kInSlots * (nr + 2 * cps) + kInSlots * cps +
+  return (4ull * nr * D + 4ull * S * nr + S * (nr + 2 * cps) + (S + 1) * cps +
           4ull * slots * nr * (psi ? D : 1)) * eb;
 }
 
