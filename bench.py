@@ -71,13 +71,52 @@ def cpu_baseline(wl, n_sweeps):
                       "plain-C oracle sweep, %.1f s" % (n_sweeps, len(w), wl["nx"], wl["ny"], dt)}
 
 
+def large_sweep(args, R, W, torch, dev):
+    """The psi-writing full-angle sweep on the 1024x1024, CL(64,16) multiscale medium:
+    1024 ordinates, 2047 anti-diagonal steps, FP64 psi of 34.4 GB (written once)."""
+    wl = W.multiscale()
+    dirs, wts = R.cl_quadrature(wl["n_theta"], wl["n_z"])
+    prob = R.Problem(wl["nx"], wl["ny"], wl["domain"], dirs, wts, wl["sigma_t"], wl["sigma_s"])
+    ncell, ndirs = wl["nx"] * wl["ny"], len(wts)
+    dt = torch.float32 if args.mixed else torch.float64
+    wsize = 4 if args.mixed else 8
+    src = torch.ones((wl["ny"], wl["nx"], 4), dtype=dt, device=dev)  # uniform Q = 1
+    psi = torch.empty((ndirs, wl["ny"], wl["nx"], 4), dtype=dt, device=dev)
+    plan = R.SweepPlan(prob, np.arange(ndirs), mixed=args.mixed)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        plan.execute(src, psi=psi)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        plan.execute(src, psi=psi)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    alg = ncell * (4 * wsize * ndirs + 4 * wsize + 8)
+    updates = 4 * ncell * ndirs
+    print(json.dumps({"metric": "angle-cell-DOF sweep updates/s (psi sweep only)",
+                      "value": updates / (ms * 1e-3), "unit": "angle-cell-DOF updates/s",
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+                      "dtype": "f32" if args.mixed else "f64", "data": "synthetic",
+                      "config": {"workload": "multiscale 1024x1024 DG-Q1, CL(64,16) 1024 ordinates, "
+                                             "log-normal sigma_t, c=0.999, psi sweep only"},
+                      "roofline": {"bound": "hbm", "achieved": alg / (ms * 1e-3) / 1e9,
+                                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                   "algorithmic_bytes_per_launch": alg}}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--only", choices=["step", "sweep", "copy"], default="step",
+    ap.add_argument("--only", choices=["step", "sweep", "sweep_large", "copy"], default="step",
                     help="sweep: only the psi-writing full-angle sweep (profiling); "
+                         "sweep_large: the same on the 1024x1024, CL(64,16) multiscale medium "
+                         "(34.4 GB of FP64 psi), one JSON line of its own; "
                          "copy: a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=10)
@@ -105,6 +144,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8,
                           "launches": args.warmup + args.steps}))
+        return
+    if args.only == "sweep_large":
+        large_sweep(args, R, W, torch, dev)
         return
 
     wl = W.checkerboard()
