@@ -108,15 +108,68 @@ def large_sweep(args, R, W, torch, dev):
                                    "algorithmic_bytes_per_launch": alg}}))
 
 
+def effective_rank(s, eps):
+    """Smallest l with sum_{i > l} s_i <= eps sum_i s_i (the truncation rule of the solver)."""
+    tail = np.concatenate([np.cumsum(s[::-1])[::-1][1:], [0.0]])
+    return int(np.argmax(tail <= eps * s.sum())) + 1
+
+
+def paper_examples(R, W, torch, dev):
+    """Full-rank and low-rank SI-DSA (FP64) on the paper's own media: Sec. 4.1 (homogeneous,
+    L = 2..5, sigma_s in {0.1, 1, 10, 100}), Sec. 4.3 (variable scattering) and Sec. 4.4
+    (pin cell); p = 1, q = 8, eps_SI = 1e-6.  Per case one JSON line: iterations, ranks,
+    ||phi_LR - phi_FR||_2, compression ratio, times, and the effective rank of the
+    full-rank angular flux (its truncated SVD with the solver's rule and eps_SVD = 1e-8)."""
+    cases = [("sec4.1 homogeneous sigma_s=%g L=%d" % (sg, L), W.homogeneous(sg, L))
+             for L in (2, 3, 4, 5) for sg in (0.1, 1.0, 10.0, 100.0)]
+    cases += [("sec4.3 variable scattering", W.variable_scattering()),
+              ("sec4.4 pin cell", W.pin_cell())]
+    for name, wl in cases:
+        d, w = R.cl_quadrature(wl["n_theta"], wl["n_z"])
+        amp, alpha, centre = wl["source_gauss"]
+        G = R.gaussian_source_moments(wl["nx"], wl["ny"], wl["domain"], amp, alpha, centre)
+        prob = R.Problem(wl["nx"], wl["ny"], wl["domain"], d, w, wl["sigma_t"], wl["sigma_s"], G=G)
+        kw = dict(eps_si=wl["eps_si"], max_outer=wl["max_outer"], eps_dsa=1e-12)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fr = R.solve(prob, full_rank=1, **kw)
+        torch.cuda.synchronize()
+        t_fr = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        lr = R.solve(prob, rand=W.random_stream(wl["seed"]), full_rank=0, p=wl["p"], q=wl["q"],
+                     eps_res=wl["eps_res"], eps_diff=wl["eps_diff"], eps_svd=wl["eps_svd"],
+                     eps_mgs=wl["eps_mgs"], m_max=wl["m_max"], **kw)
+        torch.cuda.synchronize()
+        t_lr = time.perf_counter() - t0
+        # full-rank angular flux: one sweep of the converged source
+        src = (prob.sigma_s[..., None] * fr["phi"] + prob.G).contiguous()
+        psi, _ = R.sweep(prob, np.arange(len(w)), src)
+        s = np.linalg.svd(psi.reshape(len(w), -1).cpu().numpy().T, compute_uv=False)
+        nd = prob.ndof
+        diff = (lr["phi"] - fr["phi"]).double().cpu().numpy().reshape(-1)
+        print(json.dumps({"example": name, "cells": "%dx%d" % (wl["nx"], wl["ny"]),
+                          "ordinates": len(w), "p": wl["p"], "q": wl["q"],
+                          "fr_iters": fr["iters"], "lr_iters": lr["iters"], "lr_rank": lr["rank"],
+                          "fr_effective_rank": effective_rank(s, wl["eps_svd"]),
+                          "phi_lr_minus_fr_l2": float(np.linalg.norm(diff)),
+                          "phi_lr_minus_fr_rel_l2": float(np.linalg.norm(diff) / np.linalg.norm(
+                              fr["phi"].double().cpu().numpy())),
+                          "compression_ratio": lr["rank"] * (nd + len(w) + 1) / (nd * len(w)),
+                          "lr_angles_swept": int(sum(lr["swept"])),
+                          "fr_time_s": t_fr, "lr_time_s": t_lr, "data": "synthetic",
+                          "dtype": "f64"}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--only", choices=["step", "sweep", "sweep_large", "copy"], default="step",
+    ap.add_argument("--only", choices=["step", "sweep", "sweep_large", "paper", "copy"], default="step",
                     help="sweep: only the psi-writing full-angle sweep (profiling); "
                          "sweep_large: the same on the 1024x1024, CL(64,16) multiscale medium "
                          "(34.4 GB of FP64 psi), one JSON line of its own; "
+                         "paper: the paper's own examples (Sec. 4.1, 4.3, 4.4), one JSON line each; "
                          "copy: a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=10)
@@ -147,6 +200,9 @@ def main():
         return
     if args.only == "sweep_large":
         large_sweep(args, R, W, torch, dev)
+        return
+    if args.only == "paper":
+        paper_examples(R, W, torch, dev)
         return
 
     wl = W.checkerboard()

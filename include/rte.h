@@ -229,6 +229,15 @@ rte_status rte_box_source_moments(int32_t nx, int32_t ny, double x0, double x1, 
                                   double y1, double value, double bx0, double bx1,
                                   double by0, double by1, double* G_host);
 
+/* Adds the moments of the Gaussian source G = amp exp(-alpha ((x-cx)^2 + (y-cy)^2))
+ * (the source of the examples of Sec. 4: amp = 1, alpha = 100, centre 0) to G_host
+ * [ny][nx][4] (Appendix B, G(k) = int_cell G eta_k): the source is separable, so each
+ * moment is a product of one-axis integrals, evaluated in closed form (error function).
+ * alpha > 0; the mesh and the inputs must be finite.                                 */
+rte_status rte_gaussian_source_moments(int32_t nx, int32_t ny, double x0, double x1, double y0,
+                                       double y1, double amp, double alpha, double cx,
+                                       double cy, double* G_host);
+
 const char* rte_last_error(void);
 int32_t rte_abi_version(void);
 

@@ -395,4 +395,53 @@ rte_status rte_box_source_moments(int32_t nx, int32_t ny, double x0, double x1, 
   }
 }
 
+rte_status rte_gaussian_source_moments(int32_t nx, int32_t ny, double x0, double x1, double y0,
+                                       double y1, double amp, double alpha, double cx, double cy,
+                                       double* G) {
+  try {
+    RTE_REQUIRE(nx >= 1 && ny >= 1 && x1 > x0 && y1 > y0, "bad mesh");
+    RTE_REQUIRE(alpha > 0.0 && std::isfinite(alpha), "alpha must be positive and finite");
+    RTE_REQUIRE(std::isfinite(amp) && std::isfinite(cx) && std::isfinite(cy), "non-finite input");
+    RTE_REQUIRE(G, "G is NULL");
+    const double hx = (x1 - x0) / nx, hy = (y1 - y0) / ny;
+    const double r3 = std::sqrt(3.0), sa = std::sqrt(alpha);
+    const double k0 = 0.5 * std::sqrt(M_PI / alpha);
+    // erf(b) - erf(a) for a <= b, through erfc on the side away from 0 (no cancellation
+    // of two values close to +-1)
+    auto derf = [](double a, double b) {
+      if (a >= 0.0) return std::erfc(a) - std::erfc(b);
+      if (b <= 0.0) return std::erfc(-b) - std::erfc(-a);
+      return std::erf(b) - std::erf(a);
+    };
+    // moments of g(t) = exp(-alpha (t - t0)^2) on the cells of one axis against
+    // l_0 = 1/sqrt(h) and l_1 = sqrt3 xi / sqrt(h), xi = 2 (t - c) / h:
+    //   int g = k0 [erf(sa u)]_ua^ub,  int (t - c) g = [-g / (2 alpha)]_ua^ub + (t0 - c) int g,
+    // with u = t - t0
+    auto axis = [&](int n, double lo, double h, double t0, std::vector<double>& m) {
+      m.assign(2 * (size_t)n, 0.0);
+      for (int i = 0; i < n; ++i) {
+        const double a = lo + i * h, b = a + h, c = a + 0.5 * h;
+        const double ua = a - t0, ub = b - t0;
+        const double i0 = k0 * derf(sa * ua, sa * ub);
+        const double i1 = (std::exp(-alpha * ua * ua) - std::exp(-alpha * ub * ub)) / (2.0 * alpha) +
+                          (t0 - c) * i0;
+        m[2 * i] = i0 / std::sqrt(h);
+        m[2 * i + 1] = r3 * 2.0 * i1 / (h * std::sqrt(h));
+      }
+    };
+    std::vector<double> mx, my;
+    axis(nx, x0, hx, cx, mx);
+    axis(ny, y0, hy, cy, my);
+    for (int b = 0; b < ny; ++b)
+      for (int a = 0; a < nx; ++a) {
+        double* c = G + 4 * ((long)b * nx + a);
+        for (int q = 0; q < 2; ++q)
+          for (int p = 0; p < 2; ++p) c[2 * q + p] += amp * mx[2 * a + p] * my[2 * b + q];
+      }
+    return RTE_OK;
+  } catch (const Error& e) {
+    return e.code;
+  }
+}
+
 }  // extern "C"

@@ -73,6 +73,8 @@ SIGNATURES = {
     "rte_cl_quadrature": ([ctypes.c_int32, ctypes.c_int32, _D, _D], ctypes.c_int),
     "rte_box_source_moments": ([ctypes.c_int32, ctypes.c_int32] + [ctypes.c_double] * 9 + [_D],
                                ctypes.c_int),
+    "rte_gaussian_source_moments": ([ctypes.c_int32, ctypes.c_int32] + [ctypes.c_double] * 8 + [_D],
+                                    ctypes.c_int),
     "rte_sweep_plan_create": ([ctypes.POINTER(Problem_), _I, ctypes.c_int32, ctypes.c_int,
                                ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)],
                               ctypes.c_int),
@@ -137,6 +139,15 @@ def box_source_moments(nx, ny, domain, boxes):
     for value, (bx0, bx1, by0, by1) in boxes:
         _check(lib().rte_box_source_moments(nx, ny, x0, x1, y0, y1, value, bx0, bx1, by0, by1,
                                             G.ctypes.data_as(_D)))
+    return G
+
+
+def gaussian_source_moments(nx, ny, domain, amp=1.0, alpha=100.0, center=(0.0, 0.0)):
+    """Moments of G = amp exp(-alpha |x - center|^2), [ny, nx, 4] float64 (host)."""
+    G = np.zeros((ny, nx, 4))
+    x0, x1, y0, y1 = domain
+    _check(lib().rte_gaussian_source_moments(nx, ny, x0, x1, y0, y1, amp, alpha, center[0],
+                                             center[1], G.ctypes.data_as(_D)))
     return G
 
 

@@ -14,7 +14,7 @@ def oracle_problem(wl, bc_faces=None):
     for val, box in wl.get("source_boxes", []):
         G += dg.source_moments_box(m, val, box)
     if wl.get("source_fn") is not None:
-        G += dg.source_moments_function(m, wl["source_fn"])
+        G += dg.source_moments_function(m, wl["source_fn"], nq=12)
     bc = None
     if bc_faces:
         bc = np.zeros((4, max(m.nx, m.ny), 2))
@@ -28,6 +28,9 @@ def gpu_problem(wl, bc_faces=None, bc=None):
     import paper_2603_25233_amd as R
     d, w = R.cl_quadrature(wl["n_theta"], wl["n_z"])
     G = R.box_source_moments(wl["nx"], wl["ny"], wl["domain"], wl.get("source_boxes", []))
+    if wl.get("source_gauss") is not None:
+        amp, alpha, centre = wl["source_gauss"]
+        G = G + R.gaussian_source_moments(wl["nx"], wl["ny"], wl["domain"], amp, alpha, centre)
     if bc is None and bc_faces:
         bc = R.inflow_moments(wl["nx"], wl["ny"], wl["domain"], bc_faces)
     return R.Problem(wl["nx"], wl["ny"], wl["domain"], d, w, wl["sigma_t"], wl["sigma_s"],

@@ -25,6 +25,16 @@ of the sizes and structure the benchmark configurations name:
   multiscale     1024x1024 cells, CL(64,16); log sigma_t = mu + z with z smoothed at
                  32 cells, mu = ln 100 - 1/2 (arithmetic mean 100); sigma_s = 0.999
                  sigma_t; Q = 1 everywhere; p = 1, q = 8.
+The paper's own examples (Sec. 4), on [-1,1]^2 with no absorption (sigma_t = sigma_s),
+vacuum boundaries and the Gaussian source exp(-100 (x^2 + y^2)), p = 1, q = 8:
+  homogeneous         Sec. 4.1: sigma_s in {0.1, 1, 10, 100}, 16L x 16L cells, CL(8L, 4L).
+  variable_scattering Sec. 4.3: sigma_s = 99.9 r^4 (r^2 - 2)^2 + 0.1 for r <= 1, else 100
+                      (at the cell centre), 80 x 80 cells, CL(40, 20).
+  pin_cell            Sec. 4.4: sigma_s = 0.1 on |x|, |y| <= 0.5, else 100 (at the cell
+                      centre; the 80 x 80 mesh resolves the square exactly), CL(32, 16).
+The Gaussian source is described twice: `source_gauss` = (amplitude, alpha, centre) for
+the library's closed-form moments and `source_fn`, a callable the oracle integrates with
+its own quadrature.
 A workload can be shrunk (`scaled`) for tests that must finish in seconds; the
 structure (block pattern, source placement relative to the domain) is kept.
 """
@@ -125,6 +135,41 @@ def homogeneous(sigma, L):
     return Workload(name="homogeneous", nx=n, ny=n, domain=(-1.0, 1.0, -1.0, 1.0),
                     n_theta=8 * L, n_z=4 * L, sigma_t=sigma * np.ones((n, n)),
                     sigma_s=sigma * np.ones((n, n)), source_boxes=[], inflow_faces=[],
-                    source_fn=lambda x, y: np.exp(-100.0 * (x * x + y * y)),
+                    source_fn=gaussian_source, source_gauss=(1.0, 100.0, (0.0, 0.0)),
                     eps_si=1e-6, max_outer=100, p=1, q=8, eps_res=1e-7, eps_diff=1e-7,
                     eps_svd=1e-8, eps_mgs=1e-10, m_max=4, seed=33)
+
+
+def gaussian_source(x, y):
+    """The isotropic source of Sec. 4, exp(-100 (x^2 + y^2))."""
+    return np.exp(-100.0 * (x * x + y * y))
+
+
+def _cell_centres(n, lo=-1.0, hi=1.0):
+    h = (hi - lo) / n
+    c = lo + h * (np.arange(n) + 0.5)
+    return np.meshgrid(c, c, indexing="xy")  # [y][x]
+
+
+def _paper_example(name, sig_s, n, n_theta, n_z, seed, p=1, q=8):
+    return Workload(name=name, nx=n, ny=n, domain=(-1.0, 1.0, -1.0, 1.0), n_theta=n_theta,
+                    n_z=n_z, sigma_t=sig_s.copy(), sigma_s=sig_s, source_boxes=[],
+                    inflow_faces=[], source_fn=gaussian_source,
+                    source_gauss=(1.0, 100.0, (0.0, 0.0)), eps_si=1e-6, max_outer=100, p=p,
+                    q=q, eps_res=1e-7, eps_diff=1e-7, eps_svd=1e-8, eps_mgs=1e-10, m_max=4,
+                    seed=seed)
+
+
+def variable_scattering(n=80, n_theta=40, n_z=20, seed=66, p=1, q=8):
+    """Sec. 4.3: smooth transition from sigma_s = 0.1 at the centre to 100 outside r = 1."""
+    x, y = _cell_centres(n)
+    r2 = x * x + y * y
+    sig = np.where(r2 <= 1.0, 99.9 * r2 * r2 * (r2 - 2.0) ** 2 + 0.1, 100.0)
+    return _paper_example("variable_scattering", sig, n, n_theta, n_z, seed, p, q)
+
+
+def pin_cell(n=80, n_theta=32, n_z=16, seed=77, p=1, q=8):
+    """Sec. 4.4: sigma_s = 0.1 on the central square |x|, |y| <= 0.5, 100 elsewhere."""
+    x, y = _cell_centres(n)
+    sig = np.where((np.abs(x) <= 0.5) & (np.abs(y) <= 0.5), 0.1, 100.0)
+    return _paper_example("pin_cell", sig, n, n_theta, n_z, seed, p, q)
