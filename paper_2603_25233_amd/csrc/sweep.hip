@@ -626,14 +626,15 @@ static size_t max_lds_per_block() {
 }
 
 // compute threads, rows per compute thread and staging wavefronts for ny rows: a
-// staging wavefront carries srows rows, 64 (when requested and nc <= 256), 128 (when
-// requested and nc <= 640) or 256, so that the workgroup fits the kernels' thread counts
-// (960, or 768 with two rows per thread)
-static void sweep_threads(int ny, bool few_rows, int& nc, int& rpt, int& nst, int& srows) {
+// staging wavefront carries srows rows, at least `rows` (64 or 128 when requested: 64
+// only while nc <= 256, 128 while nc <= 640) and otherwise 256, so that the workgroup
+// fits the kernels' thread counts (960, or 768 with two rows per thread)
+static void sweep_threads(int ny, int rows, int& nc, int& rpt, int& nst, int& srows) {
   rpt = ny <= 768 ? 1 : 2;
   nc = ((ny + rpt - 1) / rpt + 63) / 64 * 64;
   srows = kStageRows;
-  if (few_rows && rpt == 1) srows = nc <= 256 ? 64 : (nc <= 640 ? 128 : kStageRows);
+  if (rows < kStageRows && rpt == 1)
+    srows = rows <= 64 && nc <= 256 ? 64 : (nc <= 640 ? 128 : kStageRows);
   nst = (nc * rpt + srows - 1) / srows;
 }
 
@@ -647,10 +648,12 @@ SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool
   RTE_REQUIRE(!dirs.empty(), "sweep: no directions");
   SweepPlan pl;
   // Staging wavefronts: the issue of a step's copies bounds the step when few workgroups
-  // run (small plans) and for FP64 psi; there a wavefront copies 64 rows, else 256.
+  // run (small plans: 64 rows per staging wavefront) and for FP64 psi (128 rows,
+  // measured 3 % faster than 64 at 256 rows and 512 ordinates); else 256 rows.
   const bool small = dirs.size() < 64;
   int nc, rpt, nst, srows;
-  sweep_threads(g.ny, small || (want_psi && elem_bytes == 8), nc, rpt, nst, srows);
+  sweep_threads(g.ny, small ? 64 : (want_psi && elem_bytes == 8 ? 128 : kStageRows), nc, rpt,
+                nst, srows);
   pl.nc = nc;
   pl.nt = nc + 64 * nst;
   pl.rpt = rpt;
