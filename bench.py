@@ -123,6 +123,9 @@ def paper_examples(R, W, torch, dev):
     cases = [("sec4.1 homogeneous sigma_s=%g L=%d" % (sg, L), W.homogeneous(sg, L))
              for L in (2, 3, 4, 5) for sg in (0.1, 1.0, 10.0, 100.0)]
     cases += [("sec4.3 variable scattering", W.variable_scattering()),
+              # fully greedy selection: every unsampled ordinate class a candidate (400
+              # classes of CL(40,20), Omega_z twins folded)
+              ("sec4.3 variable scattering, fully greedy", W.variable_scattering(q=400)),
               ("sec4.4 pin cell", W.pin_cell())]
     for name, wl in cases:
         d, w = R.cl_quadrature(wl["n_theta"], wl["n_z"])

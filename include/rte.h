@@ -125,7 +125,9 @@ typedef struct {
                             (full_rank only); G must be NULL                          */
   int32_t use_dsa;       /* 1: apply the diffusion correction (default 1)            */
   int32_t p;             /* angles added per inner iteration (>= 1)                   */
-  int32_t q;             /* random candidates per inner iteration (>= p)              */
+  int32_t q;             /* random candidates per inner iteration (p <= q <= number of
+                            ordinate classes; q >= the unsampled count makes every
+                            unsampled class a candidate: fully greedy selection)      */
   int32_t m_max;         /* MGS2-A cleanup passes (Alg. 2), 4 in the paper            */
   int32_t max_outer;     /* cap on outer iterations                                   */
   int32_t max_rank;      /* cap on the basis size (0: number of distinct angles)      */

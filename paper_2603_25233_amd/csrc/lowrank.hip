@@ -1194,6 +1194,9 @@ struct Stream {
   }
 };
 
+// candidates whose residuals are evaluated together (X C for at most 32 columns)
+constexpr int kCandChunk = 32;
+
 std::vector<int> draw(Stream& s, std::vector<int> pool, int k) {
   std::sort(pool.begin(), pool.end());
   const int n = (int)pool.size();
@@ -1320,7 +1323,7 @@ struct LowRank {
     RTE_REQUIRE(p <= kMaxP, "p = %d exceeds the supported maximum %d", p, kMaxP);
     RTE_REQUIRE((size_t)2 * p * rcap * sizeof(double) <= 65536,
                 "p * max_rank = %d too large for the bordered factorisation", p * rcap);
-    RTE_REQUIRE(prm->q <= 32, "q = %d exceeds the supported maximum 32", prm->q);
+    RTE_REQUIRE(prm->q <= K, "q = %d exceeds the number of ordinate classes %d", prm->q, K);
     const bool mixed = sizeof(T) == sizeof(float);
     eps_mgs = mixed ? std::max(prm->eps_mgs, 1e-6) : prm->eps_mgs;
     tol_break = mixed ? 1e-6 : 1e-12;
@@ -1702,9 +1705,23 @@ struct LowRank {
   }
 
   // Galerkin solves and residual norms of the candidates (host values in draw order)
+  // Residual norms of the candidates, evaluated kCandChunk at a time (q may exceed it:
+  // with q >= the number of unsampled ordinates every one of them is a candidate, the
+  // fully greedy selection).
   std::vector<double> residuals(const std::vector<int>& cand) {
+    const int ntot = (int)cand.size();
+    std::vector<double> out(ntot, 0.0);
+    for (int c0 = 0; c0 < ntot; c0 += kCandChunk) {
+      const int nm = std::min(kCandChunk, ntot - c0);
+      residual_chunk(std::vector<int>(cand.begin() + c0, cand.begin() + c0 + nm), out.data() + c0);
+    }
+    for (auto& x : out) x = std::sqrt(x);
+    return out;
+  }
+
+  // squared residual norms of nm <= kCandChunk candidates into out (synchronous)
+  void residual_chunk(const std::vector<int>& cand, double* out) {
     const int nm = (int)cand.size();
-    std::vector<double> out(nm, 0.0);
     const int* dl = upload_list(1, cand);
     if (r > 0) {
       hipLaunchKernelGGL(backsub_kernel, dim3((unsigned)nm), dim3(kLuThreads),
@@ -1722,10 +1739,8 @@ struct LowRank {
                        dl, d_cd.get(), rpart.get());
     reduce_cols(rpart.get(), rblk, nm, nm, rsums.get(), nullptr, st);
     RTE_CHECK_HIP(hipGetLastError());
-    RTE_CHECK_HIP(hipMemcpyAsync(out.data(), rsums.get(), nm * sizeof(double), hipMemcpyDeviceToHost, st));
+    RTE_CHECK_HIP(hipMemcpyAsync(out, rsums.get(), nm * sizeof(double), hipMemcpyDeviceToHost, st));
     sync();
-    for (auto& x : out) x = std::sqrt(x);
-    return out;
   }
 
   // phi_k = X (C w) with the current coefficients; Bsvd optional

@@ -76,6 +76,9 @@ LR_CASES = [
     ("homog16_s10", W.homogeneous(10.0, 1), 1, 8),
     ("varscat16", W.variable_scattering(n=16, n_theta=8, n_z=4), 1, 8),
     ("pincell16", W.pin_cell(n=16, n_theta=8, n_z=4), 1, 8),
+    # fully greedy (every unsampled class a candidate: q = 64 >= N_Omega / 2 classes),
+    # candidates evaluated in several chunks of 32
+    ("greedy_small20", W.small_fr(n=20, n_theta=16, n_z=8), 2, 64),
 ]
 
 
