@@ -255,7 +255,9 @@ typedef __attribute__((address_space(3))) void lds_void;
 // cells (none in the others), so that the counts waited for are constants of the kernel
 // and the staging loop keeps no per-step tallies.
 //
-// Output.  With use_ring, step t leaves its results in LDS ring slot t mod kRingSlots
+// Output mode OUT (compile time): bit 0 the LDS ring, bit 1 psi, bit 2 the weighted
+// partial sums of the scalar flux (psi and the partial sums together only for D = 1).
+// With the ring, step t leaves its results in LDS ring slot t mod kRingSlots
 // (per direction for psi, or the weighted sum over the group's directions for the
 // scalar flux).  A row's cells are grouped into aligned chunks of kChunkCells
 // physical columns; at the start of step t each compute wavefront writes back, from
@@ -263,13 +265,16 @@ typedef __attribute__((address_space(3))) void lds_void;
 // in kChunkCells, plus the short end chunk of one row when nx is not a multiple of
 // kChunkCells and the sweep runs towards +x), so every store instruction writes whole
 // 128-byte lines.  Without the ring (LDS too small) each thread stores its cell.
-template <typename T, int D, int NTB, int RPT, int SR>
+template <typename T, int D, int NTB, int RPT, int SR, int OUT>
 __global__ __launch_bounds__(NTB) void sweep_kernel(
-    int nx, int ny, int mb, int nc, int use_ring, double shx, double shy,
+    int nx, int ny, int mb, int nc, double shx, double shy,
     const SweepDir* __restrict__ dirs, const T* __restrict__ dsrc_all,
     const T* __restrict__ dsig_all, const T* __restrict__ dbnd_all, const double* __restrict__ bc,
     T* __restrict__ psi, T* __restrict__ part, long ndof) {
   using WB = WriteBack<T>;
+  constexpr bool RING = (OUT & 1) != 0, PSI = (OUT & 2) != 0, PP = (OUT & 4) != 0;
+  static_assert(PSI || PP, "no output");
+  static_assert(!(PSI && PP) || D == 1, "psi with the scalar flux needs one direction per workgroup");
   constexpr int CW = WB::kChunkCells, NS = WB::kRingSlots, LPC = WB::kLanesPerCell;
   constexpr int CPC = 4 * (int)sizeof(T) / 16;  // 16-byte pieces per source cell
   constexpr int CPS = 16 / (int)sizeof(T);      // sigma_t cells per 16-byte piece
@@ -277,7 +282,7 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
   const int tid = threadIdx.x;
   const int nr = nc * RPT;                    // padded rows
   const int nrs = nr + 2 * CPS;               // sigma_t slot length
-  const int RD = psi ? D : 1;                 // ring entries per row and step
+  constexpr int RD = PSI ? D : 1;             // ring entries per row and step
   constexpr int BS = kPiece<T>;                // elements of a 16-byte piece
   T* vbuf = reinterpret_cast<T*>(smem_raw);   // [2][nr][D][2] y-inflow traces by row
   constexpr int S = kInSlots;
@@ -450,19 +455,19 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
   auto put_cell = [&](long c, int slot, int r) {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      if (d > 0 && !psi) break;
+      if (d > 0 && !PSI) break;
       const T* e = ring + (((long)slot * nr + r) * RD + d) * 4 + eoff;
       if constexpr (sizeof(T) == 8) {
         const double2 v = *reinterpret_cast<const double2*>(e);
-        if (pdst[d]) *reinterpret_cast<double2*>(pdst[d] + 4 * c + eoff) = v;
-        if (pp) {
+        if (PSI && pdst[d]) *reinterpret_cast<double2*>(pdst[d] + 4 * c + eoff) = v;
+        if constexpr (PP) {
           const double2 wv = D == 1 ? make_double2(w0 * v.x, w0 * v.y) : v;
           *reinterpret_cast<double2*>(pp + 4 * c + eoff) = wv;
         }
       } else {
         const float4 v = *reinterpret_cast<const float4*>(e);
-        if (pdst[d]) *reinterpret_cast<float4*>(pdst[d] + 4 * c) = v;
-        if (pp) {
+        if (PSI && pdst[d]) *reinterpret_cast<float4*>(pdst[d] + 4 * c) = v;
+        if constexpr (PP) {
           const float4 wv = D == 1 ? make_float4(w0 * v.x, w0 * v.y, w0 * v.z, w0 * v.w) : v;
           *reinterpret_cast<float4*>(pp + 4 * c) = wv;
         }
@@ -505,7 +510,8 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
   int si = 0;       // t mod 3: input slot
   for (int t = 0; t < nsteps; ++t) {
     const int sl = t & 1;
-    if (use_ring && t > 0) write_back(t, ns);
+    if constexpr (RING)
+      if (t > 0) write_back(t, ns);
     const int lo = t >= nx ? t - nx + 1 : 0;
     const T* sigs = in_sig + (long)si * nrs + ((-lo) & (CPS - 1));
 #pragma unroll
@@ -530,14 +536,14 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
           wr[2 * d] = cell.vo[0];
           wr[2 * d + 1] = cell.vo[1];
           const T ph[4] = {cell.p[0], fx * cell.p[1], fy * cell.p[2], fxy * cell.p[3]};
-          if (psi) {
-            if (use_ring) {
+          if constexpr (PSI) {
+            if constexpr (RING) {
               store4(rg + 4 * d, ph);
             } else {
               const int brow = sy > 0 ? r : ny - 1 - r;
               const long c = (long)brow * nx + (sx > 0 ? ap : nx - 1 - ap);
               if (pdst[d]) store4(pdst[d] + 4 * c, ph);
-              if (pp) {  // D == 1 here
+              if constexpr (PP) {  // D == 1 here
                 T wv[4];
 #pragma unroll
                 for (int m = 0; m < 4; ++m) wv[m] = w0 * ph[m];
@@ -549,8 +555,8 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
             for (int m = 0; m < 4; ++m) acc[m] = D == 1 ? ph[m] : acc[m] + w[d] * ph[m];
           }
         }
-        if (!psi) {
-          if (use_ring) {
+        if constexpr (!PSI) {
+          if constexpr (RING) {
             store4(rg, acc);
           } else {
             const int brow = sy > 0 ? r : ny - 1 - r;
@@ -566,7 +572,7 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
     ns = ns + 1 == NS ? 0 : ns + 1;
     si = si + 1 == S ? 0 : si + 1;
   }
-  if (use_ring) write_back(nsteps, ns);  // chunks closed by the last step
+  if constexpr (RING) write_back(nsteps, ns);  // chunks closed by the last step
 }
 
 // phi[i] = sum_g part[g][i] in group order (deterministic).
@@ -717,9 +723,31 @@ void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
   const size_t lds = sweep_lds_bytes(pl.nc * pl.rpt, pl.D, psi != nullptr, pl.ring != 0, sizeof(T));
   dim3 grid(pl.ngroups), block(pl.nt);
   T* pp = phi ? part : nullptr;
-#define RTE_SWEEP_CASE(DD, NTB, RP, SR)                                                        \
-  hipLaunchKernelGGL((sweep_kernel<T, DD, NTB, RP, SR>), grid, block, lds, st, g.nx, g.ny, g.mb,  \
-                     pl.nc, pl.ring, shx, shy, dirs_dev, dsrc, dsig, dbnd, bc, psi, pp, g.ndof)
+  // output mode: bit 0 the LDS ring, bit 1 psi, bit 2 the scalar-flux partial sums
+  const int mode = (pl.ring ? 1 : 0) | (psi ? 2 : 0) | (pp ? 4 : 0);
+#define RTE_SWEEP_K(DD, NTB, RP, SR, M)                                                         \
+  hipLaunchKernelGGL((sweep_kernel<T, DD, NTB, RP, SR, M>), grid, block, lds, st, g.nx, g.ny,    \
+                     g.mb, pl.nc, shx, shy, dirs_dev, dsrc, dsig, dbnd, bc, psi, pp, g.ndof)
+#define RTE_SWEEP_CASE(DD, NTB, RP, SR)                        \
+  do {                                                         \
+    if constexpr (DD == 1) {                                   \
+      switch (mode) {                                          \
+        case 2: RTE_SWEEP_K(DD, NTB, RP, SR, 2); break;        \
+        case 3: RTE_SWEEP_K(DD, NTB, RP, SR, 3); break;        \
+        case 4: RTE_SWEEP_K(DD, NTB, RP, SR, 4); break;        \
+        case 5: RTE_SWEEP_K(DD, NTB, RP, SR, 5); break;        \
+        case 6: RTE_SWEEP_K(DD, NTB, RP, SR, 6); break;        \
+        case 7: RTE_SWEEP_K(DD, NTB, RP, SR, 7); break;        \
+        default: bad();                                        \
+      }                                                        \
+    } else if (mode == 4) {                                    \
+      RTE_SWEEP_K(DD, NTB, RP, SR, 4);                         \
+    } else if (mode == 5) {                                    \
+      RTE_SWEEP_K(DD, NTB, RP, SR, 5);                         \
+    } else {                                                   \
+      bad();                                                   \
+    }                                                          \
+  } while (0)
   // FP64 plans use D = 2 only with at most 576 threads (register budget)
 #define RTE_SWEEP_D(NTB, RP, SR)                                     \
   if (pl.D == 1) RTE_SWEEP_CASE(1, NTB, RP, SR);                     \
@@ -753,6 +781,7 @@ void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
   }
 #undef RTE_SWEEP_D
 #undef RTE_SWEEP_CASE
+#undef RTE_SWEEP_K
   RTE_CHECK_HIP(hipGetLastError());
   if (phi) {
     const int tb = 256;
