@@ -295,7 +295,7 @@ def main():
         "sweep_kernel": {"updates_per_s": k1_updates / (k1_ms * 1e-3), "ms": k1_ms,
                          "launch": "diag_layout_kernel, then sweep_kernel: 1 ordinate per "
                                    "workgroup (512 workgroups, 2 per CU), 256 compute threads "
-                                   "(one per row) + 2 staging wavefronts of 128 rows"},
+                                   "(one per row) + 2 staging wavefronts of 128 rows + 4 write-back wavefronts of 64 rows"},
         "roofline": {"kernel": "psi sweep (diag_layout_kernel + sweep_kernel), full angle set",
                      "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -301,26 +301,35 @@ __global__ void coef_col_kernel(const double* __restrict__ cb, int pn, int l, in
   if (i < n) cvec[i] = i < r0 ? cb[(long)i * pn + l] : 0.0;
 }
 // out[c] = sum_b part[b][c] for c < n (and acc_into[c] += out[c] for c < n_acc).  A block of
-// 256 threads handles 8 columns: 32 lanes per column take every 32nd partial (four
-// running sums, fixed assignment), then a fixed pairwise tree combines the lanes, so
-// the sum is the same on every run.
+// 256 threads handles 8 columns: 32 lanes per column take every 32nd partial (eight
+// running sums, fixed assignment), then fixed pairwise trees combine the sums and the
+// lanes, so the result is the same on every run.
 __global__ __launch_bounds__(256) void reduce_cols_kernel(const double* __restrict__ part, int nblk,
                                                           int stride, int n, double* __restrict__ out,
                                                           double* __restrict__ acc_into, int n_acc) {
+  constexpr int NS = 8;
   __shared__ double red[256];
   const int c = blockIdx.x * 8 + (threadIdx.x >> 5);
   const int l = threadIdx.x & 31;
-  double s4[4] = {0.0, 0.0, 0.0, 0.0};
-  if (c < n) {
-    int b = l;
-    for (; b + 96 < nblk; b += 128)
+  double sv[NS];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) s4[u] += part[(long)(b + 32 * u) * stride + c];
-    if (b < nblk) s4[0] += part[(long)b * stride + c];
-    if (b + 32 < nblk) s4[1] += part[(long)(b + 32) * stride + c];
-    if (b + 64 < nblk) s4[2] += part[(long)(b + 64) * stride + c];
+  for (int u = 0; u < NS; ++u) sv[u] = 0.0;
+  if (c < n) {
+    // Every load is issued from a row clamped into range and masked at the add, so that
+    // none waits behind a branch.
+    for (int b0 = l; b0 - l < nblk; b0 += 32 * NS) {
+      double v[NS];
+#pragma unroll
+      for (int u = 0; u < NS; ++u) v[u] = part[(long)min(b0 + 32 * u, nblk - 1) * stride + c];
+#pragma unroll
+      for (int u = 0; u < NS; ++u) sv[u] += b0 + 32 * u < nblk ? v[u] : 0.0;
+    }
   }
-  red[threadIdx.x] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+#pragma unroll
+  for (int h = NS / 2; h > 0; h >>= 1)
+#pragma unroll
+    for (int u = 0; u < h; ++u) sv[u] += sv[u + h];
+  red[threadIdx.x] = sv[0];
   __syncthreads();
   for (int h = 16; h > 0; h >>= 1) {
     if (l < h) red[threadIdx.x] += red[threadIdx.x + h];

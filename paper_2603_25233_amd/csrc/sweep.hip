@@ -228,8 +228,9 @@ struct WriteBack {
   static constexpr int kChunkCells = 128 / kCellBytes;  // 4 (FP64) or 8 (FP32)
   static constexpr int kLanesPerCell = kCellBytes / 16;  // 2 or 1
   static constexpr int kRingSlots = kChunkCells + 1;
-  static constexpr int kInstr = 64 / kChunkCells / 8;    // store instructions per wave and step
 };
+// Rows whose chunks one write-back wavefront stores.
+constexpr int kWbRows = 64;
 
 typedef __attribute__((address_space(3))) void lds_void;
 
@@ -239,9 +240,10 @@ typedef __attribute__((address_space(3))) void lds_void;
 //
 // Roles.  The first nc threads compute; compute thread j owns the canonical rows
 // j + k nc, k < RPT (both on the current anti-diagonal, so they are independent
-// work).  The remaining wavefronts stage inputs, 256 rows each, with direct
-// global-to-LDS loads.  Compute wavefronts read their inputs from LDS and issue only
-// global stores, which they never wait for.
+// work).  The next wavefronts stage inputs, SR rows each, with direct global-to-LDS
+// loads.  With the LDS output ring, the last wavefronts (one per kWbRows rows) store
+// the results from the ring.  Compute wavefronts read their inputs from LDS and issue
+// only LDS writes with the ring, otherwise global stores, which they never wait for.
 //
 // Per step t: the compute threads solve the cells of canonical column t - r, taking
 // the source and sigma_t of step t from LDS input slot t mod 3 and the y-inflow trace
@@ -260,11 +262,13 @@ typedef __attribute__((address_space(3))) void lds_void;
 // With the ring, step t leaves its results in LDS ring slot t mod kRingSlots
 // (per direction for psi, or the weighted sum over the group's directions for the
 // scalar flux).  A row's cells are grouped into aligned chunks of kChunkCells
-// physical columns; at the start of step t each compute wavefront writes back, from
-// the ring, the chunks of its rows whose last cell was solved at step t - 1 (one row
-// in kChunkCells, plus the short end chunk of one row when nx is not a multiple of
-// kChunkCells and the sweep runs towards +x), so every store instruction writes whole
-// 128-byte lines.  Without the ring (LDS too small) each thread stores its cell.
+// physical columns; while step t is solved the write-back wavefronts store, from the
+// ring, the chunks whose last cell was solved at step t - 1 (one row in kChunkCells,
+// plus the short end chunk of one row when nx is not a multiple of kChunkCells and the
+// sweep runs towards +x), so every store instruction writes whole 128-byte lines and
+// the compute wavefronts' step does not wait for them.  Without the ring (LDS too
+// small, or plans too small for the store bandwidth to matter) each thread stores its
+// cell.
 template <typename T, int D, int NTB, int RPT, int SR, int OUT>
 __global__ __launch_bounds__(NTB) void sweep_kernel(
     int nx, int ny, int mb, int nc, double shx, double shy,
@@ -297,11 +301,109 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
   const long ncell = (long)nx * ny;
   const int q = (sx < 0 ? 1 : 0) + (sy < 0 ? 2 : 0);
   const int nsteps = nx + ny - 1;
+  const int nst = (nr + SR - 1) / SR;  // staging wavefronts
+  if (RING && tid >= nc + 64 * nst) {
+    // ---------------------------------------------- write-back wavefronts
+    // The rows are taken in blocks of kWbRows; write-back wavefront k stores the chunks
+    // of blocks per k .. per k + per - 1 (per = 1 unless the thread budget of the kernel
+    // left fewer wavefronts than blocks): 8 lanes (16 bytes each) per row, 8 rows per
+    // store instruction; instruction i of a block covers rows b + CW (jrow + 8 i) +
+    // rho(t), rho(t) the residue (mod CW) of the rows whose last cell closed an aligned
+    // chunk at step t - 1.  The flat cell index of a lane's cell is affine in its row and
+    // the step, and the ring slot of the cell depends on the step and the lane's cell only.
+    constexpr int NI = kWbRows / CW / 8;  // store instructions per block and step
+    const int lane = tid & 63;
+    const int nwb = (int)(blockDim.x >> 6) - ((nc >> 6) + nst);
+    const int nblk = (nr + kWbRows - 1) / kWbRows;
+    const int per = (nblk + nwb - 1) / nwb;
+    const int wb0 = ((tid - nc - 64 * nst) >> 6) * per * kWbRows;
+    const int wb1 = wb0 + per * kWbRows;  // rows wb0 .. wb1 - 1
+    const int jrow = lane >> 3;
+    const int cc = (lane & 7) / LPC, half = lane % LPC;  // cell within the chunk, piece
+    T* pdst = PSI && psi && grp[0].slot >= 0 ? psi + (long)grp[0].slot * ndof : nullptr;
+    T* pp = part ? part + (long)blockIdx.x * ndof : nullptr;
+    const T w0 = T(grp[0].w);
+    const long Cr = (long)sy * nx - sx;
+    const long C0 = (sy > 0 ? 0 : (long)(ny - 1) * nx) + (sx > 0 ? -CW : nx);
+    const int roff = sx > 0 ? 1 + cc : NS - 1 - cc;  // ring slot = (t + roff) mod NS
+    const int eoff = half * (16 / (int)sizeof(T));
+    // One ring entry per row and step: psi of the one direction (psi plans have D = 1),
+    // or the weighted sum over the group's directions.
+    static_assert(!PSI || D == 1, "psi write-back with one direction per workgroup");
+    using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+    // the ring piece of row r in slot `slot`
+    auto ring_piece = [&](int slot, int r) {
+      return *reinterpret_cast<const V*>(ring + ((long)slot * nr + r) * 4 + eoff);
+    };
+    // psi (and, for one direction, the weighted partial sum) of the cell c
+    auto put_piece = [&](long c, const V& v) {
+      if constexpr (sizeof(T) == 8) {
+        if (PSI && pdst) *reinterpret_cast<double2*>(pdst + 4 * c + eoff) = v;
+        if constexpr (PP) {
+          const double2 wv = D == 1 ? make_double2(w0 * v.x, w0 * v.y) : v;
+          *reinterpret_cast<double2*>(pp + 4 * c + eoff) = wv;
+        }
+      } else {
+        if (PSI && pdst) *reinterpret_cast<float4*>(pdst + 4 * c) = v;
+        if constexpr (PP) {
+          const float4 wv = D == 1 ? make_float4(w0 * v.x, w0 * v.y, w0 * v.z, w0 * v.w) : v;
+          *reinterpret_cast<float4*>(pp + 4 * c) = wv;
+        }
+      }
+    };
+    const int endc = nx % CW;  // cells in the short end chunk of a row (0: none)
+    // Chunks closed by the cells solved at step t - 1 (st = t mod NS).
+    auto write_back = [&](int t, int st) {
+      const int rho = (sx > 0 ? t : t - nx) & (CW - 1);
+      const long cu = Cr * rho + (long)sx * t;
+      int slot = st + roff;
+      slot = slot >= NS ? slot - NS : slot;
+      for (int b = wb0; b < wb1; b += kWbRows) {
+        // all ring reads of the block first (rows clamped into the ring), then the
+        // stores, so that one LDS round trip serves them
+        V v[NI];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+          const int r = b + CW * (jrow + 8 * i) + rho;
+          v[i] = ring_piece(slot, r < nr ? r : nr - 1);
+        }
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+          const int r = b + CW * (jrow + 8 * i) + rho;
+          const int apl = t - 1 - r;  // canonical column solved at step t - 1
+          const bool ok = r < ny && (unsigned)apl < (unsigned)nx &&
+                          (sx > 0 || nx - 1 - apl + cc < nx);
+          if (ok) put_piece(C0 + Cr * (r - rho) + cc + cu, v[i]);
+        }
+      }
+      // the short end chunk of row t - nx (towards +x only)
+      if (sx > 0 && endc != 0) {
+        const int r = t - nx;
+        if (r >= wb0 && r < wb1 && r < ny && jrow == 0 && cc < endc) {
+          const int col = nx - endc + cc;
+          const int brow = sy > 0 ? r : ny - 1 - r;
+          put_piece((long)brow * nx + col, ring_piece((r + col) % NS, r));
+        }
+      }
+    };
+    // Step t's chunks close at step t - 1 and leave while step t is solved: the ring
+    // slot written in step t is none of the CW read here, and the reads have landed
+    // before this wavefront reaches the barrier that ends step t.
+    __syncthreads();  // step 0 staged
+    int ns = 0;       // t mod NS
+    for (int t = 0; t < nsteps; ++t) {
+      if (t > 0) write_back(t, ns);
+      __syncthreads();
+      ns = ns + 1 == NS ? 0 : ns + 1;
+    }
+    write_back(nsteps, ns);  // chunks closed by the last step
+    return;
+  }
   if (tid >= nc) {
     // ------------------------------------------------ staging wavefronts
     // Step t's cells are rows lo..hi of anti-diagonal t, contiguous in the
-    // diagonal-major arrays.  Staging wavefront sw copies rows lo + 256 sw ..
-    // lo + 256 sw + 255 (16 bytes per lane, lanes past the step masked off): the
+    // diagonal-major arrays.  Staging wavefront sw copies rows lo + SR sw ..
+    // lo + SR sw + SR - 1 (16 bytes per lane, lanes past the step masked off): the
     // source to in_src rows lo.., sigma_t to in_sig positions sh(t) + lo.., where
     // sh(t) = -lo mod CPS keeps the copy 16-byte aligned on both sides.
     const int lane = tid & 63;
@@ -424,94 +526,19 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
       u[k][d][1] = T(shx) * g1 * fy;
     }
   }
-  // output bases per direction (null: padding direction or no psi)
+  // output bases per direction (null: padding direction or no psi); without the ring
+  // each thread stores its cells
   T* pdst[D];
 #pragma unroll
   for (int d = 0; d < D; ++d)
-    pdst[d] = psi && grp[d].slot >= 0 ? psi + (long)grp[d].slot * ndof : nullptr;
-  T* pp = part ? part + (long)blockIdx.x * ndof : nullptr;
+    pdst[d] = !RING && psi && grp[d].slot >= 0 ? psi + (long)grp[d].slot * ndof : nullptr;
+  T* pp = !RING && part ? part + (long)blockIdx.x * ndof : nullptr;
   const T w0 = T(grp[0].w);
-  // Write-back lanes: 8 per row (16 bytes each), 8 rows per store instruction;
-  // instruction i of block k covers rows wrow[k][i] + rho(t), rho(t) the residue
-  // (mod CW) of the rows whose last cell closed an aligned chunk.  The flat cell index
-  // of a lane's cell is affine in its row and the step: c = clane + (Cr rho + sx t),
-  // and the ring slot of the cell depends on the step and the lane's cell only.
-  const int lane = tid & 63, wbase = tid & ~63;
-  const int jrow = lane >> 3;
-  const int cc = (lane & 7) / LPC, half = lane % LPC;  // cell within the chunk, piece
-  const long Cr = (long)sy * nx - sx;
-  const long C0 = (sy > 0 ? 0 : (long)(ny - 1) * nx) + (sx > 0 ? -CW : nx);
-  int wrow[RPT][WB::kInstr];
-  long clane[RPT][WB::kInstr];
-#pragma unroll
-  for (int k = 0; k < RPT; ++k)
-#pragma unroll
-    for (int i = 0; i < WB::kInstr; ++i) {
-      wrow[k][i] = wbase + k * nc + CW * (jrow + 8 * i);
-      clane[k][i] = C0 + Cr * wrow[k][i] + cc;
-    }
-  const int roff = sx > 0 ? 1 + cc : NS - 1 - cc;  // ring slot = (t + roff) mod NS
-  const int eoff = half * (16 / (int)sizeof(T));
-  auto put_cell = [&](long c, int slot, int r) {
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      if (d > 0 && !PSI) break;
-      const T* e = ring + (((long)slot * nr + r) * RD + d) * 4 + eoff;
-      if constexpr (sizeof(T) == 8) {
-        const double2 v = *reinterpret_cast<const double2*>(e);
-        if (PSI && pdst[d]) *reinterpret_cast<double2*>(pdst[d] + 4 * c + eoff) = v;
-        if constexpr (PP) {
-          const double2 wv = D == 1 ? make_double2(w0 * v.x, w0 * v.y) : v;
-          *reinterpret_cast<double2*>(pp + 4 * c + eoff) = wv;
-        }
-      } else {
-        const float4 v = *reinterpret_cast<const float4*>(e);
-        if (PSI && pdst[d]) *reinterpret_cast<float4*>(pdst[d] + 4 * c) = v;
-        if constexpr (PP) {
-          const float4 wv = D == 1 ? make_float4(w0 * v.x, w0 * v.y, w0 * v.z, w0 * v.w) : v;
-          *reinterpret_cast<float4*>(pp + 4 * c) = wv;
-        }
-      }
-    }
-  };
-  const int endc = nx % CW;  // cells in the short end chunk of a row (0: none)
-  // Chunks closed by the cells solved at step t - 1 (st = t mod NS).
-  auto write_back = [&](int t, int st) {
-    const int rho = (sx > 0 ? t : t - nx) & (CW - 1);
-    const long cu = Cr * rho + (long)sx * t;
-    int slot = st + roff;
-    slot = slot >= NS ? slot - NS : slot;
-#pragma unroll
-    for (int k = 0; k < RPT; ++k)
-#pragma unroll
-      for (int i = 0; i < WB::kInstr; ++i) {
-        const int r = wrow[k][i] + rho;
-        const int apl = t - 1 - r;  // canonical column solved at step t - 1
-        const bool ok = r < ny && (unsigned)apl < (unsigned)nx &&
-                        (sx > 0 || nx - 1 - apl + cc < nx);
-        if (ok) put_cell(clane[k][i] + cu, slot, r);
-      }
-    // the short end chunk of row t - nx (towards +x only)
-    if (sx > 0 && endc != 0) {
-      const int r = t - nx;
-#pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int j = r - wbase - k * nc;
-        if (r >= 0 && r < ny && j >= 0 && j < 64 && jrow == 0 && cc < endc) {
-          const int col = nx - endc + cc;
-          const int brow = sy > 0 ? r : ny - 1 - r;
-          put_cell((long)brow * nx + col, (r + col) % NS, r);
-        }
-      }
-    }
-  };
   __syncthreads();  // step 0 staged
   int ns = 0;       // t mod NS
   int si = 0;       // t mod 3: input slot
   for (int t = 0; t < nsteps; ++t) {
     const int sl = t & 1;
-    if constexpr (RING)
-      if (t > 0) write_back(t, ns);
     const int lo = t >= nx ? t - nx + 1 : 0;
     const T* sigs = in_sig + (long)si * nrs + ((-lo) & (CPS - 1));
 #pragma unroll
@@ -572,7 +599,6 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
     ns = ns + 1 == NS ? 0 : ns + 1;
     si = si + 1 == S ? 0 : si + 1;
   }
-  if constexpr (RING) write_back(nsteps, ns);  // chunks closed by the last step
 }
 
 // phi[i] = sum_g part[g][i] in group order (deterministic).
@@ -644,6 +670,9 @@ static void sweep_threads(int ny, int rows, int& nc, int& rpt, int& nst, int& sr
   nst = (nc * rpt + srows - 1) / srows;
 }
 
+// Accelerator complex dies (XCDs) of the device, each with its own L2
+constexpr int kXcds = 8;
+
 // LDS per workgroup that still lets two workgroups share a compute unit (160 KB)
 constexpr size_t kLdsTwoPerCU = 80 * 1024;
 
@@ -661,7 +690,7 @@ SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool
   sweep_threads(g.ny, small ? 64 : (want_psi && elem_bytes == 8 ? 128 : kStageRows), nc, rpt,
                 nst, srows);
   pl.nc = nc;
-  pl.nt = nc + 64 * nst;
+  pl.nt = nc + 64 * nst;  // write-back wavefronts are added below with the ring
   pl.rpt = rpt;
   pl.srows = srows;
   const int nr = nc * rpt;
@@ -679,15 +708,37 @@ SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool
     D *= 2;
   // the output ring if it fits and the plan is large enough for the store bandwidth to
   // matter (else each thread stores its cells directly, which is shorter per step)
-  const bool ring = dirs.size() >= 64 && sweep_lds_bytes(nr, D, want_psi, true, elem_bytes) <= lmax;
+  // Write-back wavefronts (with the ring): one per kWbRows rows, fewer (each storing
+  // several blocks of rows) where the kernel's thread budget (FP64 with D = 2: 576,
+  // else 960) would be exceeded.
+  const int tcap = elem_bytes == 8 && D > 1 ? 576 : 960;
+  const int nwb = std::min((nr + kWbRows - 1) / kWbRows, (tcap - pl.nt) / 64);
+  const bool ring = dirs.size() >= 64 && nwb >= 1 &&
+                    sweep_lds_bytes(nr, D, want_psi, true, elem_bytes) <= lmax;
   RTE_REQUIRE(sweep_lds_bytes(nr, D, want_psi, ring, elem_bytes) <= lmax,
               "sweep: %d x %d cells need %zu bytes of LDS per workgroup (device limit %zu)", g.nx,
               g.ny, sweep_lds_bytes(nr, D, want_psi, ring, elem_bytes), lmax);
   pl.D = D;
   pl.ring = ring ? 1 : 0;
+  if (ring) pl.nt += 64 * nwb;
   pl.psi = want_psi ? 1 : 0;
   pl.groups = make_groups(dirs, D);
   pl.ngroups = (int)(pl.groups.size() / D);
+  // Workgroups are dealt to the XCDs in turn (workgroup b to XCD b mod kXcds), each with
+  // its own L2.  Giving each XCD a contiguous run of the quadrant-ordered groups lets its
+  // L2 hold the staged inputs of one or two quadrants instead of all four.
+  if (pl.ngroups >= 2 * kXcds) {
+    std::vector<SweepDir> perm(pl.groups.size());
+    const int G = pl.ngroups;
+    for (int x = 0, start = 0; x < kXcds; ++x) {
+      const int nx_ = (G - x + kXcds - 1) / kXcds;  // workgroups b = x + kXcds j < G
+      for (int j = 0; j < nx_; ++j)
+        std::copy_n(pl.groups.begin() + (long)(start + j) * D, D,
+                    perm.begin() + (long)(x + kXcds * j) * D);
+      start += nx_;
+    }
+    pl.groups.swap(perm);
+  }
   for (const auto& d : pl.groups) pl.qmask |= 1 << ((d.sx < 0 ? 1 : 0) + (d.sy < 0 ? 2 : 0));
   return pl;
 }

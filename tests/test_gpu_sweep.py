@@ -37,7 +37,13 @@ def oracle_sweep(m, do, sig_t, src, bc, sel, transpose=False, w=None):
                         want_psi=True, w=w, transpose=transpose)
 
 
-CASES = [(37, 70, 8, 4), (64, 64, 16, 8), (5, 129, 8, 2), (130, 3, 4, 2), (1, 1, 4, 2)]
+# (13, 300, 16, 4): 64 ordinates over 300 rows, the write-back ring with five write-back
+# wavefronts and a short end chunk in every row (13 columns); (7, 400, 16, 4): the
+# thread budget leaves fewer write-back wavefronts than 64-row blocks (two blocks each;
+# with FP32 the last two wavefronts' rows are all past the grid), rows shorter than one
+# FP32 chunk
+CASES = [(37, 70, 8, 4), (64, 64, 16, 8), (5, 129, 8, 2), (130, 3, 4, 2), (1, 1, 4, 2),
+         (13, 300, 16, 4), (7, 400, 16, 4)]
 
 
 @pytest.mark.parametrize("nx,ny,nt,nz", CASES)
@@ -64,7 +70,8 @@ def test_adjoint_sweep_fp64_matches_oracle(nx, ny, nt, nz):
     assert (np.abs(got - ref) / scale).max() < 1e-13
 
 
-@pytest.mark.parametrize("nx,ny,nt,nz", [(20, 30, 32, 16), (9, 40, 64, 32), (33, 17, 8, 4)])
+@pytest.mark.parametrize("nx,ny,nt,nz", [(20, 30, 32, 16), (9, 40, 64, 32), (33, 17, 8, 4),
+                                         (13, 300, 16, 4), (7, 400, 16, 4)])
 def test_scalar_flux_accumulation(nx, ny, nt, nz):
     """phi = sum_j w_j psi_j through the partial-sum path (1, 2 and 4 directions per group)."""
     import paper_2603_25233_amd as R
@@ -76,7 +83,8 @@ def test_scalar_flux_accumulation(nx, ny, nt, nz):
     assert np.abs(got - ref).max() < 1e-13 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("nx,ny,nt,nz", [(37, 70, 8, 4), (64, 64, 16, 8), (9, 40, 64, 32)])
+@pytest.mark.parametrize("nx,ny,nt,nz", [(37, 70, 8, 4), (64, 64, 16, 8), (9, 40, 64, 32),
+                                         (13, 300, 16, 4), (7, 400, 16, 4)])
 def test_sweep_fp32_within_mixed_tolerance(nx, ny, nt, nz):
     import paper_2603_25233_amd as R
     prob, m, do, wo, sig_t, src, bc = make(nx, ny, nt, nz, seed=11)
