@@ -226,6 +226,10 @@ def main():
 
     def sweep_once():
         e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+        # A short spin keeps the GPU busy while the host enqueues the sweep, so that the
+        # events bracket its kernels and not the host's launch latency (after a solver run
+        # the GPU is idle when the step starts).
+        torch.cuda._sleep(200000)
         e0.record(stream)
         plan.execute(src, psi=psi)
         e1.record(stream)

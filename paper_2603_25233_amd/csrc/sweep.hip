@@ -63,33 +63,54 @@ __device__ __forceinline__ T recip(T x) {
   }
 }
 
+// FP64: the x-coupling a L is folded into the diagonal coefficients of the first factor
+// and the second factor is expanded into three scalars (54 FP64 operations per cell).
+// FP32 keeps the factored form: the mixed-precision solves amplify the rounding of the
+// FP32 sweeps through the diffusion correction, and the factored form's rounding is the
+// one their accuracy was measured with.
 template <typename T>
 __device__ __forceinline__ void solve_cell(T sig, T a, T b, const T s[4], const T u[2],
                                            const T v[2], Cell<T>& out) {
   const T r3 = T(kSqrt3);
+  const T ar3 = r3 * a, rb = r3 * b;
   const T R0 = s[0] + a * u[0] + b * v[0];
-  const T R1 = s[1] - r3 * a * u[0] + b * v[1];
-  const T R2 = s[2] + a * u[1] - r3 * b * v[0];
-  const T R3 = s[3] - r3 * a * u[1] - r3 * b * v[1];
-  // L applied to the two p-vectors (R0,R1) and (R2,R3)
-  const T l00 = R0 + r3 * R1, l01 = T(3) * R1 - r3 * R0;
-  const T l10 = R2 + r3 * R3, l11 = T(3) * R3 - r3 * R2;
-  const T c3 = sig + T(3) * b, c1 = sig + b, rb = r3 * b;
-  const T y00 = c3 * R0 + a * l00 - rb * R2;
-  const T y01 = c3 * R1 + a * l01 - rb * R3;
-  const T y10 = rb * R0 + c1 * R2 + a * l10;
-  const T y11 = rb * R1 + c1 * R3 + a * l11;
+  const T R1 = s[1] - ar3 * u[0] + b * v[1];
+  const T R2 = s[2] + a * u[1] - rb * v[0];
+  const T R3 = s[3] - ar3 * u[1] - rb * v[1];
   const T d0 = sig * sig + T(4) * b * sig + T(6) * (b * b - a * a);
   const T d1 = T(2) * a * (sig + T(2) * (a + b));
   const T det = d0 * d0 + T(4) * d0 * d1 + T(6) * d1 * d1;
   const T inv = recip(det);  // det >= sigma^4 > 0 (sigma_t in [1e-30, 1e30])
-  const T e0 = (d0 + T(4) * d1) * inv, e1 = -d1 * inv;
-  const T m0 = y00 + r3 * y01, m1 = T(3) * y01 - r3 * y00;
-  const T n0 = y10 + r3 * y11, n1 = T(3) * y11 - r3 * y10;
-  out.p[0] = e0 * y00 + e1 * m0;
-  out.p[1] = e0 * y01 + e1 * m1;
-  out.p[2] = e0 * y10 + e1 * n0;
-  out.p[3] = e0 * y11 + e1 * n1;
+  if constexpr (sizeof(T) == 8) {
+    // (A + 3b) R_0 - sqrt3 b R_1 and sqrt3 b R_0 + (A + b) R_1 with A = sigma + a L
+    const T y00 = (sig + (T(3) * b + a)) * R0 + ar3 * R1 - rb * R2;
+    const T y01 = (sig + T(3) * (a + b)) * R1 - ar3 * R0 - rb * R3;
+    const T y10 = rb * R0 + (sig + (a + b)) * R2 + ar3 * R3;
+    const T y11 = rb * R1 + (sig + (b + T(3) * a)) * R3 - ar3 * R2;
+    // e0 I + e1 L with e0 = (d0 + 4 d1)/det, e1 = -d1/det, expanded: f1 = e0 + e1,
+    // f3 = e0 + 3 e1, g = sqrt3 e1
+    const T f1 = (d0 + T(3) * d1) * inv, f3 = (d0 + d1) * inv, g = -r3 * d1 * inv;
+    out.p[0] = f1 * y00 + g * y01;
+    out.p[1] = f3 * y01 - g * y00;
+    out.p[2] = f1 * y10 + g * y11;
+    out.p[3] = f3 * y11 - g * y10;
+  } else {
+    // L applied to the two p-vectors (R0,R1) and (R2,R3)
+    const T l00 = R0 + r3 * R1, l01 = T(3) * R1 - r3 * R0;
+    const T l10 = R2 + r3 * R3, l11 = T(3) * R3 - r3 * R2;
+    const T c3 = sig + T(3) * b, c1 = sig + b;
+    const T y00 = c3 * R0 + a * l00 - rb * R2;
+    const T y01 = c3 * R1 + a * l01 - rb * R3;
+    const T y10 = rb * R0 + c1 * R2 + a * l10;
+    const T y11 = rb * R1 + c1 * R3 + a * l11;
+    const T e0 = (d0 + T(4) * d1) * inv, e1 = -d1 * inv;
+    const T m0 = y00 + r3 * y01, m1 = T(3) * y01 - r3 * y00;
+    const T n0 = y10 + r3 * y11, n1 = T(3) * y11 - r3 * y10;
+    out.p[0] = e0 * y00 + e1 * m0;
+    out.p[1] = e0 * y01 + e1 * m1;
+    out.p[2] = e0 * y10 + e1 * n0;
+    out.p[3] = e0 * y11 + e1 * n1;
+  }
   out.uo[0] = out.p[0] + r3 * out.p[1];
   out.uo[1] = out.p[2] + r3 * out.p[3];
   out.vo[0] = out.p[0] + r3 * out.p[2];
@@ -335,19 +356,24 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
     auto ring_piece = [&](int slot, int r) {
       return *reinterpret_cast<const V*>(ring + ((long)slot * nr + r) * 4 + eoff);
     };
+    // The ring holds canonical-frame moments: the odd-in-x ones take the sign sx and the
+    // odd-in-y ones sy here (FP64: a lane's piece is (p0, p1) or (p2, p3)).
+    const T sg0 = LPC == 2 && half ? fy : T(1), sg1 = LPC == 2 && half ? fxy : fx;
+    const T wg0 = D == 1 ? w0 * sg0 : sg0, wg1 = D == 1 ? w0 * sg1 : sg1;
     // psi (and, for one direction, the weighted partial sum) of the cell c
     auto put_piece = [&](long c, const V& v) {
       if constexpr (sizeof(T) == 8) {
-        if (PSI && pdst) *reinterpret_cast<double2*>(pdst + 4 * c + eoff) = v;
-        if constexpr (PP) {
-          const double2 wv = D == 1 ? make_double2(w0 * v.x, w0 * v.y) : v;
-          *reinterpret_cast<double2*>(pp + 4 * c + eoff) = wv;
-        }
+        if (PSI && pdst)
+          *reinterpret_cast<double2*>(pdst + 4 * c + eoff) = make_double2(sg0 * v.x, sg1 * v.y);
+        if constexpr (PP)
+          *reinterpret_cast<double2*>(pp + 4 * c + eoff) = make_double2(wg0 * v.x, wg1 * v.y);
       } else {
-        if (PSI && pdst) *reinterpret_cast<float4*>(pdst + 4 * c) = v;
+        if (PSI && pdst)
+          *reinterpret_cast<float4*>(pdst + 4 * c) = make_float4(v.x, fx * v.y, fy * v.z, fxy * v.w);
         if constexpr (PP) {
-          const float4 wv = D == 1 ? make_float4(w0 * v.x, w0 * v.y, w0 * v.z, w0 * v.w) : v;
-          *reinterpret_cast<float4*>(pp + 4 * c) = wv;
+          const float wgt = D == 1 ? w0 : 1.0f;
+          *reinterpret_cast<float4*>(pp + 4 * c) =
+              make_float4(wgt * v.x, wgt * fx * v.y, wgt * fy * v.z, wgt * fxy * v.w);
         }
       }
     };
@@ -401,6 +427,11 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
   }
   if (tid >= nc) {
     // ------------------------------------------------ staging wavefronts
+    // Issue priority: staging wavefronts first, then compute, then write-back.  A copy
+    // issued late lands late and holds up the barrier that waits for it; giving the
+    // staging wavefronts the top priority took the full-angle sweep from 473 to 458 us
+    // (FP64) and from 318 to 285 us (FP32).
+    __builtin_amdgcn_s_setprio(3);
     // Step t's cells are rows lo..hi of anti-diagonal t, contiguous in the
     // diagonal-major arrays.  Staging wavefront sw copies rows lo + SR sw ..
     // lo + SR sw + SR - 1 (16 bytes per lane, lanes past the step masked off): the
@@ -499,6 +530,7 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
     return;
   }
   // -------------------------------------------------- compute wavefronts
+  __builtin_amdgcn_s_setprio(2);  // below the staging wavefronts, above the write-back
   T a[D], b[D], w[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) {
@@ -562,7 +594,14 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
           u[k][d][1] = cell.uo[1];
           wr[2 * d] = cell.vo[0];
           wr[2 * d + 1] = cell.vo[1];
-          const T ph[4] = {cell.p[0], fx * cell.p[1], fy * cell.p[2], fxy * cell.p[3]};
+          // back to the physical frame's signs of the odd moments; with the ring the
+          // write-back wavefronts apply them
+          T ph[4] = {cell.p[0], cell.p[1], cell.p[2], cell.p[3]};
+          if constexpr (!RING) {
+            ph[1] *= fx;
+            ph[2] *= fy;
+            ph[3] *= fxy;
+          }
           if constexpr (PSI) {
             if constexpr (RING) {
               store4(rg + 4 * d, ph);
@@ -683,11 +722,12 @@ SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool
   RTE_REQUIRE(!dirs.empty(), "sweep: no directions");
   SweepPlan pl;
   // Staging wavefronts: the issue of a step's copies bounds the step when few workgroups
-  // run (small plans: 64 rows per staging wavefront) and for FP64 psi (128 rows,
-  // measured 3 % faster than 64 at 256 rows and 512 ordinates); else 256 rows.
+  // run (small plans: 64 rows per staging wavefront) and for psi (128 rows; at 256 rows
+  // and 512 ordinates FP64 measured 3 % faster than 64 and 7 % faster than 256, FP32 1 %
+  // faster than 256); else 256 rows.
   const bool small = dirs.size() < 64;
   int nc, rpt, nst, srows;
-  sweep_threads(g.ny, small ? 64 : (want_psi && elem_bytes == 8 ? 128 : kStageRows), nc, rpt,
+  sweep_threads(g.ny, small ? 64 : (want_psi ? 128 : kStageRows), nc, rpt,
                 nst, srows);
   pl.nc = nc;
   pl.nt = nc + 64 * nst;  // write-back wavefronts are added below with the ring
@@ -709,9 +749,9 @@ SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool
   // the output ring if it fits and the plan is large enough for the store bandwidth to
   // matter (else each thread stores its cells directly, which is shorter per step)
   // Write-back wavefronts (with the ring): one per kWbRows rows, fewer (each storing
-  // several blocks of rows) where the kernel's thread budget (FP64 with D = 2: 576,
-  // else 960) would be exceeded.
-  const int tcap = elem_bytes == 8 && D > 1 ? 576 : 960;
+  // several blocks of rows) where the kernel's thread budget (two rows per thread: 768;
+  // FP64 with D = 2: 576; else 960) would be exceeded.
+  const int tcap = rpt == 2 ? 768 : elem_bytes == 8 && D > 1 ? 576 : 960;
   const int nwb = std::min((nr + kWbRows - 1) / kWbRows, (tcap - pl.nt) / 64);
   const bool ring = dirs.size() >= 64 && nwb >= 1 &&
                     sweep_lds_bytes(nr, D, want_psi, true, elem_bytes) <= lmax;
@@ -777,6 +817,7 @@ void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
   // output mode: bit 0 the LDS ring, bit 1 psi, bit 2 the scalar-flux partial sums
   const int mode = (pl.ring ? 1 : 0) | (psi ? 2 : 0) | (pp ? 4 : 0);
 #define RTE_SWEEP_K(DD, NTB, RP, SR, M)                                                         \
+  RTE_REQUIRE(pl.nt <= NTB, "internal: %d threads for a sweep kernel of %d", pl.nt, NTB);        \
   hipLaunchKernelGGL((sweep_kernel<T, DD, NTB, RP, SR, M>), grid, block, lds, st, g.nx, g.ny,    \
                      g.mb, pl.nc, shx, shy, dirs_dev, dsrc, dsig, dbnd, bc, psi, pp, g.ndof)
 #define RTE_SWEEP_CASE(DD, NTB, RP, SR)                        \
