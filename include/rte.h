@@ -231,6 +231,14 @@ rte_status rte_box_source_moments(int32_t nx, int32_t ny, double x0, double x1, 
                                   double y1, double value, double bx0, double bx1,
                                   double by0, double by1, double* G_host);
 
+/* Adds the face moments of a constant isotropic inflow g = value on boundary face
+ * `index` of side `side` (0 L, 1 R, 2 B, 3 T; index along y on L/R, along x on B/T) to
+ * bc_host [4][max(nx,ny)][2] (Appendix B, g_m = int_face g l_m ds): (value sqrt(h), 0)
+ * for a face of length h.  Out-of-range side or index gives RTE_EINVAL.              */
+rte_status rte_inflow_face_moments(int32_t nx, int32_t ny, double x0, double x1, double y0,
+                                   double y1, int32_t side, int32_t index, double value,
+                                   double* bc_host);
+
 /* Adds the moments of the Gaussian source G = amp exp(-alpha ((x-cx)^2 + (y-cy)^2))
  * (the source of the examples of Sec. 4: amp = 1, alpha = 100, centre 0) to G_host
  * [ny][nx][4] (Appendix B, G(k) = int_cell G eta_k): the source is separable, so each

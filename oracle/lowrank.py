@@ -125,6 +125,12 @@ def direction_classes(dirs, tol=1e-12):
     return cls, np.array(reps, dtype=np.int64)
 
 
+def _project_out(X, v):
+    """One classical Gram-Schmidt pass: (v - X X^T v, X^T v)."""
+    dc = X.T @ v
+    return v - X @ dc, dc
+
+
 class LowRankSI:
     """One low-rank SI solve (Sec. 3.1) for a fixed source Sigma_s phi^{n-1} + G."""
 
@@ -138,36 +144,44 @@ class LowRankSI:
 
     # ---------------- Alg. 2 (MGS2-A) ----------------
     def mgs2a_append(self, psi):
-        """Orthogonalise one snapshot against X (Alg. 2, one pass of the l-loop).
+        """Alg. 2 for one snapshot: block Gram-Schmidt against the current basis X,
+        repeated where the orthogonality test against the first basis vector fails, then
+        append the normalised remainder.
 
-        Returns the R column for this snapshot (length r_new) and whether it was appended.
+        The remainder v and the coefficient vector satisfy psi = X coef + v at every
+        stage.  Two projection passes always run; then, while the normalised remainder
+        u = v/alpha still has a component above eps_mgs along X(:,1), the un-normalised
+        alpha u is projected again (at most m_max more times).  Returns the R column
+        (coef, alpha) and whether the snapshot was appended; a remainder of relative size
+        tol_break or less is not appended (breakdown: psi already lies in span(X)).
         """
         X = self.X
         r = X.shape[1]
-        psi_hat = psi.copy()
-        c = np.zeros(r)
+        coef = np.zeros(r)
+        v = psi.copy()
         for _ in range(2):
-            dc = X.T @ psi_hat
-            psi_hat = psi_hat - X @ dc
-            c = c + dc
-        alpha = float(np.linalg.norm(psi_hat))
+            v, dc = _project_out(X, v)
+            coef = coef + dc
+        alpha = float(np.linalg.norm(v))
         if alpha <= self.tol_break * float(np.linalg.norm(psi)):
             self.breakdowns += 1
-            return c, False
-        psi_hat = psi_hat / alpha
-        for _ in range(self.m_max):
-            if r == 0 or abs(float(X[:, 0] @ psi_hat)) <= self.eps_mgs:
-                break
-            psi_hat = alpha * psi_hat
-            dc = X.T @ psi_hat
-            psi_hat = psi_hat - X @ dc
-            c = c + dc
-            alpha = float(np.linalg.norm(psi_hat))
-            psi_hat = psi_hat / alpha
-        if r > 0 and abs(float(X[:, 0] @ psi_hat)) > self.eps_mgs:
+            return coef, False
+        u = v / alpha
+
+        def leaks(u):
+            return r > 0 and abs(float(X[:, 0] @ u)) > self.eps_mgs
+
+        extra = 0
+        while extra < self.m_max and leaks(u):
+            v, dc = _project_out(X, alpha * u)
+            coef = coef + dc
+            alpha = float(np.linalg.norm(v))
+            u = v / alpha
+            extra += 1
+        if leaks(u):
             self.mgs_failures += 1
-        self.X = np.concatenate([X, psi_hat[:, None]], axis=1)
-        return np.concatenate([c, [alpha]]), True
+        self.X = np.concatenate([X, u[:, None]], axis=1)
+        return np.append(coef, alpha), True
 
     # ---------------- incremental bordering (Sec. 3.4) ----------------
     def border(self, P):
@@ -334,7 +348,7 @@ def lr_si_dsa(prob, eps_si, p, q, eps_res, eps_diff, eps_svd, rand, eps_mgs=1e-1
     ops = operators(prob)
     stream = RandomStream(rand)
     phi_prev = np.zeros(prob.mesh.ndof) if phi0 is None else np.asarray(phi0, dtype=np.float64).copy()
-    hist, logs, ranks, sampled = [], [], [], []
+    hist, logs, ranks, sampled, phis = [], [], [], [], []
     lr = LowRankSI(prob, ops, p, q, eps_res, eps_diff, eps_mgs, m_max, tol_break, nthreads)
     mgs_fail = breakdowns = 0
     out = None
@@ -343,6 +357,7 @@ def lr_si_dsa(prob, eps_si, p, q, eps_res, eps_diff, eps_svd, rand, eps_mgs=1e-1
         src = prob.sig_s4 * phi_prev + prob.G
         rep = None if replay is None or n - 1 >= len(replay) else replay[n - 1]
         phi_star = lr.run(src, phi_prev, stream, rep)
+        phis.append(phi_star)
         mgs_fail += lr.mgs_failures
         breakdowns += lr.breakdowns
         Xn, S, V, s_all = lr.truncate(eps_svd)
@@ -357,7 +372,7 @@ def lr_si_dsa(prob, eps_si, p, q, eps_res, eps_diff, eps_svd, rand, eps_mgs=1e-1
         phi_prev = phi_star + prob.dsa().correction(phi_star, phi_prev) if use_dsa else phi_star
     if out is None:
         out = dict(phi=phi_star, iters=max_outer, converged=False)
-    out.update(history=hist, logs=logs, ranks=ranks, n_sampled=sampled, mgs_failures=mgs_fail,
+    out.update(history=hist, logs=logs, ranks=ranks, n_sampled=sampled, phis=phis, mgs_failures=mgs_fail,
                breakdowns=breakdowns, rand_used=stream.i)
     if keep_factors:
         out.update(X=Xn, S=S, V=V, singular_values=s_all, C=lr.C, Xfull=lr.X)

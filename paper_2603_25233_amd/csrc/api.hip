@@ -81,7 +81,7 @@ __global__ void maxdiff_kernel(const double* __restrict__ a, const double* __res
 }
 }  // namespace
 
-void validate_problem(const rte_problem* p, bool need_materials) {
+void validate_problem(const rte_problem* p, bool need_materials, hipStream_t st) {
   RTE_REQUIRE(p != nullptr, "problem is NULL");
   RTE_REQUIRE(p->nx >= 1 && p->ny >= 1, "nx, ny must be >= 1 (got %d, %d)", p->nx, p->ny);
   RTE_REQUIRE(p->x1 > p->x0 && p->y1 > p->y0, "empty domain");
@@ -101,12 +101,13 @@ void validate_problem(const rte_problem* p, bool need_materials) {
     RTE_REQUIRE(p->sigma_s, "sigma_s is required");
     const long n = (long)p->nx * p->ny;
     DevBuf<int> bad(1);
-    RTE_CHECK_HIP(hipMemset(bad.get(), 0, sizeof(int)));
-    hipLaunchKernelGGL(check_sigma_kernel, dim3((n + 255) / 256), dim3(256), 0, 0, p->sigma_t,
+    RTE_CHECK_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), st));
+    hipLaunchKernelGGL(check_sigma_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p->sigma_t,
                        p->sigma_s, n, bad.get());
     RTE_CHECK_HIP(hipGetLastError());
     int hb = 0;
-    RTE_CHECK_HIP(hipMemcpy(&hb, bad.get(), sizeof(int), hipMemcpyDeviceToHost));
+    RTE_CHECK_HIP(hipMemcpyAsync(&hb, bad.get(), sizeof(int), hipMemcpyDeviceToHost, st));
+    RTE_CHECK_HIP(hipStreamSynchronize(st));
     RTE_REQUIRE(!(hb & 1), "sigma_t must lie in [1e-30, 1e30] in every cell");
     RTE_REQUIRE(!(hb & 2), "sigma_s must satisfy 0 <= sigma_s <= sigma_t in every cell");
   }
@@ -168,7 +169,7 @@ static rte_status sweep_common(const rte_problem* prob, const int32_t* dir_idx, 
                                const void* src, void* psi, void* phi, rte_precision prec,
                                void* stream, bool adjoint) {
   try {
-    validate_problem(prob, false);
+    validate_problem(prob, false, (hipStream_t)stream);
     RTE_REQUIRE(dir_idx && n_sel >= 1, "dir_idx / n_sel");
     RTE_REQUIRE(src, "src is NULL");
     RTE_REQUIRE(psi || phi, "one of psi, phi is required");
@@ -269,7 +270,7 @@ rte_status rte_sweep_plan_create(const rte_problem* prob, const int32_t* dir_idx
   try {
     RTE_REQUIRE(plan, "plan is NULL");
     *plan = nullptr;
-    validate_problem(prob, false);
+    validate_problem(prob, false, nullptr);
     RTE_REQUIRE(dir_idx && n_sel >= 1, "dir_idx / n_sel");
     RTE_REQUIRE(prec == RTE_FP64 || prec == RTE_MIXED, "unknown precision %d", (int)prec);
     h = new rte_sweep_plan_s();
@@ -389,6 +390,25 @@ rte_status rte_box_source_moments(int32_t nx, int32_t ny, double x0, double x1, 
           for (int p = 0; p < 2; ++p) c[2 * q + p] += value * mx[p] * my[q];
       }
     }
+    return RTE_OK;
+  } catch (const Error& e) {
+    return e.code;
+  }
+}
+
+rte_status rte_inflow_face_moments(int32_t nx, int32_t ny, double x0, double x1, double y0,
+                                  double y1, int32_t side, int32_t index, double value,
+                                  double* bc) {
+  try {
+    RTE_REQUIRE(nx >= 1 && ny >= 1 && x1 > x0 && y1 > y0, "bad mesh");
+    RTE_REQUIRE(bc, "bc is NULL");
+    RTE_REQUIRE(side >= 0 && side < 4, "side must be 0..3 (L, R, B, T), got %d", side);
+    const int count = side < 2 ? ny : nx;
+    RTE_REQUIRE(index >= 0 && index < count, "face index %d out of range [0, %d)", index, count);
+    // a constant g on a face of length h: int g l_0 = g sqrt(h), int g l_1 = 0
+    const double h = side < 2 ? (y1 - y0) / ny : (x1 - x0) / nx;
+    const int mb = nx > ny ? nx : ny;
+    bc[2 * ((long)side * mb + index)] += value * std::sqrt(h);
     return RTE_OK;
   } catch (const Error& e) {
     return e.code;

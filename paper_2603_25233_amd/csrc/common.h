@@ -69,7 +69,10 @@ struct Geom {
 };
 
 Geom make_geom(const rte_problem* p);
-void validate_problem(const rte_problem* p, bool need_materials);
+// Host checks of the problem; with need_materials the per-cell cross sections are also
+// range-checked by a kernel on `st` (the caller's stream, so that it sees what earlier
+// work on that stream wrote), followed by a synchronisation of `st`.
+void validate_problem(const rte_problem* p, bool need_materials, hipStream_t st);
 
 // Per-direction sweep parameters (canonical frame: the sweep always runs towards
 // +x and +y after a reflection of the cell coordinates by the direction signs).

@@ -75,6 +75,9 @@ SIGNATURES = {
                                ctypes.c_int),
     "rte_gaussian_source_moments": ([ctypes.c_int32, ctypes.c_int32] + [ctypes.c_double] * 8 + [_D],
                                     ctypes.c_int),
+    "rte_inflow_face_moments": ([ctypes.c_int32, ctypes.c_int32] + [ctypes.c_double] * 4
+                                + [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _D],
+                                ctypes.c_int),
     "rte_sweep_plan_create": ([ctypes.POINTER(Problem_), _I, ctypes.c_int32, ctypes.c_int,
                                ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)],
                               ctypes.c_int),
@@ -152,17 +155,13 @@ def gaussian_source_moments(nx, ny, domain, amp=1.0, alpha=100.0, center=(0.0, 0
 
 
 def inflow_moments(nx, ny, domain, faces):
-    """Face moments [4, max(nx,ny), 2] of piecewise-constant isotropic inflow.
-
-    faces: iterable of (side, face index, value); the first face moment of a
-    constant g on a face of length h is g * sqrt(h).
-    """
-    x0, x1, y0, y1 = domain
-    hx, hy = (x1 - x0) / nx, (y1 - y0) / ny
+    """Face moments [4, max(nx,ny), 2] of piecewise-constant isotropic inflow
+    (rte_inflow_face_moments).  faces: iterable of (side, face index, value)."""
+    x0, x1, y0, y1 = (float(v) for v in domain)
     bc = np.zeros((4, max(nx, ny), 2))
     for side, i, val in faces:
-        h = hy if side in (SIDE_L, SIDE_R) else hx
-        bc[side, i, 0] += val * np.sqrt(h)
+        _check(lib().rte_inflow_face_moments(int(nx), int(ny), x0, x1, y0, y1, int(side), int(i),
+                                             float(val), bc.ctypes.data_as(_D)))
     return bc
 
 

@@ -87,3 +87,32 @@ def test_invalid_arguments_are_rejected(L):
         L.cl_quadrature(0, 4)
     msg = L.lib().rte_last_error().decode()
     assert "n_theta" in msg
+
+
+def test_inflow_face_moments(L):
+    """Constant isotropic inflow on one face: first face moment value * sqrt(h)."""
+    faces = [(0, 2, 1.5), (3, 4, -0.5), (0, 2, 0.25)]
+    bc = L.inflow_moments(6, 4, (0.0, 1.2, -1.0, 1.0), faces)
+    want = np.zeros((4, 6, 2))
+    want[0, 2, 0] = 1.75 * np.sqrt(2.0 / 4)
+    want[3, 4, 0] = -0.5 * np.sqrt(1.2 / 6)
+    assert np.abs(bc - want).max() < 1e-15
+    with pytest.raises(L.RTEError):
+        L.inflow_moments(6, 4, (0.0, 1.2, -1.0, 1.0), [(1, 4, 1.0)])   # L/R faces: index < ny
+    with pytest.raises(L.RTEError):
+        L.inflow_moments(6, 4, (0.0, 1.2, -1.0, 1.0), [(4, 0, 1.0)])
+
+
+@pytest.mark.gpu
+def test_library_on_the_gpu_exports_and_version(L):
+    """The same export and version checks in the GPU run, plus one tiny sweep call."""
+    test_exports_every_declared_symbol(L)
+    test_abi_version(L)
+    import torch
+    from tests.common import gpu_problem
+    import workloads as W
+    gp = gpu_problem(W.small_fr(n=4, n_theta=4, n_z=2))
+    src = torch.ones((4, 4, 4), dtype=torch.float64, device="cuda")
+    psi, phi = L.sweep(gp, [0, 3], src, want_psi=True, want_phi=True)
+    torch.cuda.synchronize()
+    assert torch.isfinite(psi).all() and torch.isfinite(phi).all()

@@ -101,6 +101,42 @@ def test_low_rank_fp64_same_decisions(name, wl, p, q):
     assert np.allclose(Sg, ref["S"], rtol=1e-9, atol=1e-12 * ref["S"][0])
 
 
+# Bases past one 64-column block: the blocked bordered LU and back substitution run on
+# several diagonal blocks, the X^T W kernel on several column tiles, the X C kernel on
+# several column chunks.  small16: 256 classes, basis up to 204 columns (four blocks),
+# every inner loop stops on the phi-difference test with about 200 of the 256 classes
+# swept.  small8: 512 classes (more classes than a 256-entry table), basis up to 252
+# columns.
+LARGE_LR_CASES = [
+    ("small16_cl32x16", W.small_fr(n=16, n_theta=32, n_z=16), 4, 32, 192),
+    ("small8_cl64x16", W.small_fr(n=8, n_theta=64, n_z=16), 4, 32, 192),
+]
+
+
+@pytest.mark.parametrize("name,wl,p,q,min_basis", LARGE_LR_CASES, ids=[c[0] for c in LARGE_LR_CASES])
+def test_low_rank_fp64_large_basis(name, wl, p, q, min_basis):
+    wl = W.Workload(wl); wl["eps_si"] = 1e-7; wl["eps_res"] = wl["eps_diff"] = 1e-8
+    wl["eps_svd"] = 1e-9
+    op, ref, got = lr_pair(wl, p, q)
+    # the case reaches the multi-block paths and stops before sampling every class
+    n_classes = len(olr.direction_classes(op.dirs)[1])
+    assert max(e["rank"] for outer in ref["logs"] for e in outer) > min_basis
+    assert any(outer[-1].get("stop") != "all_sampled" for outer in ref["logs"])
+    assert min(ref["n_sampled"]) < n_classes
+    olog = oracle_sample_log(ref)
+    assert list(got["sample_log"]) == olog, "first divergence at %d" % next(
+        (i for i, (a, b) in enumerate(zip(got["sample_log"], olog)) if a != b), min(len(olog), len(got["sample_log"])))
+    assert got["iters"] == ref["iters"]
+    assert list(got["ranks"]) == [max(e["rank"] for e in outer) for outer in ref["logs"]]
+    assert rel_l2(got["phi"].cpu().numpy(), ref["phi"]) < 1e-10
+    assert got["rank"] == ref["ranks"][-1]
+    Xg, Sg, Vg = (got[k].cpu().numpy() for k in ("X", "S", "V"))
+    lowg = Xg.T @ np.diag(Sg) @ Vg
+    lowo = ref["X"] @ np.diag(ref["S"]) @ ref["V"].T
+    assert np.linalg.norm(lowg - lowo) / np.linalg.norm(lowo) < 1e-9
+    assert np.allclose(Sg, ref["S"], rtol=1e-9, atol=1e-12 * ref["S"][0])
+
+
 def test_low_rank_at_full_rank_equals_full_rank():
     import paper_2603_25233_amd as R
     wl = W.checkerboard(n=24, n_theta=8, n_z=4, blocks=4)
@@ -211,3 +247,19 @@ def test_low_rank_breakdown_and_cleanup_paths():
             # exact zeros come from symmetric cancellation and depend on the summation
             # order, so the two counts need not agree; both take the clean-up path
             assert got["mgs_failures"] > 0 and ref["mgs_failures"] > 0
+
+
+def test_phi_checkpoints_match_oracle_iterates():
+    """phi_checkpoints holds phi^{n,*} of every outer iteration (the un-accelerated SI
+    iterate, before the DSA step), for the full-rank and the low-rank solver."""
+    wl = W.checkerboard(n=24, n_theta=8, n_z=4, blocks=4)
+    wl = W.Workload(wl); wl["eps_si"] = 1e-7; wl["eps_res"] = wl["eps_diff"] = 1e-8
+    wl["eps_svd"] = 1e-9
+    ref, got = fr_pair(wl, checkpoints=True)
+    assert got["iters"] == ref["iters"] and got["checkpoints"].shape[0] == got["iters"]
+    for n in range(got["iters"]):
+        assert rel_l2(got["checkpoints"][n].cpu().numpy(), ref["phis"][n]) < 1e-10, n
+    op, ref, got = lr_pair(wl, 2, 4, checkpoints=True)
+    assert got["iters"] == ref["iters"] and got["checkpoints"].shape[0] == got["iters"]
+    for n in range(got["iters"]):
+        assert rel_l2(got["checkpoints"][n].cpu().numpy(), ref["phis"][n]) < 1e-10, n

@@ -161,3 +161,105 @@ def test_sweep_particle_balance():
         lhs = np.sum(sig[:, None] * psi[j].reshape(-1, 4) * one) + out - inflow
         rhs = np.sum(src.reshape(-1, 4) * one)
         assert abs(lhs - rhs) < 1e-12 * (1 + abs(rhs))
+
+
+# ---------------------------------------------------------------------------
+# Source moments G_k = int_cell G eta_k (Appendix B), pinned by closed forms.
+# With xi = 2 (x - x_c)/h_x and zeta = 2 (y - y_c)/h_y the orthonormal basis is
+# (1, sqrt3 xi, sqrt3 zeta, 3 xi zeta) / sqrt(h_x h_y), local index k = 2q + p, so a
+# separable source f(x) g(y) has moments (1/sqrt(h_x h_y)) * Fx_p * Fy_q with
+#   F_0 = int f,  F_1 = sqrt3 int xi f.
+# ---------------------------------------------------------------------------
+
+def _box_1d(lo, hi, c, h):
+    """Moments (int 1, sqrt3 int xi) of the indicator of [lo, hi] over one cell."""
+    if hi <= lo:
+        return 0.0, 0.0
+    xl, xh = 2.0 * (lo - c) / h, 2.0 * (hi - c) / h      # xi at the ends
+    return hi - lo, np.sqrt(3.0) * 0.25 * h * (xh * xh - xl * xl)
+
+
+def test_box_source_fully_covered_cell():
+    """A cell inside the box gets (v sqrt(h_x h_y), 0, 0, 0): the only mode of a constant."""
+    m = dg.Mesh(6, 5, 0.0, 1.2, -0.5, 0.5)
+    v = 2.5
+    G = dg.source_moments_box(m, v, (-1.0, 2.0, -1.0, 1.0)).reshape(m.ny, m.nx, 4)
+    expect = np.array([v * np.sqrt(m.hx * m.hy), 0.0, 0.0, 0.0])
+    assert np.abs(G - expect).max() < 1e-14
+
+
+def test_box_source_partial_cells_closed_form():
+    """Cells cut by the box: separable linear moments of the covered rectangle."""
+    m = dg.Mesh(7, 5, -0.3, 1.1, 0.2, 0.9)
+    box = (0.137, 0.61, 0.33, 0.77)
+    v = 1.7
+    G = dg.source_moments_box(m, v, box).reshape(m.ny, m.nx, 4)
+    s = 1.0 / np.sqrt(m.hx * m.hy)
+    n_cut = 0
+    for b in range(m.ny):
+        y0, y1 = m.y0 + b * m.hy, m.y0 + (b + 1) * m.hy
+        fy = _box_1d(max(y0, box[2]), min(y1, box[3]), 0.5 * (y0 + y1), m.hy)
+        for a in range(m.nx):
+            x0, x1 = m.x0 + a * m.hx, m.x0 + (a + 1) * m.hx
+            fx = _box_1d(max(x0, box[0]), min(x1, box[1]), 0.5 * (x0 + x1), m.hx)
+            want = v * s * np.array([fx[0] * fy[0], fx[1] * fy[0], fx[0] * fy[1], fx[1] * fy[1]])
+            assert np.abs(G[b, a] - want).max() < 1e-14 * max(1.0, v)
+            n_cut += int(abs(fx[1]) > 0 or abs(fy[1]) > 0)
+    assert n_cut >= 8          # the box really cuts cells on all four sides
+    # total source = v * area of the box (the zeroth moments times sqrt(h_x h_y))
+    tot = G[:, :, 0].sum() * np.sqrt(m.hx * m.hy)
+    assert abs(tot - v * (box[1] - box[0]) * (box[3] - box[2])) < 1e-14
+
+
+def _gauss_1d(lo, hi, c, h, alpha, x0):
+    """Moments (int e, sqrt3 int xi e) of e(x) = exp(-alpha (x - x0)^2) over [lo, hi]:
+    int e = sqrt(pi/alpha)/2 [erf(sqrt(alpha)(x - x0))],
+    int (x - x0) e = -[e]/(2 alpha),  and xi = 2 ((x - x0) + (x0 - c))/h."""
+    import math
+    ra = math.sqrt(alpha)
+    i0 = 0.5 * math.sqrt(math.pi / alpha) * (math.erf(ra * (hi - x0)) - math.erf(ra * (lo - x0)))
+    i1 = -(math.exp(-alpha * (hi - x0) ** 2) - math.exp(-alpha * (lo - x0) ** 2)) / (2.0 * alpha)
+    return i0, np.sqrt(3.0) * 2.0 / h * (i1 + (x0 - c) * i0)
+
+
+def test_function_source_gaussian_closed_form():
+    """Moments of exp(-alpha ((x-cx)^2 + (y-cy)^2)) are products of erf integrals."""
+    m = dg.Mesh(9, 7, -1.0, 1.0, -0.8, 0.6)
+    alpha, cx, cy, amp = 30.0, 0.13, -0.21, 1.9
+    f = lambda x, y: amp * np.exp(-alpha * ((x - cx) ** 2 + (y - cy) ** 2))
+    G = dg.source_moments_function(m, f, nq=12).reshape(m.ny, m.nx, 4)
+    s = 1.0 / np.sqrt(m.hx * m.hy)
+    for b in range(m.ny):
+        y0, y1 = m.y0 + b * m.hy, m.y0 + (b + 1) * m.hy
+        fy = _gauss_1d(y0, y1, 0.5 * (y0 + y1), m.hy, alpha, cy)
+        for a in range(m.nx):
+            x0, x1 = m.x0 + a * m.hx, m.x0 + (a + 1) * m.hx
+            fx = _gauss_1d(x0, x1, 0.5 * (x0 + x1), m.hx, alpha, cx)
+            want = amp * s * np.array([fx[0] * fy[0], fx[1] * fy[0], fx[0] * fy[1], fx[1] * fy[1]])
+            assert np.abs(G[b, a] - want).max() < 1e-12 * amp
+
+
+def test_function_source_polynomial_exact():
+    """A bilinear f is reproduced exactly by its four moments (Q1 projection = identity),
+    and a quadratic in x has the Legendre-l2 part dropped: int x^2 eta_0 by hand."""
+    m = dg.Mesh(4, 3, 0.0, 2.0, 1.0, 2.5)
+    f = lambda x, y: 0.7 - 1.3 * x + 2.1 * y + 0.4 * x * y
+    G = dg.source_moments_function(m, f, nq=3).reshape(m.ny, m.nx, 4)
+    for b in range(m.ny):
+        for a in range(m.nx):
+            xc, yc = m.xc(a), m.yc(b)
+            # f in the local variables: f = A + B xi + C zeta + D xi zeta
+            Bx, Cy = 0.5 * m.hx, 0.5 * m.hy
+            A = f(xc, yc)
+            B = (-1.3 + 0.4 * yc) * Bx
+            C = (2.1 + 0.4 * xc) * Cy
+            D = 0.4 * Bx * Cy
+            # <f, eta_k> = sqrt(h_x h_y) * (A, B/sqrt3, C/sqrt3, D/3)
+            want = np.sqrt(m.hx * m.hy) * np.array([A, B / np.sqrt(3.0), C / np.sqrt(3.0), D / 3.0])
+            assert np.abs(G[b, a] - want).max() < 1e-13
+    g = lambda x, y: x * x + 0.0 * y
+    G2 = dg.source_moments_function(m, g, nq=3).reshape(m.ny, m.nx, 4)
+    for a in range(m.nx):
+        x0, x1 = a * m.hx, (a + 1) * m.hx
+        want0 = (x1 ** 3 - x0 ** 3) / 3.0 * m.hy / np.sqrt(m.hx * m.hy)
+        assert abs(G2[0, a, 0] - want0) < 1e-13
