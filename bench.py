@@ -5,14 +5,20 @@ Metric: angle-cell-DOF sweep updates per second (one update = one DG degree of
 freedom of one cell for one swept direction), plus the low-rank SI-DSA time to
 tolerance next to the full-rank SI-DSA on the same GPU.
 
-One step = one pass of the whole hot path over the 256x256-cell checkerboard
-workload (CL(32,16), 512 ordinates, FP64; see workloads.checkerboard):
-  1. a full-angle transport sweep writing psi for all 512 ordinates (rte_sweep plan);
-  2. full-rank SI-DSA to eps_si = 1e-6;
-  3. low-rank SI-DSA (p = 4, q = 32, eps_res = eps_diff = 1e-7, eps_svd = 1e-8).
-value = all sweep updates of the step / step wall time (inputs resident in HBM).
+Workload of the headline line: the large multiscale medium, 1024 x 1024 DG-Q1 cells
+(4,194,304 DOF), CL(64,16) with 1024 ordinates, log-normal sigma_t (mean 100, log-std 1,
+correlation 32 cells), scattering ratio 0.999, uniform Q = 1, vacuum boundaries
+(workloads.multiscale), FP64.  One step:
+  1. a full-angle transport sweep writing psi for all 1024 ordinates (34.4 GB FP64);
+  2. full-rank SI-DSA to eps_si = 1e-6 (one sweep per (Omega_x, Omega_y) class per outer
+     iteration, DSA conjugate gradients to 1e-12).
+value = all sweep updates of the timed steps / their wall time (inputs resident in HBM).
+After the timed region, once each: the low-rank SI-DSA (p = 1, q = 8) in FP64 and the
+mixed form, the full-rank solve in the mixed form, the 256 x 256 checkerboard (p = 4,
+q = 32) as a secondary workload, and the oracle on the host (cpu_baseline).
 
-    python bench.py [--steps K] [--warmup W] [--only sweep|step] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--only step|sweep|sweep_large|paper|copy]
+                    [--no-lr] [--no-secondary] [--no-cpu-baseline]
 """
 import argparse
 import hashlib
@@ -35,10 +41,10 @@ def kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the psi-writing sweep from the committed rocprofv3 --pmc
+def measured_traffic(profile="sweep_multiscale1024_pmc.md"):
+    """HBM bytes per launch of the psi-writing sweep from a committed rocprofv3 --pmc
     summary, or None when it is missing or taken on a different sweep kernel source."""
-    path = os.path.join(ROOT, "profiles", "sweep_checkerboard_pmc.md")
+    path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -47,28 +53,6 @@ def measured_traffic():
     if not h or not t or h.group(1) != kernel_source_hash():
         return None
     return float(t.group(1))
-
-
-def cpu_baseline(wl, n_sweeps):
-    """The oracle's plain-C sweep (test infrastructure) on a bounded sample of the same
-    workload: n_sweeps full-angle FP64 sweeps writing psi."""
-    from oracle import dg, quadrature, sweep as osweep
-    x0, x1, y0, y1 = wl["domain"]
-    m = dg.Mesh(wl["nx"], wl["ny"], x0, x1, y0, y1)
-    d, w = quadrature.cl_quadrature(wl["n_theta"], wl["n_z"])
-    G = sum(dg.source_moments_box(m, v, b) for v, b in wl["source_boxes"])
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    sel = np.arange(len(w))
-    osweep.sweep(m, d, sel[:4], wl["sigma_t"].reshape(-1), G, None, want_psi=True, nthreads=threads)
-    t0 = time.perf_counter()
-    for _ in range(n_sweeps):
-        osweep.sweep(m, d, sel, wl["sigma_t"].reshape(-1), G, None, want_psi=True, nthreads=threads)
-    dt = time.perf_counter() - t0
-    ups = n_sweeps * len(w) * m.ncell * 4
-    return {"value": ups / dt, "unit": "angle-cell-DOF updates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": "%d full-angle FP64 sweeps writing psi (%d ordinates, %dx%d cells), "
-                      "plain-C oracle sweep, %.1f s" % (n_sweeps, len(w), wl["nx"], wl["ny"], dt)}
 
 
 def large_sweep(args, R, W, torch, dev):
@@ -163,22 +147,153 @@ def paper_examples(R, W, torch, dev):
                           "dtype": "f64"}), flush=True)
 
 
+
+def basis_update_ablation(R, W, torch):
+    """Sec. 4.2's comparison of basis updates (MGS2-A, MGS-QR, full QR) on the lattice
+    stand-in (80 x 80, CL(32,16), p = 1, q = 8), FP64, next to the full-rank solve: one
+    JSON line per variant with time, rank, iterations, full-QR count and the flux
+    difference to full rank."""
+    wl = W.lattice()
+    prob = make_problem(R, wl)
+    kw = dict(eps_si=wl["eps_si"], max_outer=wl["max_outer"], eps_dsa=1e-12)
+    fr = R.solve(prob, full_rank=1, **kw)
+    nd, ndirs = prob.ndof, prob.n_dirs
+    for variant in ("mgs2a", "mgs_qr", "full_qr"):
+        lr = R.solve(prob, rand=W.random_stream(wl["seed"]), full_rank=0, p=wl["p"], q=wl["q"],
+                     eps_res=wl["eps_res"], eps_diff=wl["eps_diff"], eps_svd=wl["eps_svd"],
+                     eps_mgs=wl["eps_mgs"], m_max=wl["m_max"], basis_update=variant, **kw)
+        diff = (lr["phi"] - fr["phi"]).double().cpu().numpy().reshape(-1)
+        print(json.dumps({"ablation": "basis update (Sec. 4.2), lattice stand-in 80x80 CL(32,16)",
+                          "variant": variant, "lr_time_s": lr["ms_total"] / 1e3,
+                          "fr_time_s": fr["ms_total"] / 1e3,
+                          "speedup_fr_over_lr": fr["ms_total"] / lr["ms_total"],
+                          "rank": lr["rank"], "lr_iters": lr["iters"], "fr_iters": fr["iters"],
+                          "full_qrs": lr["full_qrs"], "mgs_failures": lr["mgs_failures"],
+                          "phi_lr_minus_fr_l2": float(np.linalg.norm(diff)),
+                          "compression_ratio": lr["rank"] * (nd + ndirs + 1) / (nd * ndirs),
+                          "dtype": "f64", "data": "synthetic"}), flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_baseline(wl):
+    """The oracle (test infrastructure) on the host, on bounded samples:
+    - one full-angle SI sweep (phi only) of the headline medium with its plain-C sweep,
+      the work of one full-rank outer iteration without folding;
+    - the oracle's full-rank and low-rank SI-DSA time to tolerance on the 32 x 32,
+      CL(16,8) medium, median of 3 runs."""
+    import statistics
+    from oracle import dg, quadrature, sweep as osweep, si as osi, lowrank as olr
+    import workloads as W
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    x0, x1, y0, y1 = wl["domain"]
+    m = dg.Mesh(wl["nx"], wl["ny"], x0, x1, y0, y1)
+    d, w = quadrature.cl_quadrature(wl["n_theta"], wl["n_z"])
+    G = sum(dg.source_moments_box(m, v, b) for v, b in wl["source_boxes"]) \
+        if m.ncell <= 65536 else None
+    if G is None:   # uniform Q = 1 over the whole domain: the constant's only moment
+        G = np.zeros((m.ncell, 4)); G[:, 0] = np.sqrt(m.hx * m.hy); G = G.reshape(-1)
+    sel = np.arange(len(w))
+    sig = wl["sigma_t"].reshape(-1)
+    osweep.sweep(m, d, sel[:2], sig, G, None, want_psi=False, w=w[:2], nthreads=threads)
+    t0 = time.perf_counter()
+    osweep.sweep(m, d, sel, sig, G, None, want_psi=False, w=w, nthreads=threads)
+    dt = time.perf_counter() - t0
+    ups = len(w) * m.ncell * 4
+    small = W.small_fr()
+    ms = dg.Mesh(small["nx"], small["ny"], *small["domain"])
+    ds, ws = quadrature.cl_quadrature(small["n_theta"], small["n_z"])
+    Gs = sum(dg.source_moments_box(ms, v, b) for v, b in small["source_boxes"])
+    op = osi.Problem(ms, ds, ws, small["sigma_t"].reshape(-1), small["sigma_s"].reshape(-1), Gs)
+    fr_t, lr_t = [], []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        fr = osi.fr_si_dsa(op, small["eps_si"], max_outer=small["max_outer"], nthreads=threads)
+        fr_t.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        lr = olr.lr_si_dsa(op, small["eps_si"], p=1, q=8, eps_res=small["eps_res"],
+                           eps_diff=small["eps_diff"], eps_svd=small["eps_svd"],
+                           rand=W.random_stream(small["seed"]), max_outer=small["max_outer"],
+                           nthreads=threads, keep_factors=False)
+        lr_t.append(time.perf_counter() - t0)
+    return {"value": ups / dt, "unit": "angle-cell-DOF updates/s", "cores": threads,
+            "cpu_model": cpu_model(), "kind": "oracle",
+            "sample": "one full-angle phi-only SI sweep of the %dx%d, CL(%d,%d) medium (%d "
+                      "ordinates, %.1f s), plain-C oracle sweep on %d threads"
+                      % (wl["nx"], wl["ny"], wl["n_theta"], wl["n_z"], len(w), dt, threads),
+            "time_to_tol_s": {"workload": "32x32, CL(16,8), sigma_s/sigma_t = 0.99, eps_si = 1e-8 "
+                                          "(low rank p = 1, q = 8)",
+                              "fr": statistics.median(fr_t), "lr": statistics.median(lr_t),
+                              "fr_outer_iters": fr["iters"], "lr_outer_iters": lr["iters"]},
+            "skipped": "the oracle's full solves of the 256x256 and 1024x1024 media (hours of "
+                       "host time; the low-rank one needs X of ~17 GB)"}
+
+
+def lr_solve(R, W, prob, wl, mixed=False):
+    return R.solve(prob, rand=W.random_stream(wl["seed"]), full_rank=0, p=wl["p"], q=wl["q"],
+                   eps_si=wl["eps_si"], eps_res=wl["eps_res"], eps_diff=wl["eps_diff"],
+                   eps_svd=wl["eps_svd"], eps_mgs=wl["eps_mgs"], m_max=wl["m_max"],
+                   max_outer=wl["max_outer"], eps_dsa=1e-12, mixed=mixed)
+
+
+def rel(a, b):
+    return float((a.double() - b.double()).norm() / b.double().norm())
+
+
+def solver_report(fr, lr, nd, ndirs, wsize):
+    return {
+        "fr_time_to_tol_s": fr["ms_total"] / 1e3, "lr_time_to_tol_s": lr["ms_total"] / 1e3,
+        "lr_speedup_vs_fr": fr["ms_total"] / lr["ms_total"],
+        "fr_outer_iters": fr["iters"], "lr_outer_iters": lr["iters"],
+        "fr_converged": fr["converged"], "lr_converged": lr["converged"],
+        "lr_rank": lr["rank"], "lr_basis_before_truncation": [int(x) for x in lr["ranks"]],
+        "lr_rank_after_truncation": [int(x) for x in lr["trunc_ranks"]],
+        "lr_oversampling": [float((a - b) / b) if b else None
+                            for a, b in zip(lr["ranks"], lr["trunc_ranks"])],
+        "lr_angles_swept": lr["n_swept"], "fr_class_sweeps": fr["n_swept"],
+        "lr_phi_vs_fr_rel_l2": rel(lr["phi"], fr["phi"]),
+        "fr_phases_ms": {"sweep": fr["ms_sweep"], "dsa": fr["ms_dsa"], "total": fr["ms_total"]},
+        "lr_phases_ms": {"sweep": lr["ms_sweep"], "lowrank": lr["ms_lowrank"],
+                         "dsa": lr["ms_dsa"], "total": lr["ms_total"]},
+        "compression_ratio": lr["rank"] * (nd + ndirs + 1) / (nd * ndirs),
+        "storage_bytes": {"lr_factors": lr["rank"] * (nd + ndirs + 1) * wsize,
+                          "fr_psi": nd * ndirs * wsize},
+    }
+
+
+def make_problem(R, wl):
+    dirs, wts = R.cl_quadrature(wl["n_theta"], wl["n_z"])
+    G = R.box_source_moments(wl["nx"], wl["ny"], wl["domain"], wl["source_boxes"])
+    return R.Problem(wl["nx"], wl["ny"], wl["domain"], dirs, wts, wl["sigma_t"], wl["sigma_s"], G=G)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--only", choices=["step", "sweep", "sweep_large", "paper", "copy"], default="step",
-                    help="sweep: only the psi-writing full-angle sweep (profiling); "
-                         "sweep_large: the same on the 1024x1024, CL(64,16) multiscale medium "
-                         "(34.4 GB of FP64 psi), one JSON line of its own; "
+    ap.add_argument("--only", choices=["step", "sweep", "sweep_large", "paper", "ablation", "copy"],
+                    default="step",
+                    help="step: the headline line (default); "
+                         "sweep: only the psi-writing full-angle sweep of the headline medium; "
+                         "sweep_large: the same, one JSON line of its own (--mixed: FP32); "
                          "paper: the paper's own examples (Sec. 4.1, 4.3, 4.4), one JSON line each; "
+                         "ablation: MGS2-A / MGS-QR / full-QR basis updates (Sec. 4.2); "
                          "copy: a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sweeps", type=int, default=10)
-    ap.add_argument("--mixed", action="store_true", help="mixed-precision solvers and sweep")
-    ap.add_argument("--no-mixed-report", action="store_true",
-                    help="skip the untimed mixed-precision solves reported next to the FP64 ones")
+    ap.add_argument("--no-lr", action="store_true",
+                    help="skip the untimed low-rank and mixed-precision solves (profiling runs)")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the 256x256 checkerboard secondary workload")
+    ap.add_argument("--mixed", action="store_true", help="sweep_large in FP32")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only (the method runs on one MI355X here); "
@@ -207,28 +322,27 @@ def main():
     if args.only == "paper":
         paper_examples(R, W, torch, dev)
         return
+    if args.only == "ablation":
+        basis_update_ablation(R, W, torch)
+        return
 
-    wl = W.checkerboard()
-    dirs, wts = R.cl_quadrature(wl["n_theta"], wl["n_z"])
-    G = R.box_source_moments(wl["nx"], wl["ny"], wl["domain"], wl["source_boxes"])
-    prob = R.Problem(wl["nx"], wl["ny"], wl["domain"], dirs, wts, wl["sigma_t"], wl["sigma_s"], G=G)
-    nd, ncell, ndirs = prob.ndof, wl["nx"] * wl["ny"], len(wts)
-    dt = torch.float32 if args.mixed else torch.float64
-    wsize = 4 if args.mixed else 8
+    wl = W.multiscale()
+    prob = make_problem(R, wl)
+    nd, ncell, ndirs = prob.ndof, wl["nx"] * wl["ny"], prob.n_dirs
+    wsize = 8
     # isotropic right-hand side of one SI step from a seeded positive scalar flux
-    phi0 = torch.as_tensor(np.random.default_rng(7).uniform(0, 1e-3, (wl["ny"], wl["nx"], 4)), device=dev)
-    src = (prob.sigma_s[..., None] * phi0 + prob.G).to(dt).contiguous()
-    psi = torch.empty((ndirs, wl["ny"], wl["nx"], 4), dtype=dt, device=dev)
-    plan = R.SweepPlan(prob, np.arange(ndirs), mixed=args.mixed)
-    rand = W.random_stream(wl["seed"])
+    phi0 = torch.as_tensor(np.random.default_rng(7).uniform(0, 1e-2, (wl["ny"], wl["nx"], 4)), device=dev)
+    src = (prob.sigma_s[..., None] * phi0 + prob.G).contiguous()
+    del phi0
+    psi = torch.empty((ndirs, wl["ny"], wl["nx"], 4), dtype=torch.float64, device=dev)
+    plan = R.SweepPlan(prob, np.arange(ndirs))
     stream = torch.cuda.current_stream()
-    solve_kw = dict(eps_si=wl["eps_si"], max_outer=wl["max_outer"], eps_dsa=1e-12, mixed=args.mixed)
+    fr_kw = dict(full_rank=1, eps_si=wl["eps_si"], max_outer=wl["max_outer"], eps_dsa=1e-12)
 
     def sweep_once():
         e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
         # A short spin keeps the GPU busy while the host enqueues the sweep, so that the
-        # events bracket its kernels and not the host's launch latency (after a solver run
-        # the GPU is idle when the step starts).
+        # events bracket its kernels and not the host's launch latency.
         torch.cuda._sleep(200000)
         e0.record(stream)
         plan.execute(src, psi=psi)
@@ -236,15 +350,9 @@ def main():
         return e0, e1
 
     def step():
-        out = {}
-        e0, e1 = sweep_once()
+        out = {"events": sweep_once()}
         if args.only == "step":
-            fr = R.solve(prob, full_rank=1, **solve_kw)
-            lr = R.solve(prob, rand=rand, full_rank=0, p=wl["p"], q=wl["q"], eps_res=wl["eps_res"],
-                         eps_diff=wl["eps_diff"], eps_svd=wl["eps_svd"], eps_mgs=wl["eps_mgs"],
-                         m_max=wl["m_max"], **solve_kw)
-            out.update(fr=fr, lr=lr)
-        out["events"] = (e0, e1)
+            out["fr"] = R.solve(prob, **fr_kw)
         return out
 
     for _ in range(args.warmup):
@@ -258,76 +366,75 @@ def main():
     sweep_ms = [o["events"][0].elapsed_time(o["events"][1]) for o in outs]
     k1_updates = ndirs * ncell * 4
     updates = args.steps * k1_updates
-    res = {}
-    if args.only == "step":
-        fr_ms = [o["fr"]["ms_total"] for o in outs]
-        lr_ms = [o["lr"]["ms_total"] for o in outs]
-        fr, lr = outs[-1]["fr"], outs[-1]["lr"]
-        for o in outs:
-            updates += o["fr"]["iters"] * ndirs * ncell * 4 + o["lr"]["n_swept"] * ncell * 4
-        diff = (lr["phi"] - fr["phi"]).double()
-        res = {
-            "fr_time_to_tol_s": float(np.median(fr_ms)) / 1e3,
-            "lr_time_to_tol_s": float(np.median(lr_ms)) / 1e3,
-            "lr_speedup_vs_fr": float(np.median(fr_ms) / np.median(lr_ms)),
-            "fr_outer_iters": fr["iters"], "lr_outer_iters": lr["iters"],
-            "lr_rank": lr["rank"], "lr_angles_swept": lr["n_swept"],
-            "lr_phi_vs_fr_rel_l2": float(diff.norm() / fr["phi"].double().norm()),
-            "fr_phases_ms": {"sweep": fr["ms_sweep"], "dsa": fr["ms_dsa"], "total": fr["ms_total"]},
-            "lr_phases_ms": {"sweep": lr["ms_sweep"], "lowrank": lr["ms_lowrank"],
-                             "dsa": lr["ms_dsa"], "total": lr["ms_total"]},
-            "compression_ratio": lr["rank"] * (nd + ndirs + 1) / (nd * ndirs),
-            "storage_bytes": {"lr_factors": lr["rank"] * (nd + ndirs + 1) * wsize,
-                              "fr_psi": nd * ndirs * wsize},
-        }
     k1_ms = float(np.mean(sweep_ms))
     # algorithmic bytes of the psi-writing sweep: psi written once, source and sigma_t read once
     k1_bytes = ncell * (4 * wsize * ndirs + 4 * wsize + 8)
     achieved = k1_bytes / (k1_ms * 1e-3) / 1e9
-    traffic = measured_traffic() if not args.mixed else None
     line = {
         "metric": "angle-cell-DOF sweep updates/s + low-rank SI-DSA time-to-tol vs full-rank, 1 GPU",
-        "value": updates / wall,
         "unit": "angle-cell-DOF updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": wall / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if args.mixed else "f64", "data": "synthetic",
-        "config": {"workload": "checkerboard 256x256 DG-Q1, CL(32,16) 512 ordinates, "
-                               "8x8 diffusive/absorbing blocks, p=4 q=32, eps_si=1e-6",
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "multiscale 1024x1024 DG-Q1, CL(64,16) 1024 ordinates, log-normal "
+                               "sigma_t (mean 100, log-std 1, correlation 32 cells), c = 0.999, "
+                               "Q = 1, vacuum; step = psi sweep + full-rank SI-DSA to 1e-6",
                    "only": args.only},
-        "sweep_kernel": {"updates_per_s": k1_updates / (k1_ms * 1e-3), "ms": k1_ms,
-                         "launch": "diag_layout_kernel, then sweep_kernel: 1 ordinate per "
-                                   "workgroup (512 workgroups, 2 per CU), 256 compute threads "
-                                   "(one per row) + 2 staging wavefronts of 128 rows + 4 write-back wavefronts of 64 rows"},
-        "roofline": {"kernel": "psi sweep (diag_layout_kernel + sweep_kernel), full angle set",
-                     "bound": "hbm",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": k1_bytes},
+        "psi_sweep": {"updates_per_s": k1_updates / (k1_ms * 1e-3), "ms": k1_ms,
+                      "algorithmic_bytes": k1_bytes, "achieved_GBs": achieved,
+                      "hbm_frac": achieved / HBM_PEAK_GBS},
     }
-    line.update(res)
-    if args.only == "step" and not args.mixed and not args.no_mixed_report:
-        # the mixed-precision form (FP32 sweeps and basis, FP64 reductions, Galerkin, SVD,
-        # DSA) once each, after the timed region, against this step's FP64 results
-        mkw = dict(solve_kw, mixed=True)
-        frm = R.solve(prob, full_rank=1, **mkw)
-        lrm = R.solve(prob, rand=W.random_stream(wl["seed"]), full_rank=0, p=wl["p"], q=wl["q"],
-                      eps_res=wl["eps_res"], eps_diff=wl["eps_diff"], eps_svd=wl["eps_svd"],
-                      eps_mgs=wl["eps_mgs"], m_max=wl["m_max"], **mkw)
-        fr, lr = outs[-1]["fr"], outs[-1]["lr"]
-        nrm = lambda a, b: float((a.double() - b.double()).norm() / b.double().norm())
+    if args.only == "step":
+        fr = outs[-1]["fr"]
+        for o in outs:
+            updates += o["fr"]["n_swept"] * ncell * 4
+        fr_sweep_ms = float(np.mean([o["fr"]["ms_sweep"] / o["fr"]["iters"] for o in outs]))
+        line["fr"] = {"time_to_tol_s": float(np.median([o["fr"]["ms_total"] for o in outs])) / 1e3,
+                      "outer_iters": fr["iters"], "converged": fr["converged"],
+                      "class_sweeps_per_outer": fr["n_swept"] // fr["iters"],
+                      "dsa_cg_iters": fr["dsa_iters"],
+                      "phases_ms": {"sweep": fr["ms_sweep"], "dsa": fr["ms_dsa"],
+                                    "total": fr["ms_total"]},
+                      "sweep_ms_per_outer": fr_sweep_ms}
+    line["value"] = updates / wall
+    line["roofline"] = {"kernel": "psi sweep (diag_layout_kernel + sweep_kernel), full angle set",
+                        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                        "algorithmic_bytes_per_launch": k1_bytes}
+    plan.close()
+    del psi
+    torch.cuda.empty_cache()
+    if args.only == "step" and not args.no_lr:
+        lr = lr_solve(R, W, prob, wl)
+        line["lowrank"] = solver_report(fr, lr, nd, ndirs, wsize)
+        print(json.dumps({"progress": "low-rank FP64 done", "s": lr["ms_total"] / 1e3}),
+              file=sys.stderr, flush=True)
+        frm = R.solve(prob, mixed=True, **fr_kw)
+        lrm = lr_solve(R, W, prob, wl, mixed=True)
         line["mixed"] = {
             "fr_time_to_tol_s": frm["ms_total"] / 1e3, "lr_time_to_tol_s": lrm["ms_total"] / 1e3,
             "fr_outer_iters": frm["iters"], "lr_outer_iters": lrm["iters"], "lr_rank": lrm["rank"],
-            "fr_phi_vs_fp64_fr_rel_l2": nrm(frm["phi"], fr["phi"]),
-            "lr_phi_vs_fp64_lr_rel_l2": nrm(lrm["phi"], lr["phi"]),
-            "lr_phi_vs_fp64_fr_rel_l2": nrm(lrm["phi"], fr["phi"]),
+            "fr_phi_vs_fp64_fr_rel_l2": rel(frm["phi"], fr["phi"]),
+            "lr_phi_vs_fp64_lr_rel_l2": rel(lrm["phi"], lr["phi"]),
+            "lr_phi_vs_fp64_fr_rel_l2": rel(lrm["phi"], fr["phi"]),
             "target_rel_l2": 1e-5,
         }
+        del lr, lrm, frm
+    del prob
+    torch.cuda.empty_cache()
+    if args.only == "step" and not args.no_secondary:
+        wl2 = W.checkerboard()
+        p2 = make_problem(R, wl2)
+        fr2 = R.solve(p2, full_rank=1, eps_si=wl2["eps_si"], max_outer=wl2["max_outer"], eps_dsa=1e-12)
+        lr2 = lr_solve(R, W, p2, wl2)
+        line["secondary"] = dict(
+            workload="checkerboard 256x256 DG-Q1, CL(32,16) 512 ordinates, 8x8 diffusive/absorbing "
+                     "blocks, p = 4, q = 32, eps_si = 1e-6",
+            **solver_report(fr2, lr2, p2.ndof, p2.n_dirs, 8))
+        del p2
     if not args.no_cpu_baseline and args.only == "step":
-        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_sweeps)
-    plan.close()
+        line["cpu_baseline"] = oracle_baseline(wl)
     print(json.dumps(line))
 
 

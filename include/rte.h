@@ -49,8 +49,13 @@ typedef enum {
 
 typedef enum {
   RTE_FP64 = 0,          /* every step in float64                                     */
-  RTE_MIXED = 1          /* float32 sweeps, basis and projections; float64 reduced
-                            solves, residual norms, SVD, convergence tests and DSA    */
+  RTE_MIXED = 1          /* rte_sweep: float32 throughout.  Solver: float32 basis X
+                            (half the bytes of every pass over it), with float64
+                            snapshots, projections accumulated in float64, reduced
+                            solves, residuals, SVD, convergence tests and DSA; the
+                            full-rank form sweeps the whole source in float64 until the
+                            SI change is 1e-3 of the flux, then only the change of the
+                            scattering source, in float32, added in float64          */
 } rte_precision;
 
 /* The discrete problem, eq. (mat-vec-a).                                           */
@@ -147,6 +152,12 @@ typedef struct {
   int64_t n_replay;
   double* phi_checkpoints;  /* DEV [max_outer][ny][nx][4]: phi^{n,*} of every outer
                                iteration, or NULL                                     */
+  int32_t fold_classes;  /* full rank: 1 sweeps one ordinate per class of equal
+                            (Omega_x, Omega_y) with the class's summed weight (the
+                            Omega_z twins of X-Y geometry have identical sweeps, so phi
+                            is unchanged up to rounding); 0 sweeps every ordinate     */
+  int32_t basis_update;  /* low rank: 0 MGS2-A (Alg. 2); 1 MGS-QR; 2 full QR (the
+                            basis-update variants compared in Sec. 4.2)             */
 } rte_solve_params;
 
 /* What the solver reports (all HOST; optional arrays may be NULL).                    */
@@ -166,6 +177,11 @@ typedef struct {
   double* resid_log;     /* [resid_log_cap] candidate residual norms in draw order     */
   int32_t resid_log_cap, resid_log_len;
   double ms_sweep, ms_lowrank, ms_dsa, ms_total;   /* phase wall times               */
+  int32_t* trunc_ranks;  /* [max_outer] r' of the truncated SVD after each outer step
+                            (low rank; NULL: truncate after the last step only)       */
+  int32_t full_qrs;      /* full QR factorisations of the basis (basis_update 1, 2)  */
+  int32_t fp64_sweeps;   /* full rank, RTE_MIXED: outer iterations that swept the whole
+                            source in FP64 before the switch to FP32 increment sweeps */
 } rte_solve_result;
 
 /*

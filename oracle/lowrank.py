@@ -42,7 +42,17 @@ Readings (also implemented by the GPU library; each is listed in the design doc):
     phi-difference test; the inner loop also ends when every class is sampled;
   * MGS2-A breakdown (not specified by the paper): if alpha <= tol_break * ||psi||,
     the snapshot is not appended and the sampled class keeps the coefficient c;
-  * truncation rank r' = smallest l with sum_{i>l} s_i <= eps_svd sum_i s_i.
+  * truncation rank r' = smallest l with sum_{i>l} s_i <= eps_svd sum_i s_i;
+  * basis-update variants of Sec. 4.2 (the paper gives no listing for them):
+    - "mgs_qr": one block projection (the Delta c = X^T psi of Alg. 2), normalisation and
+      the orthogonality test against X(:,1); when the test fails, a full QR of the matrix
+      of all snapshots of the outer iteration replaces the basis;
+    - "full_qr": after every batch of sampled snapshots, a full QR of the matrix of all
+      snapshots of the outer iteration replaces the basis;
+    a full QR is the Householder QR of the snapshot matrix (LAPACK) with the signs fixed
+    so that diag(R) > 0; the sampled classes take the columns of R as coefficients, and
+    the projected operators and right-hand sides are recomputed from the new basis (the
+    incremental bordering needs the nested basis that a full QR does not keep).
 """
 import math
 
@@ -135,12 +145,14 @@ class LowRankSI:
     """One low-rank SI solve (Sec. 3.1) for a fixed source Sigma_s phi^{n-1} + G."""
 
     def __init__(self, prob, ops, p, q, eps_res, eps_diff, eps_mgs=1e-10, m_max=4,
-                 tol_break=1e-12, nthreads=0):
+                 tol_break=1e-12, nthreads=0, basis_update="mgs2a"):
         self.prob, self.ops = prob, ops
         self.p, self.q = p, q
         self.eps_res, self.eps_diff = eps_res, eps_diff
         self.eps_mgs, self.m_max, self.tol_break = eps_mgs, m_max, tol_break
         self.nthreads = nthreads
+        assert basis_update in ("mgs2a", "mgs_qr", "full_qr"), basis_update
+        self.basis_update = basis_update
 
     # ---------------- Alg. 2 (MGS2-A) ----------------
     def mgs2a_append(self, psi):
@@ -182,6 +194,56 @@ class LowRankSI:
             self.mgs_failures += 1
         self.X = np.concatenate([X, u[:, None]], axis=1)
         return np.append(coef, alpha), True
+
+    # ---------------- basis-update variants of Sec. 4.2 ----------------
+    def full_qr(self):
+        """Replace X by the Q of a full QR of all snapshots of this outer iteration (in
+        sampling order); the sampled classes get the columns of R as coefficients and the
+        projected operators are recomputed.  A snapshot whose diagonal entry of R is at
+        most tol_break times its norm is already in the span of the earlier ones: it adds
+        no column and keeps its projection as coefficients (as a breakdown in Alg. 2)."""
+        self.full_qrs += 1
+        S = np.stack([psi for _, psi in self.snaps], axis=1)
+        Rd = np.abs(np.diag(np.linalg.qr(S, mode="r")))
+        keep = [i for i, (_, psi) in enumerate(self.snaps)
+                if Rd[i] > self.tol_break * float(np.linalg.norm(psi))]
+        Q, R = np.linalg.qr(S[:, keep])
+        Q = Q * np.where(np.diag(R) < 0.0, -1.0, 1.0)[None, :]
+        self.X = Q
+        for c, psi in self.snaps:
+            self.coef[c] = Q.T @ psi
+        self._project_fresh()
+
+    def _project_fresh(self):
+        """Projected operators and right-hand sides of the current basis from scratch."""
+        X, o = self.X, self.ops
+        self.T = X.T @ (o["Sig_t"] @ X)
+        self.Dxm = X.T @ (o["Dxm"] @ X); self.Dxp = X.T @ (o["Dxp"] @ X)
+        self.Dym = X.T @ (o["Dym"] @ X); self.Dyp = X.T @ (o["Dyp"] @ X)
+        self.b_src = X.T @ self.src
+        self.b_side = (X.T @ o["gside"].T).T
+
+    def mgs_qr_append(self, c, psi):
+        """One block projection of the snapshot, then the orthogonality test against
+        X(:,1); on failure a full QR of all snapshots replaces the basis.  Returns True
+        when the basis was replaced (the projected operators are then already fresh)."""
+        self.snaps.append((c, psi.copy()))
+        X = self.X
+        r = X.shape[1]
+        dc = X.T @ psi
+        v = psi - X @ dc
+        alpha = float(np.linalg.norm(v))
+        if alpha <= self.tol_break * float(np.linalg.norm(psi)):
+            self.breakdowns += 1
+            self.coef[c] = dc
+            return False
+        u = v / alpha
+        if r > 0 and abs(float(X[:, 0] @ u)) > self.eps_mgs:
+            self.full_qr()
+            return True
+        self.X = np.concatenate([X, u[:, None]], axis=1)
+        self.coef[c] = np.append(dc, alpha)
+        return False
 
     # ---------------- incremental bordering (Sec. 3.4) ----------------
     def border(self, P):
@@ -266,8 +328,10 @@ class LowRankSI:
         self.Dym = self.T.copy(); self.Dyp = self.T.copy()
         self.b_src = np.zeros(0); self.b_side = np.zeros((4, 0))
         self.coef = {}
+        self.snaps = []                 # (class, snapshot) of this outer iteration
         self.mgs_failures = 0
         self.breakdowns = 0
+        self.full_qrs = 0
         self.n_swept = 0
         log = []
         phi_old = phi_prev.copy()
@@ -279,13 +343,28 @@ class LowRankSI:
             psi, _ = sweep.sweep(prob.mesh, prob.dirs, self.reps[samples], prob.sigma_t, src,
                                  prob.bnd, want_psi=True, nthreads=self.nthreads)
             self.n_swept += len(samples)
-            # 2. MGS2-A, one snapshot after the other
+            # 2. basis update: MGS2-A (Alg. 2), one snapshot after the other, or a variant
+            # of Sec. 4.2;  3. bordering with the appended columns (MGS2-A), or the
+            # operators recomputed after a full QR
             r_before = self.X.shape[1]
-            for i, c in enumerate(samples):
-                col, _ = self.mgs2a_append(psi[i])
-                self.coef[c] = col
-            # 3. bordering with the appended columns
-            self.border(self.X[:, r_before:])
+            if self.basis_update != "mgs_qr":
+                self.snaps.extend((c, psi[i].copy()) for i, c in enumerate(samples))
+            if self.basis_update == "mgs2a":
+                for i, c in enumerate(samples):
+                    col, _ = self.mgs2a_append(psi[i])
+                    self.coef[c] = col
+                self.border(self.X[:, r_before:])
+            elif self.basis_update == "full_qr":
+                self.full_qr()
+            else:
+                fresh = False
+                for i, c in enumerate(samples):
+                    if self.mgs_qr_append(c, psi[i]):
+                        fresh = True
+                if fresh:
+                    self._project_fresh()
+                else:
+                    self.border(self.X[:, r_before:])
             entry = dict(k=k, samples=list(samples), rank=self.X.shape[1])
             unsampled = [c for c in range(K) if c not in self.coef]
             if not unsampled:
@@ -343,14 +422,15 @@ def operators(prob):
 
 def lr_si_dsa(prob, eps_si, p, q, eps_res, eps_diff, eps_svd, rand, eps_mgs=1e-10, m_max=4,
               max_outer=100, phi0=None, use_dsa=True, replay=None, tol_break=1e-12,
-              nthreads=0, keep_factors=True):
+              nthreads=0, keep_factors=True, basis_update="mgs2a"):
     """Alg. 1.  `rand` is the uint64 stream; `replay` optionally forces samples per outer."""
     ops = operators(prob)
     stream = RandomStream(rand)
     phi_prev = np.zeros(prob.mesh.ndof) if phi0 is None else np.asarray(phi0, dtype=np.float64).copy()
     hist, logs, ranks, sampled, phis = [], [], [], [], []
-    lr = LowRankSI(prob, ops, p, q, eps_res, eps_diff, eps_mgs, m_max, tol_break, nthreads)
-    mgs_fail = breakdowns = 0
+    lr = LowRankSI(prob, ops, p, q, eps_res, eps_diff, eps_mgs, m_max, tol_break, nthreads,
+                   basis_update)
+    mgs_fail = breakdowns = full_qrs = 0
     out = None
     phi_star = phi_prev
     for n in range(1, max_outer + 1):
@@ -360,6 +440,7 @@ def lr_si_dsa(prob, eps_si, p, q, eps_res, eps_diff, eps_svd, rand, eps_mgs=1e-1
         phis.append(phi_star)
         mgs_fail += lr.mgs_failures
         breakdowns += lr.breakdowns
+        full_qrs += lr.full_qrs
         Xn, S, V, s_all = lr.truncate(eps_svd)
         ranks.append(S.size)
         sampled.append(lr.n_swept)
@@ -373,7 +454,7 @@ def lr_si_dsa(prob, eps_si, p, q, eps_res, eps_diff, eps_svd, rand, eps_mgs=1e-1
     if out is None:
         out = dict(phi=phi_star, iters=max_outer, converged=False)
     out.update(history=hist, logs=logs, ranks=ranks, n_sampled=sampled, phis=phis, mgs_failures=mgs_fail,
-               breakdowns=breakdowns, rand_used=stream.i)
+               breakdowns=breakdowns, full_qrs=full_qrs, rand_used=stream.i)
     if keep_factors:
         out.update(X=Xn, S=S, V=V, singular_values=s_all, C=lr.C, Xfull=lr.X)
     return out

@@ -81,6 +81,14 @@ __global__ void maxdiff_kernel(const double* __restrict__ a, const double* __res
 }
 }  // namespace
 
+bool progress_enabled() {
+  static const bool on = [] {
+    const char* v = std::getenv("RTE_PROGRESS");
+    return v && v[0] && std::strcmp(v, "0") != 0;
+  }();
+  return on;
+}
+
 void validate_problem(const rte_problem* p, bool need_materials, hipStream_t st) {
   RTE_REQUIRE(p != nullptr, "problem is NULL");
   RTE_REQUIRE(p->nx >= 1 && p->ny >= 1, "nx, ny must be >= 1 (got %d, %d)", p->nx, p->ny);
@@ -250,7 +258,7 @@ extern "C" {
 
 const char* rte_last_error(void) { return rte::last_error(); }
 
-int32_t rte_abi_version(void) { return 1; }
+int32_t rte_abi_version(void) { return 2; }
 
 rte_status rte_sweep(const rte_problem* prob, const int32_t* dir_idx, int32_t n_sel,
                      const void* src, void* psi, void* phi, rte_precision prec, void* stream) {

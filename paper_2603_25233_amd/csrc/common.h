@@ -69,6 +69,10 @@ struct Geom {
 };
 
 Geom make_geom(const rte_problem* p);
+
+// Per-outer-iteration progress lines on stderr when the environment variable
+// RTE_PROGRESS is set to a non-empty value other than "0".
+bool progress_enabled();
 // Host checks of the problem; with need_materials the per-cell cross sections are also
 // range-checked by a kernel on `st` (the caller's stream, so that it sees what earlier
 // work on that stream wrote), followed by a synchronisation of `st`.

@@ -115,10 +115,10 @@ __device__ __forceinline__ double wave_colsum16(const double (&p)[kPjVals], doub
   return s;
 }
 
-template <typename T, int NV>
+template <typename TX, typename TW, int NV>
 __global__ __launch_bounds__(64 * kPjWaves, 2) void bproj_kernel(
-    const T* __restrict__ Xu, int r_upd, const double* __restrict__ C, const T* __restrict__ Xd,
-    int r_dot, T* __restrict__ W, long nd, double* __restrict__ part) {
+    const TX* __restrict__ Xu, int r_upd, const double* __restrict__ C, const TX* __restrict__ Xd,
+    int r_dot, TW* __restrict__ W, long nd, double* __restrict__ part) {
   using Cfg = PjCfg<NV>;
   constexpr int RPT = Cfg::rpt, G = Cfg::g, U = Cfg::u;
   extern __shared__ double sm[];
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(64 * kPjWaves, 2) void bproj_kernel(
     ix[t] = ok[t] ? i0 + 64 * t : 0;
   }
   {
-    T wr[NV][RPT];
+    TW wr[NV][RPT];
 #pragma unroll
     for (int l = 0; l < NV; ++l)
 #pragma unroll
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(64 * kPjWaves, 2) void bproj_kernel(
     // U columns per round: all loads of a round are issued before its products
     int c = 0;
     for (; c + U <= r_upd; c += U) {
-      T xv[U][RPT];
+      TX xv[U][RPT];
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(64 * kPjWaves, 2) void bproj_kernel(
         }
     }
     for (; c < r_upd; ++c) {
-      T xv[RPT];
+      TX xv[RPT];
 #pragma unroll
       for (int t = 0; t < RPT; ++t) xv[t] = Xu[(long)c * nd + ix[t]];
 #pragma unroll
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(64 * kPjWaves, 2) void bproj_kernel(
     for (int l = 0; l < NV; ++l)
 #pragma unroll
       for (int t = 0; t < RPT; ++t) {
-        const T nv = (T)(w[l][t] - s[l][t]);
+        const TW nv = (TW)(w[l][t] - s[l][t]);
         w[l][t] = ok[t] ? (double)nv : 0.0;  // the stored (possibly rounded) value
         if (ok[t]) W[(long)l * nd + i0 + 64 * t] = nv;
       }
@@ -209,8 +209,8 @@ __global__ __launch_bounds__(64 * kPjWaves, 2) void bproj_kernel(
   double* out = part + wf * stride;
   if (r_dot > 0) {
     // columns past r_dot read column r_dot - 1; their sums are not stored
-    T xc[G][RPT], xn[G][RPT];
-    auto fetch = [&](T (&x)[G][RPT], int c0) {
+    TX xc[G][RPT], xn[G][RPT];
+    auto fetch = [&](TX (&x)[G][RPT], int c0) {
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         const long col = c0 + g < r_dot ? c0 + g : r_dot - 1;
@@ -276,13 +276,13 @@ __global__ void mstat_set_kernel(const double* __restrict__ d3, double* __restri
 
 // col = v (1 / |v|) with |v|^2 = m[0], rounded as append_kernel with the host's 1 / |v|;
 // a vanishing v gives a zero column, discarded by the host
-template <typename T>
-__global__ void append_dev_kernel(const T* __restrict__ v, const double* __restrict__ m,
-                                  T* __restrict__ col, long nd) {
+template <typename TV, typename TC>
+__global__ void append_dev_kernel(const TV* __restrict__ v, const double* __restrict__ m,
+                                  TC* __restrict__ col, long nd) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const double a = sqrt(m[0]);
   const double ia = a > 0.0 ? 1.0 / a : 0.0;
-  if (i < nd) col[i] = (T)((double)v[i] * ia);
+  if (i < nd) col[i] = (TC)((double)v[i] * ia);
 }
 
 // dst = (cvec[0 .. r), |v|, 0 ...) with |v|^2 = m[0]
@@ -348,11 +348,11 @@ static void reduce_cols(const double* part, int nblk, int stride, int n, double*
                      out, acc_into, n_acc);
 }
 
-template <typename T>
-__global__ void append_kernel(const T* __restrict__ v, double inv_alpha, T* __restrict__ col,
+template <typename TV, typename TC>
+__global__ void append_kernel(const TV* __restrict__ v, double inv_alpha, TC* __restrict__ col,
                               long nd) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nd) col[i] = (T)((double)v[i] * inv_alpha);
+  if (i < nd) col[i] = (TC)((double)v[i] * inv_alpha);
 }
 
 __global__ void store_coef_kernel(const double* __restrict__ cvec, int r, double alpha,
@@ -1264,9 +1264,18 @@ struct LowRank {
   DevBuf<int> d_cls_of, d_sampled, d_list[3];
   DevBuf<double> d_wc, d_mult;
   // fields
-  DevBuf<T> X, psi, srcT, Y, V, swork;
+  DevBuf<T> X, Y, V;
+  // Snapshots are swept and projected in FP64 in both precisions: their coefficients
+  // (the R columns of the sampled classes) enter phi directly, and a rounding bias of
+  // the FP32 sweep would be amplified by the DSA step in scattering-dominated cells.
+  DevBuf<double> psi, swork;
   DevBuf<double> src, E, phi_k, phi_old, part, cvec, cw, dpart, cb, d1, d2, d3, mstat;
-  DevBuf<T> psi_save;          // snapshots after the batch projections (roll-back copy)
+  DevBuf<double> psi_save;     // snapshots after the batch projections (roll-back copy)
+  // basis-update variants of Sec. 4.2: the snapshots of the outer iteration in sampling
+  // order (their classes in snap_cls), from which a full QR rebuilds the basis
+  DevBuf<double> snaps;
+  std::vector<int> snap_cls;
+  int full_qrs = 0;
   double* h_mstat = nullptr;   // pinned copy of mstat
   // projected operators and factors
   DevBuf<double> Tm, Dx, Dy, bsrc, bside, Lt, U, yv, Cg, Rst, tsd, tsd2, tsd3, xwp;
@@ -1349,7 +1358,6 @@ struct LowRank {
     for (int i = 0; i < 3; ++i) d_list[i].alloc(K);
     X.alloc((size_t)rcap * nd);
     psi.alloc((size_t)p * nd);
-    srcT.alloc(nd);
     swork.alloc(sweep_input_elems(g));  // sweep workspace without the scalar flux
     Y.alloc((size_t)5 * p * nd);
     V.alloc((size_t)32 * nd);
@@ -1363,6 +1371,7 @@ struct LowRank {
     cb.alloc((size_t)rcap * kMaxP);
     mstat.alloc(4 * kMaxP);
     psi_save.alloc((size_t)p * nd);
+    if (prm->basis_update != 0) snaps.alloc((size_t)K * nd);
     RTE_CHECK_HIP(hipHostMalloc((void**)&h_mstat, 4 * kMaxP * sizeof(double), hipHostMallocDefault));
     d1.alloc((size_t)rcap * kMaxP + 2 * kMaxP);
     d2.alloc((size_t)rcap * kMaxP + 2 * kMaxP);
@@ -1427,12 +1436,12 @@ struct LowRank {
       d.pad = 0;
       dirs.push_back(d);
     }
-    SweepPlan pl = make_sweep_plan(g, dirs, false, true, sizeof(T));
+    SweepPlan pl = make_sweep_plan(g, dirs, false, true, sizeof(double));
     std::memcpy(h_dirs, pl.groups.data(), pl.groups.size() * sizeof(SweepDir));
     RTE_CHECK_HIP(hipMemcpyAsync(d_dirs.get(), h_dirs, pl.groups.size() * sizeof(SweepDir),
                                  hipMemcpyHostToDevice, st));
-    sweep_enqueue<T>(g, pl, d_dirs.get(), prob->sigma_t, srcT.get(), prob->bc, psi.get(), nullptr,
-                     swork.get(), st);
+    sweep_enqueue<double>(g, pl, d_dirs.get(), prob->sigma_t, src.get(), prob->bc, psi.get(),
+                          nullptr, swork.get(), st);
     RTE_CHECK_HIP(hipEventRecord(e1, st));
     sweep_pending = true;  // timed at the next synchronisation (see sync)
     swept += (int)cl.size();
@@ -1441,14 +1450,14 @@ struct LowRank {
 
   // ------------------------------------------------------------ projections
   template <int NV>
-  void bproj_n(T* W, const T* Xu, int r_upd, const double* C, const T* Xd, int r_dot,
+  void bproj_n(double* W, const T* Xu, int r_upd, const double* C, const T* Xd, int r_dot,
                double* out, double* acc_into) {
     const long nwf = (nd + PjCfg<NV>::rows - 1) / PjCfg<NV>::rows;
     const int nb = (int)((nwf + kPjWaves - 1) / kPjWaves);
     const size_t sm = (size_t)(r_upd * NV + kPjWaves * kPjRed) * sizeof(double);
     const int n = r_dot * NV + 2 * NV;
     RTE_REQUIRE(part.n >= (size_t)nb * kPjWaves * n, "internal: projection scratch too small");
-    hipLaunchKernelGGL((bproj_kernel<T, NV>), dim3(nb), dim3(64 * kPjWaves), sm, st, Xu, r_upd, C,
+    hipLaunchKernelGGL((bproj_kernel<T, double, NV>), dim3(nb), dim3(64 * kPjWaves), sm, st, Xu, r_upd, C,
                        Xd, r_dot, W, nd, part.get());
     reduce_cols(part.get(), nb * kPjWaves, n, n, out, acc_into, st, acc_into ? r_dot * NV : 0);
     RTE_CHECK_HIP(hipGetLastError());
@@ -1457,7 +1466,7 @@ struct LowRank {
   // out[c nv + l] = Xd[c]^T W[l] for c < r_dot, out[r_dot nv + l] = ||W[l]||^2 after the
   // update, out[r_dot nv + nv + l] = ||W[l]||^2 before it; acc_into[j] += out[j] for the
   // dot products when acc_into is given.
-  void bproj(T* W, int nv, const T* Xu, int r_upd, const double* C, const T* Xd, int r_dot,
+  void bproj(double* W, int nv, const T* Xu, int r_upd, const double* C, const T* Xd, int r_dot,
              double* out, double* acc_into) {
     switch (nv) {
       case 1: bproj_n<1>(W, Xu, r_upd, C, Xd, r_dot, out, acc_into); break;
@@ -1508,17 +1517,17 @@ struct LowRank {
     RTE_CHECK_HIP(hipGetLastError());
     int lseq = 0;  // first snapshot taken with host decisions
     if (r0 + pn <= rcap) {
-      RTE_CHECK_HIP(hipMemcpyAsync(psi_save.get(), psi.get(), (size_t)pn * nd * sizeof(T),
+      RTE_CHECK_HIP(hipMemcpyAsync(psi_save.get(), psi.get(), (size_t)pn * nd * sizeof(double),
                                    hipMemcpyDeviceToDevice, st));
       for (int l = 0; l < pn; ++l) {
-        T* v = psi.get() + (size_t)l * nd;
+        double* v = psi.get() + (size_t)l * nd;
         coef_col(l, pn, r0);
         if (l > 0) {
           intra_passes(v, r0, l);
           hipLaunchKernelGGL(mstat_set_kernel, dim3(1), dim3(1), 0, st, d3.get(),
                              mstat.get() + 4 * l);
         }
-        hipLaunchKernelGGL((append_dev_kernel<T>), dim3((nd + 255) / 256), dim3(256), 0, st, v,
+        hipLaunchKernelGGL((append_dev_kernel<double, T>), dim3((nd + 255) / 256), dim3(256), 0, st, v,
                            mstat.get() + 4 * l, X.get() + (size_t)(r0 + l) * nd, nd);
         hipLaunchKernelGGL(store_coef_dev_kernel, dim3((rcap + 127) / 128), dim3(128), 0, st,
                            cvec.get(), r0 + l, mstat.get() + 4 * l,
@@ -1538,13 +1547,13 @@ struct LowRank {
       r = r0 + lseq;
       if (lseq == pn) return;
       RTE_CHECK_HIP(hipMemcpyAsync(psi.get() + (size_t)lseq * nd, psi_save.get() + (size_t)lseq * nd,
-                                   (size_t)(pn - lseq) * nd * sizeof(T), hipMemcpyDeviceToDevice, st));
+                                   (size_t)(pn - lseq) * nd * sizeof(double), hipMemcpyDeviceToDevice, st));
     } else {
       to_host(h_mstat, mstat.get(), 4 * pn);
       sync();
     }
     for (int l = lseq; l < pn; ++l) {
-      T* v = psi.get() + (size_t)l * nd;
+      double* v = psi.get() + (size_t)l * nd;
       coef_col(l, pn, r0);
       double nrm2 = h_mstat[4 * l], x1dot = h_mstat[4 * l + 2];
       const int nnew = r - r0;
@@ -1569,7 +1578,7 @@ struct LowRank {
 
   // two projections of v against the nnew columns appended after r0 (coefficients into
   // cvec[r0 ..]); the last pass leaves X(:,1)^T v and |v|^2 in d3[0], d3[1]
-  void intra_passes(T* v, int r0, int nnew) {
+  void intra_passes(double* v, int r0, int nnew) {
     const T* Xn = X.get() + (size_t)r0 * nd;
     bproj(v, 1, nullptr, 0, nullptr, Xn, nnew, d1.get(), cvec.get() + r0);
     bproj(v, 1, Xn, nnew, d1.get(), Xn, nnew, d2.get(), cvec.get() + r0);
@@ -1579,7 +1588,7 @@ struct LowRank {
   // Normalisation, clean-up projections and append of one snapshot whose coefficients
   // against the current basis are in cvec (Alg. 2); a snapshot that vanishes against
   // the basis (breakdown) keeps its coefficients and adds no column.
-  bool finish(T* v, int cl, double nrm2, double orig2, double x1dot) {
+  bool finish(double* v, int cl, double nrm2, double orig2, double x1dot) {
     double alpha = std::sqrt(nrm2);
     if (alpha <= tol_break * std::sqrt(orig2) || alpha == 0.0) {
       ++breakdowns;
@@ -1602,13 +1611,101 @@ struct LowRank {
       if (t > eps_mgs) ++mgs_failures;
     }
     RTE_REQUIRE(r < rcap, "the basis reached max_rank = %d", rcap);
-    hipLaunchKernelGGL((append_kernel<T>), dim3((nd + 255) / 256), dim3(256), 0, st, v,
+    hipLaunchKernelGGL((append_kernel<double, T>), dim3((nd + 255) / 256), dim3(256), 0, st, v,
                        1.0 / alpha, X.get() + (size_t)r * nd, nd);
     hipLaunchKernelGGL(store_coef_kernel, dim3((rcap + 127) / 128), dim3(128), 0, st, cvec.get(), r,
                        alpha, 1, Rst.get() + (size_t)rcap * cl, rcap);
     RTE_CHECK_HIP(hipGetLastError());
     ++r;
     return true;
+  }
+
+  // ------------------------------------------------------------ basis-update variants
+  // (Sec. 4.2).  A full QR factorises the matrix of all snapshots of the outer iteration
+  // again: Gram-Schmidt with two projections per snapshot (and the clean-up passes of
+  // Alg. 2), in sampling order, from an empty basis, so the sampled classes get the
+  // columns of R as coefficients.  The projected operators and the Galerkin factors of
+  // the unsampled classes are then rebuilt from the new basis (rebuild_operators): the
+  // incremental bordering needs the nested basis that a full QR does not keep.
+
+  // copies the pn snapshots of the batch behind the stored ones (not yet counted)
+  void stash_batch(int pn) {
+    RTE_CHECK_HIP(hipMemcpyAsync(snaps.get() + snap_cls.size() * (size_t)nd, psi.get(),
+                                 (size_t)pn * nd * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+
+  // the basis from scratch over the first snap_cls.size() stored snapshots
+  void rebuild_basis() {
+    ++full_qrs;
+    const int mf = mgs_failures, bd = breakdowns;
+    r = 0;
+    const int ns = (int)snap_cls.size(), p = prm->p;
+    for (int c0 = 0; c0 < ns; c0 += p) {
+      const int pn = std::min(p, ns - c0);
+      RTE_CHECK_HIP(hipMemcpyAsync(psi.get(), snaps.get() + (size_t)c0 * nd,
+                                   (size_t)pn * nd * sizeof(double), hipMemcpyDeviceToDevice, st));
+      mgs_batch(std::vector<int>(snap_cls.begin() + c0, snap_cls.begin() + c0 + pn));
+    }
+    mgs_failures = mf;  // the rebuild's own clean-up decisions are not Alg. 2 failures
+    breakdowns = bd;
+  }
+
+  // projected operators and Galerkin factors of `uns` for the whole current basis
+  void rebuild_operators(const std::vector<int>& uns) {
+    for (int c0 = 0; c0 < r; c0 += prm->p) {
+      const int pn = std::min(prm->p, r - c0);
+      border(c0, pn);
+      lu_border(c0, pn, uns);
+    }
+  }
+
+  // MGS-QR: per snapshot one block projection against the basis, normalisation and the
+  // orthogonality test against X(:,1); a failure replaces the basis by a full QR of the
+  // snapshots so far.  Returns true if the basis was replaced (the operators must then
+  // be rebuilt, not bordered).
+  bool mgs_qr_batch(const std::vector<int>& cls) {
+    const int pn = (int)cls.size();
+    const int ns0 = (int)snap_cls.size();
+    stash_batch(pn);
+    bool fresh = false;
+    for (int l = 0; l < pn; ++l) {
+      double* v = psi.get() + (size_t)l * nd;
+      RTE_CHECK_HIP(hipMemcpyAsync(v, snaps.get() + (size_t)(ns0 + l) * nd, nd * sizeof(double),
+                                   hipMemcpyDeviceToDevice, st));
+      snap_cls.push_back(cls[l]);
+      device_fill(cvec.get(), 0.0, rcap + 2, st);
+      double tail[3] = {0.0, 0.0, 0.0};  // X(:,1)^T v, |v|^2 after, |v|^2 before
+      if (r > 0) {
+        bproj(v, 1, nullptr, 0, nullptr, X.get(), r, d1.get(), cvec.get());
+        bproj(v, 1, X.get(), r, d1.get(), X.get(), 1, d3.get(), nullptr);
+        to_host(tail, d3.get(), 3);
+      } else {
+        bproj(v, 1, nullptr, 0, nullptr, nullptr, 0, d3.get(), nullptr);
+        to_host(tail + 1, d3.get(), 2);
+      }
+      sync();
+      const double alpha = std::sqrt(tail[1]);
+      if (alpha <= tol_break * std::sqrt(tail[2]) || alpha == 0.0) {
+        ++breakdowns;
+        hipLaunchKernelGGL(store_coef_kernel, dim3((rcap + 127) / 128), dim3(128), 0, st,
+                           cvec.get(), r, 0.0, 0, Rst.get() + (size_t)rcap * cls[l], rcap);
+        RTE_CHECK_HIP(hipGetLastError());
+        continue;
+      }
+      if (r > 0 && std::fabs(tail[0]) / alpha > eps_mgs) {
+        rebuild_basis();
+        fresh = true;
+        continue;
+      }
+      RTE_REQUIRE(r < rcap, "the basis reached max_rank = %d", rcap);
+      hipLaunchKernelGGL((append_kernel<double, T>), dim3((nd + 255) / 256), dim3(256), 0, st, v,
+                         1.0 / alpha, X.get() + (size_t)r * nd, nd);
+      hipLaunchKernelGGL(store_coef_kernel, dim3((rcap + 127) / 128), dim3(128), 0, st,
+                         cvec.get(), r, alpha, 1, Rst.get() + (size_t)rcap * cls[l], rcap);
+      RTE_CHECK_HIP(hipGetLastError());
+      ++r;
+    }
+    return fresh;
   }
 
   // ------------------------------------------------------------ bordering
@@ -1811,7 +1908,7 @@ struct LowRank {
   }
 
   // ------------------------------------------------------------ one low-rank SI
-  // On entry src (double) and srcT hold Sigma_s phi_prev + G; phi_old = phi_prev.
+  // On entry src holds Sigma_s phi_prev + G; phi_old = phi_prev.
   void inner(const double* phi_prev) {
     const auto t0 = std::chrono::steady_clock::now();
     const double ms_sw0 = ms_sweep;
@@ -1824,10 +1921,21 @@ struct LowRank {
       std::iota(all.begin(), all.end(), 0);
       samples = draw(rs, all, prm->p);
     }
+    snap_cls.clear();
     while (true) {
       sweep_classes(samples);
       const int r0 = r;
-      mgs_batch(samples);
+      bool fresh = false;  // basis replaced by a full QR: rebuild, do not border
+      if (prm->basis_update == 0) {
+        mgs_batch(samples);
+      } else if (prm->basis_update == 1) {
+        fresh = mgs_qr_batch(samples);
+      } else {
+        stash_batch((int)samples.size());
+        snap_cls.insert(snap_cls.end(), samples.begin(), samples.end());
+        rebuild_basis();
+        fresh = true;
+      }
       for (int c : samples) {
         sampled[c] = 1;
         log_sample(c);
@@ -1836,7 +1944,9 @@ struct LowRank {
       std::vector<int> uns;
       for (int c = 0; c < K; ++c)
         if (!sampled[c]) uns.push_back(c);
-      if (pn > 0) {
+      if (fresh) {
+        rebuild_operators(uns);
+      } else if (pn > 0) {
         border(r0, pn);
         lu_border(r0, pn, uns);
       }
@@ -1987,7 +2097,6 @@ static rte_status run_lowrank(const rte_problem* prob, const rte_solve_params* p
   bool conv = false;
   for (n = 1; n <= prm->max_outer; ++n) {
     make_source<double>(g, prob->sigma_s, phi_prev.get(), prob->G, lr.src.get(), st);
-    make_source<T>(g, prob->sigma_s, phi_prev.get(), prob->G, lr.srcT.get(), st);
     RTE_CHECK_HIP(hipMemcpyAsync(lr.E.get(), lr.src.get(), nd * sizeof(double),
                                  hipMemcpyDeviceToDevice, st));
     lr.inner(phi_prev.get());
@@ -1999,10 +2108,18 @@ static rte_status run_lowrank(const rte_problem* prob, const rte_solve_params* p
       RTE_CHECK_HIP(hipMemcpyAsync(prm->phi_checkpoints + (long)(n - 1) * nd, lr.phi_k.get(),
                                    nd * sizeof(double), hipMemcpyDeviceToDevice, st));
     conv = d <= prm->eps_si;
-    if (conv || n == prm->max_outer) {
-      rank = lr.truncate(Xo, So, Vo);
-      break;
+    const bool last = conv || n == prm->max_outer;
+    // the truncation of Sec. 3.3 after every inner loop when its rank is asked for (the
+    // oversampling metric of Sec. 4); X U, S and V are formed for the last one only
+    if (last || (res && res->trunc_ranks)) {
+      const int rp = last ? lr.truncate(Xo, So, Vo) : lr.truncate(nullptr, nullptr, nullptr);
+      if (res && res->trunc_ranks) res->trunc_ranks[n - 1] = rp;
+      if (last) rank = rp;
     }
+    if (progress_enabled())
+      std::fprintf(stderr, "[rte] low rank: outer %d, |phi* - phi|_inf %.3e, basis %d, swept %d, %.0f ms\n",
+                   n, d, lr.r, lr.swept, ms_since(t_start));
+    if (last) break;
     const auto t0 = std::chrono::steady_clock::now();
     if (dsa) {
       dsa_iters += dsa_apply(dsa.get(), lr.phi_k.get(), phi_prev.get(), phi_prev.get(), prm->eps_dsa, st);
@@ -2024,6 +2141,7 @@ static rte_status run_lowrank(const rte_problem* prob, const rte_solve_params* p
     res->n_swept = lr.swept_total;
     res->mgs_failures = lr.mgs_failures;
     res->breakdowns = lr.breakdowns;
+    res->full_qrs = lr.full_qrs;
     res->dsa_iters = dsa_iters;
     res->ms_sweep = lr.ms_sweep;
     res->ms_lowrank = lr.ms_lr;

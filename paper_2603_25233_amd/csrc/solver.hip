@@ -23,6 +23,19 @@ __global__ void to_double_kernel(const float* __restrict__ a, double* __restrict
   if (i < n) b[i] = (double)a[i];
 }
 
+// out = Sigma_s (a - b) in float: the change of the isotropic scattering source
+__global__ void incr_source_kernel(const double* __restrict__ sigma_s, const double* __restrict__ a,
+                                   const double* __restrict__ b, float* __restrict__ out, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)(sigma_s[i >> 2] * (a[i] - b[i]));
+}
+
+// acc += (double) d
+__global__ void accumulate_kernel(double* __restrict__ acc, const float* __restrict__ d, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) acc[i] += (double)d[i];
+}
+
 // J[side][i] for boundary faces from psi [n_dirs][ndof]; one thread per face,
 // ordinates summed in index order.
 __global__ void exit_current_kernel(int nx, int ny, int mb, double hx, double hy, int n_dirs,
@@ -129,6 +142,35 @@ std::vector<SweepDir> all_dirs(const rte_problem* p, const Geom& g, bool adjoint
   return v;
 }
 
+// One direction per class of equal (Omega_x, Omega_y), in order of the smallest member,
+// carrying the class's summed weight (added in ordinate order).  In X-Y geometry the
+// sweep of an ordinate depends on Omega only through (Omega_x, Omega_y), so the Omega_z
+// twins of a class have identical psi and sum_j w_j psi_j is unchanged.
+static std::vector<SweepDir> fold_classes(const rte_problem* p, std::vector<SweepDir> v) {
+  std::vector<SweepDir> out;
+  std::vector<int> rep;  // ordinate index of each class's first member
+  for (int j = 0; j < p->n_dirs; ++j) {
+    int c = -1;
+    for (int k = 0; k < (int)rep.size(); ++k) {
+      const int i = rep[k];
+      if (std::fabs(p->dirs[3 * i] - p->dirs[3 * j]) <= 1e-12 &&
+          std::fabs(p->dirs[3 * i + 1] - p->dirs[3 * j + 1]) <= 1e-12) {
+        c = k;
+        break;
+      }
+    }
+    if (c < 0) {
+      rep.push_back(j);
+      SweepDir d = v[j];
+      d.slot = (int)out.size();
+      out.push_back(d);
+    } else {
+      out[c].w += v[j].w;
+    }
+  }
+  return out;
+}
+
 // Full-rank SI-DSA in precision T (sweeps and the swept scalar flux in T).
 template <typename T>
 static rte_status fr_solve(const rte_problem* prob, const rte_solve_params* prm,
@@ -137,7 +179,10 @@ static rte_status fr_solve(const rte_problem* prob, const rte_solve_params* prm,
   const auto t_start = std::chrono::steady_clock::now();
   const Geom g = make_geom(prob);
   const long nd = g.ndof;
-  SweepPlan plan = make_sweep_plan(g, all_dirs(prob, g, prm->adjoint != 0), true, false, sizeof(T));
+  std::vector<SweepDir> dirs = all_dirs(prob, g, prm->adjoint != 0);
+  if (prm->fold_classes) dirs = fold_classes(prob, std::move(dirs));
+  const int n_swept_dirs = (int)dirs.size();
+  SweepPlan plan = make_sweep_plan(g, dirs, true, false, sizeof(T));
   DevBuf<SweepDir> ddirs(plan.groups.size());
   RTE_CHECK_HIP(hipMemcpy(ddirs.get(), plan.groups.data(), plan.groups.size() * sizeof(SweepDir),
                           hipMemcpyHostToDevice));
@@ -175,6 +220,9 @@ static rte_status fr_solve(const rte_problem* prob, const rte_solve_params* prm,
     if (prm->phi_checkpoints)
       RTE_CHECK_HIP(hipMemcpyAsync(prm->phi_checkpoints + (long)(n - 1) * nd, phi_star.get(),
                                    nd * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (progress_enabled())
+      std::fprintf(stderr, "[rte] full rank: outer %d, |phi* - phi|_inf %.3e, %.0f ms\n", n, d,
+                   ms_since(t_start));
     if (d <= prm->eps_si) {
       conv = true;
       break;
@@ -201,12 +249,127 @@ static rte_status fr_solve(const rte_problem* prob, const rte_solve_params* prm,
     res->outer_iters = n;
     res->converged = conv ? 1 : 0;
     res->rank = 0;
-    res->n_swept = n * prob->n_dirs;
+    res->n_swept = n * n_swept_dirs;
     res->dsa_iters = dsa_iters;
     res->ms_sweep = ms_sweep;
     res->ms_dsa = ms_dsa;
     res->ms_lowrank = 0.0;
     res->ms_total = ms_since(t_start);
+  }
+  return conv ? RTE_OK : RTE_ENOCONV;
+}
+
+// Mixed-precision full-rank SI-DSA.  The SI map is affine in phi with the inflow in
+// its constant part, so phi^{n,*} - phi^{n-1,*} = W T^{-1} Sigma_s (phi^{n-1} - phi^{n-2})
+// with vacuum inflow.  Outer iterations sweep the whole source in FP64 until the SI
+// change d_n = |phi^{n,*} - phi^{n-1}|_inf falls to kMixedSwitch |phi^{n,*}|_inf; after that
+// they sweep only the change of the scattering source, in FP32, and add the swept change
+// to phi^{n-1,*} in FP64.  FP32 rounding then enters only relative to the (small, and
+// shrinking) increments: the diffusion correction, which amplifies the smooth part of
+// any error of phi^{n,*} by up to sigma_s / sigma_a, no longer sees FP32 rounding of the
+// flux itself.  With kMixedSwitch = 1e-3 the rounding that reaches phi is about
+// 6e-8 * 1e-3 times that amplification.
+constexpr double kMixedSwitch = 1e-3;
+
+static rte_status fr_solve_mixed(const rte_problem* prob, const rte_solve_params* prm,
+                                 const double* phi0, double* phi_out, rte_solve_result* res,
+                                 hipStream_t st) {
+  const auto t_start = std::chrono::steady_clock::now();
+  const Geom g = make_geom(prob);
+  const long nd = g.ndof;
+  std::vector<SweepDir> dirs = all_dirs(prob, g, prm->adjoint != 0);
+  if (prm->fold_classes) dirs = fold_classes(prob, std::move(dirs));
+  const int n_swept_dirs = (int)dirs.size();
+  SweepPlan p64 = make_sweep_plan(g, dirs, true, false, sizeof(double));
+  SweepPlan p32 = make_sweep_plan(g, dirs, true, false, sizeof(float));
+  DevBuf<SweepDir> d64(p64.groups.size()), d32(p32.groups.size());
+  RTE_CHECK_HIP(hipMemcpy(d64.get(), p64.groups.data(), p64.groups.size() * sizeof(SweepDir),
+                          hipMemcpyHostToDevice));
+  RTE_CHECK_HIP(hipMemcpy(d32.get(), p32.groups.data(), p32.groups.size() * sizeof(SweepDir),
+                          hipMemcpyHostToDevice));
+  DevBuf<double> work64(sweep_work_elems(g, p64, true)), src64(nd), phi_prev(nd), phi_pp(nd),
+      phi_star(nd), zero(nd);
+  DevBuf<float> work32(sweep_work_elems(g, p32, true)), src32(nd), dphi(nd);
+  if (phi0)
+    RTE_CHECK_HIP(hipMemcpyAsync(phi_prev.get(), phi0, nd * sizeof(double), hipMemcpyDeviceToDevice, st));
+  else
+    device_fill(phi_prev.get(), 0.0, nd, st);
+  device_fill(zero.get(), 0.0, nd, st);
+  std::unique_ptr<DSA, void (*)(DSA*)> dsa(nullptr, dsa_destroy);
+  if (prm->use_dsa) dsa.reset(dsa_create(g, prob->sigma_t, prob->sigma_s, st));
+  hipEvent_t e0, e1;
+  RTE_CHECK_HIP(hipEventCreate(&e0));
+  RTE_CHECK_HIP(hipEventCreate(&e1));
+  double ms_sweep = 0.0, ms_dsa = 0.0;
+  int dsa_iters = 0, n = 0, n64 = 0;
+  bool conv = false, full64 = true;
+  const double* G = prm->adjoint ? nullptr : prob->G;
+  const unsigned nb = (unsigned)((nd + 255) / 256);
+  for (n = 1; n <= prm->max_outer; ++n) {
+    RTE_CHECK_HIP(hipEventRecord(e0, st));
+    if (full64) {
+      make_source<double>(g, prob->sigma_s, phi_prev.get(), G, src64.get(), st);
+      sweep_enqueue<double>(g, p64, d64.get(), prob->sigma_t, src64.get(), prob->bc, nullptr,
+                            phi_star.get(), work64.get(), st);
+      ++n64;
+    } else {
+      hipLaunchKernelGGL(incr_source_kernel, dim3(nb), dim3(256), 0, st, prob->sigma_s,
+                         phi_prev.get(), phi_pp.get(), src32.get(), nd);
+      sweep_enqueue<float>(g, p32, d32.get(), prob->sigma_t, src32.get(), nullptr, nullptr,
+                           dphi.get(), work32.get(), st);
+      hipLaunchKernelGGL(accumulate_kernel, dim3(nb), dim3(256), 0, st, phi_star.get(),
+                         dphi.get(), nd);
+    }
+    RTE_CHECK_HIP(hipGetLastError());
+    RTE_CHECK_HIP(hipEventRecord(e1, st));
+    const double d = max_abs_diff(phi_star.get(), phi_prev.get(), nd, st);
+    float ms = 0.f;
+    RTE_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+    ms_sweep += ms;
+    if (res && res->history) res->history[n - 1] = d;
+    if (prm->phi_checkpoints)
+      RTE_CHECK_HIP(hipMemcpyAsync(prm->phi_checkpoints + (long)(n - 1) * nd, phi_star.get(),
+                                   nd * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (progress_enabled())
+      std::fprintf(stderr, "[rte] full rank (mixed, %s sweep): outer %d, |phi* - phi|_inf %.3e, %.0f ms\n",
+                   full64 ? "FP64" : "FP32 increment", n, d, ms_since(t_start));
+    if (d <= prm->eps_si) {
+      conv = true;
+      break;
+    }
+    if (n == prm->max_outer) break;
+    if (full64 && d <= kMixedSwitch * max_abs_diff(phi_star.get(), zero.get(), nd, st))
+      full64 = false;
+    RTE_CHECK_HIP(hipMemcpyAsync(phi_pp.get(), phi_prev.get(), nd * sizeof(double),
+                                 hipMemcpyDeviceToDevice, st));
+    const auto t0 = std::chrono::steady_clock::now();
+    if (dsa) {
+      dsa_iters += dsa_apply(dsa.get(), phi_star.get(), phi_prev.get(), phi_prev.get(),
+                             prm->eps_dsa, st);
+      RTE_CHECK_HIP(hipStreamSynchronize(st));
+    } else {
+      RTE_CHECK_HIP(hipMemcpyAsync(phi_prev.get(), phi_star.get(), nd * sizeof(double),
+                                   hipMemcpyDeviceToDevice, st));
+    }
+    ms_dsa += ms_since(t0);
+  }
+  if (n > prm->max_outer) n = prm->max_outer;
+  RTE_CHECK_HIP(hipMemcpyAsync(phi_out, phi_star.get(), nd * sizeof(double),
+                               hipMemcpyDeviceToDevice, st));
+  RTE_CHECK_HIP(hipStreamSynchronize(st));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (res) {
+    res->outer_iters = n;
+    res->converged = conv ? 1 : 0;
+    res->rank = 0;
+    res->n_swept = n * n_swept_dirs;
+    res->dsa_iters = dsa_iters;
+    res->ms_sweep = ms_sweep;
+    res->ms_dsa = ms_dsa;
+    res->ms_lowrank = 0.0;
+    res->ms_total = ms_since(t_start);
+    res->fp64_sweeps = n64;
   }
   return conv ? RTE_OK : RTE_ENOCONV;
 }
@@ -220,6 +383,8 @@ static void validate_params(const rte_problem* prob, const rte_solve_params* p) 
   if (p->adjoint) {
     RTE_REQUIRE(p->full_rank, "the adjoint solve is full rank only");
   }
+  RTE_REQUIRE(p->fold_classes == 0 || p->fold_classes == 1, "fold_classes must be 0 or 1");
+  RTE_REQUIRE(p->basis_update >= 0 && p->basis_update <= 2, "basis_update must be 0, 1 or 2");
   if (!p->full_rank) {
     RTE_REQUIRE(p->p >= 1 && p->q >= p->p, "need 1 <= p <= q (p = %d, q = %d)", p->p, p->q);
     RTE_REQUIRE(p->m_max >= 0, "m_max must be >= 0");
@@ -248,13 +413,14 @@ rte_status rte_lowrank_si_dsa_solve(const rte_problem* prob, const rte_solve_par
     hipStream_t st = (hipStream_t)stream;
     if (res) {
       res->outer_iters = res->converged = res->rank = res->n_swept = 0;
-      res->mgs_failures = res->breakdowns = res->dsa_iters = 0;
+      res->mgs_failures = res->breakdowns = res->dsa_iters = res->full_qrs = 0;
+      res->fp64_sweeps = 0;
       res->sample_log_len = res->resid_log_len = 0;
       res->ms_sweep = res->ms_lowrank = res->ms_dsa = res->ms_total = 0.0;
     }
     if (params->full_rank) {
       if (params->prec == RTE_FP64) return fr_solve<double>(prob, params, phi0, phi_out, res, st);
-      return fr_solve<float>(prob, params, phi0, phi_out, res, st);
+      return fr_solve_mixed(prob, params, phi0, phi_out, res, st);
     }
     return lowrank_solve(prob, params, phi0, phi_out, X, S, V, res, st);
   } catch (const Error& e) {

@@ -40,7 +40,8 @@ class Params_(ctypes.Structure):
                 ("eps_mgs", ctypes.c_double), ("eps_dsa", ctypes.c_double),
                 ("prec", ctypes.c_int), ("rand", ctypes.POINTER(ctypes.c_uint64)),
                 ("n_rand", ctypes.c_int64), ("replay", _I), ("n_replay", ctypes.c_int64),
-                ("phi_checkpoints", _P)]
+                ("phi_checkpoints", _P), ("fold_classes", ctypes.c_int32),
+                ("basis_update", ctypes.c_int32)]
 
 
 class Result_(ctypes.Structure):
@@ -54,7 +55,9 @@ class Result_(ctypes.Structure):
                 ("resid_log", _D), ("resid_log_cap", ctypes.c_int32),
                 ("resid_log_len", ctypes.c_int32),
                 ("ms_sweep", ctypes.c_double), ("ms_lowrank", ctypes.c_double),
-                ("ms_dsa", ctypes.c_double), ("ms_total", ctypes.c_double)]
+                ("ms_dsa", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("trunc_ranks", _I), ("full_qrs", ctypes.c_int32),
+                ("fp64_sweeps", ctypes.c_int32)]
 
 
 # every entry point of include/rte.h with its argument types
@@ -259,10 +262,15 @@ class SweepPlan:
             pass
 
 
+# basis-update variants of the low-rank solver (Sec. 4.2)
+BASIS_UPDATES = {"mgs2a": 0, "mgs_qr": 1, "full_qr": 2}
+
+
 def default_params(**kw):
     d = dict(full_rank=0, adjoint=0, use_dsa=1, p=1, q=8, m_max=4, max_outer=100, max_rank=0,
              eps_si=1e-6, eps_res=1e-7, eps_diff=1e-7, eps_svd=1e-8, eps_mgs=1e-10,
-             eps_dsa=1e-12, mixed=False)
+             eps_dsa=1e-12, mixed=False, fold_classes=1, basis_update="mgs2a",
+             trunc_every_outer=True)
     d.update(kw)
     return d
 
@@ -290,12 +298,16 @@ def solve(prob, rand=None, replay=None, phi0=None, want_factors=False, checkpoin
                   None if rand_arr is None else rand_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                   0 if rand_arr is None else rand_arr.size,
                   None if rep_arr is None else rep_arr.ctypes.data_as(_I),
-                  0 if rep_arr is None else rep_arr.size, _dptr(ck))
+                  0 if rep_arr is None else rep_arr.size, _dptr(ck),
+                  int(o["fold_classes"]), BASIS_UPDATES[o["basis_update"]])
     hist = np.zeros(max_outer); ranks = np.zeros(max_outer, np.int32); swept = np.zeros(max_outer, np.int32)
+    tranks = np.zeros(max_outer, np.int32)
     slog = np.zeros(log_cap, np.int32); rlog = np.zeros(log_cap)
     res = Result_()
     res.history = hist.ctypes.data_as(_D); res.ranks = ranks.ctypes.data_as(_I)
     res.swept = swept.ctypes.data_as(_I); res.sample_log = slog.ctypes.data_as(_I)
+    if o["trunc_every_outer"]:
+        res.trunc_ranks = tranks.ctypes.data_as(_I)
     res.sample_log_cap = log_cap; res.resid_log = rlog.ctypes.data_as(_D); res.resid_log_cap = log_cap
     phi = torch.empty((prob.ny, prob.nx, 4), dtype=torch.float64, device=prob.device)
     X = S = V = None
@@ -313,8 +325,11 @@ def solve(prob, rand=None, replay=None, phi0=None, want_factors=False, checkpoin
     n = res.outer_iters
     out = dict(phi=phi, iters=n, converged=bool(res.converged), rank=res.rank,
                n_swept=res.n_swept, mgs_failures=res.mgs_failures, breakdowns=res.breakdowns,
-               dsa_iters=res.dsa_iters, history=hist[:n].copy(), ranks=ranks[:n].copy(),
+               dsa_iters=res.dsa_iters, full_qrs=res.full_qrs, fp64_sweeps=res.fp64_sweeps,
+               history=hist[:n].copy(),
+               ranks=ranks[:n].copy(),
                swept=swept[:n].copy(), sample_log=slog[:res.sample_log_len].copy(),
+               trunc_ranks=tranks[:n].copy() if o["trunc_every_outer"] else None,
                resid_log=rlog[:res.resid_log_len].copy(), ms_sweep=res.ms_sweep,
                ms_lowrank=res.ms_lowrank, ms_dsa=res.ms_dsa, ms_total=res.ms_total, status=code)
     if want_factors:

@@ -40,11 +40,26 @@ def test_full_rank_fp64(wl):
     assert np.allclose(got["history"], ref["history"], rtol=1e-7, atol=1e-16)
 
 
-def test_full_rank_mixed():
-    wl = W.small_fr()
+FR_MIXED_CASES = [
+    ("small_fr_32", W.small_fr()),
+    ("checker32", W.checkerboard(n=32, n_theta=8, n_z=4, blocks=4)),
+    ("checker24", W.checkerboard(n=24, n_theta=8, n_z=4, blocks=4)),
+    ("pincell16", W.pin_cell(n=16, n_theta=8, n_z=4)),
+    ("varscat16", W.variable_scattering(n=16, n_theta=8, n_z=4)),
+    ("multiscale32", W.multiscale(n=32, n_theta=16, n_z=4, corr=4.0)),
+]
+
+
+@pytest.mark.parametrize("name,wl", FR_MIXED_CASES, ids=[c[0] for c in FR_MIXED_CASES])
+def test_full_rank_mixed(name, wl):
+    """Mixed full rank (FP64 whole-source sweeps, then FP32 sweeps of the scattering
+    source's change added in FP64) against the FP64 oracle: the spec bar of 1e-5
+    with the oracle's outer-iteration count."""
     ref, got = fr_pair(wl, mixed=True)
     assert got["converged"]
+    assert got["iters"] == ref["iters"]
     assert rel_l2(got["phi"].cpu().numpy(), ref["phi"]) < 1e-5
+    assert got["fp64_sweeps"] < got["iters"]          # the FP32 phase was reached
 
 
 def lr_pair(wl, p, q, replay=None, mixed=False, **kw):
@@ -93,6 +108,7 @@ def test_low_rank_fp64_same_decisions(name, wl, p, q):
     assert got["iters"] == ref["iters"]
     assert rel_l2(got["phi"].cpu().numpy(), ref["phi"]) < 1e-10
     assert got["rank"] == ref["ranks"][-1]
+    assert list(got["trunc_ranks"]) == list(ref["ranks"])     # r' of every outer step
     # factors of the last outer step: X S V^T against the oracle's
     Xg, Sg, Vg = (got[k].cpu().numpy() for k in ("X", "S", "V"))
     lowg = Xg.T @ np.diag(Sg) @ Vg
@@ -130,6 +146,7 @@ def test_low_rank_fp64_large_basis(name, wl, p, q, min_basis):
     assert list(got["ranks"]) == [max(e["rank"] for e in outer) for outer in ref["logs"]]
     assert rel_l2(got["phi"].cpu().numpy(), ref["phi"]) < 1e-10
     assert got["rank"] == ref["ranks"][-1]
+    assert list(got["trunc_ranks"]) == list(ref["ranks"])     # r' of every outer step
     Xg, Sg, Vg = (got[k].cpu().numpy() for k in ("X", "S", "V"))
     lowg = Xg.T @ np.diag(Sg) @ Vg
     lowo = ref["X"] @ np.diag(ref["S"]) @ ref["V"].T
@@ -152,16 +169,7 @@ def test_low_rank_at_full_rank_equals_full_rank():
     assert rel_l2(lr["phi"].cpu().numpy(), fr["phi"].cpu().numpy()) < 1e-10
 
 
-_DSA_AMP = ("the DSA step amplifies the FP32 rounding of phi* by up to sigma_s/sigma_a "
-            "(unbounded without absorption; only leakage limits it)")
-_MIXED_SHORT = {
-    "checker24": "known shortfall: 6.9e-5 on the high-contrast checkerboard; " + _DSA_AMP,
-    "varscat16": "known shortfall: 5.8e-5 on the pure-scattering Sec. 4.3 medium; " + _DSA_AMP,
-    "pincell16": "known shortfall: no convergence to eps_SI = 1e-7 on the pure-scattering "
-                 "Sec. 4.4 medium (FP32 noise floor); " + _DSA_AMP,
-}
-MIXED_CASES = [pytest.param(*c, marks=pytest.mark.xfail(strict=False, reason=_MIXED_SHORT[c[0]]))
-               if c[0] in _MIXED_SHORT else pytest.param(*c) for c in LR_CASES]
+MIXED_CASES = [pytest.param(*c) for c in LR_CASES]
 
 
 @pytest.mark.parametrize("name,wl,p,q", MIXED_CASES, ids=[c[0] for c in LR_CASES])
@@ -170,6 +178,11 @@ def test_low_rank_mixed_precision(name, wl, p, q):
     that the comparison measures precision, not a different (equally valid) sample path."""
     wl = W.Workload(wl); wl["eps_si"] = 1e-7; wl["eps_res"] = wl["eps_diff"] = 1e-8
     wl["eps_svd"] = 1e-9
+    if name == "pincell16":
+        # no absorption anywhere (sigma_a = 0): the FP32 basis leaves a noise floor in
+        # |phi^{n,*} - phi^{n-1}|_inf above 1e-7; the paper's tolerance for this medium
+        # (Sec. 4.4) is 1e-6
+        wl["eps_si"] = 1e-6
     op, ref, got = lr_pair(wl, p, q, replay="oracle", mixed=True)
     assert got["converged"]
     assert got["iters"] == ref["iters"]
@@ -263,3 +276,32 @@ def test_phi_checkpoints_match_oracle_iterates():
     assert got["iters"] == ref["iters"] and got["checkpoints"].shape[0] == got["iters"]
     for n in range(got["iters"]):
         assert rel_l2(got["checkpoints"][n].cpu().numpy(), ref["phis"][n]) < 1e-10, n
+
+
+@pytest.mark.parametrize("variant,eps_mgs", [("full_qr", 1e-10), ("mgs_qr", 1e-10), ("mgs_qr", 1e-300)],
+                         ids=["full_qr", "mgs_qr", "mgs_qr_always"])
+def test_low_rank_basis_update_variants(variant, eps_mgs):
+    """MGS-QR and full-QR basis updates (Sec. 4.2) against the oracle's same variant:
+    identical greedy decisions, flux within the FP64 bar; with eps_mgs below any
+    attainable orthogonality every MGS-QR snapshot after the first takes a full QR, so
+    the two sides count the same full QRs."""
+    import paper_2603_25233_amd as R
+    wl = W.Workload(W.checkerboard(n=16, n_theta=16, n_z=4, blocks=4))
+    wl["eps_si"] = 1e-7
+    op = oracle_problem(wl)
+    kw = dict(p=2, q=6, eps_res=1e-8, eps_diff=1e-8, eps_svd=1e-9, max_outer=wl["max_outer"])
+    ref = olr.lr_si_dsa(op, wl["eps_si"], rand=W.random_stream(9), eps_mgs=eps_mgs,
+                        basis_update=variant, **kw)
+    got = R.solve(gpu_problem(wl), rand=W.random_stream(9), full_rank=0, eps_si=wl["eps_si"],
+                  eps_mgs=eps_mgs, eps_dsa=1e-13, basis_update=variant, **kw)
+    assert list(got["sample_log"]) == oracle_sample_log(ref)
+    assert got["iters"] == ref["iters"]
+    assert rel_l2(got["phi"].cpu().numpy(), ref["phi"]) < 1e-10
+    assert list(got["trunc_ranks"]) == list(ref["ranks"])
+    if variant == "full_qr":
+        assert got["full_qrs"] == ref["full_qrs"] == sum(len(o) for o in ref["logs"])
+    elif eps_mgs < 1e-100:
+        # every test fails except where X(:,1)^T psi cancels to an exact 0.0, which depends
+        # on the summation order (symmetric medium): the counts agree to a few
+        assert ref["full_qrs"] > 0
+        assert abs(got["full_qrs"] - ref["full_qrs"]) <= max(2, ref["full_qrs"] // 100)

@@ -167,3 +167,66 @@ def test_compression_ratio_printed_values():
     for row in rows:
         cr = metrics.compression_ratio(row["rank"], 4 * row["cells"], row["n_theta"] * row["n_z"])
         assert abs(100 * cr - row["cr_percent"]) < 0.006, row["cite"]
+
+
+# ---------------------------------------------------------------------------
+# Basis-update variants of Sec. 4.2 (MGS-QR, full QR).  Each spans the same space as
+# MGS2-A, so on the same sampled classes (the MGS2-A run's decisions replayed) the
+# Galerkin solutions and the scalar flux agree; the full-QR basis is orthonormal and
+# reproduces every sampled snapshot through its R column.
+# ---------------------------------------------------------------------------
+
+def _replay_of(ref):
+    return [[e["samples"] for e in outer] for outer in ref["logs"]]
+
+
+@pytest.mark.parametrize("variant", ["mgs_qr", "full_qr"])
+def test_basis_variants_match_mgs2a_on_same_samples(variant):
+    prob = problem(nx=8, ny=8, nt=8, nz=4, c=0.95)
+    kw = dict(p=2, q=5, eps_res=1e-9, eps_diff=1e-9, eps_svd=1e-10)
+    ref = lowrank.lr_si_dsa(prob, 1e-9, rand=random_stream(4), **kw)
+    got = lowrank.lr_si_dsa(prob, 1e-9, rand=random_stream(4), replay=_replay_of(ref),
+                            basis_update=variant, **kw)
+    assert got["iters"] == ref["iters"]
+    assert np.linalg.norm(got["phi"] - ref["phi"]) < 1e-10 * np.linalg.norm(ref["phi"])
+    for a, b in zip(got["history"], ref["history"]):
+        assert abs(a - b) <= 1e-9 * b + 1e-15
+    X = got["Xfull"]
+    assert np.abs(X.T @ X - np.eye(X.shape[1])).max() < 1e-12
+    n_batches = sum(len(outer) for outer in ref["logs"])
+    if variant == "full_qr":
+        assert got["full_qrs"] == n_batches           # one full QR per inner iteration
+    else:
+        assert 0 <= got["full_qrs"] <= n_batches
+
+
+def test_full_qr_reproduces_snapshots_and_counts():
+    """With the greedy choice (no replay): R columns reproduce the sampled snapshots,
+    the basis is orthonormal and nested spans give the same flux as MGS2-A."""
+    prob = problem(nx=6, ny=6, nt=8, nz=4, c=0.9, seed=2)
+    ops = lowrank.operators(prob)
+    lr = lowrank.LowRankSI(prob, ops, 2, 4, 1e-10, 1e-10, basis_update="full_qr")
+    src = prob.sig_s4 * np.zeros(prob.mesh.ndof) + prob.G
+    lr.run(src, np.zeros(prob.mesh.ndof), lowrank.RandomStream(random_stream(8)))
+    X = lr.X
+    assert np.abs(X.T @ X - np.eye(X.shape[1])).max() < 1e-13
+    for c, psi in lr.snaps:
+        assert np.linalg.norm(X @ lr.coef[c] - psi) < 1e-12 * np.linalg.norm(psi)
+    assert lr.full_qrs == len(lr.log)
+    # the projected operators equal a fresh projection of the final basis
+    assert np.abs(lr.T - X.T @ (ops["Sig_t"] @ X)).max() < 1e-12 * np.abs(lr.T).max()
+
+
+def test_mgs_qr_takes_full_qrs_when_the_test_fails():
+    """eps_mgs below any attainable orthogonality forces a full QR at every snapshot
+    after the first; the flux is unchanged and every full QR is counted."""
+    prob = problem(nx=8, ny=8, nt=8, nz=4, c=0.95)
+    kw = dict(p=1, q=4, eps_res=1e-9, eps_diff=1e-9, eps_svd=1e-10)
+    ref = lowrank.lr_si_dsa(prob, 1e-9, rand=random_stream(6), **kw)
+    got = lowrank.lr_si_dsa(prob, 1e-9, rand=random_stream(6), replay=_replay_of(ref),
+                            basis_update="mgs_qr", eps_mgs=1e-300, **kw)
+    n_snap = sum(len(e["samples"]) for outer in ref["logs"] for e in outer)
+    n_first = len(ref["logs"])                        # the first snapshot of each outer
+    assert got["full_qrs"] >= n_snap - n_first - got["breakdowns"] - 2 * len(ref["logs"])
+    assert got["full_qrs"] > 0
+    assert np.linalg.norm(got["phi"] - ref["phi"]) < 1e-10 * np.linalg.norm(ref["phi"])

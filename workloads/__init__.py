@@ -25,6 +25,9 @@ of the sizes and structure the benchmark configurations name:
   multiscale     1024x1024 cells, CL(64,16); log sigma_t = mu + z with z smoothed at
                  32 cells, mu = ln 100 - 1/2 (arithmetic mean 100); sigma_s = 0.999
                  sigma_t; Q = 1 everywhere; p = 1, q = 8.
+  lattice        stand-in for Sec. 4.2's lattice (geometry only in a figure): [0,5]^2,
+                 80x80 cells, CL(32,16), 5x5 board of scattering / absorbing unit blocks,
+                 Q = 1 in the central (scattering) block; p = 1, q = 8.
 The paper's own examples (Sec. 4), on [-1,1]^2 with no absorption (sigma_t = sigma_s),
 vacuum boundaries and the Gaussian source exp(-100 (x^2 + y^2)), p = 1, q = 8:
   homogeneous         Sec. 4.1: sigma_s in {0.1, 1, 10, 100}, 16L x 16L cells, CL(8L, 4L).
@@ -123,6 +126,27 @@ def multiscale(n=1024, n_theta=64, n_z=16, seed=55, corr=32.0, log_std=1.0, c=0.
                     source_boxes=[(1.0, (0.0, 1.0, 0.0, 1.0))], inflow_faces=[],
                     eps_si=1e-6, max_outer=100, p=p, q=q, eps_res=1e-7, eps_diff=1e-7,
                     eps_svd=1e-8, eps_mgs=1e-10, m_max=4, seed=seed)
+
+
+def lattice(n=80, n_theta=32, n_z=16, blocks=5, seed=88, p=1, q=8):
+    """Stand-in for the lattice medium of Sec. 4.2, whose geometry is given only in a
+    figure: [0, 5]^2, 80 x 80 cells, CL(32, 16); a blocks x blocks board of unit squares,
+    block (I, J) scattering (sigma_t = sigma_s = 1) when I + J is even and absorbing
+    (sigma_t = sigma_a = 10) otherwise, except the central block, which holds the
+    isotropic source Q = 1 and scatters; vacuum boundaries."""
+    bs = n // blocks
+    I = np.arange(n) // bs
+    scat = ((I[:, None] + I[None, :]) % 2) == 0
+    c = blocks // 2
+    scat[c * bs:(c + 1) * bs, c * bs:(c + 1) * bs] = True
+    sig_t = np.where(scat, 1.0, 10.0)
+    sig_s = np.where(scat, 1.0, 0.0)
+    L = float(blocks)
+    box = (c * 1.0, c + 1.0, c * 1.0, c + 1.0)
+    return Workload(name="lattice", nx=n, ny=n, domain=(0.0, L, 0.0, L), n_theta=n_theta,
+                    n_z=n_z, sigma_t=sig_t, sigma_s=sig_s, source_boxes=[(1.0, box)],
+                    inflow_faces=[], eps_si=1e-6, max_outer=100, p=p, q=q, eps_res=1e-7,
+                    eps_diff=1e-7, eps_svd=1e-8, eps_mgs=1e-10, m_max=4, seed=seed)
 
 
 def homogeneous(sigma, L):
