@@ -89,6 +89,22 @@ rte_status rte_sweep(const rte_problem* prob, const int32_t* dir_idx, int32_t n_
                      void* stream);
 
 /*
+ * Allocation-free rte_sweep, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Arguments, results and errors as rte_sweep; the caller still owns src, psi and phi.
+ * The workspace (direction table, anti-diagonal input copies, per-workgroup partial
+ * sums of the scalar flux) comes from a 256 MiB static device array that each device
+ * holds until the process ends, so the call makes no hipMalloc/hipFree.  A sweep whose
+ * workspace exceeds 256 MiB returns RTE_EINVAL (roughly: psi only up to ~1.5M cells in
+ * FP64; with phi, (number of workgroups + 2) * ndof * 8 bytes must fit).  All calls
+ * on one device share the array: calls that overlap in time on one device (other
+ * streams or host threads) race.  The call returns after its kernels have finished.
+ */
+rte_status rte_sweep_noalloc(const rte_problem* prob, const int32_t* dir_idx, int32_t n_sel,
+                             const void* src, void* psi, void* phi, rte_precision prec,
+                             void* stream);
+
+/*
  * Adjoint sweep: solves (D_j + Sigma_t)^T mu_i = src + b_j for each j = dir_idx[i],
  * where b_j holds |Omega_j . n| int_face g eta_k on the OUTFLOW sides of Omega_j
  * (g = prob->bc): the right-hand side of the adjoint of an exit-current functional.

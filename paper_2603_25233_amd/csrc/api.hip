@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -237,6 +238,58 @@ static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w
   if (n % 2 == 1) x[n / 2] = 0.0;
 }
 
+// ---------------------------------------------------------------- allocation-free sweep
+// rte_sweep_noalloc takes its workspace (the direction table, the anti-diagonal copies
+// of the inputs and the per-workgroup partial sums of the scalar flux) from this
+// file-scope device array instead of hipMalloc.  Each device holds its own copy for the
+// lifetime of the process.  In host code `scratch` only names a host-side stand-in:
+// kernels and copies get the device address from hipGetSymbolAddress (scratch_address).
+constexpr size_t kScratchBytes = size_t(256) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex scratch_mu;
+std::vector<void*> scratch_dev;  // per device ordinal: device address of `scratch`
+
+// Device address of the current device's `scratch`, looked up once per device with that
+// device current (its first rte_sweep_noalloc call).
+void* scratch_address() {
+  int dev = 0;
+  RTE_CHECK_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if ((int)scratch_dev.size() <= dev) scratch_dev.resize(dev + 1, nullptr);
+  if (!scratch_dev[dev]) {
+    void* p = nullptr;
+    RTE_CHECK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    RTE_REQUIRE(p != nullptr, "hipGetSymbolAddress gave no address for the scratch array");
+    scratch_dev[dev] = p;
+  }
+  return scratch_dev[dev];
+}
+}  // namespace
+
+// The sweep of launch_sweep with the workspace carved from `scratch`.  The workspace is
+// fully written by the layout kernel and the sweep before it is read, so nothing needs
+// clearing.  The call waits for its kernels (the direction table is copied from host
+// memory that ends with the call), like rte_sweep.
+template <typename T>
+static void noalloc_sweep(const Geom& g, const std::vector<SweepDir>& dirs, const double* sigma_t,
+                          const T* src, const double* bc, T* psi, T* phi, hipStream_t st) {
+  SweepPlan pl = make_sweep_plan(g, dirs, phi != nullptr, psi != nullptr, sizeof(T));
+  const size_t dir_bytes = (pl.groups.size() * sizeof(SweepDir) + 255) / 256 * 256;
+  const size_t work_bytes = sweep_work_elems(g, pl, phi != nullptr) * sizeof(T);
+  RTE_REQUIRE(dir_bytes + work_bytes <= kScratchBytes,
+              "rte_sweep_noalloc: this sweep needs %zu bytes of workspace; the scratch array "
+              "holds %zu (use rte_sweep or a sweep plan)", dir_bytes + work_bytes, kScratchBytes);
+  unsigned char* base = static_cast<unsigned char*>(scratch_address());
+  SweepDir* ddirs = reinterpret_cast<SweepDir*>(base);
+  T* work = reinterpret_cast<T*>(base + dir_bytes);
+  RTE_CHECK_HIP(hipMemcpyAsync(ddirs, pl.groups.data(), pl.groups.size() * sizeof(SweepDir),
+                               hipMemcpyHostToDevice, st));
+  sweep_enqueue<T>(g, pl, ddirs, sigma_t, src, bc, psi, phi, work, st);
+  RTE_CHECK_HIP(hipStreamSynchronize(st));
+}
+
 }  // namespace rte
 
 struct rte_sweep_plan_s {
@@ -263,6 +316,30 @@ int32_t rte_abi_version(void) { return 2; }
 rte_status rte_sweep(const rte_problem* prob, const int32_t* dir_idx, int32_t n_sel,
                      const void* src, void* psi, void* phi, rte_precision prec, void* stream) {
   return sweep_common(prob, dir_idx, n_sel, src, psi, phi, prec, stream, false);
+}
+
+rte_status rte_sweep_noalloc(const rte_problem* prob, const int32_t* dir_idx, int32_t n_sel,
+                             const void* src, void* psi, void* phi, rte_precision prec,
+                             void* stream) {
+  try {
+    validate_problem(prob, false, (hipStream_t)stream);
+    RTE_REQUIRE(dir_idx && n_sel >= 1, "dir_idx / n_sel");
+    RTE_REQUIRE(src, "src is NULL");
+    RTE_REQUIRE(psi || phi, "one of psi, phi is required");
+    RTE_REQUIRE(prec == RTE_FP64 || prec == RTE_MIXED, "unknown precision %d", (int)prec);
+    Geom g = make_geom(prob);
+    std::vector<SweepDir> dirs = sweep_dirs(prob, g, dir_idx, n_sel, false);
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == RTE_FP64)
+      noalloc_sweep<double>(g, dirs, prob->sigma_t, (const double*)src, prob->bc, (double*)psi,
+                            (double*)phi, st);
+    else
+      noalloc_sweep<float>(g, dirs, prob->sigma_t, (const float*)src, prob->bc, (float*)psi,
+                           (float*)phi, st);
+    return RTE_OK;
+  } catch (const Error& e) {
+    return e.code;
+  }
 }
 
 rte_status rte_adjoint_sweep(const rte_problem* prob, const int32_t* dir_idx, int32_t n_sel,

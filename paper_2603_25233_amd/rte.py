@@ -64,6 +64,8 @@ class Result_(ctypes.Structure):
 SIGNATURES = {
     "rte_sweep": ([ctypes.POINTER(Problem_), _I, ctypes.c_int32, _P, _P, _P, ctypes.c_int, _P],
                   ctypes.c_int),
+    "rte_sweep_noalloc": ([ctypes.POINTER(Problem_), _I, ctypes.c_int32, _P, _P, _P,
+                           ctypes.c_int, _P], ctypes.c_int),
     "rte_adjoint_sweep": ([ctypes.POINTER(Problem_), _I, ctypes.c_int32, _P, _P, _P,
                            ctypes.c_int, _P], ctypes.c_int),
     "rte_lowrank_si_dsa_solve": ([ctypes.POINTER(Problem_), ctypes.POINTER(Params_), _P, _P, _P,
@@ -225,6 +227,17 @@ def _sweep(entry, prob, dir_idx, src, want_psi=True, want_phi=False, mixed=False
 def sweep(prob, dir_idx, src, want_psi=True, want_phi=False, mixed=False):
     """(D_j + Sigma_t) psi_i = src + g_j^bc for j = dir_idx[i] (rte_sweep)."""
     return _sweep(lib().rte_sweep, prob, dir_idx, src, want_psi, want_phi, mixed)
+
+
+def sweep_noalloc(prob, dir_idx, src, psi=None, phi=None, mixed=False):
+    """rte_sweep into caller-provided outputs, with the library's static workspace
+    (rte_sweep_noalloc): no device allocation in the library or here."""
+    idx = np.ascontiguousarray(dir_idx, dtype=np.int32).reshape(-1)
+    cp = prob.c()
+    _check(lib().rte_sweep_noalloc(ctypes.byref(cp), idx.ctypes.data_as(_I), idx.size, _dptr(src),
+                                   _dptr(psi), _dptr(phi), RTE_MIXED if mixed else RTE_FP64,
+                                   _stream()))
+    return psi, phi
 
 
 def adjoint_sweep(prob, dir_idx, src, want_psi=True, want_phi=False, mixed=False):
