@@ -34,6 +34,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector (256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz)
+# FP64 flops of one cell solve of the sweep (the closed-form 4x4 solve: right-hand side,
+# determinant, refined reciprocal, two block products, outflow traces) and its weighted
+# contribution to the scalar flux, plus the fixed-order reduction of the group partial
+# sums: 93 + 4 per cell and swept direction (FMA = 2).
+SWEEP_FLOPS_PER_CELL_DIR = 97
 
 
 def kernel_source_hash():
@@ -42,8 +48,8 @@ def kernel_source_hash():
 
 
 def measured_traffic(profile="sweep_multiscale1024_pmc.md"):
-    """HBM bytes per launch of the psi-writing sweep from a committed rocprofv3 --pmc
-    summary, or None when it is missing or taken on a different sweep kernel source."""
+    """HBM bytes per launch of a sweep from a committed rocprofv3 --pmc summary, or None
+    when it is missing or taken on a different sweep kernel source."""
     path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
         return None
@@ -174,6 +180,59 @@ def basis_update_ablation(R, W, torch):
                           "dtype": "f64", "data": "synthetic"}), flush=True)
 
 
+def tomography_run(R, W, torch, n_fd=8):
+    """The adjoint workload at size: 256 x 256 cells, CL(32,8) (256 ordinates), log-normal
+    sigma_a smoothed over 8 cells, sigma_s = 5, 16 boundary point sources (4 per side),
+    exit currents on all 4 x 256 boundary faces; observations from a second seed's medium.
+    Loss and gradient (forward and adjoint SI-DSA to 1e-12 per source) are timed; the
+    gradient with respect to sigma_a is checked against FP64 central differences
+    (h = 1e-6) on n_fd seeded random cells.  One JSON line."""
+    wl, wtrue = W.tomography(), W.tomography(seed=45)
+    n = wl["nx"]
+    dirs, wts = R.cl_quadrature(wl["n_theta"], wl["n_z"])
+    srcs = W.tomography_sources(n)
+    bcs = np.stack([R.inflow_moments(n, n, wl["domain"], [(sd, i, 1.0)]) for sd, i in srcs])
+    base = R.Problem(n, n, wl["domain"], dirs, wts, wl["sigma_t"], wl["sigma_s"])
+    btrue = R.Problem(n, n, wl["domain"], dirs, wts, wtrue["sigma_t"], wtrue["sigma_s"])
+    kw = dict(eps_si=1e-12, eps_dsa=1e-13)
+    with torch.no_grad():
+        _, J_obs = R.detector_misfit_batch(btrue.sigma_t - btrue.sigma_s, btrue.sigma_s, btrue, bcs,
+                                           np.zeros((len(srcs), 4, n)), **kw)
+    sa = (base.sigma_t - base.sigma_s).clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L, J = R.detector_misfit_batch(sa, base.sigma_s, base, bcs, J_obs, **kw)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    g = sa.grad.reshape(-1).cpu().numpy()
+    cells = np.random.default_rng(64).choice(n * n, n_fd, replace=False)
+    h = 1e-6
+    fd = []
+    with torch.no_grad():
+        for c in cells:
+            vals = []
+            for sgn in (1.0, -1.0):
+                s2 = (base.sigma_t - base.sigma_s).clone().reshape(-1)
+                s2[c] += sgn * h
+                vals.append(R.detector_misfit_batch(s2.reshape(n, n), base.sigma_s, base, bcs,
+                                                    J_obs, **kw)[0].item())
+            fd.append((vals[0] - vals[1]) / (2 * h))
+    fd = np.array(fd)
+    print(json.dumps({"workload": "tomography 256x256 DG-Q1, CL(32,8) 256 ordinates, 16 boundary "
+                                  "point sources, 1024 boundary detectors, sigma_s = 5, log-normal "
+                                  "sigma_a (smoothed over 8 cells)",
+                      "loss": L.item(), "detectors": int(J.shape[0] * J.shape[1] * J.shape[2]),
+                      "forward_s": t1 - t0, "adjoint_and_gradient_s": t2 - t1,
+                      "fd_cells": int(n_fd), "fd_h": h,
+                      "grad_vs_fd_max_abs": float(np.abs(fd - g[cells]).max()),
+                      "grad_vs_fd_rel_to_max_grad": float(np.abs(fd - g[cells]).max() / np.abs(g).max()),
+                      "grad_vs_fd_max_rel_per_cell": float(np.max(np.abs(fd - g[cells]) / np.abs(fd))),
+                      "target": 1e-4, "dtype": "f64", "data": "synthetic"}), flush=True)
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -280,13 +339,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--only", choices=["step", "sweep", "sweep_large", "paper", "ablation", "copy"],
+    ap.add_argument("--only", choices=["step", "sweep", "sweep_large", "paper", "ablation",
+                                       "tomography", "copy"],
                     default="step",
                     help="step: the headline line (default); "
                          "sweep: only the psi-writing full-angle sweep of the headline medium; "
                          "sweep_large: the same, one JSON line of its own (--mixed: FP32); "
                          "paper: the paper's own examples (Sec. 4.1, 4.3, 4.4), one JSON line each; "
                          "ablation: MGS2-A / MGS-QR / full-QR basis updates (Sec. 4.2); "
+                         "tomography: loss and sigma gradient of the 16-source detector misfit "
+                         "at 256x256 with a central-difference check; "
                          "copy: a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lr", action="store_true",
@@ -324,6 +386,9 @@ def main():
         return
     if args.only == "ablation":
         basis_update_ablation(R, W, torch)
+        return
+    if args.only == "tomography":
+        tomography_run(R, W, torch)
         return
 
     wl = W.multiscale()
@@ -398,10 +463,25 @@ def main():
                                     "total": fr["ms_total"]},
                       "sweep_ms_per_outer": fr_sweep_ms}
     line["value"] = updates / wall
-    line["roofline"] = {"kernel": "psi sweep (diag_layout_kernel + sweep_kernel), full angle set",
-                        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                        "algorithmic_bytes_per_launch": k1_bytes}
+    psi_roof = {"kernel": "psi sweep (diag_layout_kernel + sweep_kernel), full angle set",
+                "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                "algorithmic_bytes_per_launch": k1_bytes}
+    if args.only == "step":
+        # The step's dominant kernel is the full-rank SI sweep (the phi-only sweep of one
+        # ordinate per class: source, anti-diagonal layout, sweep, fixed-order reduction of
+        # the group partial sums), timed by the solver with HIP events on its stream.
+        fr_flops = SWEEP_FLOPS_PER_CELL_DIR * ncell * line["fr"]["class_sweeps_per_outer"]
+        fr_tf = fr_flops / (fr_sweep_ms * 1e-3) / 1e12
+        line["roofline"] = {"kernel": "full-rank SI sweep, phi only (source_kernel, diag_layout_kernel, "
+                                      "sweep_kernel, reduce_parts_kernel), 512 class sweeps",
+                            "bound": "alu", "achieved": fr_tf, "peak": FP64_PEAK_TFLOPS,
+                            "unit": "TFLOP/s", "frac": fr_tf / FP64_PEAK_TFLOPS,
+                            "traffic": measured_traffic("fr_sweep_multiscale1024_pmc.md"),
+                            "algorithmic_flops_per_launch": fr_flops, "ms_per_launch": fr_sweep_ms}
+        line["roofline_psi_sweep"] = psi_roof
+    else:
+        line["roofline"] = psi_roof
     plan.close()
     del psi
     torch.cuda.empty_cache()

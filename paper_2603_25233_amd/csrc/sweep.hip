@@ -253,6 +253,58 @@ struct WriteBack {
 // Rows whose chunks one write-back wavefront stores.
 constexpr int kWbRows = 64;
 
+// Aligned groups of cells for direct stores.  A row is swept one cell per step (towards
+// +x, or towards -x when sx < 0); the cells of the flat [ny][nx] numbering form aligned
+// groups of GC = 128 bytes / cell size (4 cells in FP64, 8 in FP32: one cache line).  A
+// row's cells of one group are kept in registers until the row leaves the group (at the
+// group's end or the row's end) and then stored together, so that whole lines leave
+// the cache instead of 16- or 32-byte pieces (which cost a full 64-byte memory write
+// each).
+template <typename T>
+struct RowGroup {
+  static constexpr int GC = 128 / (4 * (int)sizeof(T));
+  T buf[GC - 1][4];  // the kept cells, newest last (a shift register: static indices only)
+  int k = 0;         // how many are kept
+};
+
+// Takes the moments v of cell c (canonical column ap) of a row swept in direction sx;
+// when base2 is given, the run is also stored there scaled by w2 (psi and its weighted
+// scalar-flux share from one buffer).
+template <typename T>
+__device__ __forceinline__ void put_grouped(T* base, long c, int ap, int nx, int sx, const T v[4],
+                                            RowGroup<T>& g, T* base2 = nullptr, T w2 = T(0)) {
+  constexpr int GC = RowGroup<T>::GC;
+  const int pos = (int)(c & (GC - 1));  // position in the group (base is 256-byte aligned)
+  const bool last = ap == nx - 1 || (sx > 0 ? pos == GC - 1 : pos == 0);
+  if (!last) {
+#pragma unroll
+    for (int i = 0; i + 1 < GC - 1; ++i)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) g.buf[i][m] = g.buf[i + 1][m];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) g.buf[GC - 2][m] = v[m];
+    ++g.k;
+    return;
+  }
+  // buf[i] (i >= GC - 1 - k) holds cell c - (GC - 1 - i) towards +x, c + (GC - 1 - i)
+  // towards -x: with c itself one contiguous run of k + 1 cells
+  const int k = g.k;
+  auto put = [&](long cell, const T x[4]) {
+    store4(base + 4 * cell, x);
+    if (base2) {
+      T wx[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) wx[m] = w2 * x[m];
+      store4(base2 + 4 * cell, wx);
+    }
+  };
+  put(c, v);
+#pragma unroll
+  for (int i = 0; i < GC - 1; ++i)
+    if (i >= GC - 1 - k) put(c + (long)sx * (i - (GC - 1)), g.buf[i]);
+  g.k = 0;
+}
+
 typedef __attribute__((address_space(3))) void lds_void;
 
 // One workgroup sweeps D directions (dirs[blockIdx.x*D + d]) of one quadrant.
@@ -566,6 +618,11 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
     pdst[d] = !RING && psi && grp[d].slot >= 0 ? psi + (long)grp[d].slot * ndof : nullptr;
   T* pp = !RING && part ? part + (long)blockIdx.x * ndof : nullptr;
   const T w0 = T(grp[0].w);
+  // Direct stores leave in aligned line-sized groups of a row's cells (put_grouped).
+  RowGroup<T> qgrp[RPT][RD];  // psi per direction ...
+  RowGroup<T> pgrp[RPT];      // ... and the weighted scalar-flux sum
+  (void)qgrp;
+  (void)pgrp;
   __syncthreads();  // step 0 staged
   int ns = 0;       // t mod NS
   int si = 0;       // t mod 3: input slot
@@ -608,13 +665,8 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
             } else {
               const int brow = sy > 0 ? r : ny - 1 - r;
               const long c = (long)brow * nx + (sx > 0 ? ap : nx - 1 - ap);
-              if (pdst[d]) store4(pdst[d] + 4 * c, ph);
-              if constexpr (PP) {  // D == 1 here
-                T wv[4];
-#pragma unroll
-                for (int m = 0; m < 4; ++m) wv[m] = w0 * ph[m];
-                store4(pp + 4 * c, wv);
-              }
+              // with the partial sums (D == 1 here) both leave from the one psi buffer
+              if (pdst[d]) put_grouped(pdst[d], c, ap, nx, sx, ph, qgrp[k][d], PP ? pp : nullptr, w0);
             }
           } else {
 #pragma unroll
@@ -629,7 +681,8 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
             T wv[4];
 #pragma unroll
             for (int m = 0; m < 4; ++m) wv[m] = D == 1 ? w0 * acc[m] : acc[m];
-            store4(pp + 4 * ((long)brow * nx + (sx > 0 ? ap : nx - 1 - ap)), wv);
+            const long c = (long)brow * nx + (sx > 0 ? ap : nx - 1 - ap);
+            put_grouped(pp, c, ap, nx, sx, wv, pgrp[k]);
           }
         }
       }

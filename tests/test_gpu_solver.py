@@ -305,3 +305,4 @@ def test_low_rank_basis_update_variants(variant, eps_mgs):
         # on the summation order (symmetric medium): the counts agree to a few
         assert ref["full_qrs"] > 0
         assert abs(got["full_qrs"] - ref["full_qrs"]) <= max(2, ref["full_qrs"] // 100)
+

@@ -42,8 +42,12 @@ def oracle_sweep(m, do, sig_t, src, bc, sel, transpose=False, w=None):
 # thread budget leaves fewer write-back wavefronts than 64-row blocks (two blocks each;
 # with FP32 the last two wavefronts' rows are all past the grid), rows shorter than one
 # FP32 chunk
+# (6, 1000, 16, 8): two rows per compute thread with 128 ordinates: the output ring does
+# not fit, every cell leaves through the paired direct stores (aligned 64-byte pairs of
+# a row's consecutive cells; with nx = 6 every row starts on a pair boundary, with
+# nx = 7 below every other row starts on the second cell of a pair)
 CASES = [(37, 70, 8, 4), (64, 64, 16, 8), (5, 129, 8, 2), (130, 3, 4, 2), (1, 1, 4, 2),
-         (13, 300, 16, 4), (7, 400, 16, 4)]
+         (13, 300, 16, 4), (7, 400, 16, 4), (6, 1000, 16, 8), (7, 777, 16, 4)]
 
 
 @pytest.mark.parametrize("nx,ny,nt,nz", CASES)
@@ -71,7 +75,7 @@ def test_adjoint_sweep_fp64_matches_oracle(nx, ny, nt, nz):
 
 
 @pytest.mark.parametrize("nx,ny,nt,nz", [(20, 30, 32, 16), (9, 40, 64, 32), (33, 17, 8, 4),
-                                         (13, 300, 16, 4), (7, 400, 16, 4)])
+                                         (13, 300, 16, 4), (7, 400, 16, 4), (5, 1024, 16, 8)])
 def test_scalar_flux_accumulation(nx, ny, nt, nz):
     """phi = sum_j w_j psi_j through the partial-sum path (1, 2 and 4 directions per group)."""
     import paper_2603_25233_amd as R
