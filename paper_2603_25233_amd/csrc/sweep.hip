@@ -234,7 +234,13 @@ __global__ void diag_layout_kernel(int nx, int ny, int qmask, const double* __re
 // more staging wavefronts, when the issue of the copies bounds the step).
 constexpr int kStageRows = 256;
 // Input slots in LDS: the staging wavefronts fill step t + 2 while step t is solved.
+// FP64 workgroups of two directions with two rows per thread (up to 1024 rows) have the
+// LDS for two slots only: they fill step t + 1 while step t is solved and wait for it
+// before the barrier that ends step t (such a step is long enough to cover the copy).
 constexpr int kInSlots = 3;
+__host__ __device__ constexpr int in_slots(size_t eb, int D, int RPT) {
+  return eb == 8 && D == 2 && RPT == 2 ? 2 : kInSlots;
+}
 
 // s_waitcnt immediate for vmcnt(n), n <= 63 (the 6-bit counter: bits 3:0 and 15:14),
 // with expcnt and lgkmcnt not waited for.
@@ -362,7 +368,7 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
   constexpr int RD = PSI ? D : 1;             // ring entries per row and step
   constexpr int BS = kPiece<T>;                // elements of a 16-byte piece
   T* vbuf = reinterpret_cast<T*>(smem_raw);   // [2][nr][D][2] y-inflow traces by row
-  constexpr int S = kInSlots;
+  constexpr int S = in_slots(sizeof(T), D, RPT);
   T* in_src = vbuf + 4L * nr * D;             // [S][nr][4] source moments of the step
   T* in_sig = in_src + 4L * S * nr;           // [S][nrs] sigma_t of the step (shifted)
   T* in_bnd = in_sig + (long)S * nrs;         // [S][BS] y-inflow of canonical row 0
@@ -504,12 +510,13 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
     constexpr int NIS = SR * CPC / 64;         // source copies
     constexpr int NIG = (SR / CPS + 63) / 64;  // sigma_t copies
     constexpr int K = NIS + NIG;
-    static_assert(kInSlots == 3 && K + 1 <= 63, "outstanding copies exceed the vmcnt range");
+    static_assert(K + 1 <= 63, "outstanding copies exceed the vmcnt range");
     const bool w0 = sw == 0;
     // after the copies of step t + 2 (any: whether it had cells for this wavefront), those
     // of step t + 1 have landed
+    // (two slots: every copy issued so far has landed)
     auto wait_next = [&](bool any) {
-      if (!any) __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+      if (S == 2 || !any) __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
       else if (w0) __builtin_amdgcn_s_waitcnt(vmcnt_imm(K + 1));
       else __builtin_amdgcn_s_waitcnt(vmcnt_imm(K));
     };
@@ -557,26 +564,28 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
       df += (t < ny ? t : ny - 1) - lo + 1;
       lo += t + 1 >= nx ? 1 : 0;
     };
-    // Plain barriers: the copies are waited for explicitly.
+    // Plain barriers: the copies are waited for explicitly.  AHEAD = S - 1 steps are
+    // staged before the loop; step t + AHEAD is staged during step t.
+    constexpr int AHEAD = S - 1;
     stage(0, lo, df, 0);
     advance(0);
     bool any = false;
-    if (nsteps > 1) {
+    if (AHEAD == 2 && nsteps > 1) {
       any = stage(1, lo, df, 1);
       advance(1);
     }
     wait_next(any);                // step 0 landed
     __builtin_amdgcn_s_barrier();  // step 0 staged
-    int sl2 = 2;                   // (t + 2) mod 3
+    int sla = AHEAD;               // (t + AHEAD) mod S
     for (int t = 0; t < nsteps; ++t) {
       any = false;
-      if (t + 2 < nsteps) {
-        any = stage(t + 2, lo, df, sl2);
-        advance(t + 2);
+      if (t + AHEAD < nsteps) {
+        any = stage(t + AHEAD, lo, df, sla);
+        advance(t + AHEAD);
       }
       wait_next(any);                // copies of step t + 1 landed
       __builtin_amdgcn_s_barrier();  // end of step t
-      sl2 = sl2 == S - 1 ? 0 : sl2 + 1;
+      sla = sla == S - 1 ? 0 : sla + 1;
     }
     __builtin_amdgcn_s_waitcnt(0);
     return;
@@ -625,7 +634,7 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
   (void)pgrp;
   __syncthreads();  // step 0 staged
   int ns = 0;       // t mod NS
-  int si = 0;       // t mod 3: input slot
+  int si = 0;       // t mod S: input slot
   for (int t = 0; t < nsteps; ++t) {
     const int sl = t & 1;
     const int lo = t >= nx ? t - nx + 1 : 0;
@@ -731,9 +740,9 @@ static std::vector<SweepDir> make_groups(const std::vector<SweepDir>& in, int D)
 
 // vbuf [2][nr][D][2] + in_src [S][nr][4] + in_sig [S][nr + 2 CPS] + in_bnd [S + 1][CPS]
 // + ring [kRingSlots][nr][RD][4] (with the ring; RD = D for psi, 1 for the scalar
-// flux), nr = padded rows, S = kInSlots
-static size_t sweep_lds_bytes(int nr, int D, bool psi, bool ring, size_t eb) {
-  constexpr size_t S = kInSlots;
+// flux), nr = padded rows, S = in_slots(eb, D, rows per thread)
+static size_t sweep_lds_bytes(int nr, int D, bool psi, bool ring, size_t eb, int rpt) {
+  const size_t S = in_slots(eb, D, rpt);
   const size_t slots = ring ? (eb == 8 ? WriteBack<double>::kRingSlots : WriteBack<float>::kRingSlots) : 0;
   const size_t cps = 16 / eb;
   return (4ull * nr * D + 4ull * S * nr + S * (nr + 2 * cps) + (S + 1) * cps +
@@ -791,13 +800,14 @@ SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool
   const size_t lcap = std::min(lmax, kLdsTwoPerCU);
   // Directions per workgroup (scalar flux only): enough workgroups to cover the chip
   // first; then D > 1 shares the staged inputs and the partial sums among directions.
-  // D is bounded by the register budget (FP64: 2, and 1 beyond 576 threads; FP32: 4)
-  // and by LDS.  With psi, one direction per workgroup (measured faster: two
-  // workgroups share a compute unit).
-  const int dmax = want_psi ? 1 : elem_bytes == 8 ? (pl.nt <= 576 && rpt == 1 ? 2 : 1) : 4;
+  // D is bounded by the register budget (FP64: 2, with one row per thread only up to
+  // 576 threads; FP32: 4) and by LDS (FP64 with two rows per thread: two input slots).
+  // With psi, one direction per workgroup (measured faster: two workgroups share a
+  // compute unit).
+  const int dmax = want_psi ? 1 : elem_bytes == 8 ? ((pl.nt <= 576 || rpt == 2) ? 2 : 1) : 4;
   int D = 1;
   while (D < dmax && dirs.size() / (2 * D) >= 256 &&
-         sweep_lds_bytes(nr, 2 * D, want_psi, true, elem_bytes) <= lmax)
+         sweep_lds_bytes(nr, 2 * D, want_psi, rpt == 1, elem_bytes, rpt) <= lmax)
     D *= 2;
   // the output ring if it fits and the plan is large enough for the store bandwidth to
   // matter (else each thread stores its cells directly, which is shorter per step)
@@ -807,10 +817,10 @@ SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool
   const int tcap = rpt == 2 ? 768 : elem_bytes == 8 && D > 1 ? 576 : 960;
   const int nwb = std::min((nr + kWbRows - 1) / kWbRows, (tcap - pl.nt) / 64);
   const bool ring = dirs.size() >= 64 && nwb >= 1 &&
-                    sweep_lds_bytes(nr, D, want_psi, true, elem_bytes) <= lmax;
-  RTE_REQUIRE(sweep_lds_bytes(nr, D, want_psi, ring, elem_bytes) <= lmax,
+                    sweep_lds_bytes(nr, D, want_psi, true, elem_bytes, rpt) <= lmax;
+  RTE_REQUIRE(sweep_lds_bytes(nr, D, want_psi, ring, elem_bytes, rpt) <= lmax,
               "sweep: %d x %d cells need %zu bytes of LDS per workgroup (device limit %zu)", g.nx,
-              g.ny, sweep_lds_bytes(nr, D, want_psi, ring, elem_bytes), lmax);
+              g.ny, sweep_lds_bytes(nr, D, want_psi, ring, elem_bytes, rpt), lmax);
   pl.D = D;
   pl.ring = ring ? 1 : 0;
   if (ring) pl.nt += 64 * nwb;
@@ -864,7 +874,8 @@ void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
                        g.ny, pl.qmask, sigma_t, src, bc, g.mb, shy, dsrc, dsig, dbnd);
     RTE_CHECK_HIP(hipGetLastError());
   }
-  const size_t lds = sweep_lds_bytes(pl.nc * pl.rpt, pl.D, psi != nullptr, pl.ring != 0, sizeof(T));
+  const size_t lds = sweep_lds_bytes(pl.nc * pl.rpt, pl.D, psi != nullptr, pl.ring != 0, sizeof(T),
+                                     pl.rpt);
   dim3 grid(pl.ngroups), block(pl.nt);
   T* pp = phi ? part : nullptr;
   // output mode: bit 0 the LDS ring, bit 1 psi, bit 2 the scalar-flux partial sums
@@ -893,10 +904,11 @@ void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
       bad();                                                   \
     }                                                          \
   } while (0)
-  // FP64 plans use D = 2 only with at most 576 threads (register budget)
-#define RTE_SWEEP_D(NTB, RP, SR)                                     \
-  if (pl.D == 1) RTE_SWEEP_CASE(1, NTB, RP, SR);                     \
-  else if constexpr (sizeof(T) == 8 && (NTB > 576 || RP > 1)) bad(); \
+  // FP64 plans use D = 2 only with at most 576 threads or with two rows per thread
+  // (register budget)
+#define RTE_SWEEP_D(NTB, RP, SR)                                                  \
+  if (pl.D == 1) RTE_SWEEP_CASE(1, NTB, RP, SR);                                  \
+  else if constexpr (sizeof(T) == 8 && NTB > 576 && RP == 1) bad();               \
   else if (pl.D == 2) RTE_SWEEP_CASE(2, NTB, RP, SR);                \
   else if constexpr (sizeof(T) == 8) bad();                          \
   else RTE_SWEEP_CASE(4, NTB, RP, SR);

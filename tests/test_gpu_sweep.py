@@ -75,9 +75,12 @@ def test_adjoint_sweep_fp64_matches_oracle(nx, ny, nt, nz):
 
 
 @pytest.mark.parametrize("nx,ny,nt,nz", [(20, 30, 32, 16), (9, 40, 64, 32), (33, 17, 8, 4),
-                                         (13, 300, 16, 4), (7, 400, 16, 4), (5, 1024, 16, 8)])
+                                         (13, 300, 16, 4), (7, 400, 16, 4), (5, 1024, 16, 8),
+                                         (3, 800, 32, 16)])
 def test_scalar_flux_accumulation(nx, ny, nt, nz):
-    """phi = sum_j w_j psi_j through the partial-sum path (1, 2 and 4 directions per group)."""
+    """phi = sum_j w_j psi_j through the partial-sum path (1, 2 and 4 directions per group;
+    (3, 800, 32, 16): 512 ordinates over two rows per thread, two FP64 directions per
+    workgroup with two input slots)."""
     import paper_2603_25233_amd as R
     prob, m, do, wo, sig_t, src, bc = make(nx, ny, nt, nz, seed=3)
     sel = np.arange(len(wo))
