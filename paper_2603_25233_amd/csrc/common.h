@@ -98,6 +98,7 @@ struct SweepPlan {
   int nc = 64;
   int rpt = 1;    // rows per compute thread
   int ring = 1;   // results leave through the LDS ring (else direct stores)
+  int grouped = 0;  // direct stores in line-sized groups of a row's cells
   int psi = 1;    // planned for psi output (else the scalar flux only)
   int qmask = 0;  // quadrants swept (bit q = (sx < 0) + 2 (sy < 0))
   int srows = 256;  // rows of a step that each staging wavefront copies

@@ -266,9 +266,9 @@ constexpr int kWbRows = 64;
 // group's end or the row's end) and then stored together, so that whole lines leave
 // the cache instead of 16- or 32-byte pieces (which cost a full 64-byte memory write
 // each).
-template <typename T>
+template <typename T, int NC = 128 / (4 * (int)sizeof(T))>
 struct RowGroup {
-  static constexpr int GC = 128 / (4 * (int)sizeof(T));
+  static constexpr int GC = NC;  // cells per group (a power of two)
   T buf[GC - 1][4];  // the kept cells, newest last (a shift register: static indices only)
   int k = 0;         // how many are kept
 };
@@ -276,10 +276,10 @@ struct RowGroup {
 // Takes the moments v of cell c (canonical column ap) of a row swept in direction sx;
 // when base2 is given, the run is also stored there scaled by w2 (psi and its weighted
 // scalar-flux share from one buffer).
-template <typename T>
+template <typename T, int NC>
 __device__ __forceinline__ void put_grouped(T* base, long c, int ap, int nx, int sx, const T v[4],
-                                            RowGroup<T>& g, T* base2 = nullptr, T w2 = T(0)) {
-  constexpr int GC = RowGroup<T>::GC;
+                                            RowGroup<T, NC>& g, T* base2 = nullptr, T w2 = T(0)) {
+  constexpr int GC = NC;
   const int pos = (int)(c & (GC - 1));  // position in the group (base is 256-byte aligned)
   const bool last = ap == nx - 1 || (sx > 0 ? pos == GC - 1 : pos == 0);
   if (!last) {
@@ -337,7 +337,9 @@ typedef __attribute__((address_space(3))) void lds_void;
 // and the staging loop keeps no per-step tallies.
 //
 // Output mode OUT (compile time): bit 0 the LDS ring, bit 1 psi, bit 2 the weighted
-// partial sums of the scalar flux (psi and the partial sums together only for D = 1).
+// partial sums of the scalar flux (psi and the partial sums together only for D = 1),
+// bit 3 direct stores in line-sized groups of a row's cells (large plans without the
+// ring; small plans store each cell, which keeps their latency-bound step short).
 // With the ring, step t leaves its results in LDS ring slot t mod kRingSlots
 // (per direction for psi, or the weighted sum over the group's directions for the
 // scalar flux).  A row's cells are grouped into aligned chunks of kChunkCells
@@ -356,6 +358,7 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
     T* __restrict__ psi, T* __restrict__ part, long ndof) {
   using WB = WriteBack<T>;
   constexpr bool RING = (OUT & 1) != 0, PSI = (OUT & 2) != 0, PP = (OUT & 4) != 0;
+  constexpr bool GRP = (OUT & 8) != 0;  // direct stores in line-sized groups (put_grouped)
   static_assert(PSI || PP, "no output");
   static_assert(!(PSI && PP) || D == 1, "psi with the scalar flux needs one direction per workgroup");
   constexpr int CW = WB::kChunkCells, NS = WB::kRingSlots, LPC = WB::kLanesPerCell;
@@ -408,7 +411,7 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
     const int eoff = half * (16 / (int)sizeof(T));
     // One ring entry per row and step: psi of the one direction (psi plans have D = 1),
     // or the weighted sum over the group's directions.
-    static_assert(!PSI || D == 1, "psi write-back with one direction per workgroup");
+    static_assert(!RING || !PSI || D == 1, "psi write-back with one direction per workgroup");
     using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
     // the ring piece of row r in slot `slot`
     auto ring_piece = [&](int slot, int r) {
@@ -628,8 +631,11 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
   T* pp = !RING && part ? part + (long)blockIdx.x * ndof : nullptr;
   const T w0 = T(grp[0].w);
   // Direct stores leave in aligned line-sized groups of a row's cells (put_grouped).
-  RowGroup<T> qgrp[RPT][RD];  // psi per direction ...
-  RowGroup<T> pgrp[RPT];      // ... and the weighted scalar-flux sum
+  // With two psi directions per workgroup (FP64, two rows per thread) the register budget
+  // holds groups of two cells (64 bytes, the memory's write granule) per row and direction.
+  constexpr int QGC = D > 1 ? 64 / (4 * (int)sizeof(T)) : 128 / (4 * (int)sizeof(T));
+  RowGroup<T, QGC> qgrp[RPT][RD];  // psi per direction ...
+  RowGroup<T> pgrp[RPT];           // ... and the weighted scalar-flux sum
   (void)qgrp;
   (void)pgrp;
   __syncthreads();  // step 0 staged
@@ -675,7 +681,17 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
               const int brow = sy > 0 ? r : ny - 1 - r;
               const long c = (long)brow * nx + (sx > 0 ? ap : nx - 1 - ap);
               // with the partial sums (D == 1 here) both leave from the one psi buffer
-              if (pdst[d]) put_grouped(pdst[d], c, ap, nx, sx, ph, qgrp[k][d], PP ? pp : nullptr, w0);
+              if constexpr (GRP) {
+                if (pdst[d]) put_grouped(pdst[d], c, ap, nx, sx, ph, qgrp[k][d], PP ? pp : nullptr, w0);
+              } else {
+                if (pdst[d]) store4(pdst[d] + 4 * c, ph);
+                if constexpr (PP) {  // D == 1 here
+                  T wv[4];
+#pragma unroll
+                  for (int m = 0; m < 4; ++m) wv[m] = w0 * ph[m];
+                  store4(pp + 4 * c, wv);
+                }
+              }
             }
           } else {
 #pragma unroll
@@ -691,7 +707,8 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
 #pragma unroll
             for (int m = 0; m < 4; ++m) wv[m] = D == 1 ? w0 * acc[m] : acc[m];
             const long c = (long)brow * nx + (sx > 0 ? ap : nx - 1 - ap);
-            put_grouped(pp, c, ap, nx, sx, wv, pgrp[k]);
+            if constexpr (GRP) put_grouped(pp, c, ap, nx, sx, wv, pgrp[k]);
+            else store4(pp + 4 * c, wv);
           }
         }
       }
@@ -803,8 +820,10 @@ SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool
   // D is bounded by the register budget (FP64: 2, with one row per thread only up to
   // 576 threads; FP32: 4) and by LDS (FP64 with two rows per thread: two input slots).
   // With psi, one direction per workgroup (measured faster: two workgroups share a
-  // compute unit).
-  const int dmax = want_psi ? 1 : elem_bytes == 8 ? ((pl.nt <= 576 || rpt == 2) ? 2 : 1) : 4;
+  // compute unit), except FP64 with two rows per thread, where one workgroup fills a
+  // compute unit's LDS and two directions halve the rounds.
+  const int dmax = want_psi ? (elem_bytes == 8 && rpt == 2 && !want_phi ? 2 : 1)
+                            : elem_bytes == 8 ? ((pl.nt <= 576 || rpt == 2) ? 2 : 1) : 4;
   int D = 1;
   while (D < dmax && dirs.size() / (2 * D) >= 256 &&
          sweep_lds_bytes(nr, 2 * D, want_psi, rpt == 1, elem_bytes, rpt) <= lmax)
@@ -823,6 +842,11 @@ SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool
               g.ny, sweep_lds_bytes(nr, D, want_psi, ring, elem_bytes, rpt), lmax);
   pl.D = D;
   pl.ring = ring ? 1 : 0;
+  // Large plans without the ring (two rows per thread) store in line-sized groups: their
+  // direct stores would otherwise write each 32-byte piece as a 64-byte burst.  Small
+  // plans (the low-rank loop's few ordinates) store each cell: their bytes are few and
+  // the grouping's register moves lengthen their latency-bound step.
+  pl.grouped = !ring && rpt == 2 && dirs.size() >= 64 ? 1 : 0;
   if (ring) pl.nt += 64 * nwb;
   pl.psi = want_psi ? 1 : 0;
   pl.groups = make_groups(dirs, D);
@@ -879,11 +903,20 @@ void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
   dim3 grid(pl.ngroups), block(pl.nt);
   T* pp = phi ? part : nullptr;
   // output mode: bit 0 the LDS ring, bit 1 psi, bit 2 the scalar-flux partial sums
-  const int mode = (pl.ring ? 1 : 0) | (psi ? 2 : 0) | (pp ? 4 : 0);
+  const int mode = (pl.ring ? 1 : 0) | (psi ? 2 : 0) | (pp ? 4 : 0) | (pl.grouped ? 8 : 0);
 #define RTE_SWEEP_K(DD, NTB, RP, SR, M)                                                         \
   RTE_REQUIRE(pl.nt <= NTB, "internal: %d threads for a sweep kernel of %d", pl.nt, NTB);        \
   hipLaunchKernelGGL((sweep_kernel<T, DD, NTB, RP, SR, M>), grid, block, lds, st, g.nx, g.ny,    \
                      g.mb, pl.nc, shx, shy, dirs_dev, dsrc, dsig, dbnd, bc, psi, pp, g.ndof)
+// grouped direct stores (mode bit 8) exist for two rows per thread only
+#define RTE_SWEEP_GRP(DD, NTB, RP, SR, M)                      \
+  do {                                                         \
+    if constexpr (RP == 2) {                                   \
+      RTE_SWEEP_K(DD, NTB, RP, SR, M);                         \
+    } else {                                                   \
+      bad();                                                   \
+    }                                                          \
+  } while (0)
 #define RTE_SWEEP_CASE(DD, NTB, RP, SR)                        \
   do {                                                         \
     if constexpr (DD == 1) {                                   \
@@ -894,12 +927,23 @@ void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
         case 5: RTE_SWEEP_K(DD, NTB, RP, SR, 5); break;        \
         case 6: RTE_SWEEP_K(DD, NTB, RP, SR, 6); break;        \
         case 7: RTE_SWEEP_K(DD, NTB, RP, SR, 7); break;        \
+        case 10: RTE_SWEEP_GRP(DD, NTB, RP, SR, 10); break;    \
+        case 12: RTE_SWEEP_GRP(DD, NTB, RP, SR, 12); break;    \
+        case 14: RTE_SWEEP_GRP(DD, NTB, RP, SR, 14); break;    \
         default: bad();                                        \
       }                                                        \
     } else if (mode == 4) {                                    \
       RTE_SWEEP_K(DD, NTB, RP, SR, 4);                         \
     } else if (mode == 5) {                                    \
       RTE_SWEEP_K(DD, NTB, RP, SR, 5);                         \
+    } else if (mode == 12) {                                   \
+      RTE_SWEEP_GRP(DD, NTB, RP, SR, 12);                      \
+    } else if constexpr (RP == 2 && sizeof(T) == 8) {          \
+      if (mode == 10) {                                        \
+        RTE_SWEEP_K(DD, NTB, RP, SR, 10);                      \
+      } else {                                                 \
+        bad();                                                 \
+      }                                                        \
     } else {                                                   \
       bad();                                                   \
     }                                                          \
@@ -938,6 +982,7 @@ void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
   }
 #undef RTE_SWEEP_D
 #undef RTE_SWEEP_CASE
+#undef RTE_SWEEP_GRP
 #undef RTE_SWEEP_K
   RTE_CHECK_HIP(hipGetLastError());
   if (phi) {

@@ -46,8 +46,10 @@ def oracle_sweep(m, do, sig_t, src, bc, sel, transpose=False, w=None):
 # not fit, every cell leaves through the paired direct stores (aligned 64-byte pairs of
 # a row's consecutive cells; with nx = 6 every row starts on a pair boundary, with
 # nx = 7 below every other row starts on the second cell of a pair)
+# (3, 800, 32, 16): 512 ordinates over two rows per thread: two FP64 directions per
+# workgroup, psi in aligned pairs of cells per row and direction
 CASES = [(37, 70, 8, 4), (64, 64, 16, 8), (5, 129, 8, 2), (130, 3, 4, 2), (1, 1, 4, 2),
-         (13, 300, 16, 4), (7, 400, 16, 4), (6, 1000, 16, 8), (7, 777, 16, 4)]
+         (13, 300, 16, 4), (7, 400, 16, 4), (6, 1000, 16, 8), (7, 777, 16, 4), (3, 800, 32, 16)]
 
 
 @pytest.mark.parametrize("nx,ny,nt,nz", CASES)
