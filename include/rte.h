@@ -174,6 +174,13 @@ typedef struct {
                             is unchanged up to rounding); 0 sweeps every ordinate     */
   int32_t basis_update;  /* low rank: 0 MGS2-A (Alg. 2); 1 MGS-QR; 2 full QR (the
                             basis-update variants compared in Sec. 4.2)             */
+  int32_t sampling;      /* low rank: 0 greedy random subsampling (Sec. 3.2); 1 DEIM
+                            points of the angular basis V of C = U S V^T (the
+                            alternative of the Remark in Sec. 3.2): the next p samples
+                            are the first p unsampled DEIM points of the leading r'
+                            columns of V (r' by the eps_svd rule), completed from the
+                            candidates in residual order; the stopping test keeps the
+                            q random candidates                                      */
 } rte_solve_params;
 
 /* What the solver reports (all HOST; optional arrays may be NULL).                    */

@@ -52,7 +52,18 @@ Readings (also implemented by the GPU library; each is listed in the design doc):
     a full QR is the Householder QR of the snapshot matrix (LAPACK) with the signs fixed
     so that diag(R) > 0; the sampled classes take the columns of R as coefficients, and
     the projected operators and right-hand sides are recomputed from the new basis (the
-    incremental bordering needs the nested basis that a full QR does not keep).
+    incremental bordering needs the nested basis that a full QR does not keep);
+  * DEIM sampling (the alternative of the Remark in Sec. 3.2; the paper gives no
+    listing): the stopping test is unchanged (q random candidates and their residuals);
+    the next samples come from C^{(n,k)} = [c_1 .. c_{N_Omega}] (R columns for sampled
+    angles, Galerkin coefficients for all others), its thin SVD C = U S V^T and the DEIM
+    indices (Chaturantabut-Sorensen greedy interpolation points) of the leading r'
+    columns of V, r' by the truncation rule with eps_svd; the rows of V are taken per
+    class (twins have equal columns in C, hence equal rows in V).  The next p samples
+    are the first p DEIM indices that are unsampled classes; when there are fewer, the
+    candidates in greedy residual order fill the rest.  A DEIM maximum is taken over the
+    unpicked rows with the 30-bit key of the greedy order, the lower class index on ties,
+    and the point selection stops once p unsampled classes are picked.
 """
 import math
 
@@ -116,6 +127,37 @@ def truncation_rank(s, eps_svd):
     return s.size
 
 
+def deim_indices(V, stop=None):
+    """DEIM interpolation indices of the columns of V (Chaturantabut-Sorensen): index l
+    maximises |rho| with rho = v_l - V_l (P^T V_l)^{-1} P^T v_l, the error of interpolating
+    column l at the indices P picked so far from the previous columns V_l.  Rows already
+    picked are skipped; `stop(idx)` ends the selection early."""
+    V = np.asarray(V, dtype=np.float64)
+    K, m = V.shape
+    idx = []
+    zero = order_key(0.0)
+    for l in range(m):
+        v = V[:, l]
+        if idx:
+            coef = np.linalg.solve(V[idx, :l], v[idx])
+            rho = v - V[:, :l] @ coef
+        else:
+            rho = v.copy()
+        best, bi = None, -1
+        for i in range(K):
+            if i in idx:
+                continue
+            key = order_key(abs(float(rho[i])))
+            if best is None or key > best:   # first maximum: lower index on ties
+                best, bi = key, i
+        if best is None or best == zero:
+            break
+        idx.append(bi)
+        if stop is not None and stop(idx):
+            break
+    return idx
+
+
 def direction_classes(dirs, tol=1e-12):
     """Group ordinates with equal (Omega_x, Omega_y); classes ordered by smallest member.
 
@@ -145,7 +187,8 @@ class LowRankSI:
     """One low-rank SI solve (Sec. 3.1) for a fixed source Sigma_s phi^{n-1} + G."""
 
     def __init__(self, prob, ops, p, q, eps_res, eps_diff, eps_mgs=1e-10, m_max=4,
-                 tol_break=1e-12, nthreads=0, basis_update="mgs2a"):
+                 tol_break=1e-12, nthreads=0, basis_update="mgs2a", sampling="greedy",
+                 eps_svd=1e-8):
         self.prob, self.ops = prob, ops
         self.p, self.q = p, q
         self.eps_res, self.eps_diff = eps_res, eps_diff
@@ -153,6 +196,8 @@ class LowRankSI:
         self.nthreads = nthreads
         assert basis_update in ("mgs2a", "mgs_qr", "full_qr"), basis_update
         self.basis_update = basis_update
+        assert sampling in ("greedy", "deim"), sampling
+        self.sampling, self.eps_svd = sampling, eps_svd
 
     # ---------------- Alg. 2 (MGS2-A) ----------------
     def mgs2a_append(self, psi):
@@ -312,6 +357,23 @@ class LowRankSI:
                 Cc[:, c] = self.galerkin(self.reps[c])
         return Cc
 
+    def deim_samples(self, order):
+        """The next p samples by DEIM on the angular basis (Remark in Sec. 3.2)."""
+        Cc = self.class_coefficients()
+        C = Cc[:, self.cls]                          # r x N_Omega
+        _, s, Vt = np.linalg.svd(C, full_matrices=False)
+        m = truncation_rank(s, self.eps_svd)
+        Vc = Vt[:m].T[self.reps]                     # one row per class
+        uns = lambda idx: sum(1 for c in idx if c not in self.coef)
+        picked = [c for c in deim_indices(Vc, stop=lambda idx: uns(idx) >= self.p)
+                  if c not in self.coef]
+        for c in order:
+            if len(picked) >= self.p:
+                break
+            if c not in picked:
+                picked.append(c)
+        return picked[:self.p]
+
     # ---------------- the inner loop (Sec. 3.1-3.3) ----------------
     def run(self, src, phi_prev, stream, replay=None):
         """Low-rank SI for the source `src`.  `replay` forces the sampled classes per
@@ -394,6 +456,8 @@ class LowRankSI:
                 break
             if replay is not None and k < len(replay):
                 samples = list(replay[k])
+            elif self.sampling == "deim":
+                samples = self.deim_samples(order)
             else:
                 samples = order[:self.p]
         self.C = Cc[:, self.cls]            # r x N_Omega, every ordinate takes its class column
@@ -422,14 +486,14 @@ def operators(prob):
 
 def lr_si_dsa(prob, eps_si, p, q, eps_res, eps_diff, eps_svd, rand, eps_mgs=1e-10, m_max=4,
               max_outer=100, phi0=None, use_dsa=True, replay=None, tol_break=1e-12,
-              nthreads=0, keep_factors=True, basis_update="mgs2a"):
+              nthreads=0, keep_factors=True, basis_update="mgs2a", sampling="greedy"):
     """Alg. 1.  `rand` is the uint64 stream; `replay` optionally forces samples per outer."""
     ops = operators(prob)
     stream = RandomStream(rand)
     phi_prev = np.zeros(prob.mesh.ndof) if phi0 is None else np.asarray(phi0, dtype=np.float64).copy()
     hist, logs, ranks, sampled, phis = [], [], [], [], []
     lr = LowRankSI(prob, ops, p, q, eps_res, eps_diff, eps_mgs, m_max, tol_break, nthreads,
-                   basis_update)
+                   basis_update, sampling, eps_svd)
     mgs_fail = breakdowns = full_qrs = 0
     out = None
     phi_star = phi_prev

@@ -311,7 +311,7 @@ extern "C" {
 
 const char* rte_last_error(void) { return rte::last_error(); }
 
-int32_t rte_abi_version(void) { return 2; }
+int32_t rte_abi_version(void) { return 3; }
 
 rte_status rte_sweep(const rte_problem* prob, const int32_t* dir_idx, int32_t n_sel,
                      const void* src, void* psi, void* phi, rte_precision prec, void* stream) {

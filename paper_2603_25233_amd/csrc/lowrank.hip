@@ -1185,6 +1185,97 @@ __global__ void build_v_kernel(const double* __restrict__ B, int K, const int* _
   V[t] = s > 0.0 ? B[(size_t)order[m] * K + c] / (s * std::sqrt(mult[c])) : 0.0;
 }
 
+// ------------------------------------------------------------------ DEIM point selection
+// Greedy DEIM interpolation points (Chaturantabut-Sorensen) of the leading rp right
+// singular vectors of the class coefficient matrix (the alternative sampling of the
+// Remark in Sec. 3.2).  The DEIM residual of column l (column l minus its interpolant at
+// the points of the previous columns) is column l of the Schur complement after l steps
+// of Gaussian elimination, so the points are the row pivots of partial pivoting; one
+// workgroup eliminates in place.  W [K][rp] work array, V(c, l) = B[order[l]][c] /
+// (s_l sqrt(mult[c])) (B holds S V^T of the multiplicity-weighted classes after the
+// one-sided Jacobi rotations).  Pivot: the largest |W(c, l)| over unpicked rows by the
+// 30-bit ordering key of the residual norms, the lower class on ties.  Stops once `need`
+// unsampled classes are picked or the remaining column is zero; piv gets the points in
+// order, npiv[0] their number.  used [K] work flags.
+constexpr int kDeimThreads = 256;
+
+__device__ __forceinline__ unsigned long long deim_key(double v) {
+  if (!(v > 0.0)) return 0ull;
+  int e = 0;
+  const double m = frexp(v, &e);
+  long long q = (long long)floor(ldexp(m, 30) + 0.5);
+  if (q == (1ll << 30)) {
+    ++e;
+    q = 1ll << 29;
+  }
+  return ((unsigned long long)(e + 4096) << 32) | (unsigned long long)q;
+}
+
+__global__ __launch_bounds__(kDeimThreads) void deim_kernel(
+    const double* __restrict__ B, int K, const int* __restrict__ order,
+    const double* __restrict__ sv, int rp, const double* __restrict__ mult,
+    const int* __restrict__ sampled, int need, double* __restrict__ W, int* __restrict__ used,
+    int* __restrict__ piv, int* __restrict__ npiv) {
+  __shared__ unsigned long long skey[kDeimThreads];
+  __shared__ int sidx[kDeimThreads];
+  __shared__ int spiv;
+  const int tid = threadIdx.x;
+  for (long t = tid; t < (long)K * rp; t += kDeimThreads) {
+    const int c = (int)(t / rp), l = (int)(t % rp);
+    W[t] = B[(size_t)order[l] * K + c] / (sv[l] * sqrt(mult[c]));
+  }
+  for (int c = tid; c < K; c += kDeimThreads) used[c] = 0;
+  __syncthreads();
+  int np = 0, found = 0;
+  for (int l = 0; l < rp && found < need; ++l) {
+    unsigned long long bk = 0ull;
+    int bi = K;
+    for (int c = tid; c < K; c += kDeimThreads) {
+      if (used[c]) continue;
+      const unsigned long long k = deim_key(fabs(W[(size_t)c * rp + l]));
+      if (k > bk || (k == bk && c < bi)) {
+        bk = k;
+        bi = c;
+      }
+    }
+    skey[tid] = bk;
+    sidx[tid] = bi;
+    __syncthreads();
+    for (int h = kDeimThreads / 2; h > 0; h >>= 1) {
+      if (tid < h) {
+        const unsigned long long ko = skey[tid + h];
+        const int io = sidx[tid + h];
+        if (ko > skey[tid] || (ko == skey[tid] && io < sidx[tid])) {
+          skey[tid] = ko;
+          sidx[tid] = io;
+        }
+      }
+      __syncthreads();
+    }
+    if (skey[0] == 0ull) break;  // the rest of column l is zero: no more points
+    if (tid == 0) {
+      spiv = sidx[0];
+      used[spiv] = 1;
+      piv[np] = spiv;
+    }
+    __syncthreads();
+    const int pv = spiv;
+    ++np;
+    if (!sampled[pv]) ++found;
+    // eliminate column l from the unpicked rows (columns l + 1 .. rp - 1)
+    const int nr = rp - l - 1;
+    const double d = W[(size_t)pv * rp + l];
+    if (nr > 0)
+      for (long t = tid; t < (long)K * nr; t += kDeimThreads) {
+        const int c = (int)(t / nr), k = l + 1 + (int)(t % nr);
+        if (used[c]) continue;
+        W[(size_t)c * rp + k] -= W[(size_t)c * rp + l] / d * W[(size_t)pv * rp + k];
+      }
+    __syncthreads();
+  }
+  if (tid == 0) npiv[0] = np;
+}
+
 double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -1983,6 +2074,11 @@ struct LowRank {
         samples.clear();
         for (int i = 0; i < (int)order.size() && (int)samples.size() < prm->p; ++i)
           samples.push_back(cand[order[i]]);
+        if (prm->sampling == 1) {
+          std::vector<int> greedy;
+          for (int i : order) greedy.push_back(cand[i]);
+          samples = deim_samples(greedy);
+        }
       }
     }
     end_replay_outer();
@@ -1990,16 +2086,13 @@ struct LowRank {
   }
 
   // ------------------------------------------------------------ truncation (Sec. 3.3)
-  int truncate(double* Xo, double* So, double* Vo) {
-    if (r == 0) return 0;
-    DevBuf<double> B((size_t)r * K), Qt((size_t)r * r), sv(r);
-    // coefficients of every class (Galerkin for the unsampled ones)
-    std::vector<int> uns;
-    for (int c = 0; c < K; ++c)
-      if (!sampled[c]) uns.push_back(c);
-    galerkin(uns, 2);
-    scalar_flux(B.get());
-    hipLaunchKernelGGL(identity_kernel, dim3((r * r + 255) / 256), dim3(256), 0, st, Qt.get(), r);
+  // One-sided Jacobi SVD of the r x K class matrix B (columns weighted by the square roots
+  // of the class multiplicities, so that its singular values are those of the r x N_Omega
+  // coefficient matrix): on return the rows of B are s_i v_i^T, the rows of Qt the
+  // columns of U, order the rows by descending singular value and sorted the values.
+  void svd_rows(double* Bp, double* Qtp, std::vector<int>& order, std::vector<double>& sorted) {
+    DevBuf<double> sv(r);
+    hipLaunchKernelGGL(identity_kernel, dim3((r * r + 255) / 256), dim3(256), 0, st, Qtp, r);
     // round-robin pairs
     const int m = r + (r & 1);
     const int npairs = m / 2;
@@ -2024,7 +2117,7 @@ struct LowRank {
     std::vector<double> hoff((size_t)(m - 1) * npairs);
     for (int sweep = 0; sweep < 60 && m > 1; ++sweep) {
       for (int rd = 0; rd < m - 1; ++rd)
-        hipLaunchKernelGGL(jacobi_round_kernel, dim3(npairs), dim3(64), 0, st, B.get(), K, Qt.get(), r,
+        hipLaunchKernelGGL(jacobi_round_kernel, dim3(npairs), dim3(64), 0, st, Bp, K, Qtp, r,
                            dpairs.get() + (size_t)rd * npairs * 2, off.get() + (size_t)rd * npairs);
       RTE_CHECK_HIP(hipGetLastError());
       RTE_CHECK_HIP(hipMemcpyAsync(hoff.data(), off.get(), hoff.size() * sizeof(double),
@@ -2034,15 +2127,75 @@ struct LowRank {
       for (double v : hoff) mx = std::max(mx, v);
       if (mx <= 1e-15) break;
     }
-    hipLaunchKernelGGL(row_norms_kernel, dim3(r), dim3(64), 0, st, B.get(), r, K, sv.get());
+    hipLaunchKernelGGL(row_norms_kernel, dim3(r), dim3(64), 0, st, Bp, r, K, sv.get());
     std::vector<double> hs(r);
     RTE_CHECK_HIP(hipMemcpyAsync(hs.data(), sv.get(), r * sizeof(double), hipMemcpyDeviceToHost, st));
     sync();
-    std::vector<int> order(r);
+    order.resize(r);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hs[a] > hs[b]; });
-    std::vector<double> sorted(r);
+    sorted.resize(r);
     for (int i = 0; i < r; ++i) sorted[i] = hs[order[i]];
+  }
+
+  // the r x K class matrix (multiplicity-weighted columns, Galerkin coefficients for the
+  // unsampled classes) into Bp
+  void class_matrix(double* Bp) {
+    std::vector<int> uns;
+    for (int c = 0; c < K; ++c)
+      if (!sampled[c]) uns.push_back(c);
+    galerkin(uns, 2);
+    std::memcpy(h_flags, sampled.data(), K * sizeof(int));
+    RTE_CHECK_HIP(hipMemcpyAsync(d_sampled.get(), h_flags, K * sizeof(int),
+                                 hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(cw_kernel, dim3((r + 63) / 64), dim3(64), 0, st, r, rcap, K, d_sampled.get(),
+                       Rst.get(), Cg.get(), d_wc.get(), d_mult.get(), cw.get(), Bp);
+    RTE_CHECK_HIP(hipGetLastError());
+  }
+
+  // DEIM sampling (Remark in Sec. 3.2): the first p unsampled classes among the DEIM points
+  // of the leading r' right singular vectors of C (r' by the eps_svd rule); fewer are
+  // completed from `greedy` (the candidates in residual order).
+  std::vector<int> deim_samples(const std::vector<int>& greedy) {
+    std::vector<int> out;
+    if (r > 0) {
+      DevBuf<double> B((size_t)r * K), Qt((size_t)r * r);
+      class_matrix(B.get());
+      std::vector<int> order;
+      std::vector<double> sorted;
+      svd_rows(B.get(), Qt.get(), order, sorted);
+      const int rp = tail_rank(sorted, prm->eps_svd);
+      if (rp > 0) {
+        DevBuf<int> dord(rp), used(K), piv(rp + 1);
+        DevBuf<double> dsv(rp), Wk((size_t)K * rp);
+        RTE_CHECK_HIP(hipMemcpyAsync(dord.get(), order.data(), rp * sizeof(int), hipMemcpyHostToDevice, st));
+        RTE_CHECK_HIP(hipMemcpyAsync(dsv.get(), sorted.data(), rp * sizeof(double), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(deim_kernel, dim3(1), dim3(kDeimThreads), 0, st, B.get(), K, dord.get(),
+                           dsv.get(), rp, d_mult.get(), d_sampled.get(), prm->p, Wk.get(), used.get(),
+                           piv.get(), piv.get() + rp);
+        RTE_CHECK_HIP(hipGetLastError());
+        std::vector<int> hp(rp + 1);
+        RTE_CHECK_HIP(hipMemcpyAsync(hp.data(), piv.get(), (rp + 1) * sizeof(int), hipMemcpyDeviceToHost, st));
+        sync();
+        for (int i = 0; i < hp[rp]; ++i)
+          if (!sampled[hp[i]] && (int)out.size() < prm->p) out.push_back(hp[i]);
+      }
+    }
+    for (int c : greedy) {
+      if ((int)out.size() >= prm->p) break;
+      if (std::find(out.begin(), out.end(), c) == out.end()) out.push_back(c);
+    }
+    return out;
+  }
+
+  int truncate(double* Xo, double* So, double* Vo) {
+    if (r == 0) return 0;
+    DevBuf<double> B((size_t)r * K), Qt((size_t)r * r);
+    // coefficients of every class (Galerkin for the unsampled ones)
+    class_matrix(B.get());
+    std::vector<int> order;
+    std::vector<double> sorted;
+    svd_rows(B.get(), Qt.get(), order, sorted);
     const int rp = tail_rank(sorted, prm->eps_svd);
     if (rp > 0 && (Xo || So || Vo)) {
       DevBuf<int> dord(rp);

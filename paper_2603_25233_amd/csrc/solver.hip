@@ -385,6 +385,7 @@ static void validate_params(const rte_problem* prob, const rte_solve_params* p) 
   }
   RTE_REQUIRE(p->fold_classes == 0 || p->fold_classes == 1, "fold_classes must be 0 or 1");
   RTE_REQUIRE(p->basis_update >= 0 && p->basis_update <= 2, "basis_update must be 0, 1 or 2");
+  RTE_REQUIRE(p->sampling == 0 || p->sampling == 1, "sampling must be 0 (greedy) or 1 (DEIM)");
   if (!p->full_rank) {
     RTE_REQUIRE(p->p >= 1 && p->q >= p->p, "need 1 <= p <= q (p = %d, q = %d)", p->p, p->q);
     RTE_REQUIRE(p->m_max >= 0, "m_max must be >= 0");

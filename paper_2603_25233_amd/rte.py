@@ -41,7 +41,7 @@ class Params_(ctypes.Structure):
                 ("prec", ctypes.c_int), ("rand", ctypes.POINTER(ctypes.c_uint64)),
                 ("n_rand", ctypes.c_int64), ("replay", _I), ("n_replay", ctypes.c_int64),
                 ("phi_checkpoints", _P), ("fold_classes", ctypes.c_int32),
-                ("basis_update", ctypes.c_int32)]
+                ("basis_update", ctypes.c_int32), ("sampling", ctypes.c_int32)]
 
 
 class Result_(ctypes.Structure):
@@ -277,12 +277,14 @@ class SweepPlan:
 
 # basis-update variants of the low-rank solver (Sec. 4.2)
 BASIS_UPDATES = {"mgs2a": 0, "mgs_qr": 1, "full_qr": 2}
+# angle sampling of the low-rank inner loop (Sec. 3.2 and the DEIM alternative of its Remark)
+SAMPLINGS = {"greedy": 0, "deim": 1}
 
 
 def default_params(**kw):
     d = dict(full_rank=0, adjoint=0, use_dsa=1, p=1, q=8, m_max=4, max_outer=100, max_rank=0,
              eps_si=1e-6, eps_res=1e-7, eps_diff=1e-7, eps_svd=1e-8, eps_mgs=1e-10,
-             eps_dsa=1e-12, mixed=False, fold_classes=1, basis_update="mgs2a",
+             eps_dsa=1e-12, mixed=False, fold_classes=1, basis_update="mgs2a", sampling="greedy",
              trunc_every_outer=True)
     d.update(kw)
     return d
@@ -312,7 +314,8 @@ def solve(prob, rand=None, replay=None, phi0=None, want_factors=False, checkpoin
                   0 if rand_arr is None else rand_arr.size,
                   None if rep_arr is None else rep_arr.ctypes.data_as(_I),
                   0 if rep_arr is None else rep_arr.size, _dptr(ck),
-                  int(o["fold_classes"]), BASIS_UPDATES[o["basis_update"]])
+                  int(o["fold_classes"]), BASIS_UPDATES[o["basis_update"]],
+                  SAMPLINGS[o["sampling"]])
     hist = np.zeros(max_outer); ranks = np.zeros(max_outer, np.int32); swept = np.zeros(max_outer, np.int32)
     tranks = np.zeros(max_outer, np.int32)
     slog = np.zeros(log_cap, np.int32); rlog = np.zeros(log_cap)

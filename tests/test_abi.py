@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_abi_version(L):
-    assert L.lib().rte_abi_version() == 2
+    assert L.lib().rte_abi_version() == 3
 
 
 @pytest.mark.parametrize("nt,nz", [(4, 2), (8, 4), (16, 8), (32, 8), (32, 16), (64, 16), (6, 3)])

@@ -306,3 +306,34 @@ def test_low_rank_basis_update_variants(variant, eps_mgs):
         assert ref["full_qrs"] > 0
         assert abs(got["full_qrs"] - ref["full_qrs"]) <= max(2, ref["full_qrs"] // 100)
 
+
+
+DEIM_CASES = [
+    ("multiscale10_cl32x4", W.multiscale(n=10, n_theta=32, n_z=4, corr=3.0), 2, 16),
+    ("multiscale12_cl16x8", W.multiscale(n=12, n_theta=16, n_z=8, corr=4.0, seed=7), 1, 8),
+]
+
+
+@pytest.mark.parametrize("name,wl,p,q", DEIM_CASES, ids=[c[0] for c in DEIM_CASES])
+def test_low_rank_deim_sampling(name, wl, p, q):
+    """DEIM sampling (the alternative of the Remark in Sec. 3.2) against the oracle's:
+    after the random first group every sample is a DEIM point of the angular basis of C
+    (or, when the points run short of unsampled classes, a greedy candidate), so equal
+    sample sequences check the class coefficient matrix, its SVD and the point selection;
+    outer count, flux and truncation ranks as for the greedy sampling.  Random log-normal
+    media: no symmetry makes two singular values or two DEIM residuals equal."""
+    import paper_2603_25233_amd as R
+    wl = W.Workload(wl); wl["eps_si"] = 1e-6
+    op = oracle_problem(wl)
+    kw = dict(p=p, q=q, eps_res=1e-7, eps_diff=1e-7, eps_svd=1e-8, max_outer=wl["max_outer"])
+    ref = olr.lr_si_dsa(op, wl["eps_si"], rand=W.random_stream(wl["seed"]), sampling="deim", **kw)
+    grd = olr.lr_si_dsa(op, wl["eps_si"], rand=W.random_stream(wl["seed"]), **kw)
+    assert oracle_sample_log(ref) != oracle_sample_log(grd)      # DEIM decides
+    got = R.solve(gpu_problem(wl), rand=W.random_stream(wl["seed"]), full_rank=0,
+                  eps_si=wl["eps_si"], eps_mgs=1e-10, eps_dsa=1e-13, sampling="deim", **kw)
+    olog = oracle_sample_log(ref)
+    assert list(got["sample_log"]) == olog, "first divergence at %d" % next(
+        (i for i, (a, b) in enumerate(zip(got["sample_log"], olog)) if a != b), min(len(olog), len(got["sample_log"])))
+    assert got["iters"] == ref["iters"]
+    assert rel_l2(got["phi"].cpu().numpy(), ref["phi"]) < 1e-10
+    assert list(got["trunc_ranks"]) == list(ref["ranks"])

@@ -230,3 +230,46 @@ def test_mgs_qr_takes_full_qrs_when_the_test_fails():
     assert got["full_qrs"] >= n_snap - n_first - got["breakdowns"] - 2 * len(ref["logs"])
     assert got["full_qrs"] > 0
     assert np.linalg.norm(got["phi"] - ref["phi"]) < 1e-10 * np.linalg.norm(ref["phi"])
+
+
+def test_deim_indices_small_example_by_hand():
+    """v_1 = (1, 0, 2): largest entry in row 2.  v_2 = (0, 1, 1) interpolated at row 2 by
+    0.5 v_1 leaves rho = (-0.5, 1, 0): row 1."""
+    V = np.array([[1.0, 0.0], [0.0, 1.0], [2.0, 1.0]])
+    assert lowrank.deim_indices(V) == [2, 1]
+    # sign and scale of a column do not move the points
+    assert lowrank.deim_indices(V * np.array([-3.0, 0.5])) == [2, 1]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_deim_indices_are_the_row_pivots_of_partial_pivoting_lu(seed):
+    """The DEIM residual of column l is column l of the Schur complement after l steps of
+    Gaussian elimination, so the DEIM points are LAPACK's partial-pivoting row pivots."""
+    import scipy.linalg as sla
+    V = np.random.default_rng(seed).standard_normal((40, 12))
+    P, _, _ = sla.lu(V)
+    perm = np.argmax(P, axis=0)          # (P^T V)[i] = V[perm[i]]
+    assert lowrank.deim_indices(V) == list(perm[:12])
+    # the points interpolate: the DEIM projector reproduces every column of V
+    idx = lowrank.deim_indices(V)
+    proj = V @ np.linalg.solve(V[idx], V[idx])
+    assert np.abs(proj - V).max() < 1e-12
+    # early stop after the first 5 points
+    assert lowrank.deim_indices(V, stop=lambda ix: len(ix) >= 5) == list(perm[:5])
+
+
+def test_deim_sampling_converges_to_full_rank():
+    """DEIM sampling (Remark in Sec. 3.2) reaches the full-rank fixed point within the
+    inner thresholds, samples each class at most once per outer iteration, and takes a
+    different sample sequence from the greedy random subsampling."""
+    prob = problem(nx=8, ny=8, nt=8, nz=4)
+    fr = si.fr_si_dsa(prob, 1e-10)
+    kw = dict(p=2, q=4, eps_res=1e-10, eps_diff=1e-10, eps_svd=1e-11)
+    de = lowrank.lr_si_dsa(prob, 1e-10, rand=random_stream(4), sampling="deim", **kw)
+    gr = lowrank.lr_si_dsa(prob, 1e-10, rand=random_stream(4), **kw)
+    assert de["converged"] and de["iters"] == fr["iters"]
+    assert np.abs(de["phi"] - fr["phi"]).max() < 1e-8 * np.abs(fr["phi"]).max()
+    for outer in de["logs"]:
+        seq = [c for e in outer for c in e["samples"]]
+        assert len(seq) == len(set(seq))
+    assert [e["samples"] for e in de["logs"][0]] != [e["samples"] for e in gr["logs"][0]]
