@@ -198,6 +198,7 @@ class LowRankSI:
         self.basis_update = basis_update
         assert sampling in ("greedy", "deim"), sampling
         self.sampling, self.eps_svd = sampling, eps_svd
+        self.extra = None   # [N_Omega][ndof] angular source added to eq. (SI) (time steps)
 
     # ---------------- Alg. 2 (MGS2-A) ----------------
     def mgs2a_append(self, psi):
@@ -325,6 +326,8 @@ class LowRankSI:
         A += ox * (self.Dxm if ox >= 0 else self.Dxp)
         A += oy * (self.Dym if oy >= 0 else self.Dyp)
         b = self.b_src.copy()
+        if self.extra is not None:
+            b += self.X.T @ self.extra[j]
         if ox > 0: b += ox * self.b_side[0]
         elif ox < 0: b += -ox * self.b_side[1]
         if oy > 0: b += oy * self.b_side[2]
@@ -342,6 +345,8 @@ class LowRankSI:
         v = self.X @ c
         Dv = ox * ((o["Dxm"] if ox >= 0 else o["Dxp"]) @ v) + oy * ((o["Dym"] if oy >= 0 else o["Dyp"]) @ v)
         res = self.src + self.prob.g_bc(j) - Dv - o["Sig_t"] @ v
+        if self.extra is not None:
+            res = res + self.extra[j]
         return float(np.linalg.norm(res))
 
     def class_coefficients(self):
@@ -402,8 +407,14 @@ class LowRankSI:
         while True:
             k += 1
             # 1. sweeps of the sampled angles, eq. (sampled-sweep)
-            psi, _ = sweep.sweep(prob.mesh, prob.dirs, self.reps[samples], prob.sigma_t, src,
-                                 prob.bnd, want_psi=True, nthreads=self.nthreads)
+            if self.extra is None:
+                psi, _ = sweep.sweep(prob.mesh, prob.dirs, self.reps[samples], prob.sigma_t, src,
+                                     prob.bnd, want_psi=True, nthreads=self.nthreads)
+            else:   # the angular source differs per class: one sweep each
+                psi = np.concatenate([
+                    sweep.sweep(prob.mesh, prob.dirs, self.reps[[c]], prob.sigma_t,
+                                src + self.extra[self.reps[c]], prob.bnd, want_psi=True,
+                                nthreads=self.nthreads)[0] for c in samples])
             self.n_swept += len(samples)
             # 2. basis update: MGS2-A (Alg. 2), one snapshot after the other, or a variant
             # of Sec. 4.2;  3. bordering with the appended columns (MGS2-A), or the
@@ -486,14 +497,18 @@ def operators(prob):
 
 def lr_si_dsa(prob, eps_si, p, q, eps_res, eps_diff, eps_svd, rand, eps_mgs=1e-10, m_max=4,
               max_outer=100, phi0=None, use_dsa=True, replay=None, tol_break=1e-12,
-              nthreads=0, keep_factors=True, basis_update="mgs2a", sampling="greedy"):
-    """Alg. 1.  `rand` is the uint64 stream; `replay` optionally forces samples per outer."""
+              nthreads=0, keep_factors=True, basis_update="mgs2a", sampling="greedy",
+              extra=None):
+    """Alg. 1.  `rand` is the uint64 stream; `replay` optionally forces samples per outer;
+    `extra` [N_Omega][ndof] is an angular source added to the right-hand side of every
+    ordinate's transport equation (the psi^m / dt of a backward Euler step)."""
     ops = operators(prob)
     stream = RandomStream(rand)
     phi_prev = np.zeros(prob.mesh.ndof) if phi0 is None else np.asarray(phi0, dtype=np.float64).copy()
     hist, logs, ranks, sampled, phis = [], [], [], [], []
     lr = LowRankSI(prob, ops, p, q, eps_res, eps_diff, eps_mgs, m_max, tol_break, nthreads,
                    basis_update, sampling, eps_svd)
+    lr.extra = None if extra is None else np.asarray(extra, dtype=np.float64)
     mgs_fail = breakdowns = full_qrs = 0
     out = None
     phi_star = phi_prev
