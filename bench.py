@@ -251,6 +251,42 @@ def lowrank_run(R, W, torch):
                                     "dsa": lr["ms_dsa"]}}), flush=True)
 
 
+def timestep_run(R, W, torch, steps=3, dt=0.01):
+    """Backward Euler time marching (Sec. 3.7) on the 256 x 256 checkerboard, CL(32,16):
+    `steps` steps of size dt from psi = 0 with the box source on, full rank and low rank
+    (p = 4, q = 32), each step's SI-DSA to 1e-6.  One JSON line per method with the time
+    per step, outer iterations, ranks and the final flux difference between the two."""
+    wl = W.checkerboard()
+    prob = make_problem(R, wl)
+    kw = dict(eps_si=wl["eps_si"], max_outer=wl["max_outer"], eps_dsa=1e-12)
+    lr_kw = dict(p=wl["p"], q=wl["q"], eps_res=wl["eps_res"], eps_diff=wl["eps_diff"],
+                 eps_svd=wl["eps_svd"], eps_mgs=wl["eps_mgs"], m_max=wl["m_max"],
+                 trunc_every_outer=False)
+    phis = {}
+    for method in ("full_rank", "low_rank"):
+        prev, times, iters, ranks = None, [], [], []
+        for m in range(steps):
+            if method == "full_rank":
+                out = R.backward_euler_step(prob, dt, prev, full_rank=1, **kw)
+            else:
+                out = R.backward_euler_step(prob, dt, prev, full_rank=0,
+                                            rand=W.random_stream(wl["seed"] + m), **kw, **lr_kw)
+            prev = (out["X"], out["S"], out["V"])
+            times.append(out["ms_total"] / 1e3)
+            iters.append(out["iters"])
+            ranks.append(out["rank"])
+        phis[method] = out["phi"]
+        line = {"workload": "backward Euler, checkerboard 256x256, CL(32,16), dt = %g, %d steps "
+                            "from psi = 0" % (dt, steps),
+                "method": method, "step_time_s": times, "outer_iters": iters, "rank": ranks,
+                "dtype": "f64", "data": "synthetic"}
+        if method == "low_rank":
+            d = (phis["low_rank"] - phis["full_rank"]).cpu().numpy()
+            line["phi_lr_minus_fr_rel_l2"] = float(np.linalg.norm(d) /
+                                                   np.linalg.norm(phis["full_rank"].cpu().numpy()))
+        print(json.dumps(line), flush=True)
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -367,7 +403,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--only", choices=["step", "sweep", "sweep_large", "paper", "ablation",
-                                       "tomography", "lowrank", "copy"],
+                                       "tomography", "lowrank", "timestep", "copy"],
                     default="step",
                     help="step: the headline line (default); "
                          "sweep: only the psi-writing full-angle sweep of the headline medium; "
@@ -377,6 +413,7 @@ def main():
                          "tomography: loss and sigma gradient of the 16-source detector misfit "
                          "at 256x256 with a central-difference check; "
                          "lowrank: one FP64 low-rank solve of the 256x256 checkerboard (profiling); "
+                         "timestep: backward Euler steps (Sec. 3.7), full and low rank, 256x256; "
                          "copy: a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lr", action="store_true",
@@ -420,6 +457,9 @@ def main():
         return
     if args.only == "lowrank":
         lowrank_run(R, W, torch)
+        return
+    if args.only == "timestep":
+        timestep_run(R, W, torch)
         return
 
     wl = W.multiscale()

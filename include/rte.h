@@ -226,6 +226,38 @@ rte_status rte_lowrank_si_dsa_solve(const rte_problem* prob, const rte_solve_par
                                     void* stream);
 
 /*
+ * One backward Euler step of size dt of the time-dependent equation with unit speed,
+ *   d psi/dt + Omega . grad psi + sigma_t psi = sigma_s phi + Q
+ * (the implicit time marching outlined in Sec. 3.7): the steady problem with
+ * sigma_t + 1/dt per cell and the angular source psi_j^m / dt (the mass matrix of the
+ * orthonormal DG basis is the identity), solved by the full-rank SI-DSA (params->full_rank
+ * = 1) or the low-rank SI-DSA of Sec. 3 (0), with the DSA on the step's cross sections.
+ * FP64 only (params->prec = RTE_FP64), forward only; the other settings as for
+ * rte_lowrank_si_dsa_solve.
+ *   dt             > 0, finite.
+ *   r_prev, X_prev, S_prev, V_prev
+ *                  psi^m = X_prev diag(S_prev) V_prev^T, DEV X_prev [r_prev][ny*nx*4]
+ *                  (column i contiguous), S_prev [r_prev], V_prev [r_prev][n_dirs] (the
+ *                  layout of the X, S, V this call returns, so that steps chain);
+ *                  r_prev = 0: psi^m = 0 (the pointers are not read).  V_prev must be
+ *                  equal on ordinates of equal (Omega_x, Omega_y) (as every V returned
+ *                  here is), else RTE_EINVAL.
+ *   phi0           DEV initial scalar flux of the SI, or NULL (zero).
+ *   phi_out        DEV [ny][nx][4] phi^{m+1}.
+ *   X, S, V        DEV psi^{m+1} in the same factor form (required; X must not overlap
+ *                  X_prev): low rank, the truncated factors of the last outer iteration
+ *                  (res->rank columns); full rank, the psi of the last SI sweep per class
+ *                  of equal (Omega_x, Omega_y) as K columns of X with S = 1 and V the class
+ *                  indicator (res->rank = K; needs max_rank = 0 or >= K).
+ * Returns RTE_OK, RTE_ENOCONV (outputs hold the last iterate), or an error.
+ */
+rte_status rte_backward_euler_step(const rte_problem* prob, const rte_solve_params* params,
+                                   double dt, int32_t r_prev, const double* X_prev,
+                                   const double* S_prev, const double* V_prev, const double* phi0,
+                                   double* phi_out, double* X, double* S, double* V,
+                                   rte_solve_result* res, void* stream);
+
+/*
  * Exit partial currents of a converged scalar flux: regenerates psi_j by one sweep
  * of Sigma_s phi + G (+ inflow) and returns, for every boundary face e,
  *     J_e = sum_j w_j (Omega_j . n_e)^+ |e|^{-1} int_e psi_j ds.

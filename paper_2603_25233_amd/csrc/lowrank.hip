@@ -32,6 +32,7 @@
 #include <cstring>
 #include <memory>
 #include <numeric>
+#include <type_traits>
 
 #include "lowrank.h"
 
@@ -758,12 +759,13 @@ __global__ __launch_bounds__(256) void residual_kernel(
     int nx, int ny, double ihx, double ihy, const double* __restrict__ sig,
     const double* __restrict__ src, const double* __restrict__ E, long nd,
     const T* __restrict__ V, int nm, const int* __restrict__ cls,
-    const ClassDev* __restrict__ cd, double* __restrict__ part) {
+    const ClassDev* __restrict__ cd, const double* __restrict__ ex, double* __restrict__ part) {
   __shared__ double red[8];
   const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const int m = blockIdx.y;
   const ClassDev k = cd[cls[m]];
   const T* u = V + (long)m * nd;
+  const double* exm = ex ? ex + (long)m * nd : nullptr;  // angular source of the candidate
   double s2 = 0.0;
   if (c < (long)nx * ny) {
     const int a = (int)(c % nx), b = (int)(c / nx);
@@ -773,8 +775,9 @@ __global__ __launch_bounds__(256) void residual_kernel(
     const double* gx = E + (long)(1 + (k.sx > 0 ? 0 : 1)) * nd + 4 * c;
     const double* gy = E + (long)(1 + (k.sy > 0 ? 2 : 3)) * nd + 4 * c;
     for (int q = 0; q < 4; ++q) {
-      const double rr = src[4 * c + q] + k.ax * gx[q] + k.ay * gy[q] - k.ax * dx.v[q] -
-                        k.ay * dy.v[q] - sig[c] * x.v[q];
+      double rr = src[4 * c + q] + k.ax * gx[q] + k.ay * gy[q] - k.ax * dx.v[q] -
+                  k.ay * dy.v[q] - sig[c] * x.v[q];
+      if (exm) rr += exm[4 * c + q];
       s2 += rr * rr;
     }
   }
@@ -956,8 +959,9 @@ __global__ __launch_bounds__(kLuThreads, 2) void lu_border_kernel(
 __global__ __launch_bounds__(kLuThreads) void lu_corner_kernel(
     int r0, int pn, int rcap, const int* __restrict__ cls, const ClassDev* __restrict__ cd,
     const double* __restrict__ Tm, const double* __restrict__ Dx, const double* __restrict__ Dy,
-    const double* __restrict__ bsrc, const double* __restrict__ bside, double* __restrict__ Lt_all,
-    double* __restrict__ U_all, double* __restrict__ y_all) {
+    const double* __restrict__ bsrc, const double* __restrict__ bside,
+    const double* __restrict__ btime, double* __restrict__ Lt_all, double* __restrict__ U_all,
+    double* __restrict__ y_all) {
   __shared__ double S[kMaxP][kMaxP], yn[kMaxP];
   const int cl = cls[blockIdx.x];
   const ClassDev k = cd[cl];
@@ -975,7 +979,11 @@ __global__ __launch_bounds__(kLuThreads) void lu_corner_kernel(
       s += Lt[(size_t)i * rcap + r0 + m] * (isy ? y[i] : U[(size_t)i * rcap + r0 + mm]);
     s = wave_sum(s);
     if (lane == 0) {
-      if (isy) yn[m] = bvec(bsrc, bside, rcap, k, r0 + m) - s;
+      if (isy) {
+        double b = bvec(bsrc, bside, rcap, k, r0 + m);
+        if (btime) b += btime[(size_t)rcap * cl + r0 + m];
+        yn[m] = b - s;
+      }
       else S[m][mm] = amat(Tm, Dx, Dy, rcap, k, r0 + m, r0 + mm) - s;
     }
   }
@@ -1103,6 +1111,29 @@ __global__ void diff2_kernel(const double* __restrict__ a, const double* __restr
     for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += red[k];
     part[blockIdx.x] = t;
   }
+}
+
+// ------------------------------------------------------------------ backward Euler source
+// Rows r0 .. r0 + pn - 1 of the projected angular source of every class:
+// btime[k][r0 + l] = sum_i (Xp_i^T x_{r0+l}) ct[k][i], with xtp[i pn + l] = Xp_i^T x_{r0+l}.
+__global__ void time_rows_kernel(int K, int rp, int pn, int r0, int rcap,
+                                 const double* __restrict__ xtp, const double* __restrict__ ct,
+                                 double* __restrict__ btime) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= K * pn) return;
+  const int k = t / pn, l = t % pn;
+  double s = 0.0;
+  for (int i = 0; i < rp; ++i) s += xtp[(size_t)i * pn + l] * ct[(size_t)k * rp + i];
+  btime[(size_t)k * rcap + r0 + l] = s;
+}
+
+// Ctm[i][m] = ct[cls[m]][i]: the source coefficients of nm candidate classes
+__global__ void gather_ct_kernel(const double* __restrict__ ct, int rp, const int* __restrict__ cls,
+                                 int nm, double* __restrict__ Ctm) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rp * nm) return;
+  const int i = t / nm, m = t % nm;
+  Ctm[t] = ct[(size_t)cls[m] * rp + i];
 }
 
 // ------------------------------------------------------------------ one-sided Jacobi SVD
@@ -1386,6 +1417,9 @@ struct LowRank {
   rte_solve_result* res;
   double ms_sweep = 0.0, ms_lr = 0.0;
   hipEvent_t e0, e1;
+  // backward Euler step: the angular source psi^m / dt (FP64 only) and its projections
+  const TimeSrc* ts = nullptr;
+  DevBuf<double> tsrc, btime, tex, tctm, txp;
 
   bool sweep_pending = false;
   // waits for the stream; adds the time of a sweep enqueued since the last wait
@@ -1458,7 +1492,8 @@ struct LowRank {
     phi_old.alloc(nd);
     // projection partials: one row per wavefront (at least 128 rows each), rcap kMaxP dot
     // products and 2 kMaxP norms per row
-    part.alloc((size_t)((nd + 127) / 128 + kPjWaves) * ((size_t)rcap * kMaxP + 2 * kMaxP));
+    const int rdot_cap = std::max(rcap, ts ? ts->rp : 0);  // widest projection basis
+    part.alloc((size_t)((nd + 127) / 128 + kPjWaves) * ((size_t)rdot_cap * kMaxP + 2 * kMaxP));
     cb.alloc((size_t)rcap * kMaxP);
     mstat.alloc(4 * kMaxP);
     psi_save.alloc((size_t)p * nd);
@@ -1474,8 +1509,17 @@ struct LowRank {
     bsrc.alloc(rcap); bside.alloc((size_t)4 * rcap);
     Lt.alloc((size_t)K * rcap * rcap); U.alloc((size_t)K * rcap * rcap);
     yv.alloc((size_t)K * rcap); Cg.alloc((size_t)K * rcap); Rst.alloc((size_t)K * rcap);
-    d_dirs.alloc(kMaxP);
-    RTE_CHECK_HIP(hipHostMalloc((void**)&h_dirs, kMaxP * sizeof(SweepDir), hipHostMallocDefault));
+    // a p-class plan, or (backward Euler) p one-class plans of up to two entries each
+    d_dirs.alloc(2 * kMaxP);
+    RTE_CHECK_HIP(hipHostMalloc((void**)&h_dirs, 2 * kMaxP * sizeof(SweepDir), hipHostMallocDefault));
+    if (ts && ts->rp > 0) {
+      RTE_REQUIRE((std::is_same<T, double>::value), "the backward Euler step is FP64 only");
+      tsrc.alloc(nd);
+      btime.alloc((size_t)K * rcap);
+      tex.alloc((size_t)kCandChunk * nd);
+      tctm.alloc((size_t)ts->rp * kCandChunk);
+      txp.alloc((size_t)ts->rp * kMaxP + 2 * kMaxP);
+    }
     for (int i = 0; i < 3; ++i)
       RTE_CHECK_HIP(hipHostMalloc((void**)&h_list[i], (size_t)K * sizeof(int), hipHostMallocDefault));
     RTE_CHECK_HIP(hipHostMalloc((void**)&h_flags, (size_t)K * sizeof(int), hipHostMallocDefault));
@@ -1513,6 +1557,10 @@ struct LowRank {
 
   // ------------------------------------------------------------ sweeps
   void sweep_classes(const std::vector<int>& cl) {
+    if (ts && ts->rp > 0) {
+      sweep_classes_time(cl);
+      return;
+    }
     RTE_CHECK_HIP(hipEventRecord(e0, st));
     std::vector<SweepDir> dirs;
     for (size_t i = 0; i < cl.size(); ++i) {
@@ -1535,6 +1583,37 @@ struct LowRank {
                           nullptr, swork.get(), st);
     RTE_CHECK_HIP(hipEventRecord(e1, st));
     sweep_pending = true;  // timed at the next synchronisation (see sync)
+    swept += (int)cl.size();
+    swept_total += (int)cl.size();
+  }
+
+  // Backward Euler: the classes differ in their angular source, so each is swept alone
+  // with src + psi^m_c / dt.
+  void sweep_classes_time(const std::vector<int>& cl) {
+    RTE_CHECK_HIP(hipEventRecord(e0, st));
+    size_t off = 0;
+    for (size_t i = 0; i < cl.size(); ++i) {
+      const ClassDev& k = cd[cl[i]];
+      SweepDir d;
+      d.a = k.ax / g.hx;
+      d.b = k.ay / g.hy;
+      d.w = 0.0;
+      d.sx = k.sx;
+      d.sy = k.sy;
+      d.slot = (int)i;
+      d.pad = 0;
+      SweepPlan pl = make_sweep_plan(g, {d}, false, true, sizeof(double));
+      RTE_REQUIRE(off + pl.groups.size() <= 2 * (size_t)kMaxP, "internal: sweep staging too small");
+      std::memcpy(h_dirs + off, pl.groups.data(), pl.groups.size() * sizeof(SweepDir));
+      RTE_CHECK_HIP(hipMemcpyAsync(d_dirs.get() + off, h_dirs + off, pl.groups.size() * sizeof(SweepDir),
+                                   hipMemcpyHostToDevice, st));
+      time_class_source(*ts, cl[i], nd, src.get(), tsrc.get(), st);
+      sweep_enqueue<double>(g, pl, d_dirs.get() + off, prob->sigma_t, tsrc.get(), prob->bc, psi.get(),
+                            nullptr, swork.get(), st);
+      off += pl.groups.size();
+    }
+    RTE_CHECK_HIP(hipEventRecord(e1, st));
+    sweep_pending = true;
     swept += (int)cl.size();
     swept_total += (int)cl.size();
   }
@@ -1864,6 +1943,16 @@ struct LowRank {
                        rcap, tsd2.get(), ext, Tm.get(), Dx.get(), Dy.get(), bsrc.get(),
                        bside.get());
     RTE_CHECK_HIP(hipGetLastError());
+    if constexpr (std::is_same<T, double>::value) {
+      if (ts && ts->rp > 0) {
+        // X_new^T psi^m_k / dt = (Xp^T X_new)^T ct[k]: the new rows of every class's
+        // right-hand side
+        bproj(const_cast<double*>(P), pn, nullptr, 0, nullptr, ts->Xp, ts->rp, txp.get(), nullptr);
+        hipLaunchKernelGGL(time_rows_kernel, dim3((K * pn + 127) / 128), dim3(128), 0, st, K, ts->rp,
+                           pn, r0, rcap, txp.get(), ts->ct, btime.get());
+        RTE_CHECK_HIP(hipGetLastError());
+      }
+    }
   }
 
   // Class lists: 0 for the bordered factorisations, 1 for the candidates, 2 for the
@@ -1887,7 +1976,7 @@ struct LowRank {
                          U.get());
     hipLaunchKernelGGL(lu_corner_kernel, dim3((unsigned)classes.size()), dim3(kLuThreads), 0, st,
                        r0, pn, rcap, dl, d_cd.get(), Tm.get(), Dx.get(), Dy.get(), bsrc.get(),
-                       bside.get(), Lt.get(), U.get(), yv.get());
+                       bside.get(), btime.get(), Lt.get(), U.get(), yv.get());
     RTE_CHECK_HIP(hipGetLastError());
   }
 
@@ -1931,9 +2020,19 @@ struct LowRank {
     } else {
       RTE_CHECK_HIP(hipMemsetAsync(V.get(), 0, (size_t)nm * nd * sizeof(T), st));
     }
+    double* exv = nullptr;  // backward Euler: psi^m / dt of each candidate
+    if constexpr (std::is_same<T, double>::value) {
+      if (ts && ts->rp > 0) {
+        hipLaunchKernelGGL(gather_ct_kernel, dim3((ts->rp * nm + 255) / 256), dim3(256), 0, st, ts->ct,
+                           ts->rp, dl, nm, tctm.get());
+        hipLaunchKernelGGL((xc_kernel<double, double, 32>), dim3((nd + 255) / 256), dim3(256), 0, st,
+                           ts->Xp, ts->rp, nd, tctm.get(), nm, nm, tex.get());
+        exv = tex.get();
+      }
+    }
     hipLaunchKernelGGL((residual_kernel<T>), dim3(rblk, nm), dim3(256), 0, st, g.nx, g.ny,
                        1.0 / g.hx, 1.0 / g.hy, prob->sigma_t, src.get(), E.get(), nd, V.get(), nm,
-                       dl, d_cd.get(), rpart.get());
+                       dl, d_cd.get(), exv, rpart.get());
     reduce_cols(rpart.get(), rblk, nm, nm, rsums.get(), nullptr, st);
     RTE_CHECK_HIP(hipGetLastError());
     RTE_CHECK_HIP(hipMemcpyAsync(out, rsums.get(), nm * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -2228,13 +2327,15 @@ struct LowRank {
 template <typename T>
 static rte_status run_lowrank(const rte_problem* prob, const rte_solve_params* prm,
                               const double* phi0, double* phi_out, double* Xo, double* So,
-                              double* Vo, rte_solve_result* res, hipStream_t st) {
+                              double* Vo, rte_solve_result* res, hipStream_t st,
+                              const TimeSrc* ts) {
   const auto t_start = std::chrono::steady_clock::now();
   LowRank<T> lr;
   lr.prob = prob;
   lr.prm = prm;
   lr.st = st;
   lr.res = res;
+  lr.ts = ts;
   lr.setup();
   const long nd = lr.nd;
   const Geom& g = lr.g;
@@ -2308,9 +2409,10 @@ static rte_status run_lowrank(const rte_problem* prob, const rte_solve_params* p
 
 rte_status lowrank_solve(const rte_problem* prob, const rte_solve_params* prm, const double* phi0,
                          double* phi_out, double* X, double* S, double* V, rte_solve_result* res,
-                         hipStream_t st) {
-  if (prm->prec == RTE_FP64) return run_lowrank<double>(prob, prm, phi0, phi_out, X, S, V, res, st);
-  return run_lowrank<float>(prob, prm, phi0, phi_out, X, S, V, res, st);
+                         hipStream_t st, const TimeSrc* ts) {
+  if (prm->prec == RTE_FP64) return run_lowrank<double>(prob, prm, phi0, phi_out, X, S, V, res, st, ts);
+  RTE_REQUIRE(!ts || ts->rp == 0, "the backward Euler step is FP64 only");
+  return run_lowrank<float>(prob, prm, phi0, phi_out, X, S, V, res, st, ts);
 }
 
 }  // namespace rte

@@ -146,7 +146,7 @@ std::vector<SweepDir> all_dirs(const rte_problem* p, const Geom& g, bool adjoint
 // carrying the class's summed weight (added in ordinate order).  In X-Y geometry the
 // sweep of an ordinate depends on Omega only through (Omega_x, Omega_y), so the Omega_z
 // twins of a class have identical psi and sum_j w_j psi_j is unchanged.
-static std::vector<SweepDir> fold_classes(const rte_problem* p, std::vector<SweepDir> v) {
+std::vector<SweepDir> fold_classes(const rte_problem* p, std::vector<SweepDir> v) {
   std::vector<SweepDir> out;
   std::vector<int> rep;  // ordinate index of each class's first member
   for (int j = 0; j < p->n_dirs; ++j) {
@@ -169,6 +169,10 @@ static std::vector<SweepDir> fold_classes(const rte_problem* p, std::vector<Swee
     }
   }
   return out;
+}
+
+std::vector<SweepDir> class_dirs(const rte_problem* p, const Geom& g) {
+  return fold_classes(p, all_dirs(p, g, false));
 }
 
 // Full-rank SI-DSA in precision T (sweeps and the swept scalar flux in T).
@@ -396,6 +400,10 @@ static void validate_params(const rte_problem* prob, const rte_solve_params* p) 
     RTE_REQUIRE(p->max_rank >= 0, "max_rank must be >= 0");
   }
   (void)prob;
+}
+
+void validate_solve_params(const rte_problem* prob, const rte_solve_params* p) {
+  validate_params(prob, p);
 }
 
 }  // namespace rte

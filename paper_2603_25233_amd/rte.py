@@ -90,6 +90,9 @@ SIGNATURES = {
     "rte_sweep_plan_destroy": ([_P], ctypes.c_int),
     "rte_last_error": ([], ctypes.c_char_p),
     "rte_abi_version": ([], ctypes.c_int32),
+    "rte_backward_euler_step": ([ctypes.POINTER(Problem_), ctypes.POINTER(Params_), ctypes.c_double,
+                                 ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P,
+                                 ctypes.POINTER(Result_), _P], ctypes.c_int),
 }
 
 _lib = None
@@ -290,69 +293,112 @@ def default_params(**kw):
     return d
 
 
+class _Call:
+    """Host-side settings and report buffers of one solver call (argument marshalling)."""
+
+    def __init__(self, prob, rand, replay, checkpoints, log_cap, kw):
+        o = self.o = default_params(**kw)
+        self.rand_arr = None if rand is None else np.ascontiguousarray(rand, dtype=np.uint64)
+        self.rep_arr = None
+        if replay is not None:
+            # per outer iteration, a list of groups (angle class ids per inner iteration)
+            flat = []
+            for outer in replay:
+                for group in outer:
+                    flat.append(len(group)); flat.extend(int(x) for x in group)
+                flat.append(0)
+            self.rep_arr = np.ascontiguousarray(flat, dtype=np.int32)
+        mo = self.max_outer = int(o["max_outer"])
+        self.ck = (torch.zeros((mo, prob.ny, prob.nx, 4), dtype=torch.float64, device=prob.device)
+                   if checkpoints else None)
+        ra, rp = self.rand_arr, self.rep_arr
+        self.prm = Params_(int(o["full_rank"]), int(o["adjoint"]), int(o["use_dsa"]), int(o["p"]),
+                           int(o["q"]), int(o["m_max"]), mo, int(o["max_rank"]),
+                           o["eps_si"], o["eps_res"], o["eps_diff"], o["eps_svd"], o["eps_mgs"],
+                           o["eps_dsa"], RTE_MIXED if o["mixed"] else RTE_FP64,
+                           None if ra is None else ra.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                           0 if ra is None else ra.size,
+                           None if rp is None else rp.ctypes.data_as(_I),
+                           0 if rp is None else rp.size, _dptr(self.ck),
+                           int(o["fold_classes"]), BASIS_UPDATES[o["basis_update"]],
+                           SAMPLINGS[o["sampling"]])
+        self.hist = np.zeros(mo); self.ranks = np.zeros(mo, np.int32)
+        self.swept = np.zeros(mo, np.int32); self.tranks = np.zeros(mo, np.int32)
+        self.slog = np.zeros(log_cap, np.int32); self.rlog = np.zeros(log_cap)
+        res = self.res = Result_()
+        res.history = self.hist.ctypes.data_as(_D); res.ranks = self.ranks.ctypes.data_as(_I)
+        res.swept = self.swept.ctypes.data_as(_I); res.sample_log = self.slog.ctypes.data_as(_I)
+        if o["trunc_every_outer"]:
+            res.trunc_ranks = self.tranks.ctypes.data_as(_I)
+        res.sample_log_cap = log_cap; res.resid_log = self.rlog.ctypes.data_as(_D)
+        res.resid_log_cap = log_cap
+
+    def report(self, code, phi):
+        res, n = self.res, self.res.outer_iters
+        out = dict(phi=phi, iters=n, converged=bool(res.converged), rank=res.rank,
+                   n_swept=res.n_swept, mgs_failures=res.mgs_failures, breakdowns=res.breakdowns,
+                   dsa_iters=res.dsa_iters, full_qrs=res.full_qrs, fp64_sweeps=res.fp64_sweeps,
+                   history=self.hist[:n].copy(), ranks=self.ranks[:n].copy(),
+                   swept=self.swept[:n].copy(), sample_log=self.slog[:res.sample_log_len].copy(),
+                   trunc_ranks=self.tranks[:n].copy() if self.o["trunc_every_outer"] else None,
+                   resid_log=self.rlog[:res.resid_log_len].copy(), ms_sweep=res.ms_sweep,
+                   ms_lowrank=res.ms_lowrank, ms_dsa=res.ms_dsa, ms_total=res.ms_total, status=code)
+        if self.ck is not None:
+            out["checkpoints"] = self.ck[:n]
+        return out
+
+
+def _factor_buffers(prob, mr):
+    X = torch.zeros((mr, prob.ndof), dtype=torch.float64, device=prob.device)
+    S = torch.zeros(mr, dtype=torch.float64, device=prob.device)
+    V = torch.zeros((mr, prob.n_dirs), dtype=torch.float64, device=prob.device)
+    return X, S, V
+
+
 def solve(prob, rand=None, replay=None, phi0=None, want_factors=False, checkpoints=False,
           log_cap=1 << 16, **kw):
     """SI-DSA (rte_lowrank_si_dsa_solve).  Returns a dict with phi and the report."""
-    o = default_params(**kw)
-    rand_arr = None if rand is None else np.ascontiguousarray(rand, dtype=np.uint64)
-    rep_arr = None
-    if replay is not None:
-        # replay: per outer iteration, a list of groups (angle class ids per inner iteration)
-        flat = []
-        for outer in replay:
-            for group in outer:
-                flat.append(len(group)); flat.extend(int(x) for x in group)
-            flat.append(0)
-        rep_arr = np.ascontiguousarray(flat, dtype=np.int32)
-    max_outer = int(o["max_outer"])
-    ck = torch.zeros((max_outer, prob.ny, prob.nx, 4), dtype=torch.float64, device=prob.device) if checkpoints else None
-    prm = Params_(int(o["full_rank"]), int(o["adjoint"]), int(o["use_dsa"]), int(o["p"]),
-                  int(o["q"]), int(o["m_max"]), max_outer, int(o["max_rank"]),
-                  o["eps_si"], o["eps_res"], o["eps_diff"], o["eps_svd"], o["eps_mgs"],
-                  o["eps_dsa"], RTE_MIXED if o["mixed"] else RTE_FP64,
-                  None if rand_arr is None else rand_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
-                  0 if rand_arr is None else rand_arr.size,
-                  None if rep_arr is None else rep_arr.ctypes.data_as(_I),
-                  0 if rep_arr is None else rep_arr.size, _dptr(ck),
-                  int(o["fold_classes"]), BASIS_UPDATES[o["basis_update"]],
-                  SAMPLINGS[o["sampling"]])
-    hist = np.zeros(max_outer); ranks = np.zeros(max_outer, np.int32); swept = np.zeros(max_outer, np.int32)
-    tranks = np.zeros(max_outer, np.int32)
-    slog = np.zeros(log_cap, np.int32); rlog = np.zeros(log_cap)
-    res = Result_()
-    res.history = hist.ctypes.data_as(_D); res.ranks = ranks.ctypes.data_as(_I)
-    res.swept = swept.ctypes.data_as(_I); res.sample_log = slog.ctypes.data_as(_I)
-    if o["trunc_every_outer"]:
-        res.trunc_ranks = tranks.ctypes.data_as(_I)
-    res.sample_log_cap = log_cap; res.resid_log = rlog.ctypes.data_as(_D); res.resid_log_cap = log_cap
+    call = _Call(prob, rand, replay, checkpoints, log_cap, kw)
     phi = torch.empty((prob.ny, prob.nx, 4), dtype=torch.float64, device=prob.device)
     X = S = V = None
     if want_factors:
-        mr = int(o["max_rank"]) or prob.n_dirs
-        X = torch.zeros((mr, prob.ndof), dtype=torch.float64, device=prob.device)
-        S = torch.zeros(mr, dtype=torch.float64, device=prob.device)
-        V = torch.zeros((mr, prob.n_dirs), dtype=torch.float64, device=prob.device)
+        X, S, V = _factor_buffers(prob, int(call.o["max_rank"]) or prob.n_dirs)
     p0 = None if phi0 is None else phi0.to(torch.float64).contiguous()
     cp = prob.c(G=kw.get("G_override", "self"), bc=kw.get("bc_override", "self"))
-    code = lib().rte_lowrank_si_dsa_solve(ctypes.byref(cp), ctypes.byref(prm), _dptr(p0),
+    code = lib().rte_lowrank_si_dsa_solve(ctypes.byref(cp), ctypes.byref(call.prm), _dptr(p0),
                                           _dptr(phi), _dptr(X), _dptr(S), _dptr(V),
-                                          ctypes.byref(res), _stream())
+                                          ctypes.byref(call.res), _stream())
     _check(code, allow_noconv=True)
-    n = res.outer_iters
-    out = dict(phi=phi, iters=n, converged=bool(res.converged), rank=res.rank,
-               n_swept=res.n_swept, mgs_failures=res.mgs_failures, breakdowns=res.breakdowns,
-               dsa_iters=res.dsa_iters, full_qrs=res.full_qrs, fp64_sweeps=res.fp64_sweeps,
-               history=hist[:n].copy(),
-               ranks=ranks[:n].copy(),
-               swept=swept[:n].copy(), sample_log=slog[:res.sample_log_len].copy(),
-               trunc_ranks=tranks[:n].copy() if o["trunc_every_outer"] else None,
-               resid_log=rlog[:res.resid_log_len].copy(), ms_sweep=res.ms_sweep,
-               ms_lowrank=res.ms_lowrank, ms_dsa=res.ms_dsa, ms_total=res.ms_total, status=code)
+    out = call.report(code, phi)
     if want_factors:
-        r = res.rank
+        r = call.res.rank
         out.update(X=X[:r], S=S[:r], V=V[:r])
-    if checkpoints:
-        out["checkpoints"] = ck[:n]
+    return out
+
+
+def backward_euler_step(prob, dt, prev=None, rand=None, replay=None, phi0=None,
+                        checkpoints=False, log_cap=1 << 16, **kw):
+    """One backward Euler step of size dt (rte_backward_euler_step): prev = (X, S, V) of
+    psi^m = X^T diag(S) V as returned by the previous step (None: psi^m = 0).  Returns
+    the solve report with phi^{m+1} and the factors X, S, V of psi^{m+1}."""
+    call = _Call(prob, rand, replay, checkpoints, log_cap, kw)
+    phi = torch.empty((prob.ny, prob.nx, 4), dtype=torch.float64, device=prob.device)
+    X, S, V = _factor_buffers(prob, int(call.o["max_rank"]) or prob.n_dirs)
+    if prev is None:
+        rp, Xp, Sp, Vp = 0, None, None, None
+    else:
+        Xp, Sp, Vp = (t.to(torch.float64).contiguous() for t in prev)
+        rp = Sp.numel()
+    p0 = None if phi0 is None else phi0.to(torch.float64).contiguous()
+    cp = prob.c()
+    code = lib().rte_backward_euler_step(ctypes.byref(cp), ctypes.byref(call.prm), float(dt), rp,
+                                         _dptr(Xp), _dptr(Sp), _dptr(Vp), _dptr(p0), _dptr(phi),
+                                         _dptr(X), _dptr(S), _dptr(V), ctypes.byref(call.res),
+                                         _stream())
+    _check(code, allow_noconv=True)
+    out = call.report(code, phi)
+    r = call.res.rank
+    out.update(X=X[:r], S=S[:r], V=V[:r])
     return out
 
 
