@@ -545,7 +545,7 @@ def main():
         fr_flops = SWEEP_FLOPS_PER_CELL_DIR * ncell * line["fr"]["class_sweeps_per_outer"]
         fr_tf = fr_flops / (fr_sweep_ms * 1e-3) / 1e12
         line["roofline"] = {"kernel": "full-rank SI sweep, phi only (source_kernel, diag_layout_kernel, "
-                                      "sweep_kernel, reduce_parts_kernel), 512 class sweeps",
+                                      "sweep_kernel, reduce_quadrants_kernel, gather_quadrants_kernel), 512 class sweeps",
                             "bound": "alu", "achieved": fr_tf, "peak": FP64_PEAK_TFLOPS,
                             "unit": "TFLOP/s", "frac": fr_tf / FP64_PEAK_TFLOPS,
                             "traffic": measured_traffic("fr_sweep_multiscale1024_pmc.md"),

@@ -338,8 +338,10 @@ typedef __attribute__((address_space(3))) void lds_void;
 //
 // Output mode OUT (compile time): bit 0 the LDS ring, bit 1 psi, bit 2 the weighted
 // partial sums of the scalar flux (psi and the partial sums together only for D = 1),
-// bit 3 direct stores in line-sized groups of a row's cells (large plans without the
-// ring; small plans store each cell, which keeps their latency-bound step short).
+// bit 3 large plans without the ring: psi leaves in line-sized groups of a row's cells,
+// partial sums without psi in the diagonal-major order of the canonical frame (one
+// contiguous run per step); small plans store each cell, which keeps their
+// latency-bound step short.
 // With the ring, step t leaves its results in LDS ring slot t mod kRingSlots
 // (per direction for psi, or the weighted sum over the group's directions for the
 // scalar flux).  A row's cells are grouped into aligned chunks of kChunkCells
@@ -707,7 +709,9 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
 #pragma unroll
             for (int m = 0; m < 4; ++m) wv[m] = D == 1 ? w0 * acc[m] : acc[m];
             const long c = (long)brow * nx + (sx > 0 ? ap : nx - 1 - ap);
-            if constexpr (GRP) put_grouped(pp, c, ap, nx, sx, wv, pgrp[k]);
+            // large plans: the partial sums in diagonal-major order, so that each step's
+            // cells leave as one contiguous run (reduce_quadrants_kernel reorders them)
+            if constexpr (GRP) store4(pp + 4 * (diag_first(t, nx, ny) + r - lo), wv);
             else store4(pp + 4 * c, wv);
           }
         }
@@ -728,6 +732,49 @@ __global__ void reduce_parts_kernel(const T* __restrict__ part, int ngroups, lon
   T s = T(0);
   for (int g = 0; g < ngroups; ++g) s += part[(long)g * ndof + i];
   phi[i] = s;
+}
+
+// Diagonal-major partial sums (large phi-only plans): the groups of quadrant q, in
+// group order, summed into the slot of its first group g0[q] (in place: each element is
+// read and written by one thread).
+template <typename T>
+__global__ void reduce_quadrants_kernel(T* __restrict__ part, int ngroups, int D,
+                                        const SweepDir* __restrict__ dirs, long ndof, int g00,
+                                        int g01, int g02, int g03) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  const int g0 = q == 0 ? g00 : q == 1 ? g01 : q == 2 ? g02 : g03;
+  if (i >= ndof || g0 < 0) return;
+  T s = T(0);
+  for (int g = g0; g < ngroups; ++g) {
+    const SweepDir d = dirs[(long)g * D];
+    if ((d.sx < 0 ? 1 : 0) + (d.sy < 0 ? 2 : 0) != q) continue;
+    s += part[(long)g * ndof + i];
+  }
+  part[(long)g0 * ndof + i] = s;
+}
+
+// phi of cell (a, b) = sum over the swept quadrants q (in order) of the quadrant sum at the
+// cell's diagonal-major position in q's canonical frame.
+template <typename T>
+__global__ void gather_quadrants_kernel(const T* __restrict__ part, long ndof, int nx, int ny,
+                                        int g00, int g01, int g02, int g03, T* __restrict__ phi) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (long)nx * ny) return;
+  const int a = (int)(c % nx), b = (int)(c / nx);
+  T s[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int g0 = q == 0 ? g00 : q == 1 ? g01 : q == 2 ? g02 : g03;
+    if (g0 < 0) continue;
+    const int ap = (q & 1) ? nx - 1 - a : a, r = (q & 2) ? ny - 1 - b : b;
+    const int t = ap + r;
+    const int lo = t >= nx ? t - nx + 1 : 0;
+    const Vec4<T> v = load4(part + (long)g0 * ndof + 4 * (diag_first(t, nx, ny) + r - lo));
+#pragma unroll
+    for (int m = 0; m < 4; ++m) s[m] += v.v[m];
+  }
+  store4(phi + 4 * c, s);
 }
 
 }  // namespace
@@ -987,8 +1034,22 @@ void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
   RTE_CHECK_HIP(hipGetLastError());
   if (phi) {
     const int tb = 256;
-    hipLaunchKernelGGL((reduce_parts_kernel<T>), dim3((g.ndof + tb - 1) / tb), dim3(tb), 0, st,
-                       part, pl.ngroups, g.ndof, phi);
+    if (mode == 12) {  // diagonal-major partial sums: per quadrant, then gathered per cell
+      int g0[4] = {-1, -1, -1, -1};
+      for (int b = 0; b < pl.ngroups; ++b) {
+        const SweepDir& d = pl.groups[(size_t)b * pl.D];
+        const int q = (d.sx < 0 ? 1 : 0) + (d.sy < 0 ? 2 : 0);
+        if (g0[q] < 0) g0[q] = b;
+      }
+      hipLaunchKernelGGL((reduce_quadrants_kernel<T>), dim3((unsigned)((g.ndof + tb - 1) / tb), 4),
+                         dim3(tb), 0, st, part, pl.ngroups, pl.D, dirs_dev, g.ndof, g0[0], g0[1],
+                         g0[2], g0[3]);
+      hipLaunchKernelGGL((gather_quadrants_kernel<T>), dim3((unsigned)((g.ncell + tb - 1) / tb)),
+                         dim3(tb), 0, st, part, g.ndof, g.nx, g.ny, g0[0], g0[1], g0[2], g0[3], phi);
+    } else {
+      hipLaunchKernelGGL((reduce_parts_kernel<T>), dim3((g.ndof + tb - 1) / tb), dim3(tb), 0, st,
+                         part, pl.ngroups, g.ndof, phi);
+    }
     RTE_CHECK_HIP(hipGetLastError());
   }
 }
