@@ -21,6 +21,13 @@
 // weighting, Galerkin coarse operators, l1-Jacobi smoothing, exact solve on the
 // coarsest grid).  The continuous coarse space carries the smooth error that block
 // Jacobi alone removes only in O(1/h) iterations.
+// Layout for the bandwidth-bound CG iteration: the blocks are Kronecker sums (an x-face
+// couples only the x-degrees, a y-face only the y-degrees, the volume term is diagonal),
+// so the matrix product reads 14 numbers per cell (the diagonal block's 4 diagonal
+// entries and its two off-diagonal couplings, a 2 x 2 x-coupling and a 2 x 2 y-coupling)
+// instead of three 4 x 4 blocks; the V-cycle reads its stencils in FP32 (the Galerkin
+// hierarchy is built in FP64 and rounded once, so the cycle stays a fixed symmetric
+// operator, as CG needs; every sum is FP64).
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -36,6 +43,7 @@ static constexpr double kCip = 8.0;
 struct MgLevel {
   int mx = 0, my = 0;
   DevBuf<double> A9;    // [node][9] stencil, entry (dj + 1) 3 + (di + 1)
+  DevBuf<float> A9c;    // the same rounded to FP32: the stencils the cycle reads
   DevBuf<double> dinv;  // l1-Jacobi: 1 / (a_ii + sum_{j != i} |a_ij|)
   DevBuf<double> x, b, t;
 };
@@ -43,7 +51,7 @@ struct MgLevel {
 // device view of a level (for the single-workgroup V-cycle of the small grids)
 struct MgDev {
   int mx, my;
-  const double* A9;
+  const float* A9;
   const double* dinv;
   double *x, *b, *t;
 };
@@ -51,6 +59,8 @@ struct MgDev {
 struct DSA {
   Geom g;
   DevBuf<double> diag, ax, ay, minv, sig_s;  // [ncell][16] blocks, [ncell]
+  DevBuf<double> cc;                           // [14][ncell] the blocks' distinct entries
+  DevBuf<double> mc;                           // [10][ncell] upper triangle of B^{-1}
   DevBuf<double> x, r, z, p0, p1, q, b;
   DevBuf<double> part1, part2;                 // per-block partial sums
   DevBuf<double> scal;                         // device scalars (see Sc below)
@@ -142,12 +152,17 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return r;
 }
 
-// p_new = z + beta p_old (on the fly for the neighbours), q = A p_new, part = p.q
+// p_new = z + beta p_old (on the fly for the neighbours), q = A p_new, part = p.q.
+// cc[k][c], k < 14 = (B_00, B_11, B_22, B_33, B_01, B_02, X_00, X_01, X_10, X_11, Y_00, Y_01,
+// Y_10, Y_11) of cell c (one array per entry, so each load is contiguous over a wavefront):
+// the diagonal block B couples k with k ^ 1 (x-degree) through B_01 and with k ^ 2
+// (y-degree) through B_02; the coupling to the right neighbour is X (x) I on the x-degree,
+// to the top neighbour Y (x) I on the y-degree (DOF k = 2 q + p); the left and bottom
+// couplings are the neighbours' X^T and Y^T.
 __global__ __launch_bounds__(256) void spmv_kernel(
-    int nx, int ny, const double* __restrict__ diag, const double* __restrict__ ax,
-    const double* __restrict__ ay, const double* __restrict__ z, const double* __restrict__ pold,
-    double* __restrict__ pnew, double* __restrict__ q, double* __restrict__ part,
-    const double* __restrict__ sc) {
+    int nx, int ny, const double* __restrict__ cc, const double* __restrict__ z,
+    const double* __restrict__ pold, double* __restrict__ pnew, double* __restrict__ q,
+    double* __restrict__ part, const double* __restrict__ sc) {
   __shared__ double red[256];
   if (sc[S_DONE] != 0.0) return;
   const double beta = sc[S_BETA];
@@ -156,17 +171,49 @@ __global__ __launch_bounds__(256) void spmv_kernel(
   double dot = 0.0;
   if (c < ncell) {
     const int a = (int)(c % nx), b = (int)(c / nx);
-    auto pv = [&](long cc, double* o) {
+    auto pv = [&](long cc2, double* o) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) o[k] = z[4 * cc + k] + beta * pold[4 * cc + k];
+      for (int k = 0; k < 4; ++k) o[k] = z[4 * cc2 + k] + beta * pold[4 * cc2 + k];
     };
-    double u[4], acc[4] = {0, 0, 0, 0}, nb[4];
+    auto m = [&](int k) { return cc[(long)k * ncell + c]; };
+    double u[4], acc[4], nb[4];
     pv(c, u);
-    mv4(diag + 16 * c, u, acc);
-    if (a + 1 < nx) { pv(c + 1, nb); mv4(ax + 16 * c, nb, acc); }
-    if (a > 0) { pv(c - 1, nb); mtv4(ax + 16 * (c - 1), nb, acc); }
-    if (b + 1 < ny) { pv(c + nx, nb); mv4(ay + 16 * c, nb, acc); }
-    if (b > 0) { pv(c - nx, nb); mtv4(ay + 16 * (c - nx), nb, acc); }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] = m(k) * u[k] + m(4) * u[k ^ 1] + m(5) * u[k ^ 2];
+    if (a + 1 < nx) {  // X (x) I: acc[2q + p] += X[p][.] nb[2q + .]
+      pv(c + 1, nb);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int p = k & 1, qb = k & 2;
+        acc[k] += m(6 + 2 * p) * nb[qb] + m(7 + 2 * p) * nb[qb + 1];
+      }
+    }
+    if (a > 0) {  // the left neighbour's X^T
+      auto ml = [&](int k) { return cc[(long)k * ncell + c - 1]; };
+      pv(c - 1, nb);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int p = k & 1, qb = k & 2;
+        acc[k] += ml(6 + p) * nb[qb] + ml(8 + p) * nb[qb + 1];
+      }
+    }
+    if (b + 1 < ny) {  // Y (x) I: acc[2q + p] += Y[q][.] nb[2 . + p]
+      pv(c + nx, nb);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int p = k & 1, qq = k >> 1;
+        acc[k] += m(10 + 2 * qq) * nb[p] + m(11 + 2 * qq) * nb[2 + p];
+      }
+    }
+    if (b > 0) {  // the bottom neighbour's Y^T
+      auto mb = [&](int k) { return cc[(long)k * ncell + c - nx]; };
+      pv(c - nx, nb);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int p = k & 1, qq = k >> 1;
+        acc[k] += mb(10 + qq) * nb[p] + mb(12 + qq) * nb[2 + p];
+      }
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       pnew[4 * c + k] = u[k];
@@ -176,6 +223,29 @@ __global__ __launch_bounds__(256) void spmv_kernel(
   }
   const double s = block_sum(dot, red);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// The 14 distinct entries of a cell's blocks (see spmv_kernel) from the full 4 x 4 blocks.
+__global__ __launch_bounds__(256) void dsa_compact_kernel(long ncell, const double* __restrict__ diag,
+                                                         const double* __restrict__ ax,
+                                                         const double* __restrict__ ay,
+                                                         const double* __restrict__ minv,
+                                                         double* __restrict__ cc,
+                                                         double* __restrict__ mc) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const double* B = diag + 16 * c;
+  const double* X = ax + 16 * c;  // X (x) I: entry (p, p') at (2q + p) 4 + 2q + p', q = 0
+  const double* Y = ay + 16 * c;  // Y (x) I: entry (q, q') at 2q 4 + 2q', p = 0
+  const double v[14] = {B[0], B[5], B[10], B[15], B[1], B[2],
+                        X[0], X[1], X[4], X[5], Y[0], Y[2], Y[8], Y[10]};
+#pragma unroll
+  for (int k = 0; k < 14; ++k) cc[(long)k * ncell + c] = v[k];
+  // the inverse diagonal block (symmetric) as its upper triangle, one array per entry
+  const double* M = minv + 16 * c;
+  const double w[10] = {M[0], M[1], M[2], M[3], M[5], M[6], M[7], M[10], M[11], M[15]};
+#pragma unroll
+  for (int k = 0; k < 10; ++k) mc[(long)k * ncell + c] = w[k];
 }
 
 // sums nblk partials in a fixed order into sc[slot]
@@ -188,21 +258,38 @@ __global__ __launch_bounds__(1024) void reduce_kernel(const double* __restrict__
   if (threadIdx.x == 0) *out = s;
 }
 
-__global__ void alpha_kernel(double* sc) {
-  if (sc[S_DONE] != 0.0) return;
-  sc[S_ALPHA] = sc[S_RHO] / sc[S_PQ];
+// reduce_kernel into sc[S_PQ], then alpha = rho / (p.q) (one launch)
+__global__ __launch_bounds__(1024) void reduce_alpha_kernel(const double* __restrict__ part, int nblk,
+                                                            double* __restrict__ sc) {
+  __shared__ double red[1024];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) v += part[i];
+  const double s = block_sum(v, red);
+  if (threadIdx.x == 0) {
+    sc[S_PQ] = s;
+    if (sc[S_DONE] == 0.0) sc[S_ALPHA] = sc[S_RHO] / s;
+  }
 }
 
-// after reductions of r.z into sc[S_PQ] (reused as scratch) and r.r into sc[S_RR]
-__global__ void beta_kernel(double* sc, double rz_new_unused) {
-  if (sc[S_DONE] != 0.0) return;
-  sc[S_ITERS] += 1.0;
-  if (sc[S_RR] <= sc[S_TOL2]) {
-    sc[S_DONE] = 1.0;
-    return;
+// reduce_kernel of r.z into sc[S_PQ], then the convergence test and beta (one launch)
+__global__ __launch_bounds__(1024) void reduce_beta_kernel(const double* __restrict__ part, int nblk,
+                                                           double* __restrict__ sc) {
+  __shared__ double red[1024];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) v += part[i];
+  const double s = block_sum(v, red);
+  if (threadIdx.x == 0) {
+    sc[S_PQ] = s;
+    if (sc[S_DONE] == 0.0) {
+      sc[S_ITERS] += 1.0;
+      if (sc[S_RR] <= sc[S_TOL2]) {
+        sc[S_DONE] = 1.0;
+      } else {
+        sc[S_BETA] = s / sc[S_RHO];
+        sc[S_RHO] = s;
+      }
+    }
   }
-  sc[S_BETA] = sc[S_PQ] / sc[S_RHO];
-  sc[S_RHO] = sc[S_PQ];
 }
 
 // rho = r.z, rr = r.r, tol2 = tol^2 * rr, beta = 0
@@ -233,10 +320,10 @@ struct Emb {
   }
 };
 
-__device__ __forceinline__ double stencil9(const double* __restrict__ A9,
+__device__ __forceinline__ double stencil9(const float* __restrict__ A9,
                                            const double* __restrict__ x, int mx, int my, int i,
                                            int j) {
-  const double* a = A9 + 9L * ((long)j * mx + i);
+  const float* a = A9 + 9L * ((long)j * mx + i);
   double s = 0.0;
 #pragma unroll
   for (int dj = -1; dj <= 1; ++dj) {
@@ -246,100 +333,119 @@ __device__ __forceinline__ double stencil9(const double* __restrict__ A9,
     for (int di = -1; di <= 1; ++di) {
       const int ii = i + di;
       if (ii < 0 || ii >= mx) continue;
-      s += a[(dj + 1) * 3 + di + 1] * x[(long)jj * mx + ii];
+      s += (double)a[(dj + 1) * 3 + di + 1] * x[(long)jj * mx + ii];
     }
   }
   return s;
 }
 
+// The stencil kernels of the cycle work on tiles of kTX x kTY nodes (one node per thread):
+// the vector the stencil multiplies is formed once per node of the tile and its ring in
+// LDS (0 outside the grid, where the stencil's entries are 0 too), so each node's nine
+// neighbours come from LDS; the sums run in the same order as stencil9's.
+constexpr int kTX = 64, kTY = 4, kTW = kTX + 2, kTH = kTY + 2;
+
+template <class F>
+__device__ __forceinline__ void fill_tile(double* t, int mx, int my, F f) {
+  const int i0 = (int)blockIdx.x * kTX - 1, j0 = (int)blockIdx.y * kTY - 1;
+  for (int e = threadIdx.x; e < kTW * kTH; e += blockDim.x) {
+    const int ii = i0 + e % kTW, jj = j0 + e / kTW;
+    t[e] = (ii >= 0 && ii < mx && jj >= 0 && jj < my) ? f(ii, jj) : 0.0;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ double tile_stencil(const float* __restrict__ a, const double* t, int lx,
+                                               int ly) {
+  double s = 0.0;
+#pragma unroll
+  for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+    for (int di = -1; di <= 1; ++di)
+      s += (double)a[(dj + 1) * 3 + di + 1] * t[(ly + 1 + dj) * kTW + lx + 1 + di];
+  return s;
+}
+
+dim3 tile_grid(int mx, int my) { return dim3((unsigned)((mx + kTX - 1) / kTX), (unsigned)((my + kTY - 1) / kTY)); }
+
 // xout = x + dinv (b - A x)   (x == nullptr: x = 0)
 __global__ __launch_bounds__(256) void mg_jacobi_kernel(int mx, int my,
-                                                       const double* __restrict__ A9,
+                                                       const float* __restrict__ A9,
                                                        const double* __restrict__ dinv,
                                                        const double* __restrict__ b,
                                                        const double* __restrict__ x,
                                                        double* __restrict__ xout,
                                                        const double* __restrict__ sc) {
+  __shared__ double t[kTW * kTH];
   if (sc[S_DONE] != 0.0) return;
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= (long)mx * my) return;
-  const int i = (int)(n % mx), j = (int)(n / mx);
-  if (x) xout[n] = x[n] + dinv[n] * (b[n] - stencil9(A9, x, mx, my, i, j));
-  else xout[n] = dinv[n] * b[n];
+  const int lx = (int)threadIdx.x % kTX, ly = (int)threadIdx.x / kTX;
+  const int i = (int)blockIdx.x * kTX + lx, j = (int)blockIdx.y * kTY + ly;
+  const bool in = i < mx && j < my;
+  const long n = (long)j * mx + i;
+  if (!x) {
+    if (in) xout[n] = dinv[n] * b[n];
+    return;
+  }
+  fill_tile(t, mx, my, [&](int ii, int jj) { return x[(long)jj * mx + ii]; });
+  if (in) xout[n] = t[(ly + 1) * kTW + lx + 1] + dinv[n] * (b[n] - tile_stencil(A9 + 9 * n, t, lx, ly));
 }
 
 // the first two sweeps from x = 0: x = y + dinv (b - A y) with y = dinv b
-__global__ __launch_bounds__(256) void mg_pre_kernel(int mx, int my, const double* __restrict__ A9,
+__global__ __launch_bounds__(256) void mg_pre_kernel(int mx, int my, const float* __restrict__ A9,
                                                     const double* __restrict__ dinv,
                                                     const double* __restrict__ b,
                                                     double* __restrict__ x,
                                                     const double* __restrict__ sc) {
+  __shared__ double t[kTW * kTH];
   if (sc[S_DONE] != 0.0) return;
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= (long)mx * my) return;
-  const int i = (int)(n % mx), j = (int)(n / mx);
-  const double* a = A9 + 9 * n;
-  double s = 0.0;
-#pragma unroll
-  for (int dj = -1; dj <= 1; ++dj) {
-    const int jj = j + dj;
-    if (jj < 0 || jj >= my) continue;
-#pragma unroll
-    for (int di = -1; di <= 1; ++di) {
-      const int ii = i + di;
-      if (ii < 0 || ii >= mx) continue;
-      const long m = (long)jj * mx + ii;
-      s += a[(dj + 1) * 3 + di + 1] * (dinv[m] * b[m]);
-    }
-  }
-  x[n] = dinv[n] * b[n] + dinv[n] * (b[n] - s);
+  const int lx = (int)threadIdx.x % kTX, ly = (int)threadIdx.x / kTX;
+  const int i = (int)blockIdx.x * kTX + lx, j = (int)blockIdx.y * kTY + ly;
+  fill_tile(t, mx, my, [&](int ii, int jj) {
+    const long m = (long)jj * mx + ii;
+    return dinv[m] * b[m];
+  });
+  if (i >= mx || j >= my) return;
+  const long n = (long)j * mx + i;
+  x[n] = t[(ly + 1) * kTW + lx + 1] + dinv[n] * (b[n] - tile_stencil(A9 + 9 * n, t, lx, ly));
 }
 
 // prolongation and the first post-smoothing sweep: t = y + dinv (b - A y), y = x + P xc
-__global__ __launch_bounds__(256) void mg_post_kernel(int mx, int my, const double* __restrict__ A9,
+__global__ __launch_bounds__(256) void mg_post_kernel(int mx, int my, const float* __restrict__ A9,
                                                      const double* __restrict__ dinv,
                                                      const double* __restrict__ b,
                                                      const double* __restrict__ x, int mxc,
                                                      const double* __restrict__ xc,
-                                                     double* __restrict__ t,
+                                                     double* __restrict__ tout,
                                                      const double* __restrict__ sc) {
+  __shared__ double t[kTW * kTH];
   if (sc[S_DONE] != 0.0) return;
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= (long)mx * my) return;
-  const int i = (int)(n % mx), j = (int)(n / mx);
-  auto y = [&](int ii, int jj) {
+  const int lx = (int)threadIdx.x % kTX, ly = (int)threadIdx.x / kTX;
+  const int i = (int)blockIdx.x * kTX + lx, j = (int)blockIdx.y * kTY + ly;
+  fill_tile(t, mx, my, [&](int ii, int jj) {
     const int i0 = ii >> 1, i1 = (ii + 1) >> 1, j0 = jj >> 1, j1 = (jj + 1) >> 1;
     return x[(long)jj * mx + ii] + 0.25 * (xc[(long)j0 * mxc + i0] + xc[(long)j0 * mxc + i1] +
                                            xc[(long)j1 * mxc + i0] + xc[(long)j1 * mxc + i1]);
-  };
-  const double* a = A9 + 9 * n;
-  double s = 0.0;
-#pragma unroll
-  for (int dj = -1; dj <= 1; ++dj) {
-    const int jj = j + dj;
-    if (jj < 0 || jj >= my) continue;
-#pragma unroll
-    for (int di = -1; di <= 1; ++di) {
-      const int ii = i + di;
-      if (ii < 0 || ii >= mx) continue;
-      s += a[(dj + 1) * 3 + di + 1] * y(ii, jj);
-    }
-  }
-  t[n] = y(i, j) + dinv[n] * (b[n] - s);
+  });
+  if (i >= mx || j >= my) return;
+  const long n = (long)j * mx + i;
+  tout[n] = t[(ly + 1) * kTW + lx + 1] + dinv[n] * (b[n] - tile_stencil(A9 + 9 * n, t, lx, ly));
 }
 
 // r = b - A x
 __global__ __launch_bounds__(256) void mg_residual_kernel(int mx, int my,
-                                                         const double* __restrict__ A9,
+                                                         const float* __restrict__ A9,
                                                          const double* __restrict__ b,
                                                          const double* __restrict__ x,
                                                          double* __restrict__ r,
                                                          const double* __restrict__ sc) {
+  __shared__ double t[kTW * kTH];
   if (sc[S_DONE] != 0.0) return;
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= (long)mx * my) return;
-  const int i = (int)(n % mx), j = (int)(n / mx);
-  r[n] = b[n] - stencil9(A9, x, mx, my, i, j);
+  const int lx = (int)threadIdx.x % kTX, ly = (int)threadIdx.x / kTX;
+  const int i = (int)blockIdx.x * kTX + lx, j = (int)blockIdx.y * kTY + ly;
+  fill_tile(t, mx, my, [&](int ii, int jj) { return x[(long)jj * mx + ii]; });
+  if (i >= mx || j >= my) return;
+  const long n = (long)j * mx + i;
+  r[n] = b[n] - tile_stencil(A9 + 9 * n, t, lx, ly);
 }
 
 // full weighting (transpose of bilinear interpolation): fine node (2I + di, 2J + dj) has
@@ -483,7 +589,7 @@ __global__ __launch_bounds__(256) void dg_restrict_kernel(int nx, int ny, Emb em
 
 // z = B^{-1} r + P x0 on every cell; part1 = r.z per block
 __global__ __launch_bounds__(256) void dg_precond_kernel(int nx, int ny, Emb em,
-                                                        const double* __restrict__ minv,
+                                                        const double* __restrict__ mc,
                                                         const double* __restrict__ r,
                                                         const double* __restrict__ x0,
                                                         double* __restrict__ z,
@@ -499,7 +605,15 @@ __global__ __launch_bounds__(256) void dg_precond_kernel(int nx, int ny, Emb em,
     double rv[4], zv[4] = {0, 0, 0, 0}, u[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) rv[k] = r[4 * c + k];
-    mv4(minv + 16 * c, rv, zv);
+    {  // B^{-1} r from the upper triangle (row-major: 00 01 02 03 11 12 13 22 23 33)
+      double m[10];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) m[k] = mc[(long)k * ncell + c];
+      zv[0] = m[0] * rv[0] + m[1] * rv[1] + m[2] * rv[2] + m[3] * rv[3];
+      zv[1] = m[1] * rv[0] + m[4] * rv[1] + m[5] * rv[2] + m[6] * rv[3];
+      zv[2] = m[2] * rv[0] + m[5] * rv[1] + m[7] * rv[2] + m[8] * rv[3];
+      zv[3] = m[3] * rv[0] + m[6] * rv[1] + m[8] * rv[2] + m[9] * rv[3];
+    }
 #pragma unroll
     for (int cj = 0; cj < 2; ++cj)
 #pragma unroll
@@ -780,6 +894,11 @@ __global__ __launch_bounds__(256) void mg_dinv_kernel(long n, const double* __re
   dinv[i] = s > 0.0 ? 1.0 / s : 0.0;
 }
 
+__global__ void to_float_kernel(long n, const double* __restrict__ a, float* __restrict__ b) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
 // ------------------------------------------------------------ set-up
 constexpr int kCoarseDense = 100;  // largest grid solved by its dense inverse
 constexpr int kCoarseSweeps = 20;  // l1-Jacobi sweeps on a coarsest grid that is larger
@@ -860,6 +979,10 @@ DSA* dsa_create(const Geom& g, const double* sigma_t_dev, const double* sigma_s_
     hipLaunchKernelGGL(dsa_blocks_kernel, dim3(nblocks(n)), dim3(256), 0, st, g.nx, g.ny, g.hx,
                        g.hy, sigma_t_dev, sigma_s_dev, d->diag.get(), d->ax.get(), d->ay.get(),
                        d->minv.get(), bad.get());
+    d->cc.alloc(14 * n);
+    d->mc.alloc(10 * n);
+    hipLaunchKernelGGL(dsa_compact_kernel, dim3(nblocks(n)), dim3(256), 0, st, n, d->diag.get(),
+                       d->ax.get(), d->ay.get(), d->minv.get(), d->cc.get(), d->mc.get());
     // grid hierarchy: vertex-centred halving while both node counts allow it
     std::vector<std::pair<int, int>> dims{{g.nx + 1, g.ny + 1}};
     while (true) {
@@ -889,6 +1012,9 @@ DSA* dsa_create(const Geom& g, const double* sigma_t_dev, const double* sigma_s_
       }
       hipLaunchKernelGGL(mg_dinv_kernel, dim3(nblocks(nn)), dim3(256), 0, st, nn, L.A9.get(),
                          L.dinv.get(), bad.get());
+      L.A9c.alloc(9 * nn);
+      hipLaunchKernelGGL(to_float_kernel, dim3(nblocks(9 * nn)), dim3(256), 0, st, 9 * nn, L.A9.get(),
+                         L.A9c.get());
       RTE_CHECK_HIP(hipGetLastError());
     }
     const MgLevel& Lc = *d->mg.back();
@@ -918,7 +1044,7 @@ DSA* dsa_create(const Geom& g, const double* sigma_t_dev, const double* sigma_s_
       --d->lsmall;
     std::vector<MgDev> views;
     for (auto& L : d->mg)
-      views.push_back(MgDev{L->mx, L->my, L->A9.get(), L->dinv.get(), L->x.get(), L->b.get(), L->t.get()});
+      views.push_back(MgDev{L->mx, L->my, L->A9c.get(), L->dinv.get(), L->x.get(), L->b.get(), L->t.get()});
     d->mgdev.alloc(views.size());
     RTE_CHECK_HIP(hipMemcpy(d->mgdev.get(), views.data(), views.size() * sizeof(MgDev),
                             hipMemcpyHostToDevice));
@@ -951,21 +1077,20 @@ void vcycle(DSA* d, int l, hipStream_t st) {
                        (int)d->mg.size(), d->cinv.get(), d->ncoarse, kCoarseSweeps, sc);
     return;
   }
-  const long n = (long)L.mx * L.my;
-  const unsigned nb = nblocks(n);
+  const dim3 nb = tile_grid(L.mx, L.my);
   auto jac = [&](const double* x, double* out) {
-    hipLaunchKernelGGL(mg_jacobi_kernel, dim3(nb), dim3(256), 0, st, L.mx, L.my, L.A9.get(),
+    hipLaunchKernelGGL(mg_jacobi_kernel, nb, dim3(kTX * kTY), 0, st, L.mx, L.my, L.A9c.get(),
                        L.dinv.get(), L.b.get(), x, out, sc);
   };
   MgLevel& C = *d->mg[l + 1];
-  hipLaunchKernelGGL(mg_pre_kernel, dim3(nb), dim3(256), 0, st, L.mx, L.my, L.A9.get(),
+  hipLaunchKernelGGL(mg_pre_kernel, nb, dim3(kTX * kTY), 0, st, L.mx, L.my, L.A9c.get(),
                      L.dinv.get(), L.b.get(), L.x.get(), sc);
-  hipLaunchKernelGGL(mg_residual_kernel, dim3(nb), dim3(256), 0, st, L.mx, L.my, L.A9.get(),
+  hipLaunchKernelGGL(mg_residual_kernel, nb, dim3(kTX * kTY), 0, st, L.mx, L.my, L.A9c.get(),
                      L.b.get(), L.x.get(), L.t.get(), sc);
   hipLaunchKernelGGL(mg_restrict_kernel, dim3(nblocks((long)C.mx * C.my)), dim3(256), 0, st, L.mx,
                      L.my, L.t.get(), C.mx, C.my, C.b.get(), sc);
   vcycle(d, l + 1, st);
-  hipLaunchKernelGGL(mg_post_kernel, dim3(nb), dim3(256), 0, st, L.mx, L.my, L.A9.get(),
+  hipLaunchKernelGGL(mg_post_kernel, nb, dim3(kTX * kTY), 0, st, L.mx, L.my, L.A9c.get(),
                      L.dinv.get(), L.b.get(), L.x.get(), C.mx, C.x.get(), L.t.get(), sc);
   jac(L.t.get(), L.x.get());
 }
@@ -980,7 +1105,7 @@ void precondition(DSA* d, const double* r, double* z, hipStream_t st) {
                      g.ny, em, r, L0.b.get(), sc);
   vcycle(d, 0, st);
   hipLaunchKernelGGL(dg_precond_kernel, dim3(d->nblk), dim3(256), 0, st, g.nx, g.ny, em,
-                     d->minv.get(), r, L0.x.get(), z, d->part1.get(), sc);
+                     d->mc.get(), r, L0.x.get(), z, d->part1.get(), sc);
 }
 
 }  // namespace
@@ -1006,17 +1131,14 @@ int dsa_apply(DSA* d, const double* phi_star, const double* phi_prev, double* ph
   int it = 0;
   for (; it < max_iter; it += chunk) {
     for (int k = 0; k < chunk; ++k) {
-      hipLaunchKernelGGL(spmv_kernel, dim3(nb), dim3(256), 0, st, g.nx, g.ny, d->diag.get(),
-                         d->ax.get(), d->ay.get(), d->z.get(), pold, pnew, d->q.get(),
-                         d->part1.get(), sc);
-      hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part1.get(), nb, sc + S_PQ);
-      hipLaunchKernelGGL(alpha_kernel, dim3(1), dim3(1), 0, st, sc);
+      hipLaunchKernelGGL(spmv_kernel, dim3(nb), dim3(256), 0, st, g.nx, g.ny, d->cc.get(),
+                         d->z.get(), pold, pnew, d->q.get(), d->part1.get(), sc);
+      hipLaunchKernelGGL(reduce_alpha_kernel, dim3(1), dim3(1024), 0, st, d->part1.get(), nb, sc);
       hipLaunchKernelGGL(update_r_kernel, dim3(nb), dim3(256), 0, st, n, pnew, d->q.get(),
                          d->x.get(), d->r.get(), d->part2.get(), sc);
       hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part2.get(), nb, sc + S_RR);
       precondition(d, d->r.get(), d->z.get(), st);
-      hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part1.get(), nb, sc + S_PQ);
-      hipLaunchKernelGGL(beta_kernel, dim3(1), dim3(1), 0, st, sc, 0.0);
+      hipLaunchKernelGGL(reduce_beta_kernel, dim3(1), dim3(1024), 0, st, d->part1.get(), nb, sc);
       std::swap(pold, pnew);
     }
     RTE_CHECK_HIP(hipGetLastError());

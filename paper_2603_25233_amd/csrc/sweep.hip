@@ -734,23 +734,30 @@ __global__ void reduce_parts_kernel(const T* __restrict__ part, int ngroups, lon
   phi[i] = s;
 }
 
-// Diagonal-major partial sums (large phi-only plans): the groups of quadrant q, in
-// group order, summed into the slot of its first group g0[q] (in place: each element is
-// read and written by one thread).
+// Diagonal-major partial sums (large phi-only plans): the groups of one quadrant, in group
+// order, summed into the slot of its first group g[0] (in place: each element is read and
+// written by one thread).  The list travels in the kernel arguments, up to kListMax groups
+// per launch; acc = 1 continues the sum already in the first group's slot.
+constexpr int kListMax = 1024;
+struct GroupList {
+  int n, acc;
+  int16_t g[kListMax];
+};
+
 template <typename T>
-__global__ void reduce_quadrants_kernel(T* __restrict__ part, int ngroups, int D,
-                                        const SweepDir* __restrict__ dirs, long ndof, int g00,
-                                        int g01, int g02, int g03) {
+__global__ void reduce_quadrant_kernel(T* __restrict__ part, long ndof, int g0, GroupList L) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int q = blockIdx.y;
-  const int g0 = q == 0 ? g00 : q == 1 ? g01 : q == 2 ? g02 : g03;
-  if (i >= ndof || g0 < 0) return;
-  T s = T(0);
-  for (int g = g0; g < ngroups; ++g) {
-    const SweepDir d = dirs[(long)g * D];
-    if ((d.sx < 0 ? 1 : 0) + (d.sy < 0 ? 2 : 0) != q) continue;
-    s += part[(long)g * ndof + i];
+  if (i >= ndof) return;
+  T s = L.acc ? part[(long)g0 * ndof + i] : T(0);
+  int k = 0;
+  for (; k + 8 <= L.n; k += 8) {  // eight loads in flight, added in list order
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(long)L.g[k + u] * ndof + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
   }
+  for (; k < L.n; ++k) s += part[(long)L.g[k] * ndof + i];
   part[(long)g0 * ndof + i] = s;
 }
 
@@ -1035,15 +1042,26 @@ void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
   if (phi) {
     const int tb = 256;
     if (mode == 12) {  // diagonal-major partial sums: per quadrant, then gathered per cell
-      int g0[4] = {-1, -1, -1, -1};
+      std::vector<int> lists[4];
+      RTE_REQUIRE(pl.ngroups <= 32767, "sweep: %d workgroups", pl.ngroups);
       for (int b = 0; b < pl.ngroups; ++b) {
         const SweepDir& d = pl.groups[(size_t)b * pl.D];
-        const int q = (d.sx < 0 ? 1 : 0) + (d.sy < 0 ? 2 : 0);
-        if (g0[q] < 0) g0[q] = b;
+        lists[(d.sx < 0 ? 1 : 0) + (d.sy < 0 ? 2 : 0)].push_back(b);
       }
-      hipLaunchKernelGGL((reduce_quadrants_kernel<T>), dim3((unsigned)((g.ndof + tb - 1) / tb), 4),
-                         dim3(tb), 0, st, part, pl.ngroups, pl.D, dirs_dev, g.ndof, g0[0], g0[1],
-                         g0[2], g0[3]);
+      int g0[4] = {-1, -1, -1, -1};
+      for (int q = 0; q < 4; ++q) {
+        const std::vector<int>& l = lists[q];
+        if (l.empty()) continue;
+        g0[q] = l[0];
+        for (size_t k0 = 0; k0 < l.size(); k0 += kListMax) {
+          GroupList L;
+          L.n = (int)std::min(l.size() - k0, (size_t)kListMax);
+          L.acc = k0 > 0 ? 1 : 0;
+          for (int k = 0; k < L.n; ++k) L.g[k] = (int16_t)l[k0 + k];
+          hipLaunchKernelGGL((reduce_quadrant_kernel<T>), dim3((unsigned)((g.ndof + tb - 1) / tb)),
+                             dim3(tb), 0, st, part, g.ndof, g0[q], L);
+        }
+      }
       hipLaunchKernelGGL((gather_quadrants_kernel<T>), dim3((unsigned)((g.ncell + tb - 1) / tb)),
                          dim3(tb), 0, st, part, g.ndof, g.nx, g.ny, g0[0], g0[1], g0[2], g0[3], phi);
     } else {
