@@ -271,15 +271,22 @@ __global__ __launch_bounds__(1024) void reduce_alpha_kernel(const double* __rest
   }
 }
 
-// reduce_kernel of r.z into sc[S_PQ], then the convergence test and beta (one launch)
-__global__ __launch_bounds__(1024) void reduce_beta_kernel(const double* __restrict__ part, int nblk,
+// the reductions of r.r (part2) into sc[S_RR] and of r.z (part1) into sc[S_PQ], then the
+// convergence test and beta (one launch)
+__global__ __launch_bounds__(1024) void reduce_beta_kernel(const double* __restrict__ part,
+                                                           const double* __restrict__ part2, int nblk,
                                                            double* __restrict__ sc) {
   __shared__ double red[1024];
-  double v = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += blockDim.x) v += part[i];
+  double v = 0.0, v2 = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+    v += part[i];
+    v2 += part2[i];
+  }
+  const double s2 = block_sum(v2, red);
   const double s = block_sum(v, red);
   if (threadIdx.x == 0) {
     sc[S_PQ] = s;
+    if (sc[S_DONE] == 0.0) sc[S_RR] = s2;
     if (sc[S_DONE] == 0.0) {
       sc[S_ITERS] += 1.0;
       if (sc[S_RR] <= sc[S_TOL2]) {
@@ -1136,9 +1143,9 @@ int dsa_apply(DSA* d, const double* phi_star, const double* phi_prev, double* ph
       hipLaunchKernelGGL(reduce_alpha_kernel, dim3(1), dim3(1024), 0, st, d->part1.get(), nb, sc);
       hipLaunchKernelGGL(update_r_kernel, dim3(nb), dim3(256), 0, st, n, pnew, d->q.get(),
                          d->x.get(), d->r.get(), d->part2.get(), sc);
-      hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part2.get(), nb, sc + S_RR);
       precondition(d, d->r.get(), d->z.get(), st);
-      hipLaunchKernelGGL(reduce_beta_kernel, dim3(1), dim3(1024), 0, st, d->part1.get(), nb, sc);
+      hipLaunchKernelGGL(reduce_beta_kernel, dim3(1), dim3(1024), 0, st, d->part1.get(),
+                         d->part2.get(), nb, sc);
       std::swap(pold, pnew);
     }
     RTE_CHECK_HIP(hipGetLastError());
