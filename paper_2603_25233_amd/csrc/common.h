@@ -102,18 +102,23 @@ struct SweepPlan {
   int psi = 1;    // planned for psi output (else the scalar flux only)
   int qmask = 0;  // quadrants swept (bit q = (sx < 0) + 2 (sy < 0))
   int srows = 256;  // rows of a step that each staging wavefront copies
+  int dsrc = 0;     // one source per direction: the source of psi slot s is row s of a
+                    // [nslots][ndof] array (psi only, one direction per workgroup)
+  int nslots = 0;   // 1 + the largest psi slot
 };
 // Plans for psi (want_psi) or for the scalar flux only; a psi plan also serves
 // calls that request both.
 SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool want_phi,
-                          bool want_psi, size_t elem_bytes);
+                          bool want_psi, size_t elem_bytes, bool per_dir_src = false);
 // Elements of T the sweep needs as workspace: the diagonal-major copies of the
 // source and cross section (about 5 ncell per quadrant) and, when phi is requested,
-// the per-group partial sums ([ngroups][ndof]).
+// the per-group partial sums ([ngroups][ndof]); with one source per direction, the
+// diagonal-major copy of each ([nslots][ndof]).
 size_t sweep_input_elems(const Geom& g);
 size_t sweep_work_elems(const Geom& g, const SweepPlan& pl, bool want_phi);
 // Enqueues the sweep (no synchronisation).  work: sweep_work_elems(g, pl, phi != null)
-// elements.  psi != null needs a plan made with want_psi.
+// elements.  psi != null needs a plan made with want_psi.  With a per-direction-source
+// plan, src is [nslots][ndof] (the source of psi slot s in row s).
 template <typename T>
 void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
                    const double* sigma_t, const T* src, const double* bc, T* psi, T* phi,

@@ -1115,7 +1115,7 @@ __global__ void diff2_kernel(const double* __restrict__ a, const double* __restr
 
 // ------------------------------------------------------------------ backward Euler source
 // Rows r0 .. r0 + pn - 1 of the projected angular source of every class:
-// btime[k][r0 + l] = sum_i (Xp_i^T x_{r0+l}) ct[k][i], with xtp[i pn + l] = Xp_i^T x_{r0+l}.
+// btime[k][r0 + l] = sum_i (Xp_i^T x_{r0+l}) ct[i][k], with xtp[i pn + l] = Xp_i^T x_{r0+l}.
 __global__ void time_rows_kernel(int K, int rp, int pn, int r0, int rcap,
                                  const double* __restrict__ xtp, const double* __restrict__ ct,
                                  double* __restrict__ btime) {
@@ -1123,17 +1123,26 @@ __global__ void time_rows_kernel(int K, int rp, int pn, int r0, int rcap,
   if (t >= K * pn) return;
   const int k = t / pn, l = t % pn;
   double s = 0.0;
-  for (int i = 0; i < rp; ++i) s += xtp[(size_t)i * pn + l] * ct[(size_t)k * rp + i];
+  for (int i = 0; i < rp; ++i) s += xtp[(size_t)i * pn + l] * ct[(size_t)i * K + k];
   btime[(size_t)k * rcap + r0 + l] = s;
 }
 
-// Ctm[i][m] = ct[cls[m]][i]: the source coefficients of nm candidate classes
-__global__ void gather_ct_kernel(const double* __restrict__ ct, int rp, const int* __restrict__ cls,
-                                 int nm, double* __restrict__ Ctm) {
+// Ctm[i][m] = ct[i][cls[m]]: the source coefficients of nm classes
+__global__ void gather_ct_kernel(const double* __restrict__ ct, int rp, int K,
+                                 const int* __restrict__ cls, int nm, double* __restrict__ Ctm) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= rp * nm) return;
   const int i = t / nm, m = t % nm;
-  Ctm[t] = ct[(size_t)cls[m] * rp + i];
+  Ctm[t] = ct[(size_t)i * K + cls[m]];
+}
+
+// out[m] += src for the nm vectors of out
+__global__ void add_src_kernel(long nd, int nm, const double* __restrict__ src,
+                               double* __restrict__ out) {
+  const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nd) return;
+  const double v = src[j];
+  for (int m = 0; m < nm; ++m) out[(size_t)m * nd + j] += v;
 }
 
 // ------------------------------------------------------------------ one-sided Jacobi SVD
@@ -1368,6 +1377,23 @@ int tail_rank(const std::vector<double>& s, double eps) {
 
 }  // namespace
 
+// The per-class sources of a backward Euler sweep: out[m] = src + Xp ct[:, cls[m]], the
+// product as X C in chunks of 32 classes (one pass over Xp per chunk).
+void time_class_sources(const TimeSrc& ts, const int* cls_dev, int nm, long nd, const double* src,
+                        double* out, double* ctm, hipStream_t st) {
+  const unsigned nb = (unsigned)((nd + 255) / 256);
+  if (cls_dev)
+    hipLaunchKernelGGL(gather_ct_kernel, dim3((ts.rp * nm + 255) / 256), dim3(256), 0, st, ts.ct, ts.rp,
+                       ts.K, cls_dev, nm, ctm);
+  const double* C = cls_dev ? ctm : ts.ct;
+  const int ldc = cls_dev ? nm : ts.K;
+  for (int m0 = 0; m0 < nm; m0 += 32)
+    hipLaunchKernelGGL((xc_kernel<double, double, 32>), dim3(nb), dim3(256), 0, st, ts.Xp, ts.rp, nd,
+                       C + m0, ldc, std::min(32, nm - m0), out + (size_t)m0 * nd);
+  hipLaunchKernelGGL(add_src_kernel, dim3(nb), dim3(256), 0, st, nd, nm, src, out);
+  RTE_CHECK_HIP(hipGetLastError());
+}
+
 // ================================================================== the solver
 template <typename T>
 struct LowRank {
@@ -1383,7 +1409,7 @@ struct LowRank {
   std::vector<double> wc, mult;
   std::vector<ClassDev> cd;
   DevBuf<ClassDev> d_cd;
-  DevBuf<int> d_cls_of, d_sampled, d_list[3];
+  DevBuf<int> d_cls_of, d_sampled, d_list[4];
   DevBuf<double> d_wc, d_mult;
   // fields
   DevBuf<T> X, Y, V;
@@ -1404,7 +1430,7 @@ struct LowRank {
   DevBuf<SweepDir> d_dirs;
   DevBuf<double> Cm, rpart, rsums;
   SweepDir* h_dirs = nullptr;  // pinned staging
-  int* h_list[3] = {nullptr, nullptr, nullptr};  // pinned staging for class lists
+  int* h_list[4] = {nullptr, nullptr, nullptr, nullptr};  // pinned staging for class lists
   int* h_flags = nullptr;      // pinned staging for the sampled flags
   int rblk = 0;
   // bookkeeping
@@ -1419,7 +1445,7 @@ struct LowRank {
   hipEvent_t e0, e1;
   // backward Euler step: the angular source psi^m / dt (FP64 only) and its projections
   const TimeSrc* ts = nullptr;
-  DevBuf<double> tsrc, btime, tex, tctm, txp;
+  DevBuf<double> tsrc, twork, btime, tex, tctm, txp;
 
   bool sweep_pending = false;
   // waits for the stream; adds the time of a sweep enqueued since the last wait
@@ -1480,7 +1506,7 @@ struct LowRank {
     d_mult.alloc(K);
     RTE_CHECK_HIP(hipMemcpy(d_mult.get(), mult.data(), K * sizeof(double), hipMemcpyHostToDevice));
     d_sampled.alloc(K);
-    for (int i = 0; i < 3; ++i) d_list[i].alloc(K);
+    for (int i = 0; i < 4; ++i) d_list[i].alloc(K);
     X.alloc((size_t)rcap * nd);
     psi.alloc((size_t)p * nd);
     swork.alloc(sweep_input_elems(g));  // sweep workspace without the scalar flux
@@ -1514,13 +1540,14 @@ struct LowRank {
     RTE_CHECK_HIP(hipHostMalloc((void**)&h_dirs, 2 * kMaxP * sizeof(SweepDir), hipHostMallocDefault));
     if (ts && ts->rp > 0) {
       RTE_REQUIRE((std::is_same<T, double>::value), "the backward Euler step is FP64 only");
-      tsrc.alloc(nd);
+      tsrc.alloc((size_t)p * nd);
+      twork.alloc(sweep_input_elems(g) + (size_t)p * nd);
       btime.alloc((size_t)K * rcap);
       tex.alloc((size_t)kCandChunk * nd);
       tctm.alloc((size_t)ts->rp * kCandChunk);
       txp.alloc((size_t)ts->rp * kMaxP + 2 * kMaxP);
     }
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 4; ++i)
       RTE_CHECK_HIP(hipHostMalloc((void**)&h_list[i], (size_t)K * sizeof(int), hipHostMallocDefault));
     RTE_CHECK_HIP(hipHostMalloc((void**)&h_flags, (size_t)K * sizeof(int), hipHostMallocDefault));
     rblk = (int)((g.ncell + 255) / 256);
@@ -1549,7 +1576,7 @@ struct LowRank {
 
   ~LowRank() {
     if (h_dirs) (void)hipHostFree(h_dirs);
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 4; ++i)
       if (h_list[i]) (void)hipHostFree(h_list[i]);
     if (h_mstat) (void)hipHostFree(h_mstat);
     if (h_flags) (void)hipHostFree(h_flags);
@@ -1587,11 +1614,11 @@ struct LowRank {
     swept_total += (int)cl.size();
   }
 
-  // Backward Euler: the classes differ in their angular source, so each is swept alone
-  // with src + psi^m_c / dt.
+  // Backward Euler: the classes differ in their angular source; one sweep with a source
+  // per class (row i of tsrc for slot i).
   void sweep_classes_time(const std::vector<int>& cl) {
     RTE_CHECK_HIP(hipEventRecord(e0, st));
-    size_t off = 0;
+    std::vector<SweepDir> dirs;
     for (size_t i = 0; i < cl.size(); ++i) {
       const ClassDev& k = cd[cl[i]];
       SweepDir d;
@@ -1602,16 +1629,18 @@ struct LowRank {
       d.sy = k.sy;
       d.slot = (int)i;
       d.pad = 0;
-      SweepPlan pl = make_sweep_plan(g, {d}, false, true, sizeof(double));
-      RTE_REQUIRE(off + pl.groups.size() <= 2 * (size_t)kMaxP, "internal: sweep staging too small");
-      std::memcpy(h_dirs + off, pl.groups.data(), pl.groups.size() * sizeof(SweepDir));
-      RTE_CHECK_HIP(hipMemcpyAsync(d_dirs.get() + off, h_dirs + off, pl.groups.size() * sizeof(SweepDir),
-                                   hipMemcpyHostToDevice, st));
-      time_class_source(*ts, cl[i], nd, src.get(), tsrc.get(), st);
-      sweep_enqueue<double>(g, pl, d_dirs.get() + off, prob->sigma_t, tsrc.get(), prob->bc, psi.get(),
-                            nullptr, swork.get(), st);
-      off += pl.groups.size();
+      dirs.push_back(d);
     }
+    SweepPlan pl = make_sweep_plan(g, dirs, false, true, sizeof(double), true);
+    RTE_REQUIRE(pl.groups.size() <= 2 * (size_t)kMaxP, "internal: sweep staging too small");
+    RTE_REQUIRE(sweep_work_elems(g, pl, false) <= twork.n, "internal: sweep workspace too small");
+    std::memcpy(h_dirs, pl.groups.data(), pl.groups.size() * sizeof(SweepDir));
+    RTE_CHECK_HIP(hipMemcpyAsync(d_dirs.get(), h_dirs, pl.groups.size() * sizeof(SweepDir),
+                                 hipMemcpyHostToDevice, st));
+    const int* dl = upload_list(3, cl);
+    time_class_sources(*ts, dl, (int)cl.size(), nd, src.get(), tsrc.get(), tctm.get(), st);
+    sweep_enqueue<double>(g, pl, d_dirs.get(), prob->sigma_t, tsrc.get(), prob->bc, psi.get(),
+                          nullptr, twork.get(), st);
     RTE_CHECK_HIP(hipEventRecord(e1, st));
     sweep_pending = true;
     swept += (int)cl.size();
@@ -1956,7 +1985,8 @@ struct LowRank {
   }
 
   // Class lists: 0 for the bordered factorisations, 1 for the candidates, 2 for the
-  // unsampled classes at a convergence check or the truncation.  Each kind is uploaded
+  // unsampled classes at a convergence check or the truncation, 3 for the sampled classes
+  // of a backward Euler sweep.  Each kind is uploaded
   // at most once between two synchronisations of the inner loop, so its staging buffer
   // is free again when it is next written.
   const int* upload_list(int kind, const std::vector<int>& l) {
@@ -2024,7 +2054,7 @@ struct LowRank {
     if constexpr (std::is_same<T, double>::value) {
       if (ts && ts->rp > 0) {
         hipLaunchKernelGGL(gather_ct_kernel, dim3((ts->rp * nm + 255) / 256), dim3(256), 0, st, ts->ct,
-                           ts->rp, dl, nm, tctm.get());
+                           ts->rp, ts->K, dl, nm, tctm.get());
         hipLaunchKernelGGL((xc_kernel<double, double, 32>), dim3((nd + 255) / 256), dim3(256), 0, st,
                            ts->Xp, ts->rp, nd, tctm.get(), nm, nm, tex.get());
         exv = tex.get();

@@ -212,7 +212,8 @@ __global__ void diag_layout_kernel(int nx, int ny, int qmask, const double* __re
   }
   if (c >= ncell) return;
   const int acol = (int)(c % nx), brow = (int)(c / nx);
-  const Vec4<T> s4 = load4(src + 4 * c);
+  Vec4<T> s4;  // src == null: per-direction sources, laid out by diag_src_dirs_kernel
+  if (src) s4 = load4(src + 4 * c);
   const T sg = T(sigma_t[c]);
   const long qs = sig_stride<T>(nx, ny);
 #pragma unroll
@@ -224,10 +225,41 @@ __global__ void diag_layout_kernel(int nx, int ny, int qmask, const double* __re
     const int t = r + ap;
     const int lo = t >= nx ? t - nx + 1 : 0;
     const long k = q * ncell + diag_first(t, nx, ny) + r - lo;
-    const T v[4] = {s4.v[0], T(sx) * s4.v[1], T(sy) * s4.v[2], T(sx * sy) * s4.v[3]};
-    store4(dsrc + 4 * k, v);
+    if (src) {
+      const T v[4] = {s4.v[0], T(sx) * s4.v[1], T(sy) * s4.v[2], T(sx * sy) * s4.v[3]};
+      store4(dsrc + 4 * k, v);
+    }
     dsig[q * qs + sig_first<T>(t, nx, ny) + r - lo] = sg;
   }
+}
+
+// Per-direction sources: slot s's source (row s of src, [ny][nx][4]) in the diagonal-major
+// order of its own quadrant's canonical frame, with the odd moments' signs of that frame.
+// The quadrant of each slot (q = (sx < 0) + 2 (sy < 0)) travels in the kernel arguments.
+constexpr int kSlotsMax = 2048;
+struct SlotQuads {
+  int8_t q[kSlotsMax];
+};
+
+template <typename T>
+__global__ void diag_src_dirs_kernel(int nx, int ny, int slot0, SlotQuads sq,
+                                     const T* __restrict__ src, T* __restrict__ dsrc) {
+  const long ncell = (long)nx * ny;
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const int s = slot0 + (int)blockIdx.y;
+  const int q = sq.q[blockIdx.y];
+  if (q < 0) return;  // a slot no direction writes
+  const int sx = (q & 1) ? -1 : 1, sy = (q & 2) ? -1 : 1;
+  const int acol = (int)(c % nx), brow = (int)(c / nx);
+  const int r = sy > 0 ? brow : ny - 1 - brow;
+  const int ap = sx > 0 ? acol : nx - 1 - acol;
+  const int t = r + ap;
+  const int lo = t >= nx ? t - nx + 1 : 0;
+  const long k = diag_first(t, nx, ny) + r - lo;
+  const Vec4<T> s4 = load4(src + (long)s * 4 * ncell + 4 * c);
+  const T v[4] = {s4.v[0], T(sx) * s4.v[1], T(sy) * s4.v[2], T(sx * sy) * s4.v[3]};
+  store4(dsrc + (long)s * 4 * ncell + 4 * k, v);
 }
 
 // Rows of one step that a staging wavefront carries at most (plans may use fewer, with
@@ -336,7 +368,9 @@ typedef __attribute__((address_space(3))) void lds_void;
 // cells (none in the others), so that the counts waited for are constants of the kernel
 // and the staging loop keeps no per-step tallies.
 //
-// Output mode OUT (compile time): bit 0 the LDS ring, bit 1 psi, bit 2 the weighted
+// Output mode OUT (compile time; bit 4: one source per direction, from row `slot` of
+// the per-direction layouts, for psi plans of one direction per workgroup): bit 0 the
+// LDS ring, bit 1 psi, bit 2 the weighted
 // partial sums of the scalar flux (psi and the partial sums together only for D = 1),
 // bit 3 large plans without the ring: psi leaves in line-sized groups of a row's cells,
 // partial sums without psi in the diagonal-major order of the canonical frame (one
@@ -361,6 +395,8 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
   using WB = WriteBack<T>;
   constexpr bool RING = (OUT & 1) != 0, PSI = (OUT & 2) != 0, PP = (OUT & 4) != 0;
   constexpr bool GRP = (OUT & 8) != 0;  // direct stores in line-sized groups (put_grouped)
+  constexpr bool DSRC = (OUT & 16) != 0;  // one source per direction (D == 1, psi only)
+  static_assert(!DSRC || (D == 1 && !PP), "per-direction sources: one direction, psi only");
   static_assert(PSI || PP, "no output");
   static_assert(!(PSI && PP) || D == 1, "psi with the scalar flux needs one direction per workgroup");
   constexpr int CW = WB::kChunkCells, NS = WB::kRingSlots, LPC = WB::kLanesPerCell;
@@ -503,7 +539,9 @@ __global__ __launch_bounds__(NTB) void sweep_kernel(
     const int lane = tid & 63;
     const int sw = (tid - nc) >> 6;
     const int c0 = sw * SR;  // first cell of this wavefront within a step
-    const float4* src16 = reinterpret_cast<const float4*>(dsrc_all + 4 * q * ncell);
+    // the quadrant's layout of the shared source, or this direction's own source
+    const long src_row = DSRC ? (long)grp[0].slot : (long)q;
+    const float4* src16 = reinterpret_cast<const float4*>(dsrc_all + 4 * src_row * ncell);
     const float4* sig16 = reinterpret_cast<const float4*>(dsig_all + q * sig_stride<T>(nx, ny));
     const float4* bnd16 = reinterpret_cast<const float4*>(dbnd_all) + (long)q * nsteps;
     float4* pad = reinterpret_cast<float4*>(in_bnd + S * BS);
@@ -849,7 +887,9 @@ constexpr int kXcds = 8;
 constexpr size_t kLdsTwoPerCU = 80 * 1024;
 
 SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool want_phi,
-                          bool want_psi, size_t elem_bytes) {
+                          bool want_psi, size_t elem_bytes, bool per_dir_src) {
+  RTE_REQUIRE(!per_dir_src || (want_psi && !want_phi),
+              "sweep: per-direction sources are for psi plans without the scalar flux");
   RTE_REQUIRE(g.ny >= 1 && g.ny <= 1024, "sweep: ny = %d outside [1, 1024]", g.ny);
   RTE_REQUIRE(g.nx >= 1 && g.nx <= 1 << 20, "sweep: nx = %d outside [1, 2^20]", g.nx);
   RTE_REQUIRE(!dirs.empty(), "sweep: no directions");
@@ -876,8 +916,9 @@ SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool
   // With psi, one direction per workgroup (measured faster: two workgroups share a
   // compute unit), except FP64 with two rows per thread, where one workgroup fills a
   // compute unit's LDS and two directions halve the rounds.
-  const int dmax = want_psi ? (elem_bytes == 8 && rpt == 2 && !want_phi ? 2 : 1)
-                            : elem_bytes == 8 ? ((pl.nt <= 576 || rpt == 2) ? 2 : 1) : 4;
+  const int dmax = per_dir_src ? 1
+                   : want_psi ? (elem_bytes == 8 && rpt == 2 && !want_phi ? 2 : 1)
+                              : elem_bytes == 8 ? ((pl.nt <= 576 || rpt == 2) ? 2 : 1) : 4;
   int D = 1;
   while (D < dmax && dirs.size() / (2 * D) >= 256 &&
          sweep_lds_bytes(nr, 2 * D, want_psi, rpt == 1, elem_bytes, rpt) <= lmax)
@@ -903,6 +944,8 @@ SweepPlan make_sweep_plan(const Geom& g, const std::vector<SweepDir>& dirs, bool
   pl.grouped = !ring && rpt == 2 && dirs.size() >= 64 ? 1 : 0;
   if (ring) pl.nt += 64 * nwb;
   pl.psi = want_psi ? 1 : 0;
+  pl.dsrc = per_dir_src ? 1 : 0;
+  for (const auto& d : dirs) pl.nslots = std::max(pl.nslots, d.slot + 1);
   pl.groups = make_groups(dirs, D);
   pl.ngroups = (int)(pl.groups.size() / D);
   // Workgroups are dealt to the XCDs in turn (workgroup b to XCD b mod kXcds), each with
@@ -931,7 +974,8 @@ size_t sweep_input_elems(const Geom& g) {
 }
 
 size_t sweep_work_elems(const Geom& g, const SweepPlan& pl, bool want_phi) {
-  return sweep_input_elems(g) + (want_phi ? (size_t)pl.ngroups * g.ndof : 0);
+  return sweep_input_elems(g) + (want_phi ? (size_t)pl.ngroups * g.ndof : 0) +
+         (pl.dsrc ? (size_t)pl.nslots * g.ndof : 0);
 }
 
 template <typename T>
@@ -949,7 +993,24 @@ void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
   {
     const int tb = 256;
     hipLaunchKernelGGL((diag_layout_kernel<T>), dim3((ncell + tb - 1) / tb), dim3(tb), 0, st, g.nx,
-                       g.ny, pl.qmask, sigma_t, src, bc, g.mb, shy, dsrc, dsig, dbnd);
+                       g.ny, pl.qmask, sigma_t, pl.dsrc ? nullptr : src, bc, g.mb, shy, dsrc, dsig,
+                       dbnd);
+    RTE_CHECK_HIP(hipGetLastError());
+  }
+  if (pl.dsrc) {  // each direction's own source, in its quadrant's diagonal-major order
+    RTE_REQUIRE(!phi, "sweep: per-direction sources give psi only");
+    dsrc = work + sweep_input_elems(g);
+    std::vector<int8_t> quad(pl.nslots, (int8_t)-1);
+    for (const auto& d : pl.groups)
+      if (d.slot >= 0) quad[d.slot] = (int8_t)((d.sx < 0 ? 1 : 0) + (d.sy < 0 ? 2 : 0));
+    const int tb = 256;
+    for (int s0 = 0; s0 < pl.nslots; s0 += kSlotsMax) {
+      const int ns = std::min(kSlotsMax, pl.nslots - s0);
+      SlotQuads sq;
+      for (int k = 0; k < ns; ++k) sq.q[k] = quad[s0 + k];
+      hipLaunchKernelGGL((diag_src_dirs_kernel<T>), dim3((unsigned)((ncell + tb - 1) / tb), ns),
+                         dim3(tb), 0, st, g.nx, g.ny, s0, sq, src, dsrc);
+    }
     RTE_CHECK_HIP(hipGetLastError());
   }
   const size_t lds = sweep_lds_bytes(pl.nc * pl.rpt, pl.D, psi != nullptr, pl.ring != 0, sizeof(T),
@@ -957,7 +1018,8 @@ void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
   dim3 grid(pl.ngroups), block(pl.nt);
   T* pp = phi ? part : nullptr;
   // output mode: bit 0 the LDS ring, bit 1 psi, bit 2 the scalar-flux partial sums
-  const int mode = (pl.ring ? 1 : 0) | (psi ? 2 : 0) | (pp ? 4 : 0) | (pl.grouped ? 8 : 0);
+  const int mode = (pl.ring ? 1 : 0) | (psi ? 2 : 0) | (pp ? 4 : 0) | (pl.grouped ? 8 : 0) |
+                   (pl.dsrc ? 16 : 0);
 #define RTE_SWEEP_K(DD, NTB, RP, SR, M)                                                         \
   RTE_REQUIRE(pl.nt <= NTB, "internal: %d threads for a sweep kernel of %d", pl.nt, NTB);        \
   hipLaunchKernelGGL((sweep_kernel<T, DD, NTB, RP, SR, M>), grid, block, lds, st, g.nx, g.ny,    \
@@ -984,6 +1046,9 @@ void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
         case 10: RTE_SWEEP_GRP(DD, NTB, RP, SR, 10); break;    \
         case 12: RTE_SWEEP_GRP(DD, NTB, RP, SR, 12); break;    \
         case 14: RTE_SWEEP_GRP(DD, NTB, RP, SR, 14); break;    \
+        case 18: RTE_SWEEP_K(DD, NTB, RP, SR, 18); break;      \
+        case 19: RTE_SWEEP_K(DD, NTB, RP, SR, 19); break;      \
+        case 26: RTE_SWEEP_GRP(DD, NTB, RP, SR, 26); break;    \
         default: bad();                                        \
       }                                                        \
     } else if (mode == 4) {                                    \

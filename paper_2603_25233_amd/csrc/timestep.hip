@@ -11,9 +11,10 @@
 //
 // psi^m enters in factor form, psi^m = X_prev diag(S_prev) V_prev^T, the form the
 // low-rank step returns, and is the same on the Omega_z twins of a class of equal
-// (Omega_x, Omega_y).  Per class c the source is Xp ct[c] with
-// ct[c][i] = S_prev[i] V_prev[i][rep(c)] / dt.
-//   full rank: every class is swept alone (its own source) with psi written, and
+// (Omega_x, Omega_y).  Per class c the source is sum_i Xp_i ct[i][c] with
+// ct[i][c] = S_prev[i] V_prev[i][rep(c)] / dt.
+//   full rank: one sweep of the classes, each with its own source (a per-direction-source
+//     sweep plan), psi written, and
 //     phi^{n,*} = sum_c w_c psi_c in class order; psi^{m+1} is the psi of the last SI
 //     sweep, returned as X = [psi_c], S = 1, V = the class indicator;
 //   low rank: the low-rank solver with the angular source in its sweeps, its Galerkin
@@ -37,25 +38,14 @@ __global__ void sigma_step_kernel(long n, const double* __restrict__ sig, double
   if (i < n) out[i] = sig[i] + inv_dt;
 }
 
-// ct[c][i] = S[i] V[i][rep[c]] / dt
+// ct[i][c] = S[i] V[i][rep[c]] / dt
 __global__ void time_coef_kernel(int rp, int K, const int* __restrict__ rep,
                                  const double* __restrict__ S, const double* __restrict__ V,
                                  int n_dirs, double inv_dt, double* __restrict__ ct) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= K * rp) return;
-  const int c = t / rp, i = t % rp;
+  const int i = t / K, c = t % K;
   ct[t] = S[i] * V[(size_t)i * n_dirs + rep[c]] * inv_dt;
-}
-
-// out = src + sum_i Xp[i] ctc[i], in column order
-__global__ void class_source_kernel(long nd, int rp, const double* __restrict__ Xp,
-                                    const double* __restrict__ ctc, const double* __restrict__ src,
-                                    double* __restrict__ out) {
-  const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nd) return;
-  double s = 0.0;
-  for (int i = 0; i < rp; ++i) s += Xp[(size_t)i * nd + j] * ctc[i];
-  out[j] = src[j] + s;
 }
 
 // phi = sum_c w[c] psi[c], in class order
@@ -91,22 +81,18 @@ rte_status fr_time_step(const rte_problem* prob, const rte_solve_params* prm, co
   const Geom g = make_geom(prob);
   const long nd = g.ndof;
   const int K = (int)dirs.size();
-  // one plan per class (psi written to slot c of X), their groups in one device array
-  std::vector<SweepPlan> plans;
-  std::vector<size_t> offs;
-  std::vector<SweepDir> all;
-  for (int c = 0; c < K; ++c) {
-    SweepDir d = dirs[c];
-    d.slot = c;
-    plans.push_back(make_sweep_plan(g, {d}, false, true, sizeof(double)));
-    offs.push_back(all.size());
-    all.insert(all.end(), plans.back().groups.begin(), plans.back().groups.end());
-  }
-  DevBuf<SweepDir> ddirs(all.size());
-  RTE_CHECK_HIP(hipMemcpy(ddirs.get(), all.data(), all.size() * sizeof(SweepDir), hipMemcpyHostToDevice));
+  // one plan over the classes (psi of class c to slot c of X); with psi^m each class has
+  // its own source (row c of csrc)
+  std::vector<SweepDir> cdirs(dirs);
+  for (int c = 0; c < K; ++c) cdirs[c].slot = c;
+  const SweepPlan plan = make_sweep_plan(g, cdirs, false, true, sizeof(double), ts.rp > 0);
+  DevBuf<SweepDir> ddirs(plan.groups.size());
+  RTE_CHECK_HIP(hipMemcpy(ddirs.get(), plan.groups.data(), plan.groups.size() * sizeof(SweepDir),
+                          hipMemcpyHostToDevice));
   std::vector<double> hw(K);
   for (int c = 0; c < K; ++c) hw[c] = dirs[c].w;
-  DevBuf<double> dw(K), work(sweep_input_elems(g)), src(nd), tsrc(nd), phi_prev(nd), phi_star(nd);
+  DevBuf<double> dw(K), work(sweep_work_elems(g, plan, false)), src(nd), phi_prev(nd), phi_star(nd);
+  DevBuf<double> csrc(ts.rp > 0 ? (size_t)K * nd : 0);
   RTE_CHECK_HIP(hipMemcpy(dw.get(), hw.data(), K * sizeof(double), hipMemcpyHostToDevice));
   if (phi0)
     RTE_CHECK_HIP(hipMemcpyAsync(phi_prev.get(), phi0, nd * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -124,15 +110,9 @@ rte_status fr_time_step(const rte_problem* prob, const rte_solve_params* prm, co
   for (n = 1; n <= prm->max_outer; ++n) {
     RTE_CHECK_HIP(hipEventRecord(e0, st));
     make_source<double>(g, prob->sigma_s, phi_prev.get(), prob->G, src.get(), st);
-    for (int c = 0; c < K; ++c) {
-      const double* s = src.get();
-      if (ts.rp > 0) {
-        time_class_source(ts, c, nd, src.get(), tsrc.get(), st);
-        s = tsrc.get();
-      }
-      sweep_enqueue<double>(g, plans[c], ddirs.get() + offs[c], prob->sigma_t, s, prob->bc, X,
-                            nullptr, work.get(), st);
-    }
+    if (ts.rp > 0) time_class_sources(ts, nullptr, K, nd, src.get(), csrc.get(), nullptr, st);
+    sweep_enqueue<double>(g, plan, ddirs.get(), prob->sigma_t, ts.rp > 0 ? csrc.get() : src.get(),
+                          prob->bc, X, nullptr, work.get(), st);
     hipLaunchKernelGGL(class_sum_kernel, dim3(nb), dim3(256), 0, st, nd, K, X, dw.get(), phi_star.get());
     RTE_CHECK_HIP(hipGetLastError());
     RTE_CHECK_HIP(hipEventRecord(e1, st));
@@ -189,13 +169,6 @@ rte_status fr_time_step(const rte_problem* prob, const rte_solve_params* prm, co
 }
 
 }  // namespace
-
-void time_class_source(const TimeSrc& ts, int c, long nd, const double* src, double* out,
-                       hipStream_t st) {
-  hipLaunchKernelGGL(class_source_kernel, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, st, nd,
-                     ts.rp, ts.Xp, ts.ct + (size_t)c * ts.rp, src, out);
-  RTE_CHECK_HIP(hipGetLastError());
-}
 
 void validate_solve_params(const rte_problem* prob, const rte_solve_params* p);
 
@@ -286,6 +259,7 @@ rte_status rte_backward_euler_step(const rte_problem* prob, const rte_solve_para
       RTE_CHECK_HIP(hipGetLastError());
       RTE_CHECK_HIP(hipStreamSynchronize(st));
       ts.rp = r_prev;
+      ts.K = K;
       ts.Xp = X_prev;
       ts.ct = ct.get();
     }

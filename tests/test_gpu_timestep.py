@@ -23,10 +23,27 @@ def psi_of(out):
     return (X.T @ np.diag(S) @ V).T
 
 
-@pytest.mark.parametrize("dt", [0.05, 2.0])
-def test_full_rank_steps(dt):
+def wide(nx, ny, n_theta, n_z):
+    wl = W.Workload(W.small_fr(n=nx, n_theta=n_theta, n_z=n_z))
+    wl["ny"] = ny
+    wl["sigma_t"] = np.ones((ny, nx)); wl["sigma_s"] = 0.99 * np.ones((ny, nx))
+    return wl
+
+
+# Every step after the first sweeps with one source per class: 16 classes use the small
+# plans' direct stores, 64 classes the LDS output ring, and 800 rows with 64 classes the
+# line-grouped stores of two rows per thread.
+FR_STEP_CASES = [
+    ("small12_cl8x4_dt0.05", W.Workload(W.small_fr(n=12, n_theta=8, n_z=4)), 0.05),
+    ("small12_cl8x4_dt2", W.Workload(W.small_fr(n=12, n_theta=8, n_z=4)), 2.0),
+    ("small12_cl16x8_ring", W.Workload(W.small_fr(n=12, n_theta=16, n_z=8)), 0.1),
+    ("rows800_cl16x8_grouped", wide(3, 800, 16, 8), 0.1),
+]
+
+
+@pytest.mark.parametrize("name,wl,dt", FR_STEP_CASES, ids=[c[0] for c in FR_STEP_CASES])
+def test_full_rank_steps(name, wl, dt):
     import paper_2603_25233_amd as R
-    wl = W.Workload(W.small_fr(n=12, n_theta=8, n_z=4))
     op, gp = oracle_problem(wl), gpu_problem(wl)
     kw = dict(full_rank=1, eps_si=1e-12, eps_dsa=1e-13, max_outer=200)
     o1 = ots.fr_step(op, dt, None, 1e-12)
