@@ -154,6 +154,90 @@ def paper_examples(R, W, torch, dev):
 
 
 
+def lr_against_fr(R, W, torch, prob, wl, fr, seed, p, q, eps_res, eps_diff, eps_svd, eps_si,
+                  max_outer, t_fr):
+    """One FP64 low-rank solve against a converged full-rank one: the metrics of the paper's
+    tables (rank, ||phi_LR - phi_FR||_2, C-R, iterations, speedup = full-rank time / low-rank
+    time, largest oversampling ratio).  The tables' psi column is not reproduced: the factors
+    hold the angular flux of the last SI step's source, and the full-rank solve does not keep
+    the angular flux of its own last sweep to compare with."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lr = R.solve(prob, rand=W.random_stream(seed), full_rank=0, p=p, q=q, eps_res=eps_res,
+                 eps_diff=eps_diff, eps_svd=eps_svd, eps_mgs=wl["eps_mgs"], m_max=wl["m_max"],
+                 eps_si=eps_si, max_outer=max_outer, eps_dsa=1e-12)
+    torch.cuda.synchronize()
+    t_lr = time.perf_counter() - t0
+    nd, nw = prob.ndof, prob.n_dirs
+    dphi = float(torch.linalg.norm(lr["phi"].reshape(-1) - fr["phi"].reshape(-1)))
+    over = [float(b) / float(a) - 1.0 for a, b in zip(lr["trunc_ranks"], lr["ranks"]) if a > 0]
+    return dict(rank=lr["rank"], phi_lr_minus_fr_l2=dphi,
+                compression_ratio=lr["rank"] * (nd + nw + 1) / (nd * nw), fr_iters=fr["iters"],
+                lr_iters=lr["iters"], lr_converged=lr["converged"], speedup_fr_over_lr=t_fr / t_lr,
+                lr_time_s=t_lr, max_oversampling=max(over) if over else None)
+
+
+def paper_tables(R, W, torch):
+    """The paper's robustness and threshold studies on its media (FP64): Sec. 4.3's p and q
+    sweeps on the variable-scattering medium, Sec. 4.4's eight random seeds on the pin cell,
+    and Sec. 4.2's inner-threshold scan (eps_res = eps_diff = 1e-3 .. 1e-7, eps_SVD = 0.1
+    eps_res, eps_SI = 5e-5, at most 25 outer iterations) on the lattice stand-in.  One JSON
+    line per run with the columns of the paper's tables."""
+    def setup(wl):
+        d, w = R.cl_quadrature(wl["n_theta"], wl["n_z"])
+        if wl.get("source_gauss") is not None:
+            amp, alpha, centre = wl["source_gauss"]
+            G = R.gaussian_source_moments(wl["nx"], wl["ny"], wl["domain"], amp, alpha, centre)
+        else:
+            G = R.box_source_moments(wl["nx"], wl["ny"], wl["domain"], wl["source_boxes"])
+        return R.Problem(wl["nx"], wl["ny"], wl["domain"], d, w, wl["sigma_t"], wl["sigma_s"], G=G)
+
+    def reference(prob, eps_si, max_outer):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fr = R.solve(prob, full_rank=1, eps_si=eps_si, max_outer=max_outer, eps_dsa=1e-12)
+        torch.cuda.synchronize()
+        return fr, time.perf_counter() - t0
+
+    wl = W.variable_scattering()
+    prob = setup(wl)
+    fr, t_fr = reference(prob, wl["eps_si"], wl["max_outer"])
+    for p, q in ((1, 4), (1, 8), (1, 12), (1, 16), (2, 8), (3, 8)):
+        m = lr_against_fr(R, W, torch, prob, wl, fr, wl["seed"], p, q, wl["eps_res"],
+                          wl["eps_diff"], wl["eps_svd"], wl["eps_si"], wl["max_outer"], t_fr)
+        print(json.dumps({"table": "sec4.3 variable scattering, p and q", "p": p, "q": q, **m,
+                          "dtype": "f64", "data": "synthetic"}), flush=True)
+    del prob
+    wl = W.pin_cell()
+    prob = setup(wl)
+    fr, t_fr = reference(prob, wl["eps_si"], wl["max_outer"])
+    runs = []
+    for k in range(8):
+        m = lr_against_fr(R, W, torch, prob, wl, fr, wl["seed"] + 1000 * (k + 1), wl["p"],
+                          wl["q"], wl["eps_res"], wl["eps_diff"], wl["eps_svd"], wl["eps_si"],
+                          wl["max_outer"], t_fr)
+        runs.append(m)
+        print(json.dumps({"table": "sec4.4 pin cell, random seeds", "run": k, **m, "dtype": "f64",
+                          "data": "synthetic"}), flush=True)
+    stats = {}
+    for key in ("rank", "phi_lr_minus_fr_l2", "compression_ratio",
+                "fr_iters", "lr_iters", "speedup_fr_over_lr"):
+        v = np.array([r[key] for r in runs], dtype=np.float64)
+        stats[key] = {"mean": float(v.mean()), "sd": float(v.std(ddof=1)), "min": float(v.min()),
+                      "max": float(v.max())}
+    print(json.dumps({"table": "sec4.4 pin cell, statistics of 8 seeds", **stats}), flush=True)
+    del prob
+    wl = W.lattice()
+    prob = setup(wl)
+    fr, t_fr = reference(prob, 5e-5, 25)
+    for eps in (1e-3, 1e-4, 1e-5, 1e-6, 1e-7):
+        m = lr_against_fr(R, W, torch, prob, wl, fr, wl["seed"], wl["p"], wl["q"], eps, eps,
+                          0.1 * eps, 5e-5, 25, t_fr)
+        print(json.dumps({"table": "sec4.2 lattice stand-in, inner thresholds", "eps_res": eps,
+                          "eps_diff": eps, "eps_svd": 0.1 * eps, "eps_si": 5e-5, **m,
+                          "dtype": "f64", "data": "synthetic"}), flush=True)
+
+
 def basis_update_ablation(R, W, torch):
     """Sec. 4.2's comparison of basis updates (MGS2-A, MGS-QR, full QR) and the DEIM
     sampling of the Remark in Sec. 3.2 on the lattice stand-in (80 x 80, CL(32,16), p = 1,
@@ -403,12 +487,14 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--only", choices=["step", "sweep", "sweep_large", "paper", "ablation",
-                                       "tomography", "lowrank", "timestep", "copy"],
+                                       "paper_tables", "tomography", "lowrank", "timestep",
+                                       "copy"],
                     default="step",
                     help="step: the headline line (default); "
                          "sweep: only the psi-writing full-angle sweep of the headline medium; "
                          "sweep_large: the same, one JSON line of its own (--mixed: FP32); "
                          "paper: the paper's own examples (Sec. 4.1, 4.3, 4.4), one JSON line each; "
+                         "paper_tables: the paper's p/q, random-seed and inner-threshold studies; "
                          "ablation: MGS2-A / MGS-QR / full-QR basis updates (Sec. 4.2) and DEIM sampling; "
                          "tomography: loss and sigma gradient of the 16-source detector misfit "
                          "at 256x256 with a central-difference check; "
@@ -448,6 +534,9 @@ def main():
         return
     if args.only == "paper":
         paper_examples(R, W, torch, dev)
+        return
+    if args.only == "paper_tables":
+        paper_tables(R, W, torch)
         return
     if args.only == "ablation":
         basis_update_ablation(R, W, torch)
