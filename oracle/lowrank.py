@@ -13,7 +13,7 @@ Steps of one low-rank SI (outer iteration n), in the paper's order (Sec. 3.1):
      projection phi^{n,k} = X (C w) and the test eq. (phi-diff);
   6. after the inner loop, the truncated SVD C = U S V^T and X^{n} = X U (Sec. 3.3).
 
-Readings (also implemented by the GPU library; each is listed in the design doc):
+Readings (also implemented by the GPU library):
   * X is empty at the start of every outer iteration and p initial angles are
     drawn at random (r_k = p k, Sec. 3.2 "Initial sampling");
   * "angles" in the sampling are the distinct (Omega_x, Omega_y) of the ordinate set:
