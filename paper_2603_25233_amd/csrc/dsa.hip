@@ -64,7 +64,7 @@ struct MgDev {
 struct DSA {
   Geom g;
   DevBuf<double> diag, ax, ay, minv, sig_s;  // [ncell][16] blocks, [ncell]
-  DevBuf<double> cc;                           // [14][ncell] the blocks' distinct entries
+  DevBuf<double> dcoef, sa;                    // [ncell] D = 1/(3 sigma_t), sigma_a
   DevBuf<double> mc;                           // [10][ncell] upper triangle of B^{-1}
   DevBuf<double> x, r, z, p0, p1, q, b;
   DevBuf<double> z1, t;                        // the preconditioner's smoothing passes
@@ -77,6 +77,8 @@ struct DSA {
   int ncoarse = 0;                             // its size (0: smoothing only)
   int lsmall = 0;                              // first level of the one-workgroup V-cycle
   DevBuf<MgDev> mgdev;                         // device views of every level
+  std::vector<int> small_off;                  // LDS offsets of the one-workgroup cycle
+  size_t small_lds = 0;                        // its LDS bytes (0: it runs on global memory)
 };
 
 // layout of the device scalar block
@@ -159,36 +161,138 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return r;
 }
 
-// acc = (A u)_c for cell c = (a, b) from the compact blocks:
-// cc[k][c], k < 14 = (B_00, B_11, B_22, B_33, B_01, B_02, X_00, X_01, X_10, X_11, Y_00, Y_01,
-// Y_10, Y_11) of cell c (one array per entry, so each load is contiguous over a wavefront):
-// the diagonal block B couples k with k ^ 1 (x-degree) through B_01 and with k ^ 2
-// (y-degree) through B_02; the coupling to the right neighbour is X (x) I on the x-degree,
-// to the top neighbour Y (x) I on the y-degree (DOF k = 2 q + p); the left and bottom
-// couplings are the neighbours' X^T and Y^T.  fetch(cell, v) gives u on a cell.
+// Workgroups are dealt to the eight XCDs in turn (workgroup b to XCD b mod 8), each with
+// its own L2.  This maps the n workgroups of a one-dimensional launch so that each XCD
+// runs a contiguous range: a cell's neighbours in the rows above and below then belong
+// to workgroups of the same XCD, and their loads hit its L2.  (A bijection of [0, n).)
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned n) {
+  const unsigned q = n / 8, r = n % 8, x = b % 8;
+  return x * q + min(x, r) + b / 8;
+}
+
+// Constants of the orthonormal Legendre basis across cells of width h: 1/h, the traces
+// l_0 = 1/sqrt(h) and |l_1| = sqrt(3)/sqrt(h) at the faces, the derivative
+// l_1' = 2 sqrt(3)/h^1.5, and the volume term 12/h^2 of the degree-1 function.
+struct Axis {
+  double ih, t0, t1, d1, vol;
+};
+Axis axis_of(double h) {
+  const double r3 = std::sqrt(3.0), sh = std::sqrt(h);
+  return Axis{1.0 / h, 1.0 / sh, r3 / sh, 2.0 * r3 / (h * sh), 12.0 / (h * h)};
+}
+
+// The 2 x 2 blocks of one interior face between a "-" cell (diffusion Dm) and a "+" cell
+// (Dp) in the basis of the direction across the face: Pm adds to the "-" cell's diagonal
+// block, Pp to the "+" cell's, C couples the "-" cell's test functions to the "+" cell's
+// trial functions (the terms of the assembly in dsa_blocks_kernel).
+__device__ __forceinline__ void face_blocks(double Dm, double Dp, const Axis& h, double Pm[2][2],
+                                            double Pp[2][2], double C[2][2]) {
+  const double eR[2] = {h.t0, h.t1}, eL[2] = {h.t0, -h.t1};
+  const double dd[2] = {0.0, h.d1};
+  const double kap = fmax(0.25, 0.5 * kCip * (Dm * h.ih + Dp * h.ih));
+  double jm[2], am[2], jp[2], ap[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    jm[i] = -eR[i];  // jump and average seen from the "-" cell
+    am[i] = 0.5 * Dm * dd[i];
+    jp[i] = eL[i];   // ... from the "+" cell
+    ap[i] = 0.5 * Dp * dd[i];
+  }
+  face2(Pm, kap, jm, jm, am, am);
+  face2(C, kap, jm, jp, am, ap);
+  face2(Pp, kap, jp, jp, ap, ap);
+}
+
+// The diagonal-block contribution of a boundary face (the "+" side if hi, else "-")
+__device__ __forceinline__ void boundary_block(double D, const Axis& h, bool hi, double P[2][2]) {
+  const double e[2] = {h.t0, hi ? h.t1 : -h.t1};
+  const double dd[2] = {0.0, h.d1};
+  const double kap = fmax(0.25, kCip * D * h.ih);
+  double dn[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) dn[i] = (hi ? 1.0 : -1.0) * D * dd[i];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) P[i][j] = kap * e[i] * e[j] - 0.5 * e[i] * dn[j] - 0.5 * dn[i] * e[j];
+}
+
+// The diffusion operator as the kernels see it: per-cell D = 1/(3 sigma_t) and
+// sigma_a = sigma_t - sigma_s; every block of a cell's row of A is formed from these.
+struct OpA {
+  int nx, ny;
+  Axis x, y;
+  const double* __restrict__ D;
+  const double* __restrict__ sa;
+};
+
+// Cell (a, b)'s row of A in compact form from D of the cell and its four neighbours
+// (dn[0..3] = left, right, bottom, top; unused where the neighbour is missing):
+// m[0..13] = (B_00, B_11, B_22, B_33, B_01, B_02, X_00, X_01, X_10, X_11, Y_00, Y_01, Y_10,
+// Y_11), with B the diagonal block (it couples DOF k = 2 q + p with k ^ 1 through B_01 and
+// with k ^ 2 through B_02), X (x) I the coupling to the right neighbour and Y (x) I to the
+// top one; xl and yb are the left and bottom neighbours' X and Y (the cell's couplings to
+// them are their transposes).  The diagonal entries sum the volume term and the faces
+// left, right, bottom, top in that order.
+__device__ __forceinline__ void cell_row(const OpA& op, int a, int b, double Dc, const double* dn,
+                                         double sa, double* m, double* xl, double* yb) {
+  double Pl[2][2], Pr[2][2], Qb[2][2], Qt[2][2], T[2][2], C[2][2];
+  double X[2][2] = {{0.0, 0.0}, {0.0, 0.0}}, Y[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  if (a > 0) {
+    face_blocks(dn[0], Dc, op.x, T, Pl, C);
+    xl[0] = C[0][0], xl[1] = C[0][1], xl[2] = C[1][0], xl[3] = C[1][1];
+  } else {
+    boundary_block(Dc, op.x, false, Pl);
+  }
+  if (a + 1 < op.nx) face_blocks(Dc, dn[1], op.x, Pr, T, X);
+  else boundary_block(Dc, op.x, true, Pr);
+  if (b > 0) {
+    face_blocks(dn[2], Dc, op.y, T, Qb, C);
+    yb[0] = C[0][0], yb[1] = C[0][1], yb[2] = C[1][0], yb[3] = C[1][1];
+  } else {
+    boundary_block(Dc, op.y, false, Qb);
+  }
+  if (b + 1 < op.ny) face_blocks(Dc, dn[3], op.y, Qt, T, Y);
+  else boundary_block(Dc, op.y, true, Qt);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int p = k & 1, q = k >> 1;
+    double v = sa + Dc * (p ? op.x.vol : 0.0) + Dc * (q ? op.y.vol : 0.0);
+    v += Pl[p][p];
+    v += Pr[p][p];
+    v += Qb[q][q];
+    v += Qt[q][q];
+    m[k] = v;
+  }
+  m[4] = Pl[0][1] + Pr[0][1];
+  m[5] = Qb[0][1] + Qt[0][1];
+  m[6] = X[0][0]; m[7] = X[0][1]; m[8] = X[1][0]; m[9] = X[1][1];
+  m[10] = Y[0][0]; m[11] = Y[0][1]; m[12] = Y[1][0]; m[13] = Y[1][1];
+}
+
+// acc = (A u)_c for cell c = (a, b) from its row (cell_row); fetch(cell, v) gives u on a
+// neighbouring cell.
 template <class F>
-__device__ __forceinline__ void block_apply(const double* __restrict__ cc, long ncell, int nx, int ny,
-                                            long c, int a, int b, const double* u, F fetch,
-                                            double* acc) {
-  auto m = [&](int k) { return cc[(long)k * ncell + c]; };
+__device__ __forceinline__ void block_apply(const double* m, const double* xl, const double* yb,
+                                            int nx, int ny, long c, int a, int b, const double* u,
+                                            F fetch, double* acc) {
   double nb[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) acc[k] = m(k) * u[k] + m(4) * u[k ^ 1] + m(5) * u[k ^ 2];
+  for (int k = 0; k < 4; ++k) acc[k] = m[k] * u[k] + m[4] * u[k ^ 1] + m[5] * u[k ^ 2];
   if (a + 1 < nx) {  // X (x) I: acc[2q + p] += X[p][.] nb[2q + .]
     fetch(c + 1, nb);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int p = k & 1, qb = k & 2;
-      acc[k] += m(6 + 2 * p) * nb[qb] + m(7 + 2 * p) * nb[qb + 1];
+      acc[k] += m[6 + 2 * p] * nb[qb] + m[7 + 2 * p] * nb[qb + 1];
     }
   }
   if (a > 0) {  // the left neighbour's X^T
-    auto ml = [&](int k) { return cc[(long)k * ncell + c - 1]; };
     fetch(c - 1, nb);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int p = k & 1, qb = k & 2;
-      acc[k] += ml(6 + p) * nb[qb] + ml(8 + p) * nb[qb + 1];
+      acc[k] += xl[p] * nb[qb] + xl[2 + p] * nb[qb + 1];
     }
   }
   if (b + 1 < ny) {  // Y (x) I: acc[2q + p] += Y[q][.] nb[2 . + p]
@@ -196,16 +300,15 @@ __device__ __forceinline__ void block_apply(const double* __restrict__ cc, long 
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int p = k & 1, qq = k >> 1;
-      acc[k] += m(10 + 2 * qq) * nb[p] + m(11 + 2 * qq) * nb[2 + p];
+      acc[k] += m[10 + 2 * qq] * nb[p] + m[11 + 2 * qq] * nb[2 + p];
     }
   }
   if (b > 0) {  // the bottom neighbour's Y^T
-    auto mb = [&](int k) { return cc[(long)k * ncell + c - nx]; };
     fetch(c - nx, nb);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int p = k & 1, qq = k >> 1;
-      acc[k] += mb(10 + qq) * nb[p] + mb(12 + qq) * nb[2 + p];
+      acc[k] += yb[qq] * nb[p] + yb[2 + qq] * nb[2 + p];
     }
   }
 }
@@ -225,14 +328,16 @@ __device__ __forceinline__ void binv_apply(const double* __restrict__ mc, long n
 
 // p_new = z + beta p_old (on the fly for the neighbours), q = A p_new, part = p.q
 __global__ __launch_bounds__(256) void spmv_kernel(
-    int nx, int ny, const double* __restrict__ cc, const double* __restrict__ z,
-    const double* __restrict__ pold, double* __restrict__ pnew, double* __restrict__ q,
-    double* __restrict__ part, const double* __restrict__ sc) {
+    OpA op, const double* __restrict__ z, const double* __restrict__ pold,
+    double* __restrict__ pnew, double* __restrict__ q, double* __restrict__ part,
+    const double* __restrict__ sc) {
   __shared__ double red[256];
   if (sc[S_DONE] != 0.0) return;
   const double beta = sc[S_BETA];
+  const int nx = op.nx, ny = op.ny;
   const long ncell = (long)nx * ny;
-  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  const long c = (long)blk * blockDim.x + threadIdx.x;
   double dot = 0.0;
   if (c < ncell) {
     const int a = (int)(c % nx), b = (int)(c / nx);
@@ -240,9 +345,13 @@ __global__ __launch_bounds__(256) void spmv_kernel(
 #pragma unroll
       for (int k = 0; k < 4; ++k) o[k] = z[4 * cc2 + k] + beta * pold[4 * cc2 + k];
     };
+    const double dn[4] = {a > 0 ? op.D[c - 1] : 0.0, a + 1 < nx ? op.D[c + 1] : 0.0,
+                          b > 0 ? op.D[c - nx] : 0.0, b + 1 < ny ? op.D[c + nx] : 0.0};
+    double m[14], xl[4], yb[4];
+    cell_row(op, a, b, op.D[c], dn, op.sa[c], m, xl, yb);
     double u[4], acc[4];
     pv(c, u);
-    block_apply(cc, ncell, nx, ny, c, a, b, u, pv, acc);
+    block_apply(m, xl, yb, nx, ny, c, a, b, u, pv, acc);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       pnew[4 * c + k] = u[k];
@@ -251,30 +360,25 @@ __global__ __launch_bounds__(256) void spmv_kernel(
     }
   }
   const double s = block_sum(dot, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  if (threadIdx.x == 0) part[blk] = s;
 }
 
-// The 14 distinct entries of a cell's blocks (see spmv_kernel) from the full 4 x 4 blocks.
-__global__ __launch_bounds__(256) void dsa_compact_kernel(long ncell, const double* __restrict__ diag,
-                                                         const double* __restrict__ ax,
-                                                         const double* __restrict__ ay,
-                                                         const double* __restrict__ minv,
-                                                         double* __restrict__ cc,
-                                                         double* __restrict__ mc) {
+// The symmetric inverse diagonal blocks as their upper triangles (one array per entry),
+// and the per-cell D and sigma_a the operator's rows are formed from.
+__global__ __launch_bounds__(256) void dsa_compact_kernel(long ncell, const double* __restrict__ minv,
+                                                         const double* __restrict__ sigma_t,
+                                                         const double* __restrict__ sigma_s,
+                                                         double* __restrict__ mc,
+                                                         double* __restrict__ D,
+                                                         double* __restrict__ sa) {
   const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncell) return;
-  const double* B = diag + 16 * c;
-  const double* X = ax + 16 * c;  // X (x) I: entry (p, p') at (2q + p) 4 + 2q + p', q = 0
-  const double* Y = ay + 16 * c;  // Y (x) I: entry (q, q') at 2q 4 + 2q', p = 0
-  const double v[14] = {B[0], B[5], B[10], B[15], B[1], B[2],
-                        X[0], X[1], X[4], X[5], Y[0], Y[2], Y[8], Y[10]};
-#pragma unroll
-  for (int k = 0; k < 14; ++k) cc[(long)k * ncell + c] = v[k];
-  // the inverse diagonal block (symmetric) as its upper triangle, one array per entry
   const double* M = minv + 16 * c;
   const double w[10] = {M[0], M[1], M[2], M[3], M[5], M[6], M[7], M[10], M[11], M[15]};
 #pragma unroll
   for (int k = 0; k < 10; ++k) mc[(long)k * ncell + c] = w[k];
+  D[c] = 1.0 / (3.0 * sigma_t[c]);
+  sa[c] = sigma_t[c] - sigma_s[c];
 }
 
 // sums nblk partials in a fixed order into sc[slot]
@@ -507,12 +611,30 @@ __global__ __launch_bounds__(256) void mg_restrict_kernel(int mxf, int myf,
   bc[n] = s;
 }
 
-// V-cycle of the levels l0 .. nlev-1 by one workgroup (the small grids, whose data stay
-// in L2): the same steps as the multi-kernel cycle, separated by workgroup barriers.
+// V-cycle of the levels l0 .. nlev-1 by one workgroup (the small grids): the same steps
+// as the multi-kernel cycle, separated by workgroup barriers.  Where the levels fit, the
+// workgroup first copies their stencils, smoothers and the right-hand side of level l0 into
+// LDS (with the coarsest grid's dense inverse if there is room), runs every step on LDS
+// and writes only level l0's solution back; otherwise the steps read and write the levels
+// in global memory.  Both forms do the same arithmetic in the same order.
 constexpr int kSmallThreads = 1024;
 constexpr long kSmallNodes = 1100;  // grids this small run inside the one workgroup
+constexpr int kMaxSmallLevels = 8;
+constexpr int kCoarseDense = 100;   // largest grid solved by its dense inverse
+constexpr int kCoarseSweeps = 20;   // l1-Jacobi sweeps on a coarsest grid that is larger
 
-__device__ void sm_jacobi(const MgDev& L, const double* x, double* out) {
+// LDS byte offsets of one level's arrays (-1: not held; the dense coarsest grid needs only
+// b and x)
+struct SmallLevel {
+  int mx, my, oA, od, ob, ox, ot;
+};
+struct SmallPlan {
+  int nl;     // levels l0 .. l0 + nl - 1
+  int ocinv;  // dense inverse in LDS at this offset, or -1
+  SmallLevel lv[kMaxSmallLevels];
+};
+
+__device__ __forceinline__ void sm_jacobi(const MgDev& L, const double* x, double* out) {
   const long n = (long)L.mx * L.my;
   for (long k = threadIdx.x; k < n; k += blockDim.x) {
     const int i = (int)(k % L.mx), j = (int)(k / L.mx);
@@ -522,15 +644,74 @@ __device__ void sm_jacobi(const MgDev& L, const double* x, double* out) {
   __syncthreads();
 }
 
+// n elements of 4 bytes (float) or 8 (double) into LDS, 16 bytes per load where aligned
+template <class T>
+__device__ __forceinline__ void copy_to_lds(T* __restrict__ dst, const T* __restrict__ src, long n) {
+  constexpr int kv = 16 / sizeof(T);
+  const long nv = ((reinterpret_cast<uintptr_t>(src) & 15) == 0) ? n / kv : 0;
+  const float4* s4 = reinterpret_cast<const float4*>(src);
+  float4* d4 = reinterpret_cast<float4*>(dst);
+#pragma unroll 4
+  for (long k = threadIdx.x; k < nv; k += blockDim.x) d4[k] = s4[k];
+  for (long k = nv * kv + threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
+}
+
+// red[8 i + u] = sum over j = u (mod 8) of the whole blocks of eight of ci[j][i] b[j], the
+// tail j >= 8 floor(nc / 8) added to u = 0 (the dense inverse is symmetric: column i is
+// read as row i)
+__device__ __forceinline__ void coarse_terms(const double* __restrict__ ci,
+                                             const double* __restrict__ b, int nc,
+                                             double* __restrict__ red) {
+  const int nb8 = nc / 8 * 8;
+  for (int e = threadIdx.x; e < 8 * nc; e += blockDim.x) {
+    const int i = e >> 3, u = e & 7;
+    double s = 0.0;
+    for (int j = u; j < nb8; j += 8) s += ci[(long)j * nc + i] * b[j];
+    if (u == 0)
+      for (int j = nb8; j < nc; ++j) s += ci[(long)j * nc + i] * b[j];
+    red[e] = s;
+  }
+}
+
+template <bool kLds>
 __global__ __launch_bounds__(kSmallThreads) void mg_small_kernel(const MgDev* __restrict__ lv,
                                                                  int l0, int nlev,
                                                                  const double* __restrict__ cinv,
                                                                  int nc, int coarse_sweeps,
+                                                                 SmallPlan plan,
                                                                  const double* __restrict__ sc) {
+  extern __shared__ __align__(16) unsigned char sm_small[];
+  __shared__ double red[8 * kCoarseDense];
   if (sc[S_DONE] != 0.0) return;
+  // the view of level l the steps work on
+  auto level = [&](int l) {
+    MgDev v = lv[l];
+    if constexpr (kLds) {
+      const SmallLevel& P = plan.lv[l - l0];
+      v.A9 = P.oA >= 0 ? reinterpret_cast<const float*>(sm_small + P.oA) : nullptr;
+      v.dinv = P.od >= 0 ? reinterpret_cast<const double*>(sm_small + P.od) : nullptr;
+      v.b = reinterpret_cast<double*>(sm_small + P.ob);
+      v.x = reinterpret_cast<double*>(sm_small + P.ox);
+      v.t = P.ot >= 0 ? reinterpret_cast<double*>(sm_small + P.ot) : nullptr;
+    }
+    return v;
+  };
+  if constexpr (kLds) {
+    for (int l = l0; l < nlev; ++l) {
+      const MgDev G = lv[l];
+      const SmallLevel& P = plan.lv[l - l0];
+      const long n = (long)G.mx * G.my;
+      if (P.oA >= 0) copy_to_lds(reinterpret_cast<float*>(sm_small + P.oA), G.A9, 9 * n);
+      if (P.od >= 0) copy_to_lds(reinterpret_cast<double*>(sm_small + P.od), G.dinv, n);
+      if (l == l0) copy_to_lds(reinterpret_cast<double*>(sm_small + P.ob), G.b, n);
+    }
+    if (plan.ocinv >= 0)
+      copy_to_lds(reinterpret_cast<double*>(sm_small + plan.ocinv), cinv, (long)nc * nc);
+    __syncthreads();
+  }
   // down: pre-smoothing, residual, restriction
   for (int l = l0; l + 1 < nlev; ++l) {
-    const MgDev L = lv[l], C = lv[l + 1];
+    const MgDev L = level(l), C = level(l + 1);
     sm_jacobi(L, nullptr, L.t);
     sm_jacobi(L, L.t, L.x);
     const long n = (long)L.mx * L.my;
@@ -556,17 +737,18 @@ __global__ __launch_bounds__(kSmallThreads) void mg_small_kernel(const MgDev* __
     }
     __syncthreads();
   }
-  // coarsest grid
+  // coarsest grid: x = A^{-1} b by the dense inverse (eight lanes per node, then the eight
+  // sums paired), or l1-Jacobi sweeps
   {
-    const MgDev C = lv[nlev - 1];
+    const MgDev C = level(nlev - 1);
     if (nc > 0) {
+      if (kLds && plan.ocinv >= 0)
+        coarse_terms(reinterpret_cast<const double*>(sm_small + plan.ocinv), C.b, nc, red);
+      else
+        coarse_terms(cinv, C.b, nc, red);
+      __syncthreads();
       for (int i = threadIdx.x; i < nc; i += blockDim.x) {
-        double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        int j = 0;
-        for (; j + 8 <= nc; j += 8)
-#pragma unroll
-          for (int u = 0; u < 8; ++u) s[u] += cinv[(long)(j + u) * nc + i] * C.b[j + u];
-        for (; j < nc; ++j) s[0] += cinv[(long)j * nc + i] * C.b[j];
+        const double* s = red + 8 * i;
         C.x[i] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
       }
       __syncthreads();
@@ -580,7 +762,7 @@ __global__ __launch_bounds__(kSmallThreads) void mg_small_kernel(const MgDev* __
   }
   // up: prolongation, post-smoothing
   for (int l = nlev - 2; l >= l0; --l) {
-    const MgDev L = lv[l], C = lv[l + 1];
+    const MgDev L = level(l), C = level(l + 1);
     const long n = (long)L.mx * L.my;
     for (long k = threadIdx.x; k < n; k += blockDim.x) {
       const int i = (int)(k % L.mx), j = (int)(k / L.mx);
@@ -592,6 +774,11 @@ __global__ __launch_bounds__(kSmallThreads) void mg_small_kernel(const MgDev* __
     sm_jacobi(L, L.x, L.t);
     sm_jacobi(L, L.t, L.x);
   }
+  if constexpr (kLds) {  // level l0's solution for the next finer level's prolongation
+    const MgDev L = level(l0), G = lv[l0];
+    const long n = (long)L.mx * L.my;
+    for (long k = threadIdx.x; k < n; k += blockDim.x) G.x[k] = L.x[k];
+  }
 }
 
 // b0 = P^T r: node (i, j) collects corner (i - a, j - b) of each adjacent cell (a, b)
@@ -601,7 +788,7 @@ __global__ __launch_bounds__(256) void dg_restrict_kernel(int nx, int ny, Emb em
                                                          const double* __restrict__ sc) {
   if (sc[S_DONE] != 0.0) return;
   const int mx = nx + 1, my = ny + 1;
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long n = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (n >= (long)mx * my) return;
   const int i = (int)(n % mx), j = (int)(n / mx);
   double s = 0.0;
@@ -632,32 +819,57 @@ dim3 cell_tiles(int nx, int ny) {
   return dim3((unsigned)((nx + kCX - 1) / kCX), (unsigned)((ny + kCY - 1) / kCY));
 }
 
-// fills tile[(kCH)(kCW)][4] with f(cell, out) on the block's cells and their ring
+// fills tile[(kCH)(kCW)][4] with f(cell, out) and dtile[(kCH)(kCW)] with D on the block's
+// cells and their ring
 template <class F>
-__device__ __forceinline__ void fill_cell_tile(double* tile, int nx, int ny, F f) {
+__device__ __forceinline__ void fill_cell_tile(double* tile, double* dtile, const double* D,
+                                               int nx, int ny, F f) {
   const int a0 = (int)blockIdx.x * kCX - 1, b0 = (int)blockIdx.y * kCY - 1;
   for (int e = threadIdx.x; e < kCW * kCH; e += blockDim.x) {
     const int a = a0 + e % kCW, b = b0 + e / kCW;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    if (a >= 0 && a < nx && b >= 0 && b < ny) f((long)b * nx + a, v);
+    double dv = 0.0;
+    if (a >= 0 && a < nx && b >= 0 && b < ny) {
+      f((long)b * nx + a, v);
+      dv = D[(long)b * nx + a];
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) tile[4 * e + k] = v[k];
+    dtile[e] = dv;
   }
   __syncthreads();
 }
 
+// (A u)_c of tile cell e0 (cell c = (a, b)) from the tile of u and of D
+__device__ __forceinline__ void tile_apply(const OpA& op, const double* tile, const double* dtile,
+                                           int e0, long c, int a, int b, double* u, double* acc) {
+  auto fetch = [&](long c2, double* o) {  // the tile entry of a neighbour of c
+    const long d = c2 - c;
+    const int e = d == op.nx ? e0 + kCW : d == -op.nx ? e0 - kCW : d == 1 ? e0 + 1 : e0 - 1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = tile[4 * e + k];
+  };
+  const double dn[4] = {dtile[e0 - 1], dtile[e0 + 1], dtile[e0 - kCW], dtile[e0 + kCW]};
+  double m[14], xl[4], yb[4];
+  cell_row(op, a, b, dtile[e0], dn, op.sa[c], m, xl, yb);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) u[k] = tile[4 * e0 + k];
+  block_apply(m, xl, yb, op.nx, op.ny, c, a, b, u, fetch, acc);
+}
+
 // First: z1 = S r, t = r - A z1.
-__global__ __launch_bounds__(kCX * kCY) void dg_smooth1_kernel(int nx, int ny,
-                                                              const double* __restrict__ cc,
+__global__ __launch_bounds__(kCX * kCY) void dg_smooth1_kernel(OpA op,
                                                               const double* __restrict__ mc,
                                                               const double* __restrict__ r, double w,
                                                               double* __restrict__ z1,
                                                               double* __restrict__ t,
                                                               const double* __restrict__ sc) {
   __shared__ double tile[4 * kCW * kCH];
+  __shared__ double dtile[kCW * kCH];
   if (sc[S_DONE] != 0.0) return;
+  const int nx = op.nx, ny = op.ny;
   const long ncell = (long)nx * ny;
-  fill_cell_tile(tile, nx, ny, [&](long c2, double* o) {
+  fill_cell_tile(tile, dtile, op.D, nx, ny, [&](long c2, double* o) {
     double v[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] = r[4 * c2 + k];
@@ -669,17 +881,8 @@ __global__ __launch_bounds__(kCX * kCY) void dg_smooth1_kernel(int nx, int ny,
   const int a = (int)blockIdx.x * kCX + lx, b = (int)blockIdx.y * kCY + ly;
   if (a >= nx || b >= ny) return;
   const long c = (long)b * nx + a;
-  const int e0 = (ly + 1) * kCW + lx + 1;
-  auto fetch = [&](long c2, double* o) {  // the tile entry of a neighbour of c
-    const long d = c2 - c;
-    const int e = d == nx ? e0 + kCW : d == -nx ? e0 - kCW : d == 1 ? e0 + 1 : e0 - 1;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) o[k] = tile[4 * e + k];
-  };
   double u[4], acc[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) u[k] = tile[4 * e0 + k];
-  block_apply(cc, ncell, nx, ny, c, a, b, u, fetch, acc);
+  tile_apply(op, tile, dtile, (ly + 1) * kCW + lx + 1, c, a, b, u, acc);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     z1[4 * c + k] = u[k];
@@ -689,8 +892,7 @@ __global__ __launch_bounds__(kCX * kCY) void dg_smooth1_kernel(int nx, int ny,
 
 // Second: z2 = z1 + P x0 (the prolonged coarse correction), z = z2 + S (r - A z2);
 // part1 = r.z per tile.
-__global__ __launch_bounds__(kCX * kCY) void dg_smooth2_kernel(int nx, int ny, Emb em,
-                                                              const double* __restrict__ cc,
+__global__ __launch_bounds__(kCX * kCY) void dg_smooth2_kernel(OpA op, Emb em,
                                                               const double* __restrict__ mc,
                                                               const double* __restrict__ r,
                                                               const double* __restrict__ z1,
@@ -699,11 +901,13 @@ __global__ __launch_bounds__(kCX * kCY) void dg_smooth2_kernel(int nx, int ny, E
                                                               double* __restrict__ part1,
                                                               const double* __restrict__ sc) {
   __shared__ double tile[4 * kCW * kCH];
+  __shared__ double dtile[kCW * kCH];
   __shared__ double red[kCX * kCY];
   if (sc[S_DONE] != 0.0) return;
+  const int nx = op.nx, ny = op.ny;
   const long ncell = (long)nx * ny;
   const int mx = nx + 1;
-  fill_cell_tile(tile, nx, ny, [&](long c2, double* o) {
+  fill_cell_tile(tile, dtile, op.D, nx, ny, [&](long c2, double* o) {
     const int a2 = (int)(c2 % nx), b2 = (int)(c2 / nx);
     double u[4];
 #pragma unroll
@@ -723,17 +927,8 @@ __global__ __launch_bounds__(kCX * kCY) void dg_smooth2_kernel(int nx, int ny, E
   double rz = 0.0;
   if (a < nx && b < ny) {
     const long c = (long)b * nx + a;
-    const int e0 = (ly + 1) * kCW + lx + 1;
-    auto fetch = [&](long c2, double* o) {
-      const long d = c2 - c;
-      const int e = d == nx ? e0 + kCW : d == -nx ? e0 - kCW : d == 1 ? e0 + 1 : e0 - 1;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) o[k] = tile[4 * e + k];
-    };
     double u[4], acc[4], tv[4], st[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) u[k] = tile[4 * e0 + k];
-    block_apply(cc, ncell, nx, ny, c, a, b, u, fetch, acc);
+    tile_apply(op, tile, dtile, (ly + 1) * kCW + lx + 1, c, a, b, u, acc);
 #pragma unroll
     for (int k = 0; k < 4; ++k) tv[k] = r[4 * c + k] - acc[k];
     binv_apply(mc, ncell, c, tv, st);
@@ -1018,8 +1213,6 @@ __global__ void to_float_kernel(long n, const double* __restrict__ a, float* __r
 }
 
 // ------------------------------------------------------------ set-up
-constexpr int kCoarseDense = 100;  // largest grid solved by its dense inverse
-constexpr int kCoarseSweeps = 20;  // l1-Jacobi sweeps on a coarsest grid that is larger
 
 Emb embedding(const Geom& g) {
   const double r3 = std::sqrt(3.0);
@@ -1083,6 +1276,49 @@ std::vector<double> coarse_inverse(const std::vector<double>& A, int mx, int my)
 
 }  // namespace
 
+// LDS bytes one workgroup may use on the current device
+size_t max_lds_bytes() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+    return 65536;
+  return (size_t)v;
+}
+
+// LDS layout of the one-workgroup cycle (levels lsmall .. end): b and x of every level,
+// stencil, smoother and scratch vector of every level but a dense-solved coarsest, then
+// the dense inverse if it still fits.  small_lds stays 0 when the levels do not fit.
+void plan_small_cycle(DSA* d, size_t budget) {
+  const int nl = (int)d->mg.size() - d->lsmall;
+  d->small_off.assign(7 * kMaxSmallLevels + 1, -1);
+  d->small_lds = 0;
+  if (nl > kMaxSmallLevels) return;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 15) & ~(size_t)15;
+    return (int)o;
+  };
+  for (int i = 0; i < nl; ++i) {
+    const MgLevel& L = *d->mg[d->lsmall + i];
+    const size_t n = (size_t)L.mx * L.my;
+    int* o = &d->small_off[7 * i];
+    o[0] = L.mx;
+    o[1] = L.my;
+    o[4] = take(8 * n);  // b
+    o[5] = take(8 * n);  // x
+    if (!(i == nl - 1 && d->ncoarse > 0)) {
+      o[2] = take(4 * 9 * n);  // stencils (FP32)
+      o[3] = take(8 * n);      // l1-Jacobi weights
+      o[6] = take(8 * n);      // scratch vector
+    }
+  }
+  if (off > budget) return;
+  const size_t nci = (size_t)d->ncoarse * d->ncoarse * 8;
+  if (d->ncoarse > 0 && off + nci <= budget) d->small_off[7 * kMaxSmallLevels] = take(nci);
+  d->small_lds = off;
+}
+
 // The blocks, the nodal hierarchy and its smoothers are assembled on the device; only
 // the coarsest grid (at most kCoarseDense nodes) is inverted on the host.
 DSA* dsa_create(const Geom& g, const double* sigma_t_dev, const double* sigma_s_dev,
@@ -1097,10 +1333,11 @@ DSA* dsa_create(const Geom& g, const double* sigma_t_dev, const double* sigma_s_
     hipLaunchKernelGGL(dsa_blocks_kernel, dim3(nblocks(n)), dim3(256), 0, st, g.nx, g.ny, g.hx,
                        g.hy, sigma_t_dev, sigma_s_dev, d->diag.get(), d->ax.get(), d->ay.get(),
                        d->minv.get(), bad.get());
-    d->cc.alloc(14 * n);
     d->mc.alloc(10 * n);
-    hipLaunchKernelGGL(dsa_compact_kernel, dim3(nblocks(n)), dim3(256), 0, st, n, d->diag.get(),
-                       d->ax.get(), d->ay.get(), d->minv.get(), d->cc.get(), d->mc.get());
+    d->dcoef.alloc(n);
+    d->sa.alloc(n);
+    hipLaunchKernelGGL(dsa_compact_kernel, dim3(nblocks(n)), dim3(256), 0, st, n, d->minv.get(),
+                       sigma_t_dev, sigma_s_dev, d->mc.get(), d->dcoef.get(), d->sa.get());
     // grid hierarchy: vertex-centred halving while both node counts allow it
     std::vector<std::pair<int, int>> dims{{g.nx + 1, g.ny + 1}};
     while (true) {
@@ -1160,6 +1397,7 @@ DSA* dsa_create(const Geom& g, const double* sigma_t_dev, const double* sigma_s_
     d->lsmall = (int)d->mg.size() - 1;
     while (d->lsmall > 0 && (long)d->mg[d->lsmall - 1]->mx * d->mg[d->lsmall - 1]->my <= kSmallNodes)
       --d->lsmall;
+    plan_small_cycle(d, max_lds_bytes() - sizeof(double) * 8 * kCoarseDense);
     std::vector<MgDev> views;
     for (auto& L : d->mg)
       views.push_back(MgDev{L->mx, L->my, L->A9c.get(), L->dinv.get(), L->x.get(), L->b.get(), L->t.get()});
@@ -1191,13 +1429,30 @@ void dsa_destroy(DSA* d) { delete d; }
 
 namespace {
 
+OpA op_of(const DSA* d) {
+  return OpA{d->g.nx, d->g.ny, axis_of(d->g.hx), axis_of(d->g.hy), d->dcoef.get(), d->sa.get()};
+}
+
 // one V-cycle on level l (x = V b), two l1-Jacobi sweeps before and after
 void vcycle(DSA* d, int l, hipStream_t st) {
   MgLevel& L = *d->mg[l];
   const double* sc = d->scal.get();
   if (l == d->lsmall) {
-    hipLaunchKernelGGL(mg_small_kernel, dim3(1), dim3(kSmallThreads), 0, st, d->mgdev.get(), l,
-                       (int)d->mg.size(), d->cinv.get(), d->ncoarse, kCoarseSweeps, sc);
+    SmallPlan P{};
+    P.nl = (int)d->mg.size() - l;
+    P.ocinv = d->small_off[7 * kMaxSmallLevels];
+    for (int i = 0; i < P.nl && i < kMaxSmallLevels; ++i) {
+      const int* o = &d->small_off[7 * i];
+      P.lv[i] = SmallLevel{o[0], o[1], o[2], o[3], o[4], o[5], o[6]};
+    }
+    if (d->small_lds > 0)
+      hipLaunchKernelGGL(mg_small_kernel<true>, dim3(1), dim3(kSmallThreads), d->small_lds, st,
+                         d->mgdev.get(), l, (int)d->mg.size(), d->cinv.get(), d->ncoarse,
+                         kCoarseSweeps, P, sc);
+    else
+      hipLaunchKernelGGL(mg_small_kernel<false>, dim3(1), dim3(kSmallThreads), 0, st,
+                         d->mgdev.get(), l, (int)d->mg.size(), d->cinv.get(), d->ncoarse,
+                         kCoarseSweeps, P, sc);
     return;
   }
   const dim3 nb = tile_grid(L.mx, L.my);
@@ -1228,14 +1483,14 @@ void precondition(DSA* d, const double* r, double* z, hipStream_t st) {
   const Emb em = embedding(g);
   const double* sc = d->scal.get();
   MgLevel& L0 = *d->mg[0];
-  hipLaunchKernelGGL(dg_smooth1_kernel, cell_tiles(g.nx, g.ny), dim3(kCX * kCY), 0, st, g.nx, g.ny,
-                     d->cc.get(), d->mc.get(), r, kSmoothW, d->z1.get(), d->t.get(), sc);
+  const OpA op = op_of(d);
+  hipLaunchKernelGGL(dg_smooth1_kernel, cell_tiles(g.nx, g.ny), dim3(kCX * kCY), 0, st, op,
+                     d->mc.get(), r, kSmoothW, d->z1.get(), d->t.get(), sc);
   hipLaunchKernelGGL(dg_restrict_kernel, dim3(nblocks((long)L0.mx * L0.my)), dim3(256), 0, st, g.nx,
                      g.ny, em, d->t.get(), L0.b.get(), sc);
   vcycle(d, 0, st);
-  hipLaunchKernelGGL(dg_smooth2_kernel, cell_tiles(g.nx, g.ny), dim3(kCX * kCY), 0, st, g.nx, g.ny, em,
-                     d->cc.get(), d->mc.get(), r, d->z1.get(), L0.x.get(), kSmoothW, z, d->part1.get(),
-                     sc);
+  hipLaunchKernelGGL(dg_smooth2_kernel, cell_tiles(g.nx, g.ny), dim3(kCX * kCY), 0, st, op, em,
+                     d->mc.get(), r, d->z1.get(), L0.x.get(), kSmoothW, z, d->part1.get(), sc);
 }
 
 }  // namespace
@@ -1261,8 +1516,8 @@ int dsa_apply(DSA* d, const double* phi_star, const double* phi_prev, double* ph
   int it = 0;
   for (; it < max_iter; it += chunk) {
     for (int k = 0; k < chunk; ++k) {
-      hipLaunchKernelGGL(spmv_kernel, dim3(nb), dim3(256), 0, st, g.nx, g.ny, d->cc.get(),
-                         d->z.get(), pold, pnew, d->q.get(), d->part1.get(), sc);
+      hipLaunchKernelGGL(spmv_kernel, dim3(nb), dim3(256), 0, st, op_of(d), d->z.get(), pold,
+                         pnew, d->q.get(), d->part1.get(), sc);
       hipLaunchKernelGGL(reduce_alpha_kernel, dim3(1), dim3(1024), 0, st, d->part1.get(), nb, sc);
       hipLaunchKernelGGL(update_r_kernel, dim3(nb), dim3(256), 0, st, n, pnew, d->q.get(),
                          d->x.get(), d->r.get(), d->part2.get(), sc);
