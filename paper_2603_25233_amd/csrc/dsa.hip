@@ -26,11 +26,13 @@
 // per iteration.
 // Layout for the bandwidth-bound CG iteration: the blocks are Kronecker sums (an x-face
 // couples only the x-degrees, a y-face only the y-degrees, the volume term is diagonal),
-// so the matrix product reads 14 numbers per cell (the diagonal block's 4 diagonal
-// entries and its two off-diagonal couplings, a 2 x 2 x-coupling and a 2 x 2 y-coupling)
-// instead of three 4 x 4 blocks; the V-cycle reads its stencils in FP32 (the Galerkin
-// hierarchy is built in FP64 and rounded once, so the cycle stays a fixed symmetric
-// operator, as CG needs; every sum is FP64).
+// so a cell's row of A is 14 numbers (the diagonal block's 4 diagonal entries and its two
+// off-diagonal couplings, a 2 x 2 x-coupling and a 2 x 2 y-coupling), and these follow in
+// closed form from D of the cell and its four neighbours and sigma_a of the cell: the
+// matrix products read those two numbers per cell and form the row in registers instead
+// of reading stored blocks.  The preconditioner's inverse diagonal blocks and the
+// V-cycle's stencils are read in FP32 (built in FP64 and rounded once, so the
+// preconditioner stays a fixed symmetric operator, as CG needs; every sum is FP64).
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -65,7 +67,7 @@ struct DSA {
   Geom g;
   DevBuf<double> diag, ax, ay, minv, sig_s;  // [ncell][16] blocks, [ncell]
   DevBuf<double> dcoef, sa;                    // [ncell] D = 1/(3 sigma_t), sigma_a
-  DevBuf<double> mc;                           // [10][ncell] upper triangle of B^{-1}
+  DevBuf<float> mc;                            // [10][ncell] upper triangle of B^{-1} (FP32)
   DevBuf<double> x, r, z, p0, p1, q, b;
   DevBuf<double> z1, t;                        // the preconditioner's smoothing passes
   DevBuf<double> part1, part2;                 // per-block partial sums
@@ -314,12 +316,13 @@ __device__ __forceinline__ void block_apply(const double* m, const double* xl, c
 }
 
 // out = B_c^{-1} v from the upper triangle of the symmetric inverse block
-// (mc[k][c], row-major 00 01 02 03 11 12 13 22 23 33)
-__device__ __forceinline__ void binv_apply(const double* __restrict__ mc, long ncell, long c,
+// (mc[k][c], row-major 00 01 02 03 11 12 13 22 23 33), stored in FP32: the smoother is
+// w B^{-1} rounded once, still a fixed symmetric operator (the sums are FP64)
+__device__ __forceinline__ void binv_apply(const float* __restrict__ mc, long ncell, long c,
                                            const double* v, double* out) {
   double m[10];
 #pragma unroll
-  for (int k = 0; k < 10; ++k) m[k] = mc[(long)k * ncell + c];
+  for (int k = 0; k < 10; ++k) m[k] = (double)mc[(long)k * ncell + c];
   out[0] = m[0] * v[0] + m[1] * v[1] + m[2] * v[2] + m[3] * v[3];
   out[1] = m[1] * v[0] + m[4] * v[1] + m[5] * v[2] + m[6] * v[3];
   out[2] = m[2] * v[0] + m[5] * v[1] + m[7] * v[2] + m[8] * v[3];
@@ -363,12 +366,12 @@ __global__ __launch_bounds__(256) void spmv_kernel(
   if (threadIdx.x == 0) part[blk] = s;
 }
 
-// The symmetric inverse diagonal blocks as their upper triangles (one array per entry),
-// and the per-cell D and sigma_a the operator's rows are formed from.
+// The symmetric inverse diagonal blocks as their upper triangles (one FP32 array per
+// entry), and the per-cell D and sigma_a the operator's rows are formed from.
 __global__ __launch_bounds__(256) void dsa_compact_kernel(long ncell, const double* __restrict__ minv,
                                                          const double* __restrict__ sigma_t,
                                                          const double* __restrict__ sigma_s,
-                                                         double* __restrict__ mc,
+                                                         float* __restrict__ mc,
                                                          double* __restrict__ D,
                                                          double* __restrict__ sa) {
   const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -376,7 +379,7 @@ __global__ __launch_bounds__(256) void dsa_compact_kernel(long ncell, const doub
   const double* M = minv + 16 * c;
   const double w[10] = {M[0], M[1], M[2], M[3], M[5], M[6], M[7], M[10], M[11], M[15]};
 #pragma unroll
-  for (int k = 0; k < 10; ++k) mc[(long)k * ncell + c] = w[k];
+  for (int k = 0; k < 10; ++k) mc[(long)k * ncell + c] = (float)w[k];
   D[c] = 1.0 / (3.0 * sigma_t[c]);
   sa[c] = sigma_t[c] - sigma_s[c];
 }
@@ -859,7 +862,7 @@ __device__ __forceinline__ void tile_apply(const OpA& op, const double* tile, co
 
 // First: z1 = S r, t = r - A z1.
 __global__ __launch_bounds__(kCX * kCY) void dg_smooth1_kernel(OpA op,
-                                                              const double* __restrict__ mc,
+                                                              const float* __restrict__ mc,
                                                               const double* __restrict__ r, double w,
                                                               double* __restrict__ z1,
                                                               double* __restrict__ t,
@@ -893,7 +896,7 @@ __global__ __launch_bounds__(kCX * kCY) void dg_smooth1_kernel(OpA op,
 // Second: z2 = z1 + P x0 (the prolonged coarse correction), z = z2 + S (r - A z2);
 // part1 = r.z per tile.
 __global__ __launch_bounds__(kCX * kCY) void dg_smooth2_kernel(OpA op, Emb em,
-                                                              const double* __restrict__ mc,
+                                                              const float* __restrict__ mc,
                                                               const double* __restrict__ r,
                                                               const double* __restrict__ z1,
                                                               const double* __restrict__ x0, double w,
