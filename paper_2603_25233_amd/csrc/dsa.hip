@@ -480,138 +480,228 @@ __device__ __forceinline__ double stencil9(const float* __restrict__ A9,
   return s;
 }
 
-// The stencil kernels of the cycle work on tiles of kTX x kTY nodes (one node per thread):
-// the vector the stencil multiplies is formed once per node of the tile and its ring in
-// LDS (0 outside the grid, where the stencil's entries are 0 too), so each node's nine
-// neighbours come from LDS; the sums run in the same order as stencil9's.
-constexpr int kTX = 64, kTY = 4, kTW = kTX + 2, kTH = kTY + 2;
+// The multi-kernel levels of the cycle run as two kernels per level.  Down: the two
+// pre-smoothing sweeps from x = 0, the residual and its full-weighting restriction; up: the
+// prolongation with the first post-smoothing sweep, then the second sweep.  Each block owns
+// a tile and forms the intermediate vectors on the tile and the rings its later steps need
+// (the neighbours' share recomputed, 0 outside the grid, where the stencil's entries are 0
+// too) in LDS, so a level costs two launches instead of five.  Every node's value is the
+// same sum in the same order as with one kernel per step (stencil rows dj = -1..1, in each
+// di = -1..1).
 
-template <class F>
-__device__ __forceinline__ void fill_tile(double* t, int mx, int my, F f) {
-  const int i0 = (int)blockIdx.x * kTX - 1, j0 = (int)blockIdx.y * kTY - 1;
-  for (int e = threadIdx.x; e < kTW * kTH; e += blockDim.x) {
-    const int ii = i0 + e % kTW, jj = j0 + e / kTW;
-    t[e] = (ii >= 0 && ii < mx && jj >= 0 && jj < my) ? f(ii, jj) : 0.0;
-  }
-  __syncthreads();
+// The phases below run over a thread's entries e = threadIdx.x + 256 k < N of an LDS
+// region (256-thread blocks) in two unrolled passes: first every global load of all its
+// entries (unconditional, from a node clamped into the grid; entries outside use 0), then
+// the arithmetic, so that a phase waits for memory once rather than once per entry.
+template <int N>
+constexpr int per_thread() { return (N + 255) / 256; }
+
+// a node's stencil row, smoother weight and right-hand side
+struct NodeIn {
+  float a[9];
+  double dinv, b;
+};
+__device__ __forceinline__ NodeIn load_node(const float* __restrict__ A9,
+                                           const double* __restrict__ dinv,
+                                           const double* __restrict__ b, long n) {
+  NodeIn v;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) v.a[k] = A9[9 * n + k];
+  v.dinv = dinv[n];
+  v.b = b[n];
+  return v;
 }
 
-__device__ __forceinline__ double tile_stencil(const float* __restrict__ a, const double* t, int lx,
-                                               int ly) {
+// sum of the node's stencil times the LDS array v of row width w around entry e
+__device__ __forceinline__ double lds_stencil(const float* a, const double* v, int w, int e) {
   double s = 0.0;
 #pragma unroll
   for (int dj = -1; dj <= 1; ++dj)
 #pragma unroll
-    for (int di = -1; di <= 1; ++di)
-      s += (double)a[(dj + 1) * 3 + di + 1] * t[(ly + 1 + dj) * kTW + lx + 1 + di];
+    for (int di = -1; di <= 1; ++di) s += (double)a[(dj + 1) * 3 + di + 1] * v[e + dj * w + di];
   return s;
 }
 
-dim3 tile_grid(int mx, int my) { return dim3((unsigned)((mx + kTX - 1) / kTX), (unsigned)((my + kTY - 1) / kTY)); }
-
-// xout = x + dinv (b - A x)   (x == nullptr: x = 0)
-__global__ __launch_bounds__(256) void mg_jacobi_kernel(int mx, int my,
-                                                       const float* __restrict__ A9,
-                                                       const double* __restrict__ dinv,
-                                                       const double* __restrict__ b,
-                                                       const double* __restrict__ x,
-                                                       double* __restrict__ xout,
-                                                       const double* __restrict__ sc) {
-  __shared__ double t[kTW * kTH];
-  if (sc[S_DONE] != 0.0) return;
-  const int lx = (int)threadIdx.x % kTX, ly = (int)threadIdx.x / kTX;
-  const int i = (int)blockIdx.x * kTX + lx, j = (int)blockIdx.y * kTY + ly;
-  const bool in = i < mx && j < my;
-  const long n = (long)j * mx + i;
-  if (!x) {
-    if (in) xout[n] = dinv[n] * b[n];
-    return;
-  }
-  fill_tile(t, mx, my, [&](int ii, int jj) { return x[(long)jj * mx + ii]; });
-  if (in) xout[n] = t[(ly + 1) * kTW + lx + 1] + dinv[n] * (b[n] - tile_stencil(A9 + 9 * n, t, lx, ly));
-}
-
-// the first two sweeps from x = 0: x = y + dinv (b - A y) with y = dinv b
-__global__ __launch_bounds__(256) void mg_pre_kernel(int mx, int my, const float* __restrict__ A9,
-                                                    const double* __restrict__ dinv,
-                                                    const double* __restrict__ b,
-                                                    double* __restrict__ x,
-                                                    const double* __restrict__ sc) {
-  __shared__ double t[kTW * kTH];
-  if (sc[S_DONE] != 0.0) return;
-  const int lx = (int)threadIdx.x % kTX, ly = (int)threadIdx.x / kTX;
-  const int i = (int)blockIdx.x * kTX + lx, j = (int)blockIdx.y * kTY + ly;
-  fill_tile(t, mx, my, [&](int ii, int jj) {
-    const long m = (long)jj * mx + ii;
-    return dinv[m] * b[m];
-  });
-  if (i >= mx || j >= my) return;
-  const long n = (long)j * mx + i;
-  x[n] = t[(ly + 1) * kTW + lx + 1] + dinv[n] * (b[n] - tile_stencil(A9 + 9 * n, t, lx, ly));
-}
-
-// prolongation and the first post-smoothing sweep: t = y + dinv (b - A y), y = x + P xc
-__global__ __launch_bounds__(256) void mg_post_kernel(int mx, int my, const float* __restrict__ A9,
+// Down, for the coarse nodes [I0, I0 + CX) x [J0, J0 + CY): with y = dinv b,
+// x = y + dinv (b - A y) (stored on the fine nodes [2 I0, 2 I0 + 2 CX) x [2 J0, 2 J0 + 2 CY)),
+// t = b - A x, and bc = R t.  y lives on the fine nodes 2 I0 - 3 .. 2 I0 + 2 CX + 1 (x one
+// node in, t two), so that the restriction of the block's coarse nodes finds t on all
+// their fine neighbours.
+constexpr int kDX = 32, kDY = 8;  // coarse nodes per down block (fine tile 64 x 16)
+__global__ __launch_bounds__(256) void mg_down_kernel(int mx, int my, const float* __restrict__ A9,
                                                      const double* __restrict__ dinv,
                                                      const double* __restrict__ b,
-                                                     const double* __restrict__ x, int mxc,
-                                                     const double* __restrict__ xc,
-                                                     double* __restrict__ tout,
+                                                     double* __restrict__ x, int mxc, int myc,
+                                                     double* __restrict__ bc,
                                                      const double* __restrict__ sc) {
-  __shared__ double t[kTW * kTH];
+  constexpr int WY = 2 * kDX + 5, HY = 2 * kDY + 5, WX = WY - 2, HX = HY - 2, WT = WY - 4,
+                HT = HY - 4;
+  __shared__ double Y[HY * WY], X[HX * WX], T[HT * WT];
   if (sc[S_DONE] != 0.0) return;
-  const int lx = (int)threadIdx.x % kTX, ly = (int)threadIdx.x / kTX;
-  const int i = (int)blockIdx.x * kTX + lx, j = (int)blockIdx.y * kTY + ly;
-  fill_tile(t, mx, my, [&](int ii, int jj) {
-    const int i0 = ii >> 1, i1 = (ii + 1) >> 1, j0 = jj >> 1, j1 = (jj + 1) >> 1;
-    return x[(long)jj * mx + ii] + 0.25 * (xc[(long)j0 * mxc + i0] + xc[(long)j0 * mxc + i1] +
-                                           xc[(long)j1 * mxc + i0] + xc[(long)j1 * mxc + i1]);
-  });
-  if (i >= mx || j >= my) return;
-  const long n = (long)j * mx + i;
-  tout[n] = t[(ly + 1) * kTW + lx + 1] + dinv[n] * (b[n] - tile_stencil(A9 + 9 * n, t, lx, ly));
-}
-
-// r = b - A x
-__global__ __launch_bounds__(256) void mg_residual_kernel(int mx, int my,
-                                                         const float* __restrict__ A9,
-                                                         const double* __restrict__ b,
-                                                         const double* __restrict__ x,
-                                                         double* __restrict__ r,
-                                                         const double* __restrict__ sc) {
-  __shared__ double t[kTW * kTH];
-  if (sc[S_DONE] != 0.0) return;
-  const int lx = (int)threadIdx.x % kTX, ly = (int)threadIdx.x / kTX;
-  const int i = (int)blockIdx.x * kTX + lx, j = (int)blockIdx.y * kTY + ly;
-  fill_tile(t, mx, my, [&](int ii, int jj) { return x[(long)jj * mx + ii]; });
-  if (i >= mx || j >= my) return;
-  const long n = (long)j * mx + i;
-  r[n] = b[n] - tile_stencil(A9 + 9 * n, t, lx, ly);
-}
-
-// full weighting (transpose of bilinear interpolation): fine node (2I + di, 2J + dj) has
-// weight (1 - |di|/2)(1 - |dj|/2) in coarse node (I, J)
-__global__ __launch_bounds__(256) void mg_restrict_kernel(int mxf, int myf,
-                                                         const double* __restrict__ rf, int mxc,
-                                                         int myc, double* __restrict__ bc,
-                                                         const double* __restrict__ sc) {
-  if (sc[S_DONE] != 0.0) return;
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= (long)mxc * myc) return;
-  const int I = (int)(n % mxc), J = (int)(n / mxc);
-  double s = 0.0;
+  const int I0 = (int)blockIdx.x * kDX, J0 = (int)blockIdx.y * kDY;
+  const int fi = 2 * I0 - 3, fj = 2 * J0 - 3;  // fine node of Y[0]
+  auto inside = [&](int i, int j) { return i >= 0 && i < mx && j >= 0 && j < my; };
+  auto node = [&](int i, int j) {  // clamped into the grid
+    return (long)min(max(j, 0), my - 1) * mx + min(max(i, 0), mx - 1);
+  };
+  constexpr int K1 = per_thread<HY * WY>(), K2 = per_thread<HX * WX>(), K3 = per_thread<HT * WT>();
+  double dv[K1], bv[K1];
+  NodeIn in2[K2], in3[K3];
+  auto load2 = [&] {
 #pragma unroll
-  for (int dj = -1; dj <= 1; ++dj) {
-    const int j = 2 * J + dj;
-    if (j < 0 || j >= myf) continue;
-#pragma unroll
-    for (int di = -1; di <= 1; ++di) {
-      const int i = 2 * I + di;
-      if (i < 0 || i >= mxf) continue;
-      s += (di ? 0.5 : 1.0) * (dj ? 0.5 : 1.0) * rf[(long)j * mxf + i];
+    for (int k = 0; k < K2; ++k) {
+      const int e = (int)threadIdx.x + 256 * k;
+      in2[k] = load_node(A9, dinv, b, node(fi + 1 + e % WX, fj + 1 + e / WX));
     }
+  };
+  auto load3 = [&] {
+#pragma unroll
+    for (int k = 0; k < K3; ++k) {
+      const int e = (int)threadIdx.x + 256 * k;
+      in3[k] = load_node(A9, dinv, b, node(fi + 2 + e % WT, fj + 2 + e / WT));
+    }
+  };
+#pragma unroll
+  for (int k = 0; k < K1; ++k) {
+    const int e = (int)threadIdx.x + 256 * k;
+    const long n = node(fi + e % WY, fj + e / WY);
+    dv[k] = dinv[n];
+    bv[k] = b[n];
   }
-  bc[n] = s;
+#pragma unroll
+  for (int k = 0; k < K1; ++k) {
+    const int e = (int)threadIdx.x + 256 * k;
+    if (e < HY * WY) Y[e] = inside(fi + e % WY, fj + e / WY) ? dv[k] * bv[k] : 0.0;
+  }
+  __syncthreads();
+  load2();
+#pragma unroll
+  for (int k = 0; k < K2; ++k) {
+    const int e = (int)threadIdx.x + 256 * k;
+    if (e >= HX * WX) continue;
+    const int ex = e % WX, ey = e / WX, i = fi + 1 + ex, j = fj + 1 + ey;
+    double v = 0.0;
+    if (inside(i, j)) {
+      const int ey0 = (ey + 1) * WY + ex + 1;
+      v = Y[ey0] + in2[k].dinv * (in2[k].b - lds_stencil(in2[k].a, Y, WY, ey0));
+      if (i >= 2 * I0 && i < 2 * I0 + 2 * kDX && j >= 2 * J0 && j < 2 * J0 + 2 * kDY)
+        x[(long)j * mx + i] = v;
+    }
+    X[e] = v;
+  }
+  __syncthreads();
+  load3();
+#pragma unroll
+  for (int k = 0; k < K3; ++k) {
+    const int e = (int)threadIdx.x + 256 * k;
+    if (e >= HT * WT) continue;
+    const int ex = e % WT, ey = e / WT;
+    T[e] = inside(fi + 2 + ex, fj + 2 + ey)
+               ? in3[k].b - lds_stencil(in3[k].a, X, WX, (ey + 1) * WX + ex + 1)
+               : 0.0;
+  }
+  __syncthreads();
+  // full weighting (transpose of bilinear interpolation): fine node (2I + di, 2J + dj) has
+  // weight (1 - |di|/2)(1 - |dj|/2) in coarse node (I, J)
+  for (int e = threadIdx.x; e < kDX * kDY; e += blockDim.x) {
+    const int I = I0 + e % kDX, J = J0 + e / kDX;
+    if (I >= mxc || J >= myc) continue;
+    double s = 0.0;
+#pragma unroll
+    for (int dj = -1; dj <= 1; ++dj) {
+      const int j = 2 * J + dj;
+      if (j < 0 || j >= my) continue;
+#pragma unroll
+      for (int di = -1; di <= 1; ++di) {
+        const int i = 2 * I + di;
+        if (i < 0 || i >= mx) continue;
+        s += (di ? 0.5 : 1.0) * (dj ? 0.5 : 1.0) * T[(j - fj - 2) * WT + i - fi - 2];
+      }
+    }
+    bc[(long)J * mxc + I] = s;
+  }
+}
+
+// Up, for the fine nodes [i0, i0 + kUX) x [j0, j0 + kUY): with y = x + P xc (bilinear
+// prolongation), t = y + dinv (b - A y), xout = t + dinv (b - A t).  y lives two nodes
+// around the tile, t one.
+constexpr int kUX = 64, kUY = 16;
+__global__ __launch_bounds__(256) void mg_up_kernel(int mx, int my, const float* __restrict__ A9,
+                                                   const double* __restrict__ dinv,
+                                                   const double* __restrict__ b,
+                                                   const double* __restrict__ x, int mxc,
+                                                   const double* __restrict__ xc,
+                                                   double* __restrict__ xout,
+                                                   const double* __restrict__ sc) {
+  constexpr int WY = kUX + 4, HY = kUY + 4, WT = kUX + 2, HT = kUY + 2;
+  __shared__ double Y[HY * WY], T[HT * WT];
+  if (sc[S_DONE] != 0.0) return;
+  const int i0 = (int)blockIdx.x * kUX, j0 = (int)blockIdx.y * kUY;
+  const int fi = i0 - 2, fj = j0 - 2;  // fine node of Y[0]
+  auto inside = [&](int i, int j) { return i >= 0 && i < mx && j >= 0 && j < my; };
+  auto node = [&](int i, int j) {  // clamped into the grid
+    return (long)min(max(j, 0), my - 1) * mx + min(max(i, 0), mx - 1);
+  };
+  const int myc = (my + 1) / 2;
+  auto cnode = [&](int I, int J) { return (long)min(J, myc - 1) * mxc + min(I, mxc - 1); };
+  constexpr int K1 = per_thread<HY * WY>(), K2 = per_thread<HT * WT>(), K3 = per_thread<kUX * kUY>();
+  double xv[K1], c[K1][4];
+  NodeIn in2[K2], in3[K3];
+  auto load2 = [&] {
+#pragma unroll
+    for (int k = 0; k < K2; ++k) {
+      const int e = (int)threadIdx.x + 256 * k;
+      in2[k] = load_node(A9, dinv, b, node(fi + 1 + e % WT, fj + 1 + e / WT));
+    }
+  };
+  auto load3 = [&] {
+#pragma unroll
+    for (int k = 0; k < K3; ++k) {
+      const int e = (int)threadIdx.x + 256 * k;
+      in3[k] = load_node(A9, dinv, b, node(i0 + e % kUX, j0 + e / kUX));
+    }
+  };
+#pragma unroll
+  for (int k = 0; k < K1; ++k) {
+    const int e = (int)threadIdx.x + 256 * k;
+    const int i = min(max(fi + e % WY, 0), mx - 1), j = min(max(fj + e / WY, 0), my - 1);
+    xv[k] = x[node(i, j)];
+    const int c0 = i >> 1, c1 = (i + 1) >> 1, r0 = j >> 1, r1 = (j + 1) >> 1;
+    c[k][0] = xc[cnode(c0, r0)];
+    c[k][1] = xc[cnode(c1, r0)];
+    c[k][2] = xc[cnode(c0, r1)];
+    c[k][3] = xc[cnode(c1, r1)];
+  }
+#pragma unroll
+  for (int k = 0; k < K1; ++k) {
+    const int e = (int)threadIdx.x + 256 * k;
+    if (e < HY * WY)
+      Y[e] = inside(fi + e % WY, fj + e / WY)
+                 ? xv[k] + 0.25 * (c[k][0] + c[k][1] + c[k][2] + c[k][3])
+                 : 0.0;
+  }
+  __syncthreads();
+  load2();
+#pragma unroll
+  for (int k = 0; k < K2; ++k) {
+    const int e = (int)threadIdx.x + 256 * k;
+    if (e >= HT * WT) continue;
+    const int ex = e % WT, ey = e / WT;
+    const int ey0 = (ey + 1) * WY + ex + 1;
+    T[e] = inside(fi + 1 + ex, fj + 1 + ey)
+               ? Y[ey0] + in2[k].dinv * (in2[k].b - lds_stencil(in2[k].a, Y, WY, ey0))
+               : 0.0;
+  }
+  __syncthreads();
+  load3();
+#pragma unroll
+  for (int k = 0; k < K3; ++k) {
+    const int e = (int)threadIdx.x + 256 * k;
+    const int ex = e % kUX, ey = e / kUX, i = i0 + ex, j = j0 + ey;
+    if (!inside(i, j)) continue;
+    const int ey0 = (ey + 1) * WT + ex + 1;
+    xout[(long)j * mx + i] = T[ey0] + in3[k].dinv * (in3[k].b - lds_stencil(in3[k].a, T, WT, ey0));
+  }
 }
 
 // V-cycle of the levels l0 .. nlev-1 by one workgroup (the small grids): the same steps
@@ -1436,6 +1526,13 @@ OpA op_of(const DSA* d) {
   return OpA{d->g.nx, d->g.ny, axis_of(d->g.hx), axis_of(d->g.hy), d->dcoef.get(), d->sa.get()};
 }
 
+// where level l's V-cycle leaves its solution: x for the one-workgroup cycle, t for a
+// level of the two-kernel cycle (its up kernel cannot overwrite x, which neighbouring
+// blocks still read)
+const double* level_solution(const DSA* d, int l) {
+  return l == d->lsmall ? d->mg[l]->x.get() : d->mg[l]->t.get();
+}
+
 // one V-cycle on level l (x = V b), two l1-Jacobi sweeps before and after
 void vcycle(DSA* d, int l, hipStream_t st) {
   MgLevel& L = *d->mg[l];
@@ -1458,22 +1555,14 @@ void vcycle(DSA* d, int l, hipStream_t st) {
                          kCoarseSweeps, P, sc);
     return;
   }
-  const dim3 nb = tile_grid(L.mx, L.my);
-  auto jac = [&](const double* x, double* out) {
-    hipLaunchKernelGGL(mg_jacobi_kernel, nb, dim3(kTX * kTY), 0, st, L.mx, L.my, L.A9c.get(),
-                       L.dinv.get(), L.b.get(), x, out, sc);
-  };
   MgLevel& C = *d->mg[l + 1];
-  hipLaunchKernelGGL(mg_pre_kernel, nb, dim3(kTX * kTY), 0, st, L.mx, L.my, L.A9c.get(),
-                     L.dinv.get(), L.b.get(), L.x.get(), sc);
-  hipLaunchKernelGGL(mg_residual_kernel, nb, dim3(kTX * kTY), 0, st, L.mx, L.my, L.A9c.get(),
-                     L.b.get(), L.x.get(), L.t.get(), sc);
-  hipLaunchKernelGGL(mg_restrict_kernel, dim3(nblocks((long)C.mx * C.my)), dim3(256), 0, st, L.mx,
-                     L.my, L.t.get(), C.mx, C.my, C.b.get(), sc);
+  const dim3 down((unsigned)((C.mx + kDX - 1) / kDX), (unsigned)((C.my + kDY - 1) / kDY));
+  hipLaunchKernelGGL(mg_down_kernel, down, dim3(256), 0, st, L.mx, L.my, L.A9c.get(), L.dinv.get(),
+                     L.b.get(), L.x.get(), C.mx, C.my, C.b.get(), sc);
   vcycle(d, l + 1, st);
-  hipLaunchKernelGGL(mg_post_kernel, nb, dim3(kTX * kTY), 0, st, L.mx, L.my, L.A9c.get(),
-                     L.dinv.get(), L.b.get(), L.x.get(), C.mx, C.x.get(), L.t.get(), sc);
-  jac(L.t.get(), L.x.get());
+  const dim3 up((unsigned)((L.mx + kUX - 1) / kUX), (unsigned)((L.my + kUY - 1) / kUY));
+  hipLaunchKernelGGL(mg_up_kernel, up, dim3(256), 0, st, L.mx, L.my, L.A9c.get(), L.dinv.get(),
+                     L.b.get(), L.x.get(), C.mx, level_solution(d, l + 1), L.t.get(), sc);
 }
 
 // z = M^{-1} r, part1 = r.z per block.  M^{-1} is the symmetric two-level preconditioner
@@ -1493,7 +1582,7 @@ void precondition(DSA* d, const double* r, double* z, hipStream_t st) {
                      g.ny, em, d->t.get(), L0.b.get(), sc);
   vcycle(d, 0, st);
   hipLaunchKernelGGL(dg_smooth2_kernel, cell_tiles(g.nx, g.ny), dim3(kCX * kCY), 0, st, op, em,
-                     d->mc.get(), r, d->z1.get(), L0.x.get(), kSmoothW, z, d->part1.get(), sc);
+                     d->mc.get(), r, d->z1.get(), level_solution(d, 0), kSmoothW, z, d->part1.get(), sc);
 }
 
 }  // namespace
