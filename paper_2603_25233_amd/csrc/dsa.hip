@@ -68,7 +68,7 @@ struct DSA {
   DevBuf<double> diag, ax, ay, minv, sig_s;  // [ncell][16] blocks, [ncell]
   DevBuf<double> dcoef, sa;                    // [ncell] D = 1/(3 sigma_t), sigma_a
   DevBuf<float> mc;                            // [10][ncell] upper triangle of B^{-1} (FP32)
-  DevBuf<double> x, r, z, p0, p1, q, b;
+  DevBuf<double> x, r, r2, z, p0, p1, q, b;      // r, r2: the residual, alternating
   DevBuf<double> z1, t;                        // the preconditioner's smoothing passes
   DevBuf<double> part1, part2;                 // per-block partial sums
   DevBuf<double> scal;                         // device scalars (see Sc below)
@@ -329,43 +329,6 @@ __device__ __forceinline__ void binv_apply(const float* __restrict__ mc, long nc
   out[3] = m[3] * v[0] + m[6] * v[1] + m[8] * v[2] + m[9] * v[3];
 }
 
-// p_new = z + beta p_old (on the fly for the neighbours), q = A p_new, part = p.q
-__global__ __launch_bounds__(256) void spmv_kernel(
-    OpA op, const double* __restrict__ z, const double* __restrict__ pold,
-    double* __restrict__ pnew, double* __restrict__ q, double* __restrict__ part,
-    const double* __restrict__ sc) {
-  __shared__ double red[256];
-  if (sc[S_DONE] != 0.0) return;
-  const double beta = sc[S_BETA];
-  const int nx = op.nx, ny = op.ny;
-  const long ncell = (long)nx * ny;
-  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
-  const long c = (long)blk * blockDim.x + threadIdx.x;
-  double dot = 0.0;
-  if (c < ncell) {
-    const int a = (int)(c % nx), b = (int)(c / nx);
-    auto pv = [&](long cc2, double* o) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) o[k] = z[4 * cc2 + k] + beta * pold[4 * cc2 + k];
-    };
-    const double dn[4] = {a > 0 ? op.D[c - 1] : 0.0, a + 1 < nx ? op.D[c + 1] : 0.0,
-                          b > 0 ? op.D[c - nx] : 0.0, b + 1 < ny ? op.D[c + nx] : 0.0};
-    double m[14], xl[4], yb[4];
-    cell_row(op, a, b, op.D[c], dn, op.sa[c], m, xl, yb);
-    double u[4], acc[4];
-    pv(c, u);
-    block_apply(m, xl, yb, nx, ny, c, a, b, u, pv, acc);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      pnew[4 * c + k] = u[k];
-      q[4 * c + k] = acc[k];
-      dot += u[k] * acc[k];
-    }
-  }
-  const double s = block_sum(dot, red);
-  if (threadIdx.x == 0) part[blk] = s;
-}
-
 // The symmetric inverse diagonal blocks as their upper triangles (one FP32 array per
 // entry), and the per-cell D and sigma_a the operator's rows are formed from.
 __global__ __launch_bounds__(256) void dsa_compact_kernel(long ncell, const double* __restrict__ minv,
@@ -437,14 +400,21 @@ __global__ __launch_bounds__(1024) void reduce_beta_kernel(const double* __restr
 __global__ void start_kernel(double* sc, double tol) {
   sc[S_TOL2] = tol * tol * sc[S_RR];
   sc[S_BETA] = 0.0;
+  sc[S_ALPHA] = 0.0;
   sc[S_ITERS] = 0.0;
   sc[S_DONE] = (sc[S_RR] == 0.0) ? 1.0 : 0.0;
 }
 
+// out = a + (x + alpha p_k): the last iteration's update of x, which the iterations leave
+// to the next matrix product (k = the iteration count; iteration k's direction is in p1
+// when k is odd, p0 when even; alpha = 0 and p0 = 0 when no iteration ran)
 __global__ void axpy_out_kernel(long n, const double* __restrict__ a, const double* __restrict__ x,
-                                double* __restrict__ out) {
-  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = a[i] + x[i];
+                                const double* __restrict__ p0, const double* __restrict__ p1,
+                                const double* __restrict__ sc, double* __restrict__ out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double* p = ((long)sc[S_ITERS] & 1) ? p1 : p0;
+  out[i] = a[i] + (x[i] + sc[S_ALPHA] * p[i]);
 }
 
 // ------------------------------------------------------------ two-level preconditioner
@@ -950,36 +920,96 @@ __device__ __forceinline__ void tile_apply(const OpA& op, const double* tile, co
   block_apply(m, xl, yb, op.nx, op.ny, c, a, b, u, fetch, acc);
 }
 
-// First: z1 = S r, t = r - A z1.
+// The conjugate-gradient product on the same tiles: p_new = z + beta p_old (formed on the
+// tile and its ring), q = A p_new, part = p_new.q per tile; also the previous iteration's
+// x += alpha p_old (alpha still holds that iteration's step: this launch precedes the new
+// step's reduction; alpha = 0 and p_old = 0 before the first).
+__global__ __launch_bounds__(kCX * kCY) void spmv_kernel(OpA op, const double* __restrict__ z,
+                                                        const double* __restrict__ pold,
+                                                        double* __restrict__ pnew,
+                                                        double* __restrict__ q,
+                                                        double* __restrict__ x,
+                                                        double* __restrict__ part,
+                                                        const double* __restrict__ sc) {
+  __shared__ double tile[4 * kCW * kCH];
+  __shared__ double dtile[kCW * kCH];
+  __shared__ double red[kCX * kCY];
+  if (sc[S_DONE] != 0.0) return;
+  const double beta = sc[S_BETA], alpha = sc[S_ALPHA];
+  const int nx = op.nx, ny = op.ny;
+  fill_cell_tile(tile, dtile, op.D, nx, ny, [&](long c2, double* o) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = z[4 * c2 + k] + beta * pold[4 * c2 + k];
+  });
+  const int lx = (int)threadIdx.x % kCX, ly = (int)threadIdx.x / kCX;
+  const int a = (int)blockIdx.x * kCX + lx, b = (int)blockIdx.y * kCY + ly;
+  double dot = 0.0;
+  if (a < nx && b < ny) {
+    const long c = (long)b * nx + a;
+    double u[4], acc[4];
+    tile_apply(op, tile, dtile, (ly + 1) * kCW + lx + 1, c, a, b, u, acc);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      x[4 * c + k] += alpha * pold[4 * c + k];
+      pnew[4 * c + k] = u[k];
+      q[4 * c + k] = acc[k];
+      dot += u[k] * acc[k];
+    }
+  }
+  const double s = block_sum(dot, red);
+  if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+// First: z1 = S r, t = r - A z1.  With kUpd, r is first updated from the conjugate-
+// gradient step: r = rin - alpha q (formed on the tile and its ring, stored to rout on the
+// tile: rin stays intact for the neighbouring tiles' rings), part2 = r.r per tile.
+template <bool kUpd>
 __global__ __launch_bounds__(kCX * kCY) void dg_smooth1_kernel(OpA op,
                                                               const float* __restrict__ mc,
-                                                              const double* __restrict__ r, double w,
+                                                              const double* __restrict__ rin,
+                                                              const double* __restrict__ q,
+                                                              double* __restrict__ rout, double w,
                                                               double* __restrict__ z1,
                                                               double* __restrict__ t,
+                                                              double* __restrict__ part2,
                                                               const double* __restrict__ sc) {
   __shared__ double tile[4 * kCW * kCH];
   __shared__ double dtile[kCW * kCH];
+  __shared__ double red[kCX * kCY];
   if (sc[S_DONE] != 0.0) return;
+  const double alpha = kUpd ? sc[S_ALPHA] : 0.0;
   const int nx = op.nx, ny = op.ny;
   const long ncell = (long)nx * ny;
+  auto rv = [&](long c2, double* v) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = kUpd ? rin[4 * c2 + k] - alpha * q[4 * c2 + k] : rin[4 * c2 + k];
+  };
   fill_cell_tile(tile, dtile, op.D, nx, ny, [&](long c2, double* o) {
     double v[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) v[k] = r[4 * c2 + k];
+    rv(c2, v);
     binv_apply(mc, ncell, c2, v, o);
 #pragma unroll
     for (int k = 0; k < 4; ++k) o[k] *= w;
   });
   const int lx = (int)threadIdx.x % kCX, ly = (int)threadIdx.x / kCX;
   const int a = (int)blockIdx.x * kCX + lx, b = (int)blockIdx.y * kCY + ly;
-  if (a >= nx || b >= ny) return;
-  const long c = (long)b * nx + a;
-  double u[4], acc[4];
-  tile_apply(op, tile, dtile, (ly + 1) * kCW + lx + 1, c, a, b, u, acc);
+  double rr = 0.0;
+  if (a < nx && b < ny) {
+    const long c = (long)b * nx + a;
+    double u[4], acc[4], r[4];
+    tile_apply(op, tile, dtile, (ly + 1) * kCW + lx + 1, c, a, b, u, acc);
+    rv(c, r);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    z1[4 * c + k] = u[k];
-    t[4 * c + k] = r[4 * c + k] - acc[k];
+    for (int k = 0; k < 4; ++k) {
+      if (kUpd) rout[4 * c + k] = r[k];
+      rr += r[k] * r[k];
+      z1[4 * c + k] = u[k];
+      t[4 * c + k] = r[k] - acc[k];
+    }
+  }
+  if (kUpd) {
+    const double s = block_sum(rr, red);
+    if (threadIdx.x == 0) part2[blockIdx.y * gridDim.x + blockIdx.x] = s;
   }
 }
 
@@ -1034,31 +1064,6 @@ __global__ __launch_bounds__(kCX * kCY) void dg_smooth2_kernel(OpA op, Emb em,
   }
   const double s = block_sum(rz, red);
   if (threadIdx.x == 0) part1[blockIdx.y * gridDim.x + blockIdx.x] = s;
-}
-
-// x += alpha p, r -= alpha q, part2 = r.r
-__global__ __launch_bounds__(256) void update_r_kernel(long ncell, const double* __restrict__ p,
-                                                      const double* __restrict__ q,
-                                                      double* __restrict__ x,
-                                                      double* __restrict__ r,
-                                                      double* __restrict__ part2,
-                                                      const double* __restrict__ sc) {
-  __shared__ double red[256];
-  if (sc[S_DONE] != 0.0) return;
-  const double alpha = sc[S_ALPHA];
-  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  double rr = 0.0;
-  if (c < ncell) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      x[4 * c + k] += alpha * p[4 * c + k];
-      const double rv = r[4 * c + k] - alpha * q[4 * c + k];
-      r[4 * c + k] = rv;
-      rr += rv * rv;
-    }
-  }
-  const double s = block_sum(rr, red);
-  if (threadIdx.x == 0) part2[blockIdx.x] = s;
 }
 
 // r = b = sigma_s (phi* - phi_prev); x = 0; p_old = 0; part2 = r.r
@@ -1501,14 +1506,15 @@ DSA* dsa_create(const Geom& g, const double* sigma_t_dev, const double* sigma_s_
     RTE_CHECK_HIP(hipMemcpyAsync(d->sig_s.get(), sigma_s_dev, n * sizeof(double),
                                  hipMemcpyDeviceToDevice, st));
     const long nd = g.ndof;
-    d->x.alloc(nd); d->r.alloc(nd); d->z.alloc(nd); d->p0.alloc(nd); d->p1.alloc(nd); d->q.alloc(nd);
+    d->x.alloc(nd); d->r.alloc(nd); d->r2.alloc(nd); d->z.alloc(nd); d->p0.alloc(nd); d->p1.alloc(nd);
+    d->q.alloc(nd);
     d->z1.alloc(nd); d->t.alloc(nd);
     d->nblk = (int)((n + 255) / 256);
     {
       const dim3 tg = cell_tiles(g.nx, g.ny);
       d->ntile = (int)(tg.x * tg.y);
     }
-    d->part1.alloc(std::max(d->nblk, d->ntile)); d->part2.alloc(d->nblk);
+    d->part1.alloc(std::max(d->nblk, d->ntile)); d->part2.alloc(std::max(d->nblk, d->ntile));
     d->scal.alloc(S_N);
     RTE_CHECK_HIP(hipMemsetAsync(d->scal.get(), 0, S_N * sizeof(double), st));
     return d;
@@ -1565,19 +1571,29 @@ void vcycle(DSA* d, int l, hipStream_t st) {
                      L.b.get(), L.x.get(), C.mx, level_solution(d, l + 1), L.t.get(), sc);
 }
 
-// z = M^{-1} r, part1 = r.z per block.  M^{-1} is the symmetric two-level preconditioner
+// z = M^{-1} r, part1 = r.z per tile.  M^{-1} is the symmetric two-level preconditioner
 //   z1 = S r,  z2 = z1 + P V P^T (r - A z1),  z = z2 + S (r - A z2),
 // S = w B^{-1} the damped block Jacobi smoother (w = kSmoothW), V one V-cycle.  It is
 // symmetric positive definite since 2 S^{-1} - A is (w < 1: B^{-1} A has its spectrum in
 // (0, 2)).
-void precondition(DSA* d, const double* r, double* z, hipStream_t st) {
+// With q != nullptr, r = rin - alpha q first (into rout, part2 = r.r per tile); else
+// r = rin (rout unused).
+void precondition(DSA* d, const double* rin, const double* q, double* rout, double* z,
+                  hipStream_t st) {
   const Geom& g = d->g;
   const Emb em = embedding(g);
   const double* sc = d->scal.get();
   MgLevel& L0 = *d->mg[0];
   const OpA op = op_of(d);
-  hipLaunchKernelGGL(dg_smooth1_kernel, cell_tiles(g.nx, g.ny), dim3(kCX * kCY), 0, st, op,
-                     d->mc.get(), r, kSmoothW, d->z1.get(), d->t.get(), sc);
+  const double* r = q ? rout : rin;
+  if (q)
+    hipLaunchKernelGGL(dg_smooth1_kernel<true>, cell_tiles(g.nx, g.ny), dim3(kCX * kCY), 0, st, op,
+                       d->mc.get(), rin, q, rout, kSmoothW, d->z1.get(), d->t.get(),
+                       d->part2.get(), sc);
+  else
+    hipLaunchKernelGGL(dg_smooth1_kernel<false>, cell_tiles(g.nx, g.ny), dim3(kCX * kCY), 0, st,
+                       op, d->mc.get(), rin, nullptr, nullptr, kSmoothW, d->z1.get(), d->t.get(),
+                       nullptr, sc);
   hipLaunchKernelGGL(dg_restrict_kernel, dim3(nblocks((long)L0.mx * L0.my)), dim3(256), 0, st, g.nx,
                      g.ny, em, d->t.get(), L0.b.get(), sc);
   vcycle(d, 0, st);
@@ -1597,26 +1613,31 @@ int dsa_apply(DSA* d, const double* phi_star, const double* phi_prev, double* ph
                      phi_prev, d->x.get(), d->r.get(), d->p0.get(), d->part2.get());
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part2.get(), nb, sc + S_RR);
   hipLaunchKernelGGL(clear_done_kernel, dim3(1), dim3(1), 0, st, sc);
-  precondition(d, d->r.get(), d->z.get(), st);
+  precondition(d, d->r.get(), nullptr, nullptr, d->z.get(), st);
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part1.get(), d->ntile, sc + S_RHO);
   hipLaunchKernelGGL(start_kernel, dim3(1), dim3(1), 0, st, sc, rel_tol);
   RTE_CHECK_HIP(hipGetLastError());
+  // Iteration k writes p_k to pnew and r_k to rnext; both pairs alternate (p1 holds p_k for
+  // odd k, which axpy_out_kernel relies on).
   double* pold = d->p0.get();
   double* pnew = d->p1.get();
+  double* rcur = d->r.get();
+  double* rnext = d->r2.get();
+  const dim3 tiles = cell_tiles(g.nx, g.ny);
   const int chunk = 4, max_iter = 40000;
   double hsc[S_N];
   int it = 0;
   for (; it < max_iter; it += chunk) {
     for (int k = 0; k < chunk; ++k) {
-      hipLaunchKernelGGL(spmv_kernel, dim3(nb), dim3(256), 0, st, op_of(d), d->z.get(), pold,
-                         pnew, d->q.get(), d->part1.get(), sc);
-      hipLaunchKernelGGL(reduce_alpha_kernel, dim3(1), dim3(1024), 0, st, d->part1.get(), nb, sc);
-      hipLaunchKernelGGL(update_r_kernel, dim3(nb), dim3(256), 0, st, n, pnew, d->q.get(),
-                         d->x.get(), d->r.get(), d->part2.get(), sc);
-      precondition(d, d->r.get(), d->z.get(), st);
+      hipLaunchKernelGGL(spmv_kernel, tiles, dim3(kCX * kCY), 0, st, op_of(d), d->z.get(), pold,
+                         pnew, d->q.get(), d->x.get(), d->part1.get(), sc);
+      hipLaunchKernelGGL(reduce_alpha_kernel, dim3(1), dim3(1024), 0, st, d->part1.get(), d->ntile,
+                         sc);
+      precondition(d, rcur, d->q.get(), rnext, d->z.get(), st);
       hipLaunchKernelGGL(reduce_beta_kernel, dim3(1), dim3(1024), 0, st, d->part1.get(), d->ntile,
-                         d->part2.get(), nb, sc);
+                         d->part2.get(), d->ntile, sc);
       std::swap(pold, pnew);
+      std::swap(rcur, rnext);
     }
     RTE_CHECK_HIP(hipGetLastError());
     RTE_CHECK_HIP(hipMemcpyAsync(hsc, sc, sizeof(hsc), hipMemcpyDeviceToHost, st));
@@ -1624,7 +1645,7 @@ int dsa_apply(DSA* d, const double* phi_star, const double* phi_prev, double* ph
     if (hsc[S_DONE] != 0.0) break;
   }
   hipLaunchKernelGGL(axpy_out_kernel, dim3((g.ndof + 255) / 256), dim3(256), 0, st, g.ndof,
-                     phi_star, d->x.get(), phi_next);
+                     phi_star, d->x.get(), d->p0.get(), d->p1.get(), sc, phi_next);
   RTE_CHECK_HIP(hipGetLastError());
   return (int)hsc[S_ITERS];
 }
