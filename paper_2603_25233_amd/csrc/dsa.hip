@@ -876,7 +876,7 @@ __global__ __launch_bounds__(256) void dg_restrict_kernel(int nx, int ny, Emb em
 // tiles of kCX x kCY cells, one cell per thread: the vector the block product needs is
 // formed once per cell of the tile and its ring in LDS (zero outside the grid), so the
 // neighbours' blocks are not recomputed per cell.  The partial dot products are per tile.
-constexpr int kCX = 64, kCY = 4, kCW = kCX + 2, kCH = kCY + 2;
+constexpr int kCX = 64, kCY = 8, kCW = kCX + 2, kCH = kCY + 2;
 
 dim3 cell_tiles(int nx, int ny) {
   return dim3((unsigned)((nx + kCX - 1) / kCX), (unsigned)((ny + kCY - 1) / kCY));
