@@ -20,13 +20,17 @@
  *     s = x on B/T, l_1 increasing with s.  NULL means vacuum.
  *   - "HOST" pointers are read on the host during the call.  "DEV" pointers are
  *     device (HBM) pointers owned by the caller; the library never frees them.
- *   - `stream` is a hipStream_t (NULL = the null stream).  Sweeps are asynchronous
- *     on it; the solver returns after its work on `stream` has finished (its
- *     sampling and stopping decisions are taken on the host).
+ *   - `stream` is a hipStream_t (NULL = the null stream).  rte_sweep_execute is
+ *     asynchronous on it; the other calls that take a stream return after their
+ *     work on `stream` has finished (the solver takes its sampling and stopping
+ *     decisions on the host).
  *   - Every call returns an rte_status; on error nothing is thrown or aborted and
  *     rte_last_error() gives a message (thread-local, valid until the next call
- *     from the same thread).  Workspace is allocated with hipMalloc inside the call
- *     and freed before it returns.
+ *     from the same thread).
+ *   - Workspace of the calls that take a stream comes from device memory the library
+ *     keeps between calls (blocks of the same rounded size are reused; at most an
+ *     eighth of the device's memory is kept; see rte_release_cached_memory).  Sweep
+ *     plans hold their own hipMalloc'd workspace until rte_sweep_plan_destroy.
  *   - The library runs on the current HIP device.
  */
 #ifndef RTE_H
@@ -138,6 +142,15 @@ rte_status rte_sweep_plan_create(const rte_problem* prob, const int32_t* dir_idx
 rte_status rte_sweep_execute(rte_sweep_plan plan, const void* src, void* psi, void* phi,
                              void* stream);
 rte_status rte_sweep_plan_destroy(rte_sweep_plan plan);
+
+/*
+ * Frees the device memory the library keeps for the workspace of later calls (not part
+ * of the method: repeated solves reuse their buffers instead of paying hipMalloc /
+ * hipFree every call).  Safe at any time no call of the library is running; always
+ * returns RTE_OK.  A hipMalloc that runs out of memory inside a call empties the cache
+ * by itself before it gives up.
+ */
+rte_status rte_release_cached_memory(void);
 
 /* Solver settings (paper Sec. 2.2, Alg. 1, Sec. 3.2-3.4 and the settings of Sec. 4). */
 typedef struct {

@@ -8,13 +8,14 @@ from .rte import (RTE_FP64, RTE_MIXED, SIDE_B, SIDE_L, SIDE_R, SIDE_T, Problem, 
                   adjoint_sweep, backward_euler_step, box_source_moments, cl_quadrature,
                   cross_section_gradient,
                   default_params, exit_currents, gaussian_source_moments, inflow_moments, lib,
-                  solve, sweep, sweep_noalloc)
+                  release_cached_memory, solve, sweep, sweep_noalloc)
 from .rte import detector_misfit as detector_misfit_data
 from .autograd import DetectorMisfit, DetectorMisfitBatch, detector_misfit, detector_misfit_batch
 
 __all__ = ["RTE_FP64", "RTE_MIXED", "SIDE_L", "SIDE_R", "SIDE_B", "SIDE_T", "Problem", "RTEError", "SweepPlan",
            "adjoint_sweep", "backward_euler_step", "box_source_moments", "gaussian_source_moments", "cl_quadrature",
            "cross_section_gradient",
-           "default_params", "exit_currents", "inflow_moments", "lib", "solve", "sweep", "sweep_noalloc",
+           "default_params", "exit_currents", "inflow_moments", "lib", "release_cached_memory", "solve",
+           "sweep", "sweep_noalloc",
            "detector_misfit_data", "DetectorMisfit", "detector_misfit", "DetectorMisfitBatch",
            "detector_misfit_batch"]

@@ -178,6 +178,7 @@ static rte_status sweep_common(const rte_problem* prob, const int32_t* dir_idx, 
                                const void* src, void* psi, void* phi, rte_precision prec,
                                void* stream, bool adjoint) {
   try {
+    StreamScope scope((hipStream_t)stream);
     validate_problem(prob, false, (hipStream_t)stream);
     RTE_REQUIRE(dir_idx && n_sel >= 1, "dir_idx / n_sel");
     RTE_REQUIRE(src, "src is NULL");
@@ -311,7 +312,7 @@ extern "C" {
 
 const char* rte_last_error(void) { return rte::last_error(); }
 
-int32_t rte_abi_version(void) { return 3; }
+int32_t rte_abi_version(void) { return 4; }
 
 rte_status rte_sweep(const rte_problem* prob, const int32_t* dir_idx, int32_t n_sel,
                      const void* src, void* psi, void* phi, rte_precision prec, void* stream) {

@@ -38,22 +38,40 @@ struct Error {
     }                                      \
   } while (0)
 
-// Device buffer owned by one library call (freed on scope exit, also on error).
+// ---------------------------------------------------------------- device memory
+// Inside a StreamScope (one per entry point that takes a stream) buffers come from and go
+// back to a cache of idle blocks; outside one, straight from hipMalloc / to hipFree.
+// pool_alloc sets *pooled to whether the block belongs to the cache.
+void* pool_alloc(size_t bytes, bool* pooled);
+void pool_free(void* p, size_t bytes, bool pooled);
+void pool_release_all();
+// Marks the calls on `st` that allocate the library's temporaries; at the end of the
+// outermost scope `st` is synchronised once and the buffers released in it become idle.
+struct StreamScope {
+  explicit StreamScope(hipStream_t st);
+  ~StreamScope();
+  StreamScope(const StreamScope&) = delete;
+  StreamScope& operator=(const StreamScope&) = delete;
+};
+
+// Device buffer owned by one library call (released on scope exit, also on error).
 template <typename T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
+  bool pooled = false;
   DevBuf() = default;
   explicit DevBuf(size_t count) { alloc(count); }
   void alloc(size_t count) {
     release();
     n = count;
-    if (count) RTE_CHECK_HIP(hipMalloc(&p, count * sizeof(T)));
+    if (count) p = static_cast<T*>(pool_alloc(count * sizeof(T), &pooled));
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) pool_free(p, n * sizeof(T), pooled);
     p = nullptr;
     n = 0;
+    pooled = false;
   }
   ~DevBuf() { release(); }
   DevBuf(const DevBuf&) = delete;

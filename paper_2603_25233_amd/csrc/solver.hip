@@ -416,6 +416,7 @@ rte_status rte_lowrank_si_dsa_solve(const rte_problem* prob, const rte_solve_par
                                     const double* phi0, double* phi_out, double* X, double* S,
                                     double* V, rte_solve_result* res, void* stream) {
   try {
+    StreamScope scope((hipStream_t)stream);
     validate_problem(prob, true, (hipStream_t)stream);
     validate_params(prob, params);
     RTE_REQUIRE(phi_out, "phi_out is NULL");
@@ -439,6 +440,7 @@ rte_status rte_lowrank_si_dsa_solve(const rte_problem* prob, const rte_solve_par
 
 rte_status rte_exit_currents(const rte_problem* prob, const double* phi, double* J, void* stream) {
   try {
+    StreamScope scope((hipStream_t)stream);
     validate_problem(prob, true, (hipStream_t)stream);
     RTE_REQUIRE(phi && J, "phi and J are required");
     hipStream_t st = (hipStream_t)stream;
@@ -471,6 +473,7 @@ rte_status rte_exit_currents(const rte_problem* prob, const double* phi, double*
 rte_status rte_detector_misfit(const rte_problem* prob, const double* J, const double* J_obs,
                                double* bc_adj, double* loss, void* stream) {
   try {
+    StreamScope scope((hipStream_t)stream);
     validate_problem(prob, true, (hipStream_t)stream);
     RTE_REQUIRE(J && J_obs && bc_adj && loss, "missing array");
     hipStream_t st = (hipStream_t)stream;
@@ -491,6 +494,7 @@ rte_status rte_cross_section_gradient(const rte_problem* prob, const double* phi
                                       const double* phi_adj, const double* bc_adj,
                                       double* grad_sigma_a, double* grad_sigma_s, void* stream) {
   try {
+    StreamScope scope((hipStream_t)stream);
     validate_problem(prob, true, (hipStream_t)stream);
     RTE_REQUIRE(phi && phi_adj && grad_sigma_a && grad_sigma_s, "missing array");
     hipStream_t st = (hipStream_t)stream;

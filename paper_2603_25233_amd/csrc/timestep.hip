@@ -185,6 +185,7 @@ rte_status rte_backward_euler_step(const rte_problem* prob, const rte_solve_para
                                    rte_solve_result* res, void* stream) {
   try {
     hipStream_t st = (hipStream_t)stream;
+    StreamScope scope(st);
     validate_problem(prob, true, st);
     validate_solve_params(prob, params);
     RTE_REQUIRE(params->prec == RTE_FP64, "the backward Euler step is FP64 only");

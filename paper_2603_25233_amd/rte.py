@@ -90,6 +90,7 @@ SIGNATURES = {
     "rte_sweep_plan_destroy": ([_P], ctypes.c_int),
     "rte_last_error": ([], ctypes.c_char_p),
     "rte_abi_version": ([], ctypes.c_int32),
+    "rte_release_cached_memory": ([], ctypes.c_int),
     "rte_backward_euler_step": ([ctypes.POINTER(Problem_), ctypes.POINTER(Params_), ctypes.c_double,
                                  ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P,
                                  ctypes.POINTER(Result_), _P], ctypes.c_int),
@@ -400,6 +401,11 @@ def backward_euler_step(prob, dt, prev=None, rand=None, replay=None, phi0=None,
     r = call.res.rank
     out.update(X=X[:r], S=S[:r], V=V[:r])
     return out
+
+
+def release_cached_memory():
+    """Frees the device memory the library keeps for the workspace of later calls."""
+    _check(lib().rte_release_cached_memory())
 
 
 def exit_currents(prob, phi):

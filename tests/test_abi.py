@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_abi_version(L):
-    assert L.lib().rte_abi_version() == 3
+    assert L.lib().rte_abi_version() == 4
 
 
 @pytest.mark.parametrize("nt,nz", [(4, 2), (8, 4), (16, 8), (32, 8), (32, 16), (64, 16), (6, 3)])
@@ -116,3 +116,8 @@ def test_library_on_the_gpu_exports_and_version(L):
     psi, phi = L.sweep(gp, [0, 3], src, want_psi=True, want_phi=True)
     torch.cuda.synchronize()
     assert torch.isfinite(psi).all() and torch.isfinite(phi).all()
+
+
+def test_release_cached_memory_is_safe_without_work(L):
+    """Emptying the library's workspace cache with nothing cached returns RTE_OK."""
+    assert L.lib().rte_release_cached_memory() == 0
