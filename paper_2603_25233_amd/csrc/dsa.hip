@@ -70,7 +70,9 @@ struct DSA {
   DevBuf<float> mc;                            // [10][ncell] upper triangle of B^{-1} (FP32)
   DevBuf<double> x, r, r2, z, p0, p1, q, b;      // r, r2: the residual, alternating
   DevBuf<double> z1, t;                        // the preconditioner's smoothing passes
-  DevBuf<double> part1, part2;                 // per-block partial sums
+  DevBuf<double> part1, part2, part3;          // per-block partial sums
+  DevBuf<double> bprev;                        // the previous solve's right-hand side
+  bool have_prev = false;                      // x and bprev hold a previous solve
   DevBuf<double> scal;                         // device scalars (see Sc below)
   int nblk = 0;                                // blocks of the cell kernels
   int ntile = 0;                               // tiles of the smoothing passes
@@ -84,7 +86,7 @@ struct DSA {
 };
 
 // layout of the device scalar block
-enum Sc { S_RHO = 0, S_ALPHA, S_BETA, S_RR, S_TOL2, S_DONE, S_ITERS, S_PQ, S_N };
+enum Sc { S_RHO = 0, S_ALPHA, S_BETA, S_RR, S_TOL2, S_DONE, S_ITERS, S_PQ, S_BB, S_BPBP, S_C, S_N };
 
 namespace {
 
@@ -396,25 +398,46 @@ __global__ __launch_bounds__(1024) void reduce_beta_kernel(const double* __restr
   }
 }
 
-// rho = r.z, rr = r.r, tol2 = tol^2 * rr, beta = 0
+// tol2 = tol^2 |b|^2 (the tolerance is relative to the right-hand side, whatever the
+// initial guess), beta = alpha = 0, done when the initial residual already meets it;
+// |b|^2 is kept for the next solve's initial guess
 __global__ void start_kernel(double* sc, double tol) {
-  sc[S_TOL2] = tol * tol * sc[S_RR];
+  sc[S_TOL2] = tol * tol * sc[S_BB];
+  sc[S_BPBP] = sc[S_BB];
   sc[S_BETA] = 0.0;
   sc[S_ALPHA] = 0.0;
   sc[S_ITERS] = 0.0;
-  sc[S_DONE] = (sc[S_RR] == 0.0) ? 1.0 : 0.0;
+  sc[S_DONE] = (sc[S_RR] <= sc[S_TOL2]) ? 1.0 : 0.0;
 }
 
-// out = a + (x + alpha p_k): the last iteration's update of x, which the iterations leave
-// to the next matrix product (k = the iteration count; iteration k's direction is in p1
-// when k is odd, p0 when even; alpha = 0 and p0 = 0 when no iteration ran)
-__global__ void axpy_out_kernel(long n, const double* __restrict__ a, const double* __restrict__ x,
+// c = (b . b_prev) / (b_prev . b_prev) from the partials of b . b_prev (0 if b_prev = 0)
+__global__ __launch_bounds__(1024) void guess_scale_kernel(const double* __restrict__ part, int n,
+                                                          double* __restrict__ sc) {
+  __shared__ double red[1024];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
+  const double s = block_sum(v, red);
+  if (threadIdx.x == 0) sc[S_C] = sc[S_BPBP] > 0.0 ? s / sc[S_BPBP] : 0.0;
+}
+
+__global__ void scale_kernel(long n, double* __restrict__ x, const double* __restrict__ sc) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] *= sc[S_C];
+}
+
+// x += alpha p_k, out = a + x: the last iteration's update of x, which the iterations
+// leave to the next matrix product (k = the iteration count; iteration k's direction is in
+// p1 when k is odd, p0 when even; alpha = 0 and p0 = 0 when no iteration ran).  x keeps
+// the solution for the next solve's initial guess.
+__global__ void axpy_out_kernel(long n, const double* __restrict__ a, double* __restrict__ x,
                                 const double* __restrict__ p0, const double* __restrict__ p1,
                                 const double* __restrict__ sc, double* __restrict__ out) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double* p = ((long)sc[S_ITERS] & 1) ? p1 : p0;
-  out[i] = a[i] + (x[i] + sc[S_ALPHA] * p[i]);
+  const double xi = x[i] + sc[S_ALPHA] * p[i];
+  x[i] = xi;
+  out[i] = a[i] + xi;
 }
 
 // ------------------------------------------------------------ two-level preconditioner
@@ -960,6 +983,41 @@ __global__ __launch_bounds__(kCX * kCY) void spmv_kernel(OpA op, const double* _
   if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
+// The initial residual of a guess x: r = b - A x (r holds b on entry; each block reads and
+// writes only its own cells of r), b_prev = b, part2 = r.r per tile.
+__global__ __launch_bounds__(kCX * kCY) void guess_residual_kernel(OpA op,
+                                                                  const double* __restrict__ x,
+                                                                  double* __restrict__ r,
+                                                                  double* __restrict__ bprev,
+                                                                  double* __restrict__ part2) {
+  __shared__ double tile[4 * kCW * kCH];
+  __shared__ double dtile[kCW * kCH];
+  __shared__ double red[kCX * kCY];
+  const int nx = op.nx, ny = op.ny;
+  fill_cell_tile(tile, dtile, op.D, nx, ny, [&](long c2, double* o) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = x[4 * c2 + k];
+  });
+  const int lx = (int)threadIdx.x % kCX, ly = (int)threadIdx.x / kCX;
+  const int a = (int)blockIdx.x * kCX + lx, b = (int)blockIdx.y * kCY + ly;
+  double rr = 0.0;
+  if (a < nx && b < ny) {
+    const long c = (long)b * nx + a;
+    double u[4], acc[4];
+    tile_apply(op, tile, dtile, (ly + 1) * kCW + lx + 1, c, a, b, u, acc);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double bk = r[4 * c + k];
+      const double rk = bk - acc[k];
+      bprev[4 * c + k] = bk;
+      r[4 * c + k] = rk;
+      rr += rk * rk;
+    }
+  }
+  const double s = block_sum(rr, red);
+  if (threadIdx.x == 0) part2[blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
 // First: z1 = S r, t = r - A z1.  With kUpd, r is first updated from the conjugate-
 // gradient step: r = rin - alpha q (formed on the tile and its ring, stored to rout on the
 // tile: rin stays intact for the neighbouring tiles' rings), part2 = r.r per tile.
@@ -1067,26 +1125,41 @@ __global__ __launch_bounds__(kCX * kCY) void dg_smooth2_kernel(OpA op, Emb em,
 }
 
 // r = b = sigma_s (phi* - phi_prev); x = 0; p_old = 0; part2 = r.r
+// r = b = sigma_s (phi* - phi_prev); p_old = 0; part2 = b.b.  Without a previous solve
+// (kPrev false): x = 0 and b_prev = b.  With one: x (the previous solution) is kept and
+// part3 = b.b_prev (the initial guess is then scaled and its residual formed by
+// guess_residual_kernel, which also stores b_prev = b).
+template <bool kPrev>
 __global__ __launch_bounds__(256) void init_r_kernel(
     long ncell, const double* __restrict__ sig_s, const double* __restrict__ phis,
     const double* __restrict__ phip, double* __restrict__ x, double* __restrict__ r,
-    double* __restrict__ pold, double* __restrict__ part2) {
+    double* __restrict__ pold, double* __restrict__ bprev, double* __restrict__ part2,
+    double* __restrict__ part3) {
   __shared__ double red[256];
   const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  double rr = 0.0;
+  double rr = 0.0, rb = 0.0;
   if (c < ncell) {
     const double s = sig_s[c];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const double rv = s * (phis[4 * c + k] - phip[4 * c + k]);
       r[4 * c + k] = rv;
-      x[4 * c + k] = 0.0;
       pold[4 * c + k] = 0.0;
       rr += rv * rv;
+      if (kPrev) {
+        rb += rv * bprev[4 * c + k];
+      } else {
+        x[4 * c + k] = 0.0;
+        bprev[4 * c + k] = rv;
+      }
     }
   }
   const double s = block_sum(rr, red);
   if (threadIdx.x == 0) part2[blockIdx.x] = s;
+  if (kPrev) {
+    const double t = block_sum(rb, red);
+    if (threadIdx.x == 0) part3[blockIdx.x] = t;
+  }
 }
 
 // clears the done flag before the first application of the preconditioner
@@ -1515,6 +1588,8 @@ DSA* dsa_create(const Geom& g, const double* sigma_t_dev, const double* sigma_s_
       d->ntile = (int)(tg.x * tg.y);
     }
     d->part1.alloc(std::max(d->nblk, d->ntile)); d->part2.alloc(std::max(d->nblk, d->ntile));
+    d->part3.alloc(d->nblk);
+    d->bprev.alloc(nd);
     d->scal.alloc(S_N);
     RTE_CHECK_HIP(hipMemsetAsync(d->scal.get(), 0, S_N * sizeof(double), st));
     return d;
@@ -1609,9 +1684,29 @@ int dsa_apply(DSA* d, const double* phi_star, const double* phi_prev, double* ph
   const long n = g.ncell;
   const int nb = d->nblk;
   double* sc = d->scal.get();
-  hipLaunchKernelGGL(init_r_kernel, dim3(nb), dim3(256), 0, st, n, d->sig_s.get(), phi_star,
-                     phi_prev, d->x.get(), d->r.get(), d->p0.get(), d->part2.get());
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part2.get(), nb, sc + S_RR);
+  // The initial guess: zero for the first solve; afterwards the previous solution scaled by
+  // (b . b_prev) / |b_prev|^2 (successive right-hand sides of SI-DSA are nearly parallel
+  // once the iteration settles), with its residual formed exactly.
+  if (!d->have_prev) {
+    hipLaunchKernelGGL(init_r_kernel<false>, dim3(nb), dim3(256), 0, st, n, d->sig_s.get(),
+                       phi_star, phi_prev, d->x.get(), d->r.get(), d->p0.get(), d->bprev.get(),
+                       d->part2.get(), nullptr);
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part2.get(), nb, sc + S_BB);
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part2.get(), nb, sc + S_RR);
+  } else {
+    hipLaunchKernelGGL(init_r_kernel<true>, dim3(nb), dim3(256), 0, st, n, d->sig_s.get(),
+                       phi_star, phi_prev, d->x.get(), d->r.get(), d->p0.get(), d->bprev.get(),
+                       d->part2.get(), d->part3.get());
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part2.get(), nb, sc + S_BB);
+    hipLaunchKernelGGL(guess_scale_kernel, dim3(1), dim3(1024), 0, st, d->part3.get(), nb, sc);
+    hipLaunchKernelGGL(scale_kernel, dim3((g.ndof + 255) / 256), dim3(256), 0, st, g.ndof,
+                       d->x.get(), sc);
+    hipLaunchKernelGGL(guess_residual_kernel, cell_tiles(g.nx, g.ny), dim3(kCX * kCY), 0, st,
+                       op_of(d), d->x.get(), d->r.get(), d->bprev.get(), d->part2.get());
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part2.get(), d->ntile,
+                       sc + S_RR);
+  }
+  d->have_prev = true;
   hipLaunchKernelGGL(clear_done_kernel, dim3(1), dim3(1), 0, st, sc);
   precondition(d, d->r.get(), nullptr, nullptr, d->z.get(), st);
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part1.get(), d->ntile, sc + S_RHO);
