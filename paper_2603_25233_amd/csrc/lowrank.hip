@@ -116,6 +116,54 @@ __device__ __forceinline__ double wave_colsum16(const double (&p)[kPjVals], doub
   return s;
 }
 
+// out[c] = sum_b part[b][c] for c < n (and acc_into[c] += out[c] for c < n_acc).  A block of
+// 256 threads handles 8 columns (cblk selects them): 32 lanes per column take every 32nd
+// partial (eight running sums, fixed assignment), then fixed pairwise trees combine the
+// sums and the lanes, so the result is the same on every run.  red: 256 doubles of LDS.
+__device__ void reduce_cols_block(const double* part, int nblk, int stride, int n,
+                                  double* __restrict__ out, double* __restrict__ acc_into,
+                                  int n_acc, int cblk, double* red) {
+  constexpr int NS = 8;
+  const int c = cblk * 8 + (threadIdx.x >> 5);
+  const int l = threadIdx.x & 31;
+  double sv[NS];
+#pragma unroll
+  for (int u = 0; u < NS; ++u) sv[u] = 0.0;
+  if (c < n) {
+    // Every load is issued from a row clamped into range and masked at the add, so that
+    // none waits behind a branch.
+    for (int b0 = l; b0 - l < nblk; b0 += 32 * NS) {
+      double v[NS];
+#pragma unroll
+      for (int u = 0; u < NS; ++u) v[u] = part[(long)min(b0 + 32 * u, nblk - 1) * stride + c];
+#pragma unroll
+      for (int u = 0; u < NS; ++u) sv[u] += b0 + 32 * u < nblk ? v[u] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int h = NS / 2; h > 0; h >>= 1)
+#pragma unroll
+    for (int u = 0; u < h; ++u) sv[u] += sv[u + h];
+  red[threadIdx.x] = sv[0];
+  __syncthreads();
+  for (int h = 16; h > 0; h >>= 1) {
+    if (l < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (l == 0 && c < n) {
+    const double v = red[threadIdx.x];
+    out[c] = v;
+    if (acc_into && c < n_acc) acc_into[c] += v;
+  }
+}
+
+__global__ __launch_bounds__(256) void reduce_cols_kernel(const double* __restrict__ part, int nblk,
+                                                          int stride, int n, double* __restrict__ out,
+                                                          double* __restrict__ acc_into, int n_acc) {
+  __shared__ double red[256];
+  reduce_cols_block(part, nblk, stride, n, out, acc_into, n_acc, blockIdx.x, red);
+}
+
 template <typename TX, typename TW, int NV>
 __global__ __launch_bounds__(64 * kPjWaves, 2) void bproj_kernel(
     const TX* __restrict__ Xu, int r_upd, const double* __restrict__ C, const TX* __restrict__ Xd,
@@ -253,7 +301,8 @@ __global__ __launch_bounds__(64 * kPjWaves, 2) void bproj_kernel(
 
 // Per-snapshot statistics of a batch, mstat[l] = (|psi|^2 now, |psi|^2 at the start,
 // X(:,1)^T psi): from the batch projections (d1: pass 1, d3: pass 3 or the norms-only
-// pass when the basis is empty) ...
+// pass when the basis is empty); snapshot_done_kernel updates them after the projections
+// against the columns appended earlier in the batch.
 __global__ void mstat_init_kernel(int pn, int r0, const double* __restrict__ d1,
                                   const double* __restrict__ d3, double* __restrict__ mstat) {
   const int l = threadIdx.x;
@@ -269,30 +318,36 @@ __global__ void mstat_init_kernel(int pn, int r0, const double* __restrict__ d1,
     m[2] = 0.0;
   }
 }
-// ... and after the projections against the columns appended earlier in the batch
-__global__ void mstat_set_kernel(const double* __restrict__ d3, double* __restrict__ m) {
-  m[0] = d3[1];
-  m[2] = d3[0];
-}
 
-// col = v (1 / |v|) with |v|^2 = m[0], rounded as append_kernel with the host's 1 / |v|;
-// a vanishing v gives a zero column, discarded by the host
+// The end of one snapshot of the device-side MGS2-A, in one launch: with |v|^2 = d3[1]
+// (after projections against columns appended earlier in the batch; then also
+// m[0] = d3[1], m[2] = d3[0]) or m[0] (the first snapshot), col = v (1 / |v|) (rounded as
+// append_kernel with the host's 1 / |v|; a vanishing v gives a zero column, discarded by
+// the host), and block 0 stores dst = (cvec[0 .. r), |v|, 0 ...).
 template <typename TV, typename TC>
-__global__ void append_dev_kernel(const TV* __restrict__ v, const double* __restrict__ m,
-                                  TC* __restrict__ col, long nd) {
+__global__ void snapshot_done_kernel(const TV* __restrict__ v, long nd, TC* __restrict__ col,
+                                     const double* __restrict__ d3, double* __restrict__ m,
+                                     const double* __restrict__ cvec, int r,
+                                     double* __restrict__ dst, int rcap) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const double a = sqrt(m[0]);
+  const double a = sqrt(d3 ? d3[1] : m[0]);
   const double ia = a > 0.0 ? 1.0 / a : 0.0;
   if (i < nd) col[i] = (TC)((double)v[i] * ia);
+  if (blockIdx.x == 0) {
+    if (d3 && threadIdx.x == 0) {
+      m[0] = d3[1];
+      m[2] = d3[0];
+    }
+    for (int k = threadIdx.x; k < rcap; k += blockDim.x) dst[k] = k < r ? cvec[k] : (k == r ? a : 0.0);
+  }
 }
 
-// dst = (cvec[0 .. r), |v|, 0 ...) with |v|^2 = m[0]
-__global__ void store_coef_dev_kernel(const double* __restrict__ cvec, int r,
-                                      const double* __restrict__ m, double* __restrict__ dst,
-                                      int rcap) {
+// cvecs[l][i] = cb[i pn + l] for i < r0, 0 for r0 <= i < n (every snapshot l < pn of a batch)
+__global__ void coef_cols_kernel(const double* __restrict__ cb, int pn, int r0,
+                                 double* __restrict__ cvecs, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= rcap) return;
-  dst[i] = i < r ? cvec[i] : (i == r ? sqrt(m[0]) : 0.0);
+  const int l = blockIdx.y;
+  if (i < n) cvecs[(long)l * n + i] = i < r0 ? cb[(long)i * pn + l] : 0.0;
 }
 
 // cvec[i] = cb[i pn + l] for i < r0, 0 for r0 <= i < n
@@ -301,48 +356,6 @@ __global__ void coef_col_kernel(const double* __restrict__ cb, int pn, int l, in
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) cvec[i] = i < r0 ? cb[(long)i * pn + l] : 0.0;
 }
-// out[c] = sum_b part[b][c] for c < n (and acc_into[c] += out[c] for c < n_acc).  A block of
-// 256 threads handles 8 columns: 32 lanes per column take every 32nd partial (eight
-// running sums, fixed assignment), then fixed pairwise trees combine the sums and the
-// lanes, so the result is the same on every run.
-__global__ __launch_bounds__(256) void reduce_cols_kernel(const double* __restrict__ part, int nblk,
-                                                          int stride, int n, double* __restrict__ out,
-                                                          double* __restrict__ acc_into, int n_acc) {
-  constexpr int NS = 8;
-  __shared__ double red[256];
-  const int c = blockIdx.x * 8 + (threadIdx.x >> 5);
-  const int l = threadIdx.x & 31;
-  double sv[NS];
-#pragma unroll
-  for (int u = 0; u < NS; ++u) sv[u] = 0.0;
-  if (c < n) {
-    // Every load is issued from a row clamped into range and masked at the add, so that
-    // none waits behind a branch.
-    for (int b0 = l; b0 - l < nblk; b0 += 32 * NS) {
-      double v[NS];
-#pragma unroll
-      for (int u = 0; u < NS; ++u) v[u] = part[(long)min(b0 + 32 * u, nblk - 1) * stride + c];
-#pragma unroll
-      for (int u = 0; u < NS; ++u) sv[u] += b0 + 32 * u < nblk ? v[u] : 0.0;
-    }
-  }
-#pragma unroll
-  for (int h = NS / 2; h > 0; h >>= 1)
-#pragma unroll
-    for (int u = 0; u < h; ++u) sv[u] += sv[u + h];
-  red[threadIdx.x] = sv[0];
-  __syncthreads();
-  for (int h = 16; h > 0; h >>= 1) {
-    if (l < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (l == 0 && c < n) {
-    const double v = red[threadIdx.x];
-    out[c] = v;
-    if (acc_into && c < n_acc) acc_into[c] += v;
-  }
-}
-
 static void reduce_cols(const double* part, int nblk, int stride, int n, double* out,
                         double* acc_into, hipStream_t st, int n_acc = 0) {
   hipLaunchKernelGGL(reduce_cols_kernel, dim3((n + 7) / 8), dim3(256), 0, st, part, nblk, stride, n,
@@ -1418,6 +1431,7 @@ struct LowRank {
   // the FP32 sweep would be amplified by the DSA step in scattering-dominated cells.
   DevBuf<double> psi, swork;
   DevBuf<double> src, E, phi_k, phi_old, part, cvec, cw, dpart, cb, d1, d2, d3, mstat;
+  DevBuf<double> cvecs;  // [kMaxP][rcap + 2]: the device-side MGS2-A's per-snapshot cvec
   DevBuf<double> psi_save;     // snapshots after the batch projections (roll-back copy)
   // basis-update variants of Sec. 4.2: the snapshots of the outer iteration in sampling
   // order (their classes in snap_cls), from which a full QR rebuilds the basis
@@ -1529,6 +1543,7 @@ struct LowRank {
     d2.alloc((size_t)rcap * kMaxP + 2 * kMaxP);
     d3.alloc((size_t)rcap * kMaxP + 2 * kMaxP);
     cvec.alloc(rcap + 2);
+    cvecs.alloc((size_t)kMaxP * (rcap + 2));
     cw.alloc(rcap);
     dpart.alloc(4096);
     Tm.alloc((size_t)rcap * rcap); Dx.alloc((size_t)rcap * rcap); Dy.alloc((size_t)rcap * rcap);
@@ -1718,19 +1733,17 @@ struct LowRank {
     if (r0 + pn <= rcap) {
       RTE_CHECK_HIP(hipMemcpyAsync(psi_save.get(), psi.get(), (size_t)pn * nd * sizeof(double),
                                    hipMemcpyDeviceToDevice, st));
+      // every snapshot's coefficients against the old basis at once (one slice each)
+      const int nc = rcap + 2;
+      hipLaunchKernelGGL(coef_cols_kernel, dim3((nc + 127) / 128, pn), dim3(128), 0, st, cb.get(),
+                         pn, r0, cvecs.get(), nc);
       for (int l = 0; l < pn; ++l) {
         double* v = psi.get() + (size_t)l * nd;
-        coef_col(l, pn, r0);
-        if (l > 0) {
-          intra_passes(v, r0, l);
-          hipLaunchKernelGGL(mstat_set_kernel, dim3(1), dim3(1), 0, st, d3.get(),
-                             mstat.get() + 4 * l);
-        }
-        hipLaunchKernelGGL((append_dev_kernel<double, T>), dim3((nd + 255) / 256), dim3(256), 0, st, v,
-                           mstat.get() + 4 * l, X.get() + (size_t)(r0 + l) * nd, nd);
-        hipLaunchKernelGGL(store_coef_dev_kernel, dim3((rcap + 127) / 128), dim3(128), 0, st,
-                           cvec.get(), r0 + l, mstat.get() + 4 * l,
-                           Rst.get() + (size_t)rcap * cls[l], rcap);
+        double* cv = cvecs.get() + (size_t)l * nc;
+        if (l > 0) intra_passes(v, r0, l, cv);
+        hipLaunchKernelGGL((snapshot_done_kernel<double, T>), dim3((nd + 255) / 256), dim3(256), 0,
+                           st, v, nd, X.get() + (size_t)(r0 + l) * nd, l > 0 ? d3.get() : nullptr,
+                           mstat.get() + 4 * l, cv, r0 + l, Rst.get() + (size_t)rcap * cls[l], rcap);
         RTE_CHECK_HIP(hipGetLastError());
       }
       to_host(h_mstat, mstat.get(), 4 * pn);
@@ -1776,11 +1789,13 @@ struct LowRank {
   }
 
   // two projections of v against the nnew columns appended after r0 (coefficients into
-  // cvec[r0 ..]); the last pass leaves X(:,1)^T v and |v|^2 in d3[0], d3[1]
-  void intra_passes(double* v, int r0, int nnew) {
+  // cv[r0 ..], cv = cvec by default); the last pass leaves X(:,1)^T v and |v|^2 in d3[0],
+  // d3[1]
+  void intra_passes(double* v, int r0, int nnew, double* cv = nullptr) {
     const T* Xn = X.get() + (size_t)r0 * nd;
-    bproj(v, 1, nullptr, 0, nullptr, Xn, nnew, d1.get(), cvec.get() + r0);
-    bproj(v, 1, Xn, nnew, d1.get(), Xn, nnew, d2.get(), cvec.get() + r0);
+    if (!cv) cv = cvec.get();
+    bproj(v, 1, nullptr, 0, nullptr, Xn, nnew, d1.get(), cv + r0);
+    bproj(v, 1, Xn, nnew, d1.get(), Xn, nnew, d2.get(), cv + r0);
     bproj(v, 1, Xn, nnew, d2.get(), X.get(), 1, d3.get(), nullptr);
   }
 
