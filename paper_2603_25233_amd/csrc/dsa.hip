@@ -142,17 +142,6 @@ __host__ __device__ bool inv4(const double* A, double* out) {
 }
 
 // ------------------------------------------------------------ device kernels
-__device__ __forceinline__ void mv4(const double* __restrict__ B, const double* u, double* acc) {
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-    acc[i] += B[4 * i] * u[0] + B[4 * i + 1] * u[1] + B[4 * i + 2] * u[2] + B[4 * i + 3] * u[3];
-}
-__device__ __forceinline__ void mtv4(const double* __restrict__ B, const double* u, double* acc) {
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-    acc[i] += B[i] * u[0] + B[4 + i] * u[1] + B[8 + i] * u[2] + B[12 + i] * u[3];
-}
-
 __device__ __forceinline__ double block_sum(double v, double* red) {
   red[threadIdx.x] = v;
   __syncthreads();
