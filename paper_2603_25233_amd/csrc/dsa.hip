@@ -36,6 +36,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <tuple>
 #include <vector>
 
 #include "common.h"
@@ -68,11 +69,14 @@ struct DSA {
   DevBuf<double> diag, ax, ay, minv, sig_s;  // [ncell][16] blocks, [ncell]
   DevBuf<double> dcoef, sa;                    // [ncell] D = 1/(3 sigma_t), sigma_a
   DevBuf<float> mc;                            // [10][ncell] upper triangle of B^{-1} (FP32)
-  DevBuf<double> x, r, r2, z, p0, p1, q, b;      // r, r2: the residual, alternating
+  DevBuf<double> r, r2, z, p0, p1, q, b;         // r, r2: the residual, alternating
   DevBuf<double> z1, t;                        // the preconditioner's smoothing passes
-  DevBuf<double> part1, part2, part3;          // per-block partial sums
-  DevBuf<double> bprev;                        // the previous solve's right-hand side
-  bool have_prev = false;                      // x and bprev hold a previous solve
+  DevBuf<double> part1, part2, part3, part4;   // per-block partial sums
+  // The CG solution of the current solve and of the two before (xs[xc], xs[x1], xs[x2]),
+  // and the right-hand sides of the two before plus the current one's copy (bs[b1],
+  // bs[b2], bs[bsv]); roles rotate after each solve.  nprev: previous solves held (<= 2).
+  DevBuf<double> xs[3], bs[3];
+  int xc = 0, x1 = 1, x2 = 2, bsv = 0, b1 = 1, b2 = 2, nprev = 0;
   DevBuf<double> scal;                         // device scalars (see Sc below)
   int nblk = 0;                                // blocks of the cell kernels
   int ntile = 0;                               // tiles of the smoothing passes
@@ -86,7 +90,12 @@ struct DSA {
 };
 
 // layout of the device scalar block
-enum Sc { S_RHO = 0, S_ALPHA, S_BETA, S_RR, S_TOL2, S_DONE, S_ITERS, S_PQ, S_BB, S_BPBP, S_C, S_N };
+// S_BB = b.b of the current solve; S_B1B1, S_B2B2, S_B1B2 = dot products of the previous two
+// right-hand sides b1 (the last), b2; S_BB1, S_BB2 = b.b1, b.b2; S_C1, S_C2 the guess weights
+enum Sc {
+  S_RHO = 0, S_ALPHA, S_BETA, S_RR, S_TOL2, S_DONE, S_ITERS, S_PQ,
+  S_BB, S_B1B1, S_B2B2, S_B1B2, S_BB1, S_BB2, S_C1, S_C2, S_N
+};
 
 namespace {
 
@@ -388,30 +397,56 @@ __global__ __launch_bounds__(1024) void reduce_beta_kernel(const double* __restr
 }
 
 // tol2 = tol^2 |b|^2 (the tolerance is relative to the right-hand side, whatever the
-// initial guess), beta = alpha = 0, done when the initial residual already meets it;
-// |b|^2 is kept for the next solve's initial guess
+// initial guess), beta = alpha = 0, done when the initial residual already meets it; the
+// right-hand side's dot products move down the history for the next solve's guess
 __global__ void start_kernel(double* sc, double tol) {
   sc[S_TOL2] = tol * tol * sc[S_BB];
-  sc[S_BPBP] = sc[S_BB];
+  sc[S_B2B2] = sc[S_B1B1];
+  sc[S_B1B2] = sc[S_BB1];
+  sc[S_B1B1] = sc[S_BB];
   sc[S_BETA] = 0.0;
   sc[S_ALPHA] = 0.0;
   sc[S_ITERS] = 0.0;
   sc[S_DONE] = (sc[S_RR] <= sc[S_TOL2]) ? 1.0 : 0.0;
 }
 
-// c = (b . b_prev) / (b_prev . b_prev) from the partials of b . b_prev (0 if b_prev = 0)
-__global__ __launch_bounds__(1024) void guess_scale_kernel(const double* __restrict__ part, int n,
-                                                          double* __restrict__ sc) {
+// The guess weights (c1, c2) minimise |b - c1 b1 - c2 b2| (nprev = 2; the normal equations
+// of the 2 x 2 Gram matrix, or the one-term fit c1 = b.b1 / b1.b1 when that matrix is
+// nearly singular) or |b - c1 b1| (nprev = 1); b.b1 and b.b2 from per-block partials.
+__global__ __launch_bounds__(1024) void guess_weights_kernel(const double* __restrict__ p1,
+                                                            const double* __restrict__ p2, int n,
+                                                            int nprev, double* __restrict__ sc) {
   __shared__ double red[1024];
-  double v = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
-  const double s = block_sum(v, red);
-  if (threadIdx.x == 0) sc[S_C] = sc[S_BPBP] > 0.0 ? s / sc[S_BPBP] : 0.0;
+  double v1 = 0.0, v2 = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    v1 += p1[i];
+    if (nprev > 1) v2 += p2[i];
+  }
+  const double bb1 = block_sum(v1, red);
+  const double bb2 = nprev > 1 ? block_sum(v2, red) : 0.0;
+  if (threadIdx.x == 0) {
+    sc[S_BB1] = bb1;
+    sc[S_BB2] = bb2;
+    const double g11 = sc[S_B1B1], g22 = sc[S_B2B2], g12 = sc[S_B1B2];
+    double c1 = g11 > 0.0 ? bb1 / g11 : 0.0, c2 = 0.0;
+    const double det = g11 * g22 - g12 * g12;
+    if (nprev > 1 && det > 1e-10 * g11 * g22) {
+      c1 = (bb1 * g22 - bb2 * g12) / det;
+      c2 = (bb2 * g11 - bb1 * g12) / det;
+    }
+    sc[S_C1] = c1;
+    sc[S_C2] = c2;
+  }
 }
 
-__global__ void scale_kernel(long n, double* __restrict__ x, const double* __restrict__ sc) {
+// x = c1 x1 + c2 x2 (x2 ignored when nprev = 1)
+__global__ void guess_combine_kernel(long n, const double* __restrict__ x1,
+                                     const double* __restrict__ x2, int nprev,
+                                     double* __restrict__ x, const double* __restrict__ sc) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x[i] *= sc[S_C];
+  if (i >= n) return;
+  const double c1 = sc[S_C1], c2 = sc[S_C2];
+  x[i] = nprev > 1 ? c1 * x1[i] + c2 * x2[i] : c1 * x1[i];
 }
 
 // x += alpha p_k, out = a + x: the last iteration's update of x, which the iterations
@@ -973,7 +1008,8 @@ __global__ __launch_bounds__(kCX * kCY) void spmv_kernel(OpA op, const double* _
 }
 
 // The initial residual of a guess x: r = b - A x (r holds b on entry; each block reads and
-// writes only its own cells of r), b_prev = b, part2 = r.r per tile.
+// writes only its own cells of r), bprev = b (saved for the next solve's guess), part2 =
+// r.r per tile.
 __global__ __launch_bounds__(kCX * kCY) void guess_residual_kernel(OpA op,
                                                                   const double* __restrict__ x,
                                                                   double* __restrict__ r,
@@ -1115,18 +1151,19 @@ __global__ __launch_bounds__(kCX * kCY) void dg_smooth2_kernel(OpA op, Emb em,
 
 // r = b = sigma_s (phi* - phi_prev); x = 0; p_old = 0; part2 = r.r
 // r = b = sigma_s (phi* - phi_prev); p_old = 0; part2 = b.b.  Without a previous solve
-// (kPrev false): x = 0 and b_prev = b.  With one: x (the previous solution) is kept and
-// part3 = b.b_prev (the initial guess is then scaled and its residual formed by
-// guess_residual_kernel, which also stores b_prev = b).
+// (kPrev false): x = 0 and bsave = b.  With one: part3 = b.b1 and, when there are two,
+// part4 = b.b2 (the guess is then formed and its residual by guess_residual_kernel, which
+// also stores bsave = b).
 template <bool kPrev>
 __global__ __launch_bounds__(256) void init_r_kernel(
     long ncell, const double* __restrict__ sig_s, const double* __restrict__ phis,
     const double* __restrict__ phip, double* __restrict__ x, double* __restrict__ r,
-    double* __restrict__ pold, double* __restrict__ bprev, double* __restrict__ part2,
-    double* __restrict__ part3) {
+    double* __restrict__ pold, double* __restrict__ bsave, const double* __restrict__ b1,
+    const double* __restrict__ b2, double* __restrict__ part2, double* __restrict__ part3,
+    double* __restrict__ part4) {
   __shared__ double red[256];
   const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  double rr = 0.0, rb = 0.0;
+  double rr = 0.0, r1 = 0.0, r2 = 0.0;
   if (c < ncell) {
     const double s = sig_s[c];
 #pragma unroll
@@ -1136,18 +1173,23 @@ __global__ __launch_bounds__(256) void init_r_kernel(
       pold[4 * c + k] = 0.0;
       rr += rv * rv;
       if (kPrev) {
-        rb += rv * bprev[4 * c + k];
+        r1 += rv * b1[4 * c + k];
+        if (b2) r2 += rv * b2[4 * c + k];
       } else {
         x[4 * c + k] = 0.0;
-        bprev[4 * c + k] = rv;
+        bsave[4 * c + k] = rv;
       }
     }
   }
   const double s = block_sum(rr, red);
   if (threadIdx.x == 0) part2[blockIdx.x] = s;
   if (kPrev) {
-    const double t = block_sum(rb, red);
-    if (threadIdx.x == 0) part3[blockIdx.x] = t;
+    const double t1 = block_sum(r1, red);
+    if (threadIdx.x == 0) part3[blockIdx.x] = t1;
+    if (b2) {
+      const double t2 = block_sum(r2, red);
+      if (threadIdx.x == 0) part4[blockIdx.x] = t2;
+    }
   }
 }
 
@@ -1568,7 +1610,8 @@ DSA* dsa_create(const Geom& g, const double* sigma_t_dev, const double* sigma_s_
     RTE_CHECK_HIP(hipMemcpyAsync(d->sig_s.get(), sigma_s_dev, n * sizeof(double),
                                  hipMemcpyDeviceToDevice, st));
     const long nd = g.ndof;
-    d->x.alloc(nd); d->r.alloc(nd); d->r2.alloc(nd); d->z.alloc(nd); d->p0.alloc(nd); d->p1.alloc(nd);
+    for (int i = 0; i < 3; ++i) d->xs[i].alloc(nd), d->bs[i].alloc(nd);
+    d->r.alloc(nd); d->r2.alloc(nd); d->z.alloc(nd); d->p0.alloc(nd); d->p1.alloc(nd);
     d->q.alloc(nd);
     d->z1.alloc(nd); d->t.alloc(nd);
     d->nblk = (int)((n + 255) / 256);
@@ -1578,7 +1621,7 @@ DSA* dsa_create(const Geom& g, const double* sigma_t_dev, const double* sigma_s_
     }
     d->part1.alloc(std::max(d->nblk, d->ntile)); d->part2.alloc(std::max(d->nblk, d->ntile));
     d->part3.alloc(d->nblk);
-    d->bprev.alloc(nd);
+    d->part4.alloc(d->nblk);
     d->scal.alloc(S_N);
     RTE_CHECK_HIP(hipMemsetAsync(d->scal.get(), 0, S_N * sizeof(double), st));
     return d;
@@ -1673,29 +1716,33 @@ int dsa_apply(DSA* d, const double* phi_star, const double* phi_prev, double* ph
   const long n = g.ncell;
   const int nb = d->nblk;
   double* sc = d->scal.get();
-  // The initial guess: zero for the first solve; afterwards the previous solution scaled by
-  // (b . b_prev) / |b_prev|^2 (successive right-hand sides of SI-DSA are nearly parallel
-  // once the iteration settles), with its residual formed exactly.
-  if (!d->have_prev) {
+  // The initial guess: zero for the first solve; afterwards the combination of the last
+  // two solutions whose right-hand sides best fit this one (least squares; one term after
+  // the first solve): successive right-hand sides of SI-DSA are nearly dependent once the
+  // iteration settles.  Its residual is formed exactly.
+  double* x = d->xs[d->xc].get();
+  double* bsave = d->bs[d->bsv].get();
+  if (d->nprev == 0) {
     hipLaunchKernelGGL(init_r_kernel<false>, dim3(nb), dim3(256), 0, st, n, d->sig_s.get(),
-                       phi_star, phi_prev, d->x.get(), d->r.get(), d->p0.get(), d->bprev.get(),
-                       d->part2.get(), nullptr);
+                       phi_star, phi_prev, x, d->r.get(), d->p0.get(), bsave, nullptr, nullptr,
+                       d->part2.get(), nullptr, nullptr);
     hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part2.get(), nb, sc + S_BB);
     hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part2.get(), nb, sc + S_RR);
   } else {
+    const double* bp2 = d->nprev > 1 ? d->bs[d->b2].get() : nullptr;
     hipLaunchKernelGGL(init_r_kernel<true>, dim3(nb), dim3(256), 0, st, n, d->sig_s.get(),
-                       phi_star, phi_prev, d->x.get(), d->r.get(), d->p0.get(), d->bprev.get(),
-                       d->part2.get(), d->part3.get());
+                       phi_star, phi_prev, x, d->r.get(), d->p0.get(), nullptr,
+                       d->bs[d->b1].get(), bp2, d->part2.get(), d->part3.get(), d->part4.get());
     hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part2.get(), nb, sc + S_BB);
-    hipLaunchKernelGGL(guess_scale_kernel, dim3(1), dim3(1024), 0, st, d->part3.get(), nb, sc);
-    hipLaunchKernelGGL(scale_kernel, dim3((g.ndof + 255) / 256), dim3(256), 0, st, g.ndof,
-                       d->x.get(), sc);
+    hipLaunchKernelGGL(guess_weights_kernel, dim3(1), dim3(1024), 0, st, d->part3.get(),
+                       d->part4.get(), nb, d->nprev, sc);
+    hipLaunchKernelGGL(guess_combine_kernel, dim3((g.ndof + 255) / 256), dim3(256), 0, st, g.ndof,
+                       d->xs[d->x1].get(), d->xs[d->x2].get(), d->nprev, x, sc);
     hipLaunchKernelGGL(guess_residual_kernel, cell_tiles(g.nx, g.ny), dim3(kCX * kCY), 0, st,
-                       op_of(d), d->x.get(), d->r.get(), d->bprev.get(), d->part2.get());
+                       op_of(d), x, d->r.get(), bsave, d->part2.get());
     hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part2.get(), d->ntile,
                        sc + S_RR);
   }
-  d->have_prev = true;
   hipLaunchKernelGGL(clear_done_kernel, dim3(1), dim3(1), 0, st, sc);
   precondition(d, d->r.get(), nullptr, nullptr, d->z.get(), st);
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part1.get(), d->ntile, sc + S_RHO);
@@ -1714,7 +1761,7 @@ int dsa_apply(DSA* d, const double* phi_star, const double* phi_prev, double* ph
   for (; it < max_iter; it += chunk) {
     for (int k = 0; k < chunk; ++k) {
       hipLaunchKernelGGL(spmv_kernel, tiles, dim3(kCX * kCY), 0, st, op_of(d), d->z.get(), pold,
-                         pnew, d->q.get(), d->x.get(), d->part1.get(), sc);
+                         pnew, d->q.get(), x, d->part1.get(), sc);
       hipLaunchKernelGGL(reduce_alpha_kernel, dim3(1), dim3(1024), 0, st, d->part1.get(), d->ntile,
                          sc);
       precondition(d, rcur, d->q.get(), rnext, d->z.get(), st);
@@ -1729,7 +1776,11 @@ int dsa_apply(DSA* d, const double* phi_star, const double* phi_prev, double* ph
     if (hsc[S_DONE] != 0.0) break;
   }
   hipLaunchKernelGGL(axpy_out_kernel, dim3((g.ndof + 255) / 256), dim3(256), 0, st, g.ndof,
-                     phi_star, d->x.get(), d->p0.get(), d->p1.get(), sc, phi_next);
+                     phi_star, x, d->p0.get(), d->p1.get(), sc, phi_next);
+  // this solve becomes the latest of the history
+  std::tie(d->xc, d->x1, d->x2) = std::make_tuple(d->x2, d->xc, d->x1);
+  std::tie(d->bsv, d->b1, d->b2) = std::make_tuple(d->b2, d->bsv, d->b1);
+  d->nprev = std::min(d->nprev + 1, 2);
   RTE_CHECK_HIP(hipGetLastError());
   return (int)hsc[S_ITERS];
 }
