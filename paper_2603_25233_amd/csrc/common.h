@@ -157,6 +157,15 @@ int dsa_apply(DSA* d, const double* phi_star, const double* phi_prev, double* ph
               double rel_tol, hipStream_t st);
 
 // ---------------------------------------------------------------- small device helpers
+// Workgroups are dealt to the eight XCDs in turn (workgroup b to XCD b mod 8), each with
+// its own L2.  This maps the n workgroups of a one-dimensional launch so that each XCD
+// runs a contiguous range of them: neighbouring work items then belong to workgroups of
+// the same XCD, and their loads of shared lines hit its L2.  (A bijection of [0, n).)
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned n) {
+  const unsigned q = n / 8, r = n % 8, x = b % 8;
+  return x * q + min(x, r) + b / 8;
+}
+
 void device_fill(double* p, double v, long n, hipStream_t st);
 // out = sigma_s * phi + G (per cell), G may be null
 template <typename T>

@@ -163,15 +163,6 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return r;
 }
 
-// Workgroups are dealt to the eight XCDs in turn (workgroup b to XCD b mod 8), each with
-// its own L2.  This maps the n workgroups of a one-dimensional launch so that each XCD
-// runs a contiguous range: a cell's neighbours in the rows above and below then belong
-// to workgroups of the same XCD, and their loads hit its L2.  (A bijection of [0, n).)
-__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned n) {
-  const unsigned q = n / 8, r = n % 8, x = b % 8;
-  return x * q + min(x, r) + b / 8;
-}
-
 // Constants of the orthonormal Legendre basis across cells of width h: 1/h, the traces
 // l_0 = 1/sqrt(h) and |l_1| = sqrt(3)/sqrt(h) at the faces, the derivative
 // l_1' = 2 sqrt(3)/h^1.5, and the volume term 12/h^2 of the degree-1 function.

@@ -184,52 +184,49 @@ constexpr int kPiece = 16 / (int)sizeof(T);
 // data of column t, zero for t >= nx) in a 16-byte piece.
 // dsrc: [4][ncell][4], dsig: [4][sig_stride], dbnd: [4][nx + ny - 1][kPiece].
 template <typename T>
-__global__ void diag_layout_kernel(int nx, int ny, int qmask, const double* __restrict__ sigma_t,
-                                   const T* __restrict__ src, const double* __restrict__ bc,
-                                   int mb, double shy, T* __restrict__ dsrc,
-                                   T* __restrict__ dsig, T* __restrict__ dbnd) {
-  const long ncell = (long)nx * ny;
-  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void diag_layout_kernel(int nx, int ny, int qmask,
+                                                         const double* __restrict__ sigma_t,
+                                                         const T* __restrict__ src,
+                                                         const double* __restrict__ bc, int mb,
+                                                         double shy, T* __restrict__ dsrc,
+                                                         T* __restrict__ dsig,
+                                                         T* __restrict__ dbnd) {
+  // One workgroup per anti-diagonal t of quadrant q = blockIdx.y: the diagonal's cells are
+  // gathered from the row-major arrays and stored as one contiguous run (the XCD-contiguous
+  // order of the diagonals lets neighbouring diagonals, which read the other cells of the
+  // same lines, share an L2).
+  const int q = blockIdx.y;
+  if (!((qmask >> q) & 1)) return;
   const int nsteps = nx + ny - 1;
-  if (c < nsteps) {
-    const int t = (int)c;
+  const int t = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int sx = (q & 1) ? -1 : 1, sy = (q & 2) ? -1 : 1;
+  const long ncell = (long)nx * ny;
+  if (threadIdx.x == 0) {  // the y-inflow piece of canonical row 0
+    T v[kPiece<T>];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (!((qmask >> q) & 1)) continue;
-      const int sx = (q & 1) ? -1 : 1, sy = (q & 2) ? -1 : 1;
-      T v[kPiece<T>];
-#pragma unroll
-      for (int i = 0; i < kPiece<T>; ++i) v[i] = T(0);
-      if (bc && t < nx) {
-        const int col = sx > 0 ? t : nx - 1 - t;
-        const int yside = sy > 0 ? 2 : 3;
-        v[0] = T(shy * bc[((long)yside * mb + col) * 2 + 0]);
-        v[1] = T(shy * bc[((long)yside * mb + col) * 2 + 1] * sx);
-      }
-#pragma unroll
-      for (int i = 0; i < kPiece<T>; ++i) dbnd[((long)q * nsteps + t) * kPiece<T> + i] = v[i];
+    for (int i = 0; i < kPiece<T>; ++i) v[i] = T(0);
+    if (bc && t < nx) {
+      const int col = sx > 0 ? t : nx - 1 - t;
+      const int yside = sy > 0 ? 2 : 3;
+      v[0] = T(shy * bc[((long)yside * mb + col) * 2 + 0]);
+      v[1] = T(shy * bc[((long)yside * mb + col) * 2 + 1] * sx);
     }
+#pragma unroll
+    for (int i = 0; i < kPiece<T>; ++i) dbnd[((long)q * nsteps + t) * kPiece<T> + i] = v[i];
   }
-  if (c >= ncell) return;
-  const int acol = (int)(c % nx), brow = (int)(c / nx);
-  Vec4<T> s4;  // src == null: per-direction sources, laid out by diag_src_dirs_kernel
-  if (src) s4 = load4(src + 4 * c);
-  const T sg = T(sigma_t[c]);
-  const long qs = sig_stride<T>(nx, ny);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    if (!((qmask >> q) & 1)) continue;
-    const int sx = (q & 1) ? -1 : 1, sy = (q & 2) ? -1 : 1;
-    const int r = sy > 0 ? brow : ny - 1 - brow;
-    const int ap = sx > 0 ? acol : nx - 1 - acol;
-    const int t = r + ap;
-    const int lo = t >= nx ? t - nx + 1 : 0;
-    const long k = q * ncell + diag_first(t, nx, ny) + r - lo;
-    if (src) {
+  const int lo = t >= nx ? t - nx + 1 : 0, hi = t < ny ? t : ny - 1;
+  const long k0 = q * ncell + diag_first(t, nx, ny) - lo;
+  const long s0 = q * sig_stride<T>(nx, ny) + sig_first<T>(t, nx, ny) - lo;
+  for (int r = lo + (int)threadIdx.x; r <= hi; r += blockDim.x) {
+    const int ap = t - r;
+    const int acol = sx > 0 ? ap : nx - 1 - ap, brow = sy > 0 ? r : ny - 1 - r;
+    const long c = (long)brow * nx + acol;
+    if (src) {  // src == null: per-direction sources, laid out by diag_src_dirs_kernel
+      const Vec4<T> s4 = load4(src + 4 * c);
       const T v[4] = {s4.v[0], T(sx) * s4.v[1], T(sy) * s4.v[2], T(sx * sy) * s4.v[3]};
-      store4(dsrc + 4 * k, v);
+      store4(dsrc + 4 * (k0 + r), v);
     }
-    dsig[q * qs + sig_first<T>(t, nx, ny) + r - lo] = sg;
+    dsig[s0 + r] = T(sigma_t[c]);
   }
 }
 
@@ -991,10 +988,9 @@ void sweep_enqueue(const Geom& g, const SweepPlan& pl, const SweepDir* dirs_dev,
   T* part = work + sweep_input_elems(g);
   const double shx = std::sqrt(g.hx), shy = std::sqrt(g.hy);
   {
-    const int tb = 256;
-    hipLaunchKernelGGL((diag_layout_kernel<T>), dim3((ncell + tb - 1) / tb), dim3(tb), 0, st, g.nx,
-                       g.ny, pl.qmask, sigma_t, pl.dsrc ? nullptr : src, bc, g.mb, shy, dsrc, dsig,
-                       dbnd);
+    hipLaunchKernelGGL((diag_layout_kernel<T>), dim3((unsigned)(g.nx + g.ny - 1), 4), dim3(256), 0,
+                       st, g.nx, g.ny, pl.qmask, sigma_t, pl.dsrc ? nullptr : src, bc, g.mb, shy,
+                       dsrc, dsig, dbnd);
     RTE_CHECK_HIP(hipGetLastError());
   }
   if (pl.dsrc) {  // each direction's own source, in its quadrant's diagonal-major order
