@@ -34,6 +34,7 @@
 // V-cycle's stencils are read in FP32 (built in FP64 and rounded once, so the
 // preconditioner stays a fixed symmetric operator, as CG needs; every sum is FP64).
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <tuple>
@@ -84,6 +85,8 @@ struct DSA {
   DevBuf<double> cinv;                         // dense inverse on the coarsest grid
   int ncoarse = 0;                             // its size (0: smoothing only)
   int lsmall = 0;                              // first level of the one-workgroup V-cycle
+  int tile_blocks = 0;                         // levels below this many large-tile blocks
+                                               // take the small tiles
   DevBuf<MgDev> mgdev;                         // device views of every level
   std::vector<int> small_off;                  // LDS offsets of the one-workgroup cycle
   size_t small_lds = 0;                        // its LDS bytes (0: it runs on global memory)
@@ -535,18 +538,22 @@ __device__ __forceinline__ double lds_stencil(const float* a, const double* v, i
 // t = b - A x, and bc = R t.  y lives on the fine nodes 2 I0 - 3 .. 2 I0 + 2 CX + 1 (x one
 // node in, t two), so that the restriction of the block's coarse nodes finds t on all
 // their fine neighbours.
-constexpr int kDX = 32, kDY = 8;  // coarse nodes per down block (fine tile 64 x 16)
+// The tile is CX x CY coarse nodes: 32 x 8 (fine tile 64 x 16) on the large grids, 8 x 8 on
+// the others (kSmallTileBlocks), which then run more, shorter blocks: a block's time is
+// mostly the latency of its three dependent load phases, not its arithmetic.
+constexpr int kDX = 32, kDY = 8, kDXs = 8, kDYs = 8;
+template <int CX, int CY>
 __global__ __launch_bounds__(256) void mg_down_kernel(int mx, int my, const float* __restrict__ A9,
                                                      const double* __restrict__ dinv,
                                                      const double* __restrict__ b,
                                                      double* __restrict__ x, int mxc, int myc,
                                                      double* __restrict__ bc,
                                                      const double* __restrict__ sc) {
-  constexpr int WY = 2 * kDX + 5, HY = 2 * kDY + 5, WX = WY - 2, HX = HY - 2, WT = WY - 4,
+  constexpr int WY = 2 * CX + 5, HY = 2 * CY + 5, WX = WY - 2, HX = HY - 2, WT = WY - 4,
                 HT = HY - 4;
   __shared__ double Y[HY * WY], X[HX * WX], T[HT * WT];
   if (sc[S_DONE] != 0.0) return;
-  const int I0 = (int)blockIdx.x * kDX, J0 = (int)blockIdx.y * kDY;
+  const int I0 = (int)blockIdx.x * CX, J0 = (int)blockIdx.y * CY;
   const int fi = 2 * I0 - 3, fj = 2 * J0 - 3;  // fine node of Y[0]
   auto inside = [&](int i, int j) { return i >= 0 && i < mx && j >= 0 && j < my; };
   auto node = [&](int i, int j) {  // clamped into the grid
@@ -592,7 +599,7 @@ __global__ __launch_bounds__(256) void mg_down_kernel(int mx, int my, const floa
     if (inside(i, j)) {
       const int ey0 = (ey + 1) * WY + ex + 1;
       v = Y[ey0] + in2[k].dinv * (in2[k].b - lds_stencil(in2[k].a, Y, WY, ey0));
-      if (i >= 2 * I0 && i < 2 * I0 + 2 * kDX && j >= 2 * J0 && j < 2 * J0 + 2 * kDY)
+      if (i >= 2 * I0 && i < 2 * I0 + 2 * CX && j >= 2 * J0 && j < 2 * J0 + 2 * CY)
         x[(long)j * mx + i] = v;
     }
     X[e] = v;
@@ -611,8 +618,8 @@ __global__ __launch_bounds__(256) void mg_down_kernel(int mx, int my, const floa
   __syncthreads();
   // full weighting (transpose of bilinear interpolation): fine node (2I + di, 2J + dj) has
   // weight (1 - |di|/2)(1 - |dj|/2) in coarse node (I, J)
-  for (int e = threadIdx.x; e < kDX * kDY; e += blockDim.x) {
-    const int I = I0 + e % kDX, J = J0 + e / kDX;
+  for (int e = threadIdx.x; e < CX * CY; e += blockDim.x) {
+    const int I = I0 + e % CX, J = J0 + e / CX;
     if (I >= mxc || J >= myc) continue;
     double s = 0.0;
 #pragma unroll
@@ -633,7 +640,9 @@ __global__ __launch_bounds__(256) void mg_down_kernel(int mx, int my, const floa
 // Up, for the fine nodes [i0, i0 + kUX) x [j0, j0 + kUY): with y = x + P xc (bilinear
 // prolongation), t = y + dinv (b - A y), xout = t + dinv (b - A t).  y lives two nodes
 // around the tile, t one.
-constexpr int kUX = 64, kUY = 16;
+// The tile is UX x UY fine nodes: 64 x 16 on the large grids, 16 x 16 on the small ones.
+constexpr int kUX = 64, kUY = 16, kUXs = 16, kUYs = 16;
+template <int UX, int UY>
 __global__ __launch_bounds__(256) void mg_up_kernel(int mx, int my, const float* __restrict__ A9,
                                                    const double* __restrict__ dinv,
                                                    const double* __restrict__ b,
@@ -641,10 +650,10 @@ __global__ __launch_bounds__(256) void mg_up_kernel(int mx, int my, const float*
                                                    const double* __restrict__ xc,
                                                    double* __restrict__ xout,
                                                    const double* __restrict__ sc) {
-  constexpr int WY = kUX + 4, HY = kUY + 4, WT = kUX + 2, HT = kUY + 2;
+  constexpr int WY = UX + 4, HY = UY + 4, WT = UX + 2, HT = UY + 2;
   __shared__ double Y[HY * WY], T[HT * WT];
   if (sc[S_DONE] != 0.0) return;
-  const int i0 = (int)blockIdx.x * kUX, j0 = (int)blockIdx.y * kUY;
+  const int i0 = (int)blockIdx.x * UX, j0 = (int)blockIdx.y * UY;
   const int fi = i0 - 2, fj = j0 - 2;  // fine node of Y[0]
   auto inside = [&](int i, int j) { return i >= 0 && i < mx && j >= 0 && j < my; };
   auto node = [&](int i, int j) {  // clamped into the grid
@@ -652,7 +661,7 @@ __global__ __launch_bounds__(256) void mg_up_kernel(int mx, int my, const float*
   };
   const int myc = (my + 1) / 2;
   auto cnode = [&](int I, int J) { return (long)min(J, myc - 1) * mxc + min(I, mxc - 1); };
-  constexpr int K1 = per_thread<HY * WY>(), K2 = per_thread<HT * WT>(), K3 = per_thread<kUX * kUY>();
+  constexpr int K1 = per_thread<HY * WY>(), K2 = per_thread<HT * WT>(), K3 = per_thread<UX * UY>();
   double xv[K1], c[K1][4];
   NodeIn in2[K2], in3[K3];
   auto load2 = [&] {
@@ -666,7 +675,7 @@ __global__ __launch_bounds__(256) void mg_up_kernel(int mx, int my, const float*
 #pragma unroll
     for (int k = 0; k < K3; ++k) {
       const int e = (int)threadIdx.x + 256 * k;
-      in3[k] = load_node(A9, dinv, b, node(i0 + e % kUX, j0 + e / kUX));
+      in3[k] = load_node(A9, dinv, b, node(i0 + e % UX, j0 + e / UX));
     }
   };
 #pragma unroll
@@ -705,7 +714,7 @@ __global__ __launch_bounds__(256) void mg_up_kernel(int mx, int my, const float*
 #pragma unroll
   for (int k = 0; k < K3; ++k) {
     const int e = (int)threadIdx.x + 256 * k;
-    const int ex = e % kUX, ey = e / kUX, i = i0 + ex, j = j0 + ey;
+    const int ex = e % UX, ey = e / UX, i = i0 + ex, j = j0 + ey;
     if (!inside(i, j)) continue;
     const int ey0 = (ey + 1) * WT + ex + 1;
     xout[(long)j * mx + i] = T[ey0] + in3[k].dinv * (in3[k].b - lds_stencil(in3[k].a, T, WT, ey0));
@@ -1514,11 +1523,22 @@ void plan_small_cycle(DSA* d, size_t budget) {
 
 // The blocks, the nodal hierarchy and its smoothers are assembled on the device; only
 // the coarsest grid (at most kCoarseDense nodes) is inverted on the host.
+// grids whose large-tile launch has fewer blocks than this (four per compute unit) take the
+// small tiles: at 1024 x 1024 cells, the 513^2 .. 65^2 grids.  RTE_MG_TILE_BLOCKS overrides
+// it (0: large tiles on every level); both tile shapes give bitwise the same cycle.
+constexpr int kSmallTileBlocks = 1024;
+
+static int tile_blocks_setting() {
+  const char* v = std::getenv("RTE_MG_TILE_BLOCKS");
+  return v && v[0] ? std::max(0, std::atoi(v)) : kSmallTileBlocks;
+}
+
 DSA* dsa_create(const Geom& g, const double* sigma_t_dev, const double* sigma_s_dev,
                 hipStream_t st) {
   DSA* d = new DSA();
   try {
     d->g = g;
+    d->tile_blocks = tile_blocks_setting();
     const long n = g.ncell;
     DevBuf<int> bad(1);
     RTE_CHECK_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), st));
@@ -1660,13 +1680,27 @@ void vcycle(DSA* d, int l, hipStream_t st) {
     return;
   }
   MgLevel& C = *d->mg[l + 1];
-  const dim3 down((unsigned)((C.mx + kDX - 1) / kDX), (unsigned)((C.my + kDY - 1) / kDY));
-  hipLaunchKernelGGL(mg_down_kernel, down, dim3(256), 0, st, L.mx, L.my, L.A9c.get(), L.dinv.get(),
-                     L.b.get(), L.x.get(), C.mx, C.my, C.b.get(), sc);
+  auto grid = [](int mx, int my, int tx, int ty) {
+    return dim3((unsigned)((mx + tx - 1) / tx), (unsigned)((my + ty - 1) / ty));
+  };
+  const dim3 down = grid(C.mx, C.my, kDX, kDY);
+  if (down.x * down.y >= (unsigned)d->tile_blocks)
+    hipLaunchKernelGGL((mg_down_kernel<kDX, kDY>), down, dim3(256), 0, st, L.mx, L.my,
+                       L.A9c.get(), L.dinv.get(), L.b.get(), L.x.get(), C.mx, C.my, C.b.get(), sc);
+  else
+    hipLaunchKernelGGL((mg_down_kernel<kDXs, kDYs>), grid(C.mx, C.my, kDXs, kDYs), dim3(256), 0, st,
+                       L.mx, L.my, L.A9c.get(), L.dinv.get(), L.b.get(), L.x.get(), C.mx, C.my,
+                       C.b.get(), sc);
   vcycle(d, l + 1, st);
-  const dim3 up((unsigned)((L.mx + kUX - 1) / kUX), (unsigned)((L.my + kUY - 1) / kUY));
-  hipLaunchKernelGGL(mg_up_kernel, up, dim3(256), 0, st, L.mx, L.my, L.A9c.get(), L.dinv.get(),
-                     L.b.get(), L.x.get(), C.mx, level_solution(d, l + 1), L.t.get(), sc);
+  const dim3 up = grid(L.mx, L.my, kUX, kUY);
+  if (up.x * up.y >= (unsigned)d->tile_blocks)
+    hipLaunchKernelGGL((mg_up_kernel<kUX, kUY>), up, dim3(256), 0, st, L.mx, L.my, L.A9c.get(),
+                       L.dinv.get(), L.b.get(), L.x.get(), C.mx, level_solution(d, l + 1),
+                       L.t.get(), sc);
+  else
+    hipLaunchKernelGGL((mg_up_kernel<kUXs, kUYs>), grid(L.mx, L.my, kUXs, kUYs), dim3(256), 0, st,
+                       L.mx, L.my, L.A9c.get(), L.dinv.get(), L.b.get(), L.x.get(), C.mx,
+                       level_solution(d, l + 1), L.t.get(), sc);
 }
 
 // z = M^{-1} r, part1 = r.z per tile.  M^{-1} is the symmetric two-level preconditioner

@@ -40,6 +40,29 @@ def test_full_rank_fp64(wl):
     assert np.allclose(got["history"], ref["history"], rtol=1e-7, atol=1e-16)
 
 
+def test_full_rank_multigrid_tile_shapes(monkeypatch):
+    """The DSA's fused multigrid levels run on grids larger than the one-workgroup cycle
+    holds; here 101 x 71 and 51 x 36 nodes (100 x 70 cells, log-normal sigma_t), each over
+    several ragged blocks.  RTE_MG_TILE_BLOCKS = 0 gives the large tiles on every level, a
+    huge value the small ones: both form every node's value by the same sums in the same
+    order, so the two solves agree bitwise, and they match the oracle."""
+    import paper_2603_25233_amd as R
+    base = W.multiscale(n=100, n_theta=4, n_z=2, corr=4.0)
+    wl = W.Workload(base, ny=70, sigma_t=base["sigma_t"][:70], sigma_s=base["sigma_s"][:70])
+    ref = osi.fr_si_dsa(oracle_problem(wl), wl["eps_si"], max_outer=wl["max_outer"])
+    got = {}
+    for blocks in ("0", "1000000"):
+        monkeypatch.setenv("RTE_MG_TILE_BLOCKS", blocks)
+        got[blocks] = R.solve(gpu_problem(wl), full_rank=1, eps_si=wl["eps_si"],
+                              max_outer=wl["max_outer"], eps_dsa=1e-13)
+    large, small = got["0"], got["1000000"]
+    assert large["dsa_iters"] == small["dsa_iters"] > 0
+    assert torch.equal(large["phi"], small["phi"])
+    assert large["converged"] and ref["converged"]
+    assert large["iters"] == ref["iters"]
+    assert rel_l2(large["phi"].cpu().numpy(), ref["phi"]) < 1e-10
+
+
 FR_MIXED_CASES = [
     ("small_fr_32", W.small_fr()),
     ("checker32", W.checkerboard(n=32, n_theta=8, n_z=4, blocks=4)),
