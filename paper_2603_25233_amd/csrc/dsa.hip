@@ -891,16 +891,12 @@ __global__ __launch_bounds__(kSmallThreads) void mg_small_kernel(const MgDev* __
   }
 }
 
-// b0 = P^T r: node (i, j) collects corner (i - a, j - b) of each adjacent cell (a, b)
-__global__ __launch_bounds__(256) void dg_restrict_kernel(int nx, int ny, Emb em,
-                                                         const double* __restrict__ r,
-                                                         double* __restrict__ b0,
-                                                         const double* __restrict__ sc) {
-  if (sc[S_DONE] != 0.0) return;
-  const int mx = nx + 1, my = ny + 1;
-  const long n = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (n >= (long)mx * my) return;
-  const int i = (int)(n % mx), j = (int)(n / mx);
+// b0 = P^T r at node (i, j): the corner (i - a, j - b) of each adjacent cell (a, b), the
+// cells' rows in increasing order, then their columns; tval(a, b, k) is r's entry k in cell
+// (a, b).  Every caller sums in this one order.
+template <class F>
+__device__ __forceinline__ double node_restrict(const Emb& em, int nx, int ny, int i, int j,
+                                                F tval) {
   double s = 0.0;
 #pragma unroll
   for (int cb = 0; cb < 2; ++cb) {
@@ -910,12 +906,11 @@ __global__ __launch_bounds__(256) void dg_restrict_kernel(int nx, int ny, Emb em
     for (int ca = 0; ca < 2; ++ca) {
       const int a = i - 1 + ca;
       if (a < 0 || a >= nx) continue;
-      const double* rc = r + 4 * ((long)b * nx + a);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) s += em.w(k, i - a, j - b) * rc[k];
+      for (int k = 0; k < 4; ++k) s += em.w(k, i - a, j - b) * tval(a, b, k);
     }
   }
-  b0[n] = s;
+  return s;
 }
 
 // The preconditioner's two smoothing passes (symmetric two-level, damped block Jacobi
@@ -1053,7 +1048,8 @@ __global__ __launch_bounds__(kCX * kCY) void dg_smooth1_kernel(OpA op,
                                                               const double* __restrict__ q,
                                                               double* __restrict__ rout, double w,
                                                               double* __restrict__ z1,
-                                                              double* __restrict__ t,
+                                                              Emb em, double* __restrict__ t,
+                                                              double* __restrict__ b0,
                                                               double* __restrict__ part2,
                                                               const double* __restrict__ sc) {
   __shared__ double tile[4 * kCW * kCH];
@@ -1076,24 +1072,82 @@ __global__ __launch_bounds__(kCX * kCY) void dg_smooth1_kernel(OpA op,
   });
   const int lx = (int)threadIdx.x % kCX, ly = (int)threadIdx.x / kCX;
   const int a = (int)blockIdx.x * kCX + lx, b = (int)blockIdx.y * kCY + ly;
-  double rr = 0.0;
-  if (a < nx && b < ny) {
+  double rr = 0.0, tv[4];
+  const bool in = a < nx && b < ny;
+  if (in) {
     const long c = (long)b * nx + a;
     double u[4], acc[4], r[4];
     tile_apply(op, tile, dtile, (ly + 1) * kCW + lx + 1, c, a, b, u, acc);
     rv(c, r);
+    const bool edge = lx == 0 || lx == kCX - 1 || ly == 0 || ly == kCY - 1;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       if (kUpd) rout[4 * c + k] = r[k];
       rr += r[k] * r[k];
       z1[4 * c + k] = u[k];
-      t[4 * c + k] = r[k] - acc[k];
+      tv[k] = r[k] - acc[k];
+      if (edge) t[4 * c + k] = tv[k];
+    }
+  }
+  // b0 = P^T t on the nodes whose cells all lie in this tile, from t in LDS (the tile's
+  // array is free once every thread has applied the block product)
+  __syncthreads();
+  if (in) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) tile[4 * (ly * kCX + lx) + k] = tv[k];
+  }
+  __syncthreads();
+  {
+    const int a0 = (int)blockIdx.x * kCX, c0 = (int)blockIdx.y * kCY;
+    const int aend = min(a0 + kCX, nx), cend = min(c0 + kCY, ny);
+    const int ilo = a0 == 0 ? 0 : a0 + 1, ihi = aend == nx ? nx : aend - 1;
+    const int jlo = c0 == 0 ? 0 : c0 + 1, jhi = cend == ny ? ny : cend - 1;
+    const int wn = ihi - ilo + 1, hn = jhi - jlo + 1;
+    for (int e = (int)threadIdx.x; e < wn * hn; e += kCX * kCY) {
+      const int i = ilo + e % wn, j = jlo + e / wn;
+      b0[(long)j * (nx + 1) + i] = node_restrict(em, nx, ny, i, j, [&](int ca, int cb, int k) {
+        return tile[4 * ((cb - c0) * kCX + ca - a0) + k];
+      });
     }
   }
   if (kUpd) {
     const double s = block_sum(rr, red);
     if (threadIdx.x == 0) part2[blockIdx.y * gridDim.x + blockIdx.x] = s;
   }
+}
+
+// b0 on the nodes that cell tiles share (node columns i = kCX m and rows j = kCY m strictly
+// inside the grid): dg_smooth1_kernel restricts every other node from its tile in LDS and
+// stores t on its edge cells for this kernel.  Nodes on the shared rows come first (nrow of
+// them), then those on the shared columns that are not on a shared row.
+__global__ __launch_bounds__(256) void dg_restrict_edges_kernel(int nx, int ny, Emb em,
+                                                               const double* __restrict__ t,
+                                                               double* __restrict__ b0,
+                                                               const double* __restrict__ sc) {
+  if (sc[S_DONE] != 0.0) return;
+  const int mx = nx + 1;
+  const int nxe = (nx - 1) / kCX, nye = (ny - 1) / kCY;  // shared columns, shared rows
+  const long nrow = (long)nye * mx;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  int i, j;
+  if (e < nrow) {
+    j = kCY * (int)(e / mx + 1);
+    i = (int)(e % mx);
+  } else {
+    const long f = e - nrow;
+    if (f >= (long)nxe * (ny + 1)) return;
+    i = kCX * (int)(f / (ny + 1) + 1);
+    j = (int)(f % (ny + 1));
+    if (j > 0 && j < ny && j % kCY == 0) return;  // on a shared row
+  }
+  b0[(long)j * mx + i] = node_restrict(em, nx, ny, i, j, [&](int a, int b, int k) {
+    return t[4 * ((long)b * nx + a) + k];
+  });
+}
+
+// number of nodes dg_restrict_edges_kernel handles (one thread each)
+long restrict_edge_threads(int nx, int ny) {
+  return (long)((ny - 1) / kCY) * (nx + 1) + (long)((nx - 1) / kCX) * (ny + 1);
 }
 
 // Second: z2 = z1 + P x0 (the prolonged coarse correction), z = z2 + S (r - A z2);
@@ -1720,14 +1774,16 @@ void precondition(DSA* d, const double* rin, const double* q, double* rout, doub
   const double* r = q ? rout : rin;
   if (q)
     hipLaunchKernelGGL(dg_smooth1_kernel<true>, cell_tiles(g.nx, g.ny), dim3(kCX * kCY), 0, st, op,
-                       d->mc.get(), rin, q, rout, kSmoothW, d->z1.get(), d->t.get(),
-                       d->part2.get(), sc);
+                       d->mc.get(), rin, q, rout, kSmoothW, d->z1.get(), em, d->t.get(),
+                       L0.b.get(), d->part2.get(), sc);
   else
     hipLaunchKernelGGL(dg_smooth1_kernel<false>, cell_tiles(g.nx, g.ny), dim3(kCX * kCY), 0, st,
-                       op, d->mc.get(), rin, nullptr, nullptr, kSmoothW, d->z1.get(), d->t.get(),
-                       nullptr, sc);
-  hipLaunchKernelGGL(dg_restrict_kernel, dim3(nblocks((long)L0.mx * L0.my)), dim3(256), 0, st, g.nx,
-                     g.ny, em, d->t.get(), L0.b.get(), sc);
+                       op, d->mc.get(), rin, nullptr, nullptr, kSmoothW, d->z1.get(), em,
+                       d->t.get(), L0.b.get(), nullptr, sc);
+  const long ne = restrict_edge_threads(g.nx, g.ny);
+  if (ne > 0)
+    hipLaunchKernelGGL(dg_restrict_edges_kernel, dim3(nblocks(ne)), dim3(256), 0, st, g.nx, g.ny,
+                       em, d->t.get(), L0.b.get(), sc);
   vcycle(d, 0, st);
   hipLaunchKernelGGL(dg_smooth2_kernel, cell_tiles(g.nx, g.ny), dim3(kCX * kCY), 0, st, op, em,
                      d->mc.get(), r, d->z1.get(), level_solution(d, 0), kSmoothW, z, d->part1.get(), sc);
