@@ -78,6 +78,7 @@ struct DSA {
   // bs[b2], bs[bsv]); roles rotate after each solve.  nprev: previous solves held (<= 2).
   DevBuf<double> xs[3], bs[3];
   int xc = 0, x1 = 1, x2 = 2, bsv = 0, b1 = 1, b2 = 2, nprev = 0;
+  int last_iters = 0;  // CG iterations of the previous solve
   DevBuf<double> scal;                         // device scalars (see Sc below)
   int nblk = 0;                                // blocks of the cell kernels
   int ntile = 0;                               // tiles of the smoothing passes
@@ -1836,11 +1837,15 @@ int dsa_apply(DSA* d, const double* phi_star, const double* phi_prev, double* ph
   double* rcur = d->r.get();
   double* rnext = d->r2.get();
   const dim3 tiles = cell_tiles(g.nx, g.ny);
-  const int chunk = 4, max_iter = 40000;
+  // Iterations are enqueued in batches, the done flag read back after each: the first batch
+  // is one fewer than the previous solve took (successive solves need about as many), the
+  // later ones short, so that few iterations are enqueued after convergence (they return at
+  // once) and the host waits on the stream only once or twice per solve.
+  const int max_iter = 40000;
+  int batch = std::max(d->last_iters - 1, 4);
   double hsc[S_N];
-  int it = 0;
-  for (; it < max_iter; it += chunk) {
-    for (int k = 0; k < chunk; ++k) {
+  for (int it = 0; it < max_iter; it += batch, batch = 2) {
+    for (int k = 0; k < batch; ++k) {
       hipLaunchKernelGGL(spmv_kernel, tiles, dim3(kCX * kCY), 0, st, op_of(d), d->z.get(), pold,
                          pnew, d->q.get(), x, d->part1.get(), sc);
       hipLaunchKernelGGL(reduce_alpha_kernel, dim3(1), dim3(1024), 0, st, d->part1.get(), d->ntile,
@@ -1862,8 +1867,9 @@ int dsa_apply(DSA* d, const double* phi_star, const double* phi_prev, double* ph
   std::tie(d->xc, d->x1, d->x2) = std::make_tuple(d->x2, d->xc, d->x1);
   std::tie(d->bsv, d->b1, d->b2) = std::make_tuple(d->b2, d->bsv, d->b1);
   d->nprev = std::min(d->nprev + 1, 2);
+  d->last_iters = (int)hsc[S_ITERS];
   RTE_CHECK_HIP(hipGetLastError());
-  return (int)hsc[S_ITERS];
+  return d->last_iters;
 }
 
 }  // namespace rte
