@@ -11,9 +11,10 @@
 // Legendre basis every face integral factorises: a vertical face couples the
 // x-degrees p through a 2x2 matrix and leaves the y-degree q alone (and vice
 // versa), with traces l_p(+-1) = (1, +-sqrt3)/sqrt(h) and d/dx l_p = (0, 2 sqrt3/h^1.5).
-// The 4x4 blocks are built on the host in closed form; the SPD system is solved by
-// conjugate gradients, all scalars kept on the device and every reduction done in a
-// fixed order.  Preconditioner (symmetric two-level, symmetric positive definite):
+// The 4x4 blocks are built on the device in closed form (one thread per cell); the SPD
+// system is solved by conjugate gradients, all scalars kept on the device and every
+// reduction done in a fixed order.  Preconditioner (symmetric two-level, symmetric
+// positive definite):
 //   z1 = S r,  z2 = z1 + P V P^T (r - A z1),  M^{-1} r = z2 + S (r - A z2),
 // S = w B^{-1} with B the 4x4 diagonal blocks and w = 0.7 (B^{-1} A has its spectrum in
 // (0, 2), so 2 S^{-1} - A is positive definite), P the embedding of continuous bilinear
