@@ -1205,36 +1205,34 @@ __global__ __launch_bounds__(kCX * kCY) void dg_smooth2_kernel(OpA op, Emb em,
   if (threadIdx.x == 0) part1[blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
-// r = b = sigma_s (phi* - phi_prev); x = 0; p_old = 0; part2 = r.r
 // r = b = sigma_s (phi* - phi_prev); p_old = 0; part2 = b.b.  Without a previous solve
 // (kPrev false): x = 0 and bsave = b.  With one: part3 = b.b1 and, when there are two,
 // part4 = b.b2 (the guess is then formed and its residual by guess_residual_kernel, which
-// also stores bsave = b).
+// also stores bsave = b).  One degree of freedom per thread, so that every load and store
+// is one contiguous run per wavefront; a block of kInitThreads covers kInitThreads / 4
+// cells, one partial sum each.
+constexpr int kInitThreads = 1024;
 template <bool kPrev>
-__global__ __launch_bounds__(256) void init_r_kernel(
+__global__ __launch_bounds__(kInitThreads) void init_r_kernel(
     long ncell, const double* __restrict__ sig_s, const double* __restrict__ phis,
     const double* __restrict__ phip, double* __restrict__ x, double* __restrict__ r,
     double* __restrict__ pold, double* __restrict__ bsave, const double* __restrict__ b1,
     const double* __restrict__ b2, double* __restrict__ part2, double* __restrict__ part3,
     double* __restrict__ part4) {
-  __shared__ double red[256];
-  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double red[kInitThreads];
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double rr = 0.0, r1 = 0.0, r2 = 0.0;
-  if (c < ncell) {
-    const double s = sig_s[c];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const double rv = s * (phis[4 * c + k] - phip[4 * c + k]);
-      r[4 * c + k] = rv;
-      pold[4 * c + k] = 0.0;
-      rr += rv * rv;
-      if (kPrev) {
-        r1 += rv * b1[4 * c + k];
-        if (b2) r2 += rv * b2[4 * c + k];
-      } else {
-        x[4 * c + k] = 0.0;
-        bsave[4 * c + k] = rv;
-      }
+  if (i < 4 * ncell) {
+    const double rv = sig_s[i >> 2] * (phis[i] - phip[i]);
+    r[i] = rv;
+    pold[i] = 0.0;
+    rr = rv * rv;
+    if (kPrev) {
+      r1 = rv * b1[i];
+      if (b2) r2 = rv * b2[i];
+    } else {
+      x[i] = 0.0;
+      bsave[i] = rv;
     }
   }
   const double s = block_sum(rr, red);
@@ -1806,14 +1804,14 @@ int dsa_apply(DSA* d, const double* phi_star, const double* phi_prev, double* ph
   double* x = d->xs[d->xc].get();
   double* bsave = d->bs[d->bsv].get();
   if (d->nprev == 0) {
-    hipLaunchKernelGGL(init_r_kernel<false>, dim3(nb), dim3(256), 0, st, n, d->sig_s.get(),
+    hipLaunchKernelGGL(init_r_kernel<false>, dim3(nb), dim3(kInitThreads), 0, st, n, d->sig_s.get(),
                        phi_star, phi_prev, x, d->r.get(), d->p0.get(), bsave, nullptr, nullptr,
                        d->part2.get(), nullptr, nullptr);
     hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part2.get(), nb, sc + S_BB);
     hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part2.get(), nb, sc + S_RR);
   } else {
     const double* bp2 = d->nprev > 1 ? d->bs[d->b2].get() : nullptr;
-    hipLaunchKernelGGL(init_r_kernel<true>, dim3(nb), dim3(256), 0, st, n, d->sig_s.get(),
+    hipLaunchKernelGGL(init_r_kernel<true>, dim3(nb), dim3(kInitThreads), 0, st, n, d->sig_s.get(),
                        phi_star, phi_prev, x, d->r.get(), d->p0.get(), nullptr,
                        d->bs[d->b1].get(), bp2, d->part2.get(), d->part3.get(), d->part4.get());
     hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, d->part2.get(), nb, sc + S_BB);
